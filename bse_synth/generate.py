@@ -1,0 +1,123 @@
+"""Seeded synthetic inputs of the BSE hot path.
+
+Draws the quantities the paper's earlier tasks would produce (Kohn-Sham
+energies, plane-wave pair matrix elements, the static screened interaction)
+as random arrays of the right shapes and magnitudes.  No step of the BSE
+method itself happens here.
+
+Recipe (all complex draws are standard complex normal, E|z|^2 = 1):
+  eps_v[k, v] ~ U(eps_v_range)          (or a flat core level)
+  eps_c[k, c] ~ U(eps_c_range)
+  Mcv[a, G]        ~ CN / (1 + |G+Q|^2)  (or exp(-|G+Q|^2 / (2 w^2)) for core)
+  Mvv[p, v, v', G] ~ CN / (1 + |G|^2)    (pairs p = (ik <= ik'))
+  Mcc[p, c, c', G] ~ CN / (1 + |G|^2)
+  Ncv[p, c, v', G], Nvc[p, v, c', G]  as Mvv (full BSE only)
+  W[q] = v^1/2(q+G) (I + L_q L_q^H)^-1 v^1/2(q+G'),  L_q ~ 0.3 CN (NG x 8),
+         v(p) = 4 pi / |p|^2 with |p|^2 replaced by 0.01 at p = 0.
+Transition index a = (ik * nv + iv) * nc + ic.
+
+Large arrays are drawn in fixed-size chunks, each from its own Philox stream
+keyed by (seed, array, chunk), so the result does not depend on the number of
+threads.
+"""
+from __future__ import annotations
+
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from . import lattice
+from .workloads import Workload
+
+_KIND = {"eps_v": 1, "eps_c": 2, "Mcv": 3, "Mvv": 4, "Mcc": 5, "Ncv": 6, "Nvc": 7, "L": 8}
+_CHUNK_ROWS = 1024
+_INV_SQRT2 = 1.0 / np.sqrt(2.0)
+
+
+def _rng(seed: int, kind: str, chunk: int) -> np.random.Generator:
+    ss = np.random.SeedSequence(entropy=seed, spawn_key=(_KIND[kind], chunk))
+    return np.random.Generator(np.random.Philox(ss))
+
+
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _complex_rows(seed: int, kind: str, shape: tuple, envelope: np.ndarray) -> np.ndarray:
+    """Complex normal array of `shape` (rows first), times a real envelope that
+    broadcasts against one row."""
+    out = np.empty(shape, dtype=np.complex128)
+    rows = shape[0]
+    nchunks = (rows + _CHUNK_ROWS - 1) // _CHUNK_ROWS
+    env = (envelope * _INV_SQRT2).astype(np.float64)
+
+    def fill(ci: int) -> None:
+        lo, hi = ci * _CHUNK_ROWS, min(rows, (ci + 1) * _CHUNK_ROWS)
+        blk = out[lo:hi]
+        _rng(seed, kind, ci).standard_normal(out=blk.view(np.float64))
+        blk *= env
+
+    if nchunks == 1:
+        fill(0)
+    else:
+        with ThreadPoolExecutor(_threads()) as ex:
+            list(ex.map(fill, range(nchunks)))
+    return out
+
+
+def screened_interaction(w: Workload) -> np.ndarray:
+    """W[iq, G, G'] for every q of the mesh (the BSE's input from screening)."""
+    ng, n = w.ng, w.mesh
+    G = lattice.gcart(ng)
+    qc = lattice.centred_cart(lattice.kmesh(n), n)
+    L = _complex_rows(w.seed, "L", (w.nk, ng, 8), np.full((ng, 8), 0.3))
+    W = np.empty((w.nk, ng, ng), dtype=np.complex128)
+    eye = np.eye(ng)
+    for iq in range(w.nk):
+        p2 = np.sum((qc[iq][None, :] + G) ** 2, axis=1)
+        p2 = np.where(p2 < 1e-12, 0.01, p2)
+        sv = np.sqrt(4.0 * np.pi / p2)
+        Lq = L[iq]
+        inv = np.linalg.inv(eye + Lq @ Lq.conj().T)
+        inv = 0.5 * (inv + inv.conj().T)
+        W[iq] = sv[:, None] * inv * sv[None, :]
+    return W
+
+
+def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
+    """All inputs of one BSE problem as NumPy arrays (host memory)."""
+    nk, nv, nc, ng = w.nk, w.nv, w.nc, w.ng
+    G = lattice.gcart(ng)
+    Q = np.asarray(w.q, dtype=np.float64)
+    out: dict = {"workload": w}
+    g1 = _rng(w.seed, "eps_v", 0)
+    if w.core_level is not None:
+        out["eps_v"] = np.full((nk, nv), float(w.core_level))
+    else:
+        out["eps_v"] = g1.uniform(w.eps_v_range[0], w.eps_v_range[1], size=(nk, nv))
+    out["eps_c"] = _rng(w.seed, "eps_c", 0).uniform(w.eps_c_range[0], w.eps_c_range[1],
+                                                    size=(nk, nc))
+    gq2 = np.sum((G + Q[None, :]) ** 2, axis=1)
+    if w.mcv_gauss_width is not None:
+        env_cv = np.exp(-gq2 / (2.0 * w.mcv_gauss_width ** 2))
+    else:
+        env_cv = 1.0 / (1.0 + gq2)
+    out["Mcv"] = _complex_rows(w.seed, "Mcv", (w.n, ng), env_cv)
+    env = 1.0 / (1.0 + np.sum(G ** 2, axis=1))
+    if want_pairs:
+        P = w.npairs
+        out["Mvv"] = _complex_rows(w.seed, "Mvv", (P, nv, nv, ng), env)
+        out["Mcc"] = _complex_rows(w.seed, "Mcc", (P, nc, nc, ng), env)
+        if w.coupling == "full":
+            out["Ncv"] = _complex_rows(w.seed, "Ncv", (P, nc, nv, ng), env)
+            out["Nvc"] = _complex_rows(w.seed, "Nvc", (P, nv, nc, ng), env)
+    out["W"] = screened_interaction(w)
+    qmap, qramap = lattice.q_maps(w.mesh)
+    out["qmap"], out["qramap"] = qmap, qramap
+    out["gvec"] = lattice.gvectors(ng)
+    out["kcoords"] = lattice.kmesh(w.mesh)
+    out["omega"] = np.linspace(w.wmin, w.wmax, w.nw)
+    out["alat"] = lattice.A_LATT
+    out["cell_volume"] = lattice.cell_volume()
+    return out

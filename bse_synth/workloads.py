@@ -1,0 +1,100 @@
+"""Workload table: seeded synthetic BSE problems shaped like the paper's runs.
+
+Each workload fixes the index spaces (k-mesh, band window, plane-wave shell),
+the distributions the generator draws from, the frequency grid and the
+broadening.  Sizes follow the paper's applications (Sec. 5: 8x8x8 shifted
+meshes with 4+12 bands for LiF/Si, 0.1 eV broadening for Si, core states for
+the F K-edge); the inputs themselves are synthetic because the paper's DFT
+wavefunctions are not available.
+
+kernel_scale (s) multiplies the kernel prefactor kappa = s * Ha / (Nk * Omega).
+The bare synthetic kernel is a random matrix that would destroy the positive
+definiteness of A-B and A+B that the squared form needs (Sec. 4.3), so s is the
+largest power of two for which A-B, A+B (full) or A (TDA) keep every eigenvalue
+above a tenth of the smallest transition energy.  The values below were found
+by `oracle/calibrate_scale.py` and are re-checked by the CPU tests.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    mesh: int                 # k-mesh is mesh x mesh x mesh, Gamma-centred
+    nv: int                   # occupied (valence or core) bands
+    nc: int                   # unoccupied bands
+    ng: int                   # plane waves (closed shell)
+    coupling: str             # "tda" or "full"
+    nw: int                   # frequency points
+    wmin: float               # eV
+    wmax: float               # eV
+    eta: float                # Lorentzian half width (eV) = broadening FWHM / 2
+    seed: int
+    kernel_scale: float
+    q: tuple = (0.0, 0.0, 0.0)   # momentum transfer (bohr^-1)
+    eps_v_range: tuple = (-3.0, 0.0)
+    eps_c_range: tuple = (1.0, 5.0)
+    core_level: float | None = None   # flat core levels (eV) instead of eps_v draws
+    mcv_gauss_width: float | None = None  # Gaussian |G+Q| envelope of Mcv (bohr^-1)
+    scissor: float = 0.0
+    note: str = ""
+
+    @property
+    def nk(self) -> int:
+        return self.mesh ** 3
+
+    @property
+    def n(self) -> int:
+        return self.nk * self.nv * self.nc
+
+    @property
+    def npairs(self) -> int:
+        return self.nk * (self.nk + 1) // 2
+
+
+WORKLOADS: dict[str, Workload] = {}
+
+
+def _add(w: Workload) -> Workload:
+    WORKLOADS[w.name] = w
+    return w
+
+
+# Small TDA problem at Q = 0 (N = 384): the size the oracle finishes in seconds.
+TDA_N384 = _add(Workload(
+    name="tda_q0_k4_v2c3_g59", mesh=4, nv=2, nc=3, ng=59, coupling="tda",
+    nw=2000, wmin=0.0, wmax=10.0, eta=0.05, seed=0, kernel_scale=0.125,
+    note="Plain TDA BSE at Q=0, N=384 transitions, 59 plane waves"))
+
+# Full (non-TDA) problem at Q = 0 with N = 6144 (2N = 12288): the headline size.
+FULL_N6144 = _add(Workload(
+    name="full_q0_k8_v3c4_g113", mesh=8, nv=3, nc=4, ng=113, coupling="full",
+    nw=4000, wmin=0.0, wmax=10.0, eta=0.05, seed=1, kernel_scale=0.25,
+    note="Full BSE at Q=0, N=6144 transitions, 113 plane waves"))
+
+# Tiny problems used by the CPU pins and the GPU parity tests (several tiles
+# and ragged tails).
+TINY = {
+    "tiny_tda": _add(Workload(name="tiny_tda_k2_v2c2_g9", mesh=2, nv=2, nc=2, ng=9,
+                              coupling="tda", nw=200, wmin=0.0, wmax=10.0, eta=0.05,
+                              seed=11, kernel_scale=0.0625)),
+    "tiny_full": _add(Workload(name="tiny_full_k2_v2c3_g15", mesh=2, nv=2, nc=3, ng=15,
+                               coupling="full", nw=200, wmin=0.0, wmax=10.0, eta=0.05,
+                               seed=12, kernel_scale=0.03125)),
+    "small_full": _add(Workload(name="small_full_k3_v3c4_g27", mesh=3, nv=3, nc=4, ng=27,
+                                coupling="full", nw=500, wmin=0.0, wmax=10.0, eta=0.05,
+                                seed=13, kernel_scale=0.0625)),
+    "mid_full": _add(Workload(name="mid_full_k4_v3c4_g59", mesh=4, nv=3, nc=4, ng=59,
+                              coupling="full", nw=1000, wmin=0.0, wmax=10.0, eta=0.05,
+                              seed=14, kernel_scale=0.0625)),
+}
+
+
+def get(name: str) -> Workload:
+    return WORKLOADS[name]
+
+
+def with_(w: Workload, **kw) -> Workload:
+    return replace(w, **kw)
