@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the BSE hot path on one MI355X.
+
+Workload: full (non-TDA) BSE at Q = 0, k-mesh 8x8x8, 3 valence and 4
+conduction bands (N = 6144, 2N = 12288), 113 plane waves, 4000 frequencies;
+seeded synthetic inputs resident in HBM before the timed region.
+
+One step = bse_build (kernel assembly) + bse_solve (squared-form Cholesky,
+Householder tridiagonalisation, tridiagonal eigensolve, projection of the
+probe) + bse_spectrum.  Printed metric: kernel-build TFLOP/s (algorithmic
+flops of the exchange and both direct terms, 8 flops per complex
+multiply-add, pairs ik <= ik') with the time to eps_M of the same steps.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def build_flops(w) -> dict:
+    """Algorithmic flops of the assembly (8 per complex MAC, k-pairs ik <= ik')."""
+    n, P, ng, nv, nc = w.n, w.npairs, w.ng, w.nv, w.nc
+    exch = n * (n + 1) // 2 * ng * 8
+    rr1 = P * nv * nv * ng * ng * 8
+    rr2 = P * nv * nv * ng * nc * nc * 8
+    full = w.coupling == "full"
+    ra1 = P * nc * nv * ng * ng * 8 if full else 0
+    ra2 = P * nc * nv * ng * nv * nc * 8 if full else 0
+    return {"exchange": exch, "stage1": rr1 + ra1, "stage2": rr2 + ra2,
+            "total": exch + rr1 + rr2 + ra1 + ra2}
+
+
+def kernel_roofline_table(w) -> dict:
+    """Per-step algorithmic work of the kernels that can dominate a step:
+    (bound, amount, unit).  Bytes for HBM-bound kernels, flops for MFMA."""
+    n = w.n
+    f = build_flops(w)
+    m = np.arange(1, n, dtype=np.float64)
+    return {
+        # column-r reads of the trailing Hermitian matrix, one launch per reflector
+        "k_trd_hemv": ("hbm", float(np.sum(m * m) * 16.0), "B"),
+        "k_stage1": ("mfma", float(f["stage1"]), "flop"),
+        "zgemm_direct_stage2": ("mfma", float(f["stage2"]), "flop"),
+        "zgemm_exchange": ("mfma", float(f["exchange"]), "flop"),
+        # triangular products of the squared form: n^3 / 2 complex MACs each
+        "zgemm_sq_t1": ("mfma", n ** 3 / 2 * 8.0, "flop"),
+        "zgemm_sq_s": ("mfma", n ** 3 / 4 * 8.0, "flop"),
+        # trailing updates of the tridiagonalisation: 2 x sum over panels of m^2 x 32
+        "zgemm_her2k": ("mfma", 2.0 * float(np.sum(m[::32] ** 2)) * 32 * 8.0, "flop"),
+    }
+
+
+def cpu_baseline(inputs, w, budget_s: float = 20.0) -> dict:
+    """The oracle's assembly timed on a bounded sample of k-pairs."""
+    from oracle import bse_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    P = w.npairs
+    stride = 64
+    while True:
+        sel = np.arange(0, P, stride)
+        t0 = time.perf_counter()
+        O.kernel_blocks(inputs, sel)
+        dt = time.perf_counter() - t0
+        if dt > 2.0 or stride == 1:
+            break
+        stride = max(1, stride // 4)
+    # scale the sample to ~budget if it was quick
+    f = build_flops(w)
+    frac = len(sel) / P
+    # exchange blocks of the sampled pairs: nvnc^2 * ng complex MACs per pair
+    nvnc = w.nv * w.nc
+    flops = (f["stage1"] + f["stage2"]) * frac + len(sel) * nvnc * nvnc * w.ng * 8
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle kernel_blocks (exchange + W^rr + W^ra, FP64 NumPy) on every "
+                      f"{stride}-th k-pair ({len(sel)} of {P} pairs), {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="full_q0_k8_v3c4_g113")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    from bse_synth import get, make_inputs
+    from paper_1904_05575_amd import _lib as L
+    from paper_1904_05575_amd.bse import Problem
+
+    w = get(args.workload)
+    t0 = time.perf_counter()
+    inputs = make_inputs(w)
+    print(f"[bench] inputs generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    P = Problem(inputs)
+    torch.cuda.synchronize()
+    print("[bench] inputs resident on the GPU", file=sys.stderr, flush=True)
+    H0, H1 = P.alloc_matrices()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        P.build(H0, H1)
+        if ev:
+            ev[1].record()
+        E, _, osc = P.solve(H0, H1, vectors=False)
+        if ev:
+            ev[2].record()
+        eps = P.spectrum(E, osc)
+        if ev:
+            ev[3].record()
+        return E, osc, eps
+
+    for i in range(args.warmup):
+        step()
+        P.check_info()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    L.bse_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        E, osc, eps = step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    L.bse_timing_enable(False)
+    P.check_info()
+    kern = L.bse_timing_report()
+    build_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    solve_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    spec_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    step_ms = float(np.mean([e[0].elapsed_time(e[3]) for e in evs]))
+    flops = build_flops(w)
+    value = flops["total"] / (build_ms * 1e-3) / 1e12
+
+    table = kernel_roofline_table(w)
+    timed = {k: v for k, v in kern.items() if k in table}
+    dom = max(timed, key=lambda k: timed[k][1]) if timed else None
+    roof = None
+    if dom:
+        bound, amount, unit = table[dom]
+        launches, total_ms = timed[dom]
+        per_launch = amount * args.steps / launches
+        avg_s = total_ms / launches * 1e-3
+        if bound == "hbm":
+            ach, peak, u = per_launch / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            ach, peak, u = per_launch / avg_s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+        roof = {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": u,
+                "frac": ach / peak, "traffic": None, "launches_per_step": launches / args.steps,
+                "avg_launch_us": total_ms / launches * 1e3}
+    kernels_ms = {k: round(v[1] / args.steps, 3) for k, v in
+                  sorted(kern.items(), key=lambda kv: -kv[1][1])}
+
+    out = {
+        "metric": "kernel-build TFLOP/s + time-to-eps_M at N=6144 full BSE, FP64 vs split-BF16",
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "nk": w.nk, "nv": w.nv, "nc": w.nc,
+                   "ng": w.ng, "coupling": w.coupling, "nw": w.nw,
+                   "assembly_precision": "fp64"},
+        "time_to_eps_M_ms": {"fp64": step_ms},
+        "stage_ms": {"build": build_ms, "solve": solve_ms, "spectrum": spec_ms},
+        "wall_ms_per_step": wall / args.steps * 1e3,
+        "build_gflop": flops["total"] / 1e9,
+        "build_frac_fp64_peak": value / FP64_PEAK_TFLOPS,
+        "roofline": roof,
+        "kernels_ms_per_step": kernels_ms,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inputs, w)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

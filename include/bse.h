@@ -1,0 +1,156 @@
+/* bse.h -- C ABI of the MI355X (gfx950) Bethe-Salpeter hot path.
+ *
+ * The library builds the electron-hole Hamiltonian of the Bethe-Salpeter
+ * equation in transition space, solves it (full, beyond the Tamm-Dancoff
+ * approximation, through the Hermitian squared form; or in the TDA) and
+ * forms oscillator strengths and the macroscopic dielectric function, after
+ * Vorwerk, Aurich, Cocchi and Draxl, "Bethe-Salpeter equation for absorption
+ * and scattering spectroscopy: implementation in the exciting code"
+ * (Sec. 2.3 matrix form, Sec. 4.2 matrix elements, Sec. 4.3 eigenvalue
+ * problem, Sec. 4.4 dielectric properties).
+ *
+ * Conventions shared by every entry point
+ *  - Every pointer argument is a DEVICE pointer owned by the caller unless
+ *    stated otherwise.  The library never allocates, frees or retains
+ *    caller memory; scratch space comes from the caller's `ws` buffer,
+ *    sized by bse_workspace_size().
+ *  - Complex numbers are interleaved (re, im) doubles (16 bytes).
+ *  - Transition index a = (ik * nv + iv) * nc + ic  (k-point major, then the
+ *    occupied band, then the unoccupied band); n = nk * nv * nc.
+ *  - N x N matrices are column-major with leading dimension ld >= n.  On
+ *    output of bse_build both triangles are filled and Hermitian.
+ *  - k-pairs: only pairs ik <= ik' are stored, in row-major order
+ *    (pair p = ik*nk - ik*(ik-1)/2 + (ik' - ik)); P = nk*(nk+1)/2.
+ *  - Every call only enqueues work on `stream` (no host synchronisation, no
+ *    allocation) and returns a host-side status from argument checks and
+ *    launch errors.  Failures found by the kernels are written to the
+ *    caller's device word `info` (int32, must be zero on entry):
+ *       0   success
+ *      >0   Cholesky of A-B stopped at this 1-based column: A-B is not
+ *           positive definite (the squared form needs it, Sec. 4.3)
+ *      -1   a qmap / qramap entry outside [0, nq)
+ *      -2   a non-finite value on the diagonal of an assembled matrix
+ *      -3   a squared-form eigenvalue E^2 <= 0: A+B is not positive definite
+ *      -4   the tridiagonal eigensolver did not converge
+ *    Once `info` is non-zero, later kernels of the same calls return at
+ *    entry; outputs are then undefined.
+ */
+#ifndef BSE_H
+#define BSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BSE_OK = 0,
+  BSE_ERR_ARG = 1,        /* invalid size, null pointer, ld < n, unsupported mode */
+  BSE_ERR_WORKSPACE = 2,  /* ws_bytes smaller than bse_workspace_size() */
+  BSE_ERR_HIP = 3         /* a HIP launch failed */
+} bse_status;
+
+/* Sec. 4.3: full problem through the squared form, or the TDA (B = 0). */
+typedef enum { BSE_TDA = 0, BSE_FULL = 1 } bse_coupling;
+
+/* Spin factors (gamma_x, gamma_c) of eqs. diagonalblock / couplingblock,
+ * table of calculation types in Appendix B:
+ * singlet (1,1), triplet (0,1), RPA (1,0), independent particles (0,0). */
+typedef enum { BSE_SINGLET = 0, BSE_TRIPLET = 1, BSE_RPA = 2, BSE_IP = 3 } bse_type;
+
+/* Arithmetic of the kernel assembly.  The solve is always FP64. */
+typedef enum { BSE_PREC_FP64 = 0 } bse_precision;
+
+typedef enum { BSE_STAGE_BUILD = 0, BSE_STAGE_SOLVE = 1 } bse_stage;
+
+typedef struct {
+  int32_t nk, nv, nc, ng; /* k-points, occupied and unoccupied bands, plane waves */
+  int32_t coupling;       /* bse_coupling */
+  int32_t type;           /* bse_type */
+  int32_t prec;           /* bse_precision */
+  int32_t reserved;
+  double kappa;           /* kernel prefactor: 1/V_c of eq. vft in energy units */
+  double scissor;         /* rigid shift added to every transition energy */
+  int64_t ld;             /* leading dimension of the N x N matrices, >= n */
+} bse_desc;
+
+/* Inputs of one BSE problem (all device pointers, read only). */
+typedef struct {
+  const double* eps_v;   /* [nk][nv] occupied energies */
+  const double* eps_c;   /* [nk][nc] unoccupied energies */
+  const void* Mcv;       /* complex [n][ng]: M_a(G) of eq. vrrofM (pair a = (k, v, c)) */
+  const void* Mvv;       /* complex [P][nv][nv'][ng]: M_{o o'}(G) of eq. wrrm for pair p */
+  const void* Mcc;       /* complex [P][nc][nc'][ng]: M_{u u'}(G') of eq. wrrm */
+  const void* Ncv;       /* complex [P][nc][nv'][ng]: N_{u o'}(G) of eq. wrabar (full only) */
+  const void* Nvc;       /* complex [P][nv][nc'][ng]: N_{o u'}(G') of eq. wrabar (full only) */
+  const void* W;         /* complex [nq][ng][ng]: screened interaction w_GG'(q), eq. wggq */
+  const double* vbar;    /* [ng]: Coulomb potential without the G_Q term, eq. vbar_def */
+  const int32_t* qmap;   /* [nk][nk]: class of k - k'  (index into W) */
+  const int32_t* qramap; /* [nk][nk]: class of -k - k' (index into W), full only */
+  int32_t nq;            /* number of W slices */
+  int32_t reserved;
+} bse_inputs;
+
+/* Bytes of scratch space `ws` needed by bse_build (stage BUILD) or
+ * bse_solve (stage SOLVE) for this descriptor; 0 for an invalid one. */
+size_t bse_workspace_size(const bse_desc* desc, int32_t stage);
+
+/* Kernel assembly (Sec. 2.3 eqs. diagonalblock and couplingblock with the
+ * matrix elements of Sec. 4.2).
+ *  full: H0 <- A + B,  H1 <- A - B
+ *  TDA : H0 <- A       (H1 unused, may be NULL)
+ * with A = E + kappa (2 gx V - gc W^rr), B = kappa (2 gx V - gc W^ra).
+ * Only pairs ik <= ik' are evaluated; the lower triangle is their conjugate
+ * mirror and the diagonal is real.  H0/H1: complex n x n, column-major, ld. */
+bse_status bse_build(const bse_desc* desc, const bse_inputs* in, void* H0, void* H1, void* ws,
+                     size_t ws_bytes, int32_t* info, hipStream_t stream);
+
+/* Eigenproblem (Sec. 4.3).
+ *  full: A-B = U^H U (Cholesky), S = U (A+B) U^H, S Z = E^2 Z,
+ *        X+Y = U^H Z E^-1/2  (same E and, up to phase, the same X+Y as the
+ *        (A-B)^1/2 form of eq. auxham).
+ *  TDA : A X = E X.
+ *  H0, H1: the matrices from bse_build (overwritten).
+ *  E     : [n] excitation energies, ascending (output).
+ *  XpY   : complex n x n column-major with leading dimension ldx, column l =
+ *          (X+Y)_l (X_l in the TDA); may be NULL when only the spectrum is
+ *          wanted, which skips the eigenvector back-transform.
+ *  probe : complex [n] vector p (for eps_M: p_a = conj M_a(G_Q)) or NULL.
+ *  osc   : [n] |t_l|^2 = |sum_a conj((X+Y)_al) p_a|^2 (eq. osci), written
+ *          when probe != NULL. */
+bse_status bse_solve(const bse_desc* desc, void* H0, void* H1, double* E, void* XpY, int64_t ldx,
+                     const void* probe, double* osc, void* ws, size_t ws_bytes, int32_t* info,
+                     hipStream_t stream);
+
+/* Oscillator strengths from eigenvectors: osc[l] = |sum_a conj(XpY[a,l]) probe[a]|^2
+ * (eq. osci without the 1/V_c factor, which the prefactor of bse_spectrum carries). */
+bse_status bse_oscillator(int64_t n, const void* XpY, int64_t ldx, const void* probe, double* osc,
+                          hipStream_t stream);
+
+/* Macroscopic dielectric function on a frequency grid (Sec. 4.4, eq. chir
+ * inserted in eps_M = 1 - v Pbar):
+ *   eps[j] = 1 - pref * sum_l osc[l] [1/(w_j - E_l + i eta) - 1/(w_j + E_l + i eta)]
+ * E, osc: [n]; omega: [nw]; eps: complex [nw] (output).  pref = 2 kappa v(Q)
+ * (spin factor 2), eta = half width of the Lorentzian broadening. */
+bse_status bse_spectrum(int64_t n, const double* E, const double* osc, double pref, double eta,
+                        int64_t nw, const double* omega, void* eps, hipStream_t stream);
+
+/* Measurement hook: while enabled (on != 0), every kernel launch of the
+ * library is bracketed by two HIP events recorded on the launch stream.
+ * bse_timing_report synchronises on those events, writes one line per kernel
+ * name "<name> <launches> <total milliseconds>" into the HOST buffer `buf`
+ * (truncated to len-1 bytes, NUL-terminated), clears the records and returns
+ * the full length of the report. */
+void bse_timing_enable(int32_t on);
+int64_t bse_timing_report(char* buf, int64_t len);
+
+/* Human-readable name of a status. */
+const char* bse_status_string(bse_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSE_H */

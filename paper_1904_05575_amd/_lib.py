@@ -1,0 +1,123 @@
+"""ctypes binding of libbse.so: the C entry points under the same names.
+
+Argument marshalling only.  Pointers are passed as integers (device
+addresses, e.g. `tensor.data_ptr()`), streams as the raw hipStream_t value.
+The library must be built (`python -m paper_1904_05575_amd.build`); there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbse.so")
+
+BSE_TDA, BSE_FULL = 0, 1
+BSE_SINGLET, BSE_TRIPLET, BSE_RPA, BSE_IP = 0, 1, 2, 3
+BSE_PREC_FP64 = 0
+BSE_STAGE_BUILD, BSE_STAGE_SOLVE = 0, 1
+STATUS = {0: "BSE_OK", 1: "BSE_ERR_ARG", 2: "BSE_ERR_WORKSPACE", 3: "BSE_ERR_HIP"}
+EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bse_spectrum",
+           "bse_status_string", "bse_timing_enable", "bse_timing_report")
+
+
+class BseDesc(ctypes.Structure):
+    _fields_ = [("nk", ctypes.c_int32), ("nv", ctypes.c_int32), ("nc", ctypes.c_int32),
+                ("ng", ctypes.c_int32), ("coupling", ctypes.c_int32), ("type", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("kappa", ctypes.c_double), ("scissor", ctypes.c_double),
+                ("ld", ctypes.c_int64)]
+
+
+class BseInputs(ctypes.Structure):
+    _fields_ = [("eps_v", ctypes.c_void_p), ("eps_c", ctypes.c_void_p),
+                ("Mcv", ctypes.c_void_p), ("Mvv", ctypes.c_void_p), ("Mcc", ctypes.c_void_p),
+                ("Ncv", ctypes.c_void_p), ("Nvc", ctypes.c_void_p), ("W", ctypes.c_void_p),
+                ("vbar", ctypes.c_void_p), ("qmap", ctypes.c_void_p), ("qramap", ctypes.c_void_p),
+                ("nq", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BseError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise BseError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1904_05575_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_double, ctypes.c_size_t)
+        L.bse_workspace_size.argtypes = [ctypes.POINTER(BseDesc), i32]
+        L.bse_workspace_size.restype = sz
+        L.bse_build.argtypes = [ctypes.POINTER(BseDesc), ctypes.POINTER(BseInputs), vp, vp, vp, sz,
+                                vp, vp]
+        L.bse_build.restype = ctypes.c_int
+        L.bse_solve.argtypes = [ctypes.POINTER(BseDesc), vp, vp, vp, vp, i64, vp, vp, vp, sz, vp,
+                                vp]
+        L.bse_solve.restype = ctypes.c_int
+        L.bse_oscillator.argtypes = [i64, vp, i64, vp, vp, vp]
+        L.bse_oscillator.restype = ctypes.c_int
+        L.bse_spectrum.argtypes = [i64, vp, vp, dbl, dbl, i64, vp, vp, vp]
+        L.bse_spectrum.restype = ctypes.c_int
+        L.bse_timing_enable.argtypes = [i32]
+        L.bse_timing_enable.restype = None
+        L.bse_timing_report.argtypes = [ctypes.c_char_p, i64]
+        L.bse_timing_report.restype = i64
+        L.bse_status_string.argtypes = [ctypes.c_int]
+        L.bse_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        msg = lib().bse_status_string(status).decode()
+        raise BseError(f"{what}: {STATUS.get(status, status)} ({msg})")
+
+
+def bse_workspace_size(desc: BseDesc, stage: int) -> int:
+    return int(lib().bse_workspace_size(ctypes.byref(desc), stage))
+
+
+def bse_build(desc: BseDesc, inputs: BseInputs, H0: int, H1: int, ws: int, ws_bytes: int,
+              info: int, stream: int) -> None:
+    _check(lib().bse_build(ctypes.byref(desc), ctypes.byref(inputs), H0, H1 or None, ws, ws_bytes,
+                           info, stream or None), "bse_build")
+
+
+def bse_solve(desc: BseDesc, H0: int, H1: int, E: int, XpY: int, ldx: int, probe: int, osc: int,
+              ws: int, ws_bytes: int, info: int, stream: int) -> None:
+    _check(lib().bse_solve(ctypes.byref(desc), H0, H1 or None, E, XpY or None, ldx, probe or None,
+                           osc or None, ws, ws_bytes, info, stream or None), "bse_solve")
+
+
+def bse_oscillator(n: int, XpY: int, ldx: int, probe: int, osc: int, stream: int) -> None:
+    _check(lib().bse_oscillator(n, XpY, ldx, probe, osc, stream or None), "bse_oscillator")
+
+
+def bse_spectrum(n: int, E: int, osc: int, pref: float, eta: float, nw: int, omega: int, eps: int,
+                 stream: int) -> None:
+    _check(lib().bse_spectrum(n, E, osc, pref, eta, nw, omega, eps, stream or None),
+           "bse_spectrum")
+
+
+def bse_timing_enable(on: bool) -> None:
+    lib().bse_timing_enable(1 if on else 0)
+
+
+def bse_timing_report() -> dict:
+    """{kernel name: (launches, total ms)} since the last report."""
+    n = lib().bse_timing_report(None, 0)
+    buf = ctypes.create_string_buffer(int(n) + 1)
+    lib().bse_timing_report(buf, n + 1)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

@@ -1,0 +1,162 @@
+"""Host-side driver of the BSE library: device buffers, descriptor, calls.
+
+PyTorch supplies device memory and the stream; every step of the method runs
+in libbse.so.  The small host computations here are the problem's geometry
+(Coulomb potential without its macroscopic term, eq. vbar_def; the kernel
+prefactor 1/V_c of eq. vft) and the probe vector of eq. osci.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+HARTREE_EV = 27.211386245988
+TYPES = {"singlet": L.BSE_SINGLET, "triplet": L.BSE_TRIPLET, "rpa": L.BSE_RPA, "ip": L.BSE_IP}
+
+
+def g_index_of_q(gvec: np.ndarray, alat: float, q) -> int:
+    """Index of the reciprocal lattice vector nearest to Q (Q = G_Q + q)."""
+    G = gvec.astype(np.float64) * (2.0 * np.pi / alat)
+    return int(np.argmin(((G - np.asarray(q, dtype=np.float64)) ** 2).sum(axis=1)))
+
+
+def coulomb_vbar(gvec: np.ndarray, alat: float, q) -> np.ndarray:
+    """4 pi / |G + q|^2 for every G, zero at G_Q (the macroscopic term)."""
+    G = gvec.astype(np.float64) * (2.0 * np.pi / alat)
+    Q = np.asarray(q, dtype=np.float64)
+    gq = g_index_of_q(gvec, alat, Q)
+    qred = Q - G[gq]
+    p2 = ((G + qred) ** 2).sum(axis=1)
+    out = np.zeros(len(G))
+    keep = np.arange(len(G)) != gq
+    out[keep] = 4.0 * np.pi / p2[keep]
+    return out
+
+
+def coulomb_v0(q) -> float:
+    """4 pi / |Q|^2, with |Q|^2 taken as 0.01 bohr^-2 at Q = 0."""
+    q2 = float(np.dot(q, q))
+    return 4.0 * np.pi / (q2 if q2 > 1e-12 else 0.01)
+
+
+def kernel_prefactor(kernel_scale: float, nk: int, cell_volume: float) -> float:
+    """s * Ha / (Nk * Omega): 1/V_c in eV for lengths in bohr."""
+    return kernel_scale * HARTREE_EV / (nk * cell_volume)
+
+
+def _dev(a: np.ndarray, dtype, device) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+
+
+class Problem:
+    """One BSE problem resident on the GPU."""
+
+    def __init__(self, inputs: dict, bse_type: str = "singlet", device: str = "cuda"):
+        w = inputs["workload"]
+        self.workload = w
+        self.device = torch.device(device)
+        self.nk, self.nv, self.nc, self.ng = w.nk, w.nv, w.nc, w.ng
+        self.n = w.nk * w.nv * w.nc
+        self.full = w.coupling == "full"
+        c128, f64 = torch.complex128, torch.float64
+        dv = self.device
+        self.t = {
+            "eps_v": _dev(inputs["eps_v"], f64, dv),
+            "eps_c": _dev(inputs["eps_c"], f64, dv),
+            "Mcv": _dev(inputs["Mcv"], c128, dv),
+            "Mvv": _dev(inputs["Mvv"], c128, dv),
+            "Mcc": _dev(inputs["Mcc"], c128, dv),
+            "W": _dev(inputs["W"], c128, dv),
+            "qmap": _dev(inputs["qmap"], torch.int32, dv),
+        }
+        if self.full:
+            self.t["Ncv"] = _dev(inputs["Ncv"], c128, dv)
+            self.t["Nvc"] = _dev(inputs["Nvc"], c128, dv)
+            self.t["qramap"] = _dev(inputs["qramap"], torch.int32, dv)
+        vbar = coulomb_vbar(inputs["gvec"], inputs["alat"], w.q)
+        self.t["vbar"] = _dev(vbar, f64, dv)
+        gq = g_index_of_q(inputs["gvec"], inputs["alat"], w.q)
+        self.t["probe"] = _dev(np.conj(inputs["Mcv"][:, gq]), c128, dv)
+        self.t["omega"] = _dev(inputs["omega"], f64, dv)
+        self.kappa = kernel_prefactor(w.kernel_scale, w.nk, inputs["cell_volume"])
+        self.pref = 2.0 * self.kappa * coulomb_v0(w.q)
+        self.eta = w.eta
+        self.desc = L.BseDesc(nk=w.nk, nv=w.nv, nc=w.nc, ng=w.ng,
+                              coupling=L.BSE_FULL if self.full else L.BSE_TDA,
+                              type=TYPES[bse_type], prec=L.BSE_PREC_FP64, reserved=0,
+                              kappa=self.kappa, scissor=w.scissor, ld=self.n)
+        p = lambda k: self.t[k].data_ptr() if k in self.t else None  # noqa: E731
+        self.inp = L.BseInputs(eps_v=p("eps_v"), eps_c=p("eps_c"), Mcv=p("Mcv"), Mvv=p("Mvv"),
+                               Mcc=p("Mcc"), Ncv=p("Ncv"), Nvc=p("Nvc"), W=p("W"),
+                               vbar=p("vbar"), qmap=p("qmap"), qramap=p("qramap"),
+                               nq=int(inputs["W"].shape[0]), reserved=0)
+        self.info = torch.zeros(1, dtype=torch.int32, device=dv)
+        self.ws_build = torch.empty(max(1, L.bse_workspace_size(self.desc, L.BSE_STAGE_BUILD)),
+                                    dtype=torch.uint8, device=dv)
+        self.ws_solve = torch.empty(max(1, L.bse_workspace_size(self.desc, L.BSE_STAGE_SOLVE)),
+                                    dtype=torch.uint8, device=dv)
+
+    @staticmethod
+    def stream() -> int:
+        return torch.cuda.current_stream().cuda_stream
+
+    def check_info(self) -> None:
+        torch.cuda.synchronize()
+        code = int(self.info.item())
+        if code != 0:
+            raise L.BseError(f"device status info = {code}")
+
+    def alloc_matrices(self):
+        n = self.n
+        H0 = torch.empty((n, n), dtype=torch.complex128, device=self.device)
+        H1 = torch.empty((n, n), dtype=torch.complex128, device=self.device) if self.full else None
+        return H0, H1
+
+    def build(self, H0=None, H1=None):
+        """A+B and A-B (full) or A (TDA), column-major: element (i, j) is H.T[i, j]."""
+        if H0 is None:
+            H0, H1 = self.alloc_matrices()
+        L.bse_build(self.desc, self.inp, H0.data_ptr(), H1.data_ptr() if H1 is not None else 0,
+                    self.ws_build.data_ptr(), self.ws_build.numel(), self.info.data_ptr(),
+                    self.stream())
+        return H0, H1
+
+    def solve(self, H0, H1, vectors: bool = False, probe: bool = True):
+        n = self.n
+        E = torch.empty(n, dtype=torch.float64, device=self.device)
+        XpY = torch.empty((n, n), dtype=torch.complex128, device=self.device) if vectors else None
+        osc = torch.empty(n, dtype=torch.float64, device=self.device) if probe else None
+        L.bse_solve(self.desc, H0.data_ptr(), H1.data_ptr() if H1 is not None else 0,
+                    E.data_ptr(), XpY.data_ptr() if XpY is not None else 0, n,
+                    self.t["probe"].data_ptr() if probe else 0,
+                    osc.data_ptr() if osc is not None else 0, self.ws_solve.data_ptr(),
+                    self.ws_solve.numel(), self.info.data_ptr(), self.stream())
+        return E, XpY, osc
+
+    def spectrum(self, E, osc):
+        nw = self.t["omega"].numel()
+        eps = torch.empty(nw, dtype=torch.complex128, device=self.device)
+        L.bse_spectrum(self.n, E.data_ptr(), osc.data_ptr(), self.pref, self.eta, nw,
+                       self.t["omega"].data_ptr(), eps.data_ptr(), self.stream())
+        return eps
+
+    def oscillator(self, XpY):
+        osc = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        L.bse_oscillator(self.n, XpY.data_ptr(), self.n, self.t["probe"].data_ptr(),
+                         osc.data_ptr(), self.stream())
+        return osc
+
+    def run(self, vectors: bool = False):
+        """build -> solve -> spectrum; returns host arrays."""
+        H0, H1 = self.build()
+        E, XpY, osc = self.solve(H0, H1, vectors=vectors)
+        eps = self.spectrum(E, osc)
+        self.check_info()
+        out = {"E": E.cpu().numpy(), "osc": osc.cpu().numpy(), "eps": eps.cpu().numpy()}
+        if vectors:
+            out["XpY"] = XpY.T.cpu().numpy()  # column-major storage -> [a, l]
+        return out

@@ -1,0 +1,338 @@
+// Assembly of the BSE Hamiltonian blocks (paper Sec. 2.3 eqs. diagonalblock,
+// couplingblock; Sec. 4.2 eqs. vrrofM, wrrm, wrabar).
+//
+//   exchange   V_aa'   = sum_G vbar_G M*_a(G) M_a'(G)           (one HERK-shaped GEMM)
+//   direct     W^rr    = M*_vv W(k-k') M_cc  per k-pair          (two-stage contraction)
+//   coupling   W^ra    = N*_cv W(-k-k') N_vc per k-pair
+//   A+B = E + kappa (4 gx V - gc (W^rr + W^ra)),  A-B = E - kappa gc (W^rr - W^ra)
+//   TDA: A = E + kappa (2 gx V - gc W^rr)
+//
+// Only k-pairs ik <= ik' are evaluated (the upper triangle); the lower
+// triangle is the mirror and the diagonal is made real (Hermitian rule).
+// The direct terms are contracted per momentum-transfer class so that every
+// W(q) slice is read once per class instead of once per pair:
+//   stage 1  T[pair rows, G'] = conj(M_left) x W(q)         grouped GEMM over classes
+//   stage 2  blk[pair]        = T[pair] x M_right[pair]^T    batched GEMM over pairs
+// followed by a scatter of the (nv nc)^2 block of every pair into A+B / A-B.
+#include "bse_internal.h"
+#include "common.h"
+#include "mfma_tile.h"
+#include "timing.h"
+#include "zgemm.h"
+
+namespace {
+
+// ---------------------------------------------------------------- class sort
+// perm[pos] lists the pairs grouped by class q = qm[ik][ik']; cls[q] is the
+// first position of class q; inv[p] the position of pair p.
+__global__ __launch_bounds__(1024) void k_class_sort(const int32_t* __restrict__ qm, int nk, int nq,
+                                                     int32_t* perm, int32_t* cls, int32_t* inv,
+                                                     int32_t* info) {
+  extern __shared__ int32_t sh[];
+  int32_t* hist = sh;
+  int32_t* cur = sh + nq;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int q = tid; q < nq; q += nt) hist[q] = 0;
+  __syncthreads();
+  const int64_t nn = (int64_t)nk * nk;
+  for (int64_t e = tid; e < nn; e += nt) {
+    const int ik = (int)(e / nk), jk = (int)(e % nk);
+    if (ik > jk) continue;
+    const int q = qm[e];
+    if (q < 0 || q >= nq) {
+      set_info(info, BSE_INFO_BAD_QMAP);
+      continue;
+    }
+    atomicAdd(&hist[q], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int q = 0; q < nq; ++q) {
+      cls[q] = run;
+      cur[q] = run;
+      run += hist[q];
+    }
+    cls[nq] = run;
+  }
+  // a class holds at most nk pairs on a mesh (the stage-1 grid relies on it)
+  for (int q = tid; q < nq; q += nt)
+    if (hist[q] > nk) set_info(info, BSE_INFO_BAD_QMAP);
+  __syncthreads();
+  for (int64_t e = tid; e < nn; e += nt) {
+    const int ik = (int)(e / nk), jk = (int)(e % nk);
+    if (ik > jk) continue;
+    const int q = qm[e];
+    if (q < 0 || q >= nq) continue;
+    const int p = (int)((int64_t)ik * nk - (int64_t)ik * (ik - 1) / 2 + (jk - ik));
+    const int pos = atomicAdd(&cur[q], 1);
+    perm[pos] = p;
+    inv[p] = pos;
+  }
+}
+
+// ---------------------------------------------------------------- stage 1
+// T[(pos*R + sub), G'] = sum_G conj(Left[p][sub][G]) W[q][G][G'],  p = perm[pos]
+constexpr int S1_BM = 64, S1_BN = 64;
+
+__global__ __launch_bounds__(256) void k_stage1(const double2* __restrict__ Left, int R, int ng,
+                                                const double2* __restrict__ W,
+                                                const int32_t* __restrict__ perm,
+                                                const int32_t* __restrict__ cls, int tiles_per_class,
+                                                double2* __restrict__ T, const int32_t* info) {
+  using Tile = ZTile<S1_BM, S1_BN, 2, 2>;
+  __shared__ Tile::Smem sm;
+  if (failed(info)) return;
+  const int q = blockIdx.x / tiles_per_class, mt = blockIdx.x % tiles_per_class;
+  const int s0 = cls[q], rows = (cls[q + 1] - s0) * R;
+  const int m0 = mt * S1_BM;
+  if (m0 >= rows) return;
+  const int n0 = blockIdx.y * S1_BN;
+  const double2* __restrict__ Wq = W + (int64_t)q * ng * ng;
+  auto loadA = [&](int mm, int k) -> double2 {
+    const int m = m0 + mm;
+    if (m >= rows) return make_double2(0.0, 0.0);
+    const int s = s0 + m / R, sub = m % R;
+    const int64_t p = perm[s];
+    const double2 v = Left[(p * R + sub) * ng + k];
+    return make_double2(v.x, -v.y);
+  };
+  auto loadB = [&](int k, int nn) -> double2 {
+    const int n = n0 + nn;
+    if (n >= ng) return make_double2(0.0, 0.0);
+    return Wq[(int64_t)k * ng + n];
+  };
+  Tile t;
+  t.init();
+  t.run(sm, 0, ng, false, true, loadA, loadB);
+  t.store([&](int mm, int nn, double2 v) {
+    const int m = m0 + mm, n = n0 + nn;
+    if (m < rows && n < ng) T[((int64_t)s0 * R + m) * ng + n] = v;
+  });
+}
+
+// ---------------------------------------------------------------- combine
+// Scatter the per-pair blocks into the output matrices (column-major, ld).
+//   rr block: blk_rr[pos][(v*nv + v')][(c*nc + c')]
+//   ra block: blk_ra[pos][(c*nv + v')][(v*nc + c')]
+__global__ __launch_bounds__(256) void k_combine(int npairs, int nk, int nv, int nc, int64_t ld,
+                                                 const int32_t* __restrict__ inv_rr,
+                                                 const double2* __restrict__ blk_rr,
+                                                 const int32_t* __restrict__ inv_ra,
+                                                 const double2* __restrict__ blk_ra, double c0r,
+                                                 double c0a, double c1r, double c1a,
+                                                 double2* __restrict__ out0,
+                                                 double2* __restrict__ out1, const int32_t* info) {
+  if (failed(info)) return;
+  const int nvnc = nv * nc, nb = nvnc * nvnc;
+  const int64_t total = (int64_t)npairs * nb;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(g / nb), e = (int)(g % nb);
+    const int a = e % nvnc, bcol = e / nvnc;
+    const int v = a / nc, c = a % nc, v2 = bcol / nc, c2 = bcol % nc;
+    // pair p -> (ik, jk): invert p = ik*nk - ik(ik-1)/2 + (jk - ik)
+    int ik = 0;
+    {
+      int lo = 0, hi = nk - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t start = (int64_t)mid * nk - (int64_t)mid * (mid - 1) / 2;
+        if (start <= p) lo = mid; else hi = mid - 1;
+      }
+      ik = lo;
+    }
+    const int jk = ik + (int)(p - ((int64_t)ik * nk - (int64_t)ik * (ik - 1) / 2));
+    const double2 rr =
+        blk_rr[((int64_t)inv_rr[p] * nv * nv + (v * nv + v2)) * (nc * nc) + (c * nc + c2)];
+    double2 ra = make_double2(0.0, 0.0);
+    if (blk_ra) ra = blk_ra[((int64_t)inv_ra[p] * nc * nv + (c * nv + v2)) * (nv * nc) + (v * nc + c2)];
+    const int64_t row = (int64_t)ik * nvnc + a, col = (int64_t)jk * nvnc + bcol;
+    double2* d0 = out0 + row + col * ld;
+    double2 o = *d0;
+    o.x += c0r * rr.x + c0a * ra.x;
+    o.y += c0r * rr.y + c0a * ra.y;
+    *d0 = o;
+    if (out1) out1[row + col * ld] = make_double2(c1r * rr.x + c1a * ra.x, c1r * rr.y + c1a * ra.y);
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+// Hermitian rule: lower = conj(upper), diagonal = E + Re(diagonal).
+constexpr int FT = 32;
+__global__ __launch_bounds__(256) void k_finalize(double2* __restrict__ M, int64_t n, int64_t ld,
+                                                  const double* __restrict__ eps_v,
+                                                  const double* __restrict__ eps_c, int nv, int nc,
+                                                  double scissor, int32_t* info) {
+  __shared__ double2 tile[FT][FT + 1];
+  if (failed(info)) return;
+  const int bi = blockIdx.x, bj = blockIdx.y;  // tile row / column
+  if (bi < bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  if (bi > bj) {
+    // read upper tile (rows bj*FT.., cols bi*FT..), write its conjugate transpose
+    for (int r = ty; r < FT; r += 8) {
+      const int64_t row = (int64_t)bj * FT + tx, col = (int64_t)bi * FT + r;
+      if (row < n && col < n) tile[r][tx] = M[row + col * ld];
+    }
+    __syncthreads();
+    for (int r = ty; r < FT; r += 8) {
+      const int64_t row = (int64_t)bi * FT + tx, col = (int64_t)bj * FT + r;
+      if (row < n && col < n) {
+        const double2 u = tile[tx][r];
+        M[row + col * ld] = make_double2(u.x, -u.y);
+      }
+    }
+  } else {
+    for (int r = ty; r < FT; r += 8) {
+      const int64_t row = (int64_t)bi * FT + tx, col = (int64_t)bi * FT + r;
+      if (row < n && col < n) tile[r][tx] = M[row + col * ld];
+    }
+    __syncthreads();
+    for (int r = ty; r < FT; r += 8) {
+      const int64_t row = (int64_t)bi * FT + tx, col = (int64_t)bi * FT + r;
+      if (row >= n || col >= n) continue;
+      if (row > col) {
+        const double2 u = tile[tx][r];  // element (col, row)
+        M[row + col * ld] = make_double2(u.x, -u.y);
+      } else if (row == col) {
+        const int nvnc = nv * nc;
+        const int ik = (int)(row / nvnc), a = (int)(row % nvnc);
+        const double e = eps_c[(int64_t)ik * nc + a % nc] - eps_v[(int64_t)ik * nv + a / nc] + scissor;
+        const double d = e + tile[r][tx].x;
+        if (!isfinite(d)) set_info(info, BSE_INFO_NONFINITE);
+        M[row + col * ld] = make_double2(d, 0.0);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+size_t build_workspace_fp64(const bse_desc* d) {
+  const int64_t P = (int64_t)d->nk * (d->nk + 1) / 2;
+  WsLayout L;
+  L.add(P * 4);        // perm_rr
+  L.add((kMaxQ + 1) * 4);  // cls_rr
+  L.add(P * 4);        // inv_rr
+  L.add(P * 4);        // perm_ra
+  L.add((kMaxQ + 1) * 4);  // cls_ra
+  L.add(P * 4);        // inv_ra
+  const int64_t R1 = (int64_t)d->nv * d->nv, N1 = (int64_t)d->nc * d->nc, R2 = (int64_t)d->nc * d->nv;
+  const bool full = d->coupling == BSE_FULL;
+  L.add(P * R1 * d->ng * 16);                    // T_rr
+  L.add(full ? P * R2 * d->ng * 16 : 0);         // T_ra
+  L.add(P * R1 * N1 * 16);                       // blk_rr
+  L.add(full ? P * R2 * R2 * 16 : 0);            // blk_ra
+  return L.total;
+}
+
+bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void* out1, void* ws,
+                      int32_t* info, hipStream_t s) {
+  const int nk = d->nk, nv = d->nv, nc = d->nc, ng = d->ng, nq = in->nq;
+  const int64_t n = (int64_t)nk * nv * nc, ld = d->ld;
+  const int64_t P = (int64_t)nk * (nk + 1) / 2;
+  const bool full = d->coupling == BSE_FULL;
+  double gx, gc;
+  bse_gamma(d->type, &gx, &gc);
+  const double kap = d->kappa;
+
+  WsLayout L(ws);
+  int32_t* perm_rr = (int32_t*)L.add(P * 4);
+  int32_t* cls_rr = (int32_t*)L.add((kMaxQ + 1) * 4);
+  int32_t* inv_rr = (int32_t*)L.add(P * 4);
+  int32_t* perm_ra = (int32_t*)L.add(P * 4);
+  int32_t* cls_ra = (int32_t*)L.add((kMaxQ + 1) * 4);
+  int32_t* inv_ra = (int32_t*)L.add(P * 4);
+  const int64_t R1 = (int64_t)nv * nv, N1 = (int64_t)nc * nc, R2 = (int64_t)nc * nv;
+  double2* T_rr = (double2*)L.add(P * R1 * ng * 16);
+  double2* T_ra = (double2*)L.add(full ? P * R2 * ng * 16 : 0);
+  double2* blk_rr = (double2*)L.add(P * R1 * N1 * 16);
+  double2* blk_ra = (double2*)L.add(full ? P * R2 * R2 * 16 : 0);
+  (void)cls_ra;
+
+  // class sorts
+  BSE_LAUNCH(k_class_sort, dim3(1), dim3(1024), 2 * nq * sizeof(int32_t), s, in->qmap, nk,
+                     nq, perm_rr, cls_rr, inv_rr, info);
+  if (full)
+    BSE_LAUNCH(k_class_sort, dim3(1), dim3(1024), 2 * nq * sizeof(int32_t), s, in->qramap,
+                       nk, nq, perm_ra, cls_ra, inv_ra, info);
+
+  // exchange: out0 (upper) = alpha * conj(Mcv) diag(vbar) Mcv^T
+  {
+    ZgemmParams g;
+    g.M = (int)n;
+    g.N = (int)n;
+    g.K = ng;
+    g.A = (const double2*)in->Mcv;
+    g.a_rs = ng;
+    g.a_cs = 1;
+    g.conjA = 1;
+    g.kscale = in->vbar;
+    g.B = (const double2*)in->Mcv;
+    g.b_rs = 1;
+    g.b_cs = ng;
+    g.C = (double2*)out0;
+    g.c_rs = 1;
+    g.c_cs = ld;
+    g.alpha = make_double2((full ? 4.0 : 2.0) * gx * kap, 0.0);
+    g.beta = 0.0;
+    g.c_uplo = 1;
+    g.info = info;
+    g.tag = "zgemm_exchange";
+    if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
+  }
+
+  // direct terms, stage 1 (grouped by class) and stage 2 (batched by pair)
+  auto direct = [&](const void* left, int R, const void* right, int N2, const int32_t* perm,
+                    const int32_t* cls, double2* T, double2* blk) -> bool {
+    const int tiles = cdiv((int64_t)nk * R, S1_BM);  // a class holds at most nk pairs
+    dim3 grid((unsigned)(nq * tiles), (unsigned)cdiv(ng, S1_BN));
+    BSE_LAUNCH(k_stage1, grid, dim3(256), 0, s, (const double2*)left, R, ng,
+                       (const double2*)in->W, perm, cls, tiles, T, info);
+    ZgemmParams g;
+    g.M = R;
+    g.N = N2;
+    g.K = ng;
+    g.A = T;
+    g.a_rs = ng;
+    g.a_cs = 1;
+    g.a_bs = (int64_t)R * ng;
+    g.B = (const double2*)right;
+    g.b_rs = 1;
+    g.b_cs = ng;
+    g.b_bs = (int64_t)N2 * ng;
+    g.b_batch_idx = perm;
+    g.C = blk;
+    g.c_rs = N2;
+    g.c_cs = 1;
+    g.c_bs = (int64_t)R * N2;
+    g.info = info;
+    g.tag = "zgemm_direct_stage2";
+    return zgemm(g, (int)P, s) == hipSuccess;
+  };
+  if (!direct(in->Mvv, (int)R1, in->Mcc, (int)N1, perm_rr, cls_rr, T_rr, blk_rr)) return BSE_ERR_HIP;
+  if (full && !direct(in->Ncv, (int)R2, in->Nvc, (int)R2, perm_ra, cls_ra, T_ra, blk_ra))
+    return BSE_ERR_HIP;
+
+  // scatter: A+B += -gc kappa (rr + ra), A-B = -gc kappa (rr - ra); TDA: A += -gc kappa rr
+  {
+    const double c = -gc * kap;
+    const int64_t total = P * (int64_t)(nv * nc) * (nv * nc);
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    BSE_LAUNCH(k_combine, dim3(blocks), dim3(256), 0, s, (int)P, nk, nv, nc, ld, inv_rr,
+                       blk_rr, full ? inv_ra : nullptr, full ? blk_ra : nullptr, c, c, c, -c,
+                       (double2*)out0, full ? (double2*)out1 : nullptr, info);
+  }
+  // Hermitian rule + transition energies on the diagonal
+  {
+    const int nt = cdiv(n, FT);
+    BSE_LAUNCH(k_finalize, dim3(nt, nt), dim3(256), 0, s, (double2*)out0, n, ld, in->eps_v,
+                       in->eps_c, nv, nc, d->scissor, info);
+    if (full)
+      BSE_LAUNCH(k_finalize, dim3(nt, nt), dim3(256), 0, s, (double2*)out1, n, ld,
+                         in->eps_v, in->eps_c, nv, nc, d->scissor, info);
+  }
+  return hipGetLastError() == hipSuccess ? BSE_OK : BSE_ERR_HIP;
+}

@@ -1,0 +1,57 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "../../include/bse.h"
+
+enum {
+  BSE_INFO_BAD_QMAP = -1,
+  BSE_INFO_NONFINITE = -2,
+  BSE_INFO_NOT_PD_PLUS = -3,
+  BSE_INFO_NO_CONVERGE = -4,
+};
+
+// Largest number of W slices (momentum-transfer classes) of one problem.
+constexpr int64_t kMaxQ = 8192;
+
+// Carves aligned sub-buffers out of one workspace (or only sums their sizes).
+struct WsLayout {
+  char* base = nullptr;
+  size_t total = 0;
+  WsLayout() = default;
+  explicit WsLayout(void* b) : base((char*)b) {}
+  void* add(int64_t bytes) {
+    total = (total + 255) & ~(size_t)255;
+    void* p = base ? base + total : nullptr;
+    total += (size_t)std::max<int64_t>(bytes, 0);
+    return p;
+  }
+};
+
+inline void bse_gamma(int type, double* gx, double* gc) {
+  switch (type) {
+    case BSE_SINGLET: *gx = 1.0; *gc = 1.0; break;
+    case BSE_TRIPLET: *gx = 0.0; *gc = 1.0; break;
+    case BSE_RPA: *gx = 1.0; *gc = 0.0; break;
+    default: *gx = 0.0; *gc = 0.0; break;
+  }
+}
+
+// assembly.hip
+size_t build_workspace_fp64(const bse_desc* d);
+bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void* out1, void* ws,
+                      int32_t* info, hipStream_t s);
+
+// solve.hip
+size_t solve_workspace(const bse_desc* d);
+bse_status solve_run(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, int64_t ldx,
+                     const void* probe, double* osc, void* ws, int32_t* info, hipStream_t s);
+
+// spectrum.hip
+hipError_t launch_oscillator(int64_t n, const double2* XpY, int64_t ldx, const double2* probe,
+                             double* osc, hipStream_t s);
+hipError_t launch_spectrum(int64_t n, const double* E, const double* osc, double pref, double eta,
+                           int64_t nw, const double* omega, double2* eps, hipStream_t s);

@@ -1,0 +1,111 @@
+// Block-level complex FP64 tile product on MFMA, shared by the GEMM kernels.
+//
+// A workgroup of WM x WN waves computes a BM x BN complex tile
+//   acc(m, n) = sum_k a(m, k) b(k, n)
+// staging BM x 16 and 16 x BN slices of the operands in LDS.  The caller
+// supplies loaders that return one (already conjugated / scaled / masked)
+// complex element; `a_mfast` / `b_nfast` pick the thread-to-element order
+// that keeps the global reads coalesced for the operand's layout.
+//
+// v_mfma_f64_16x16x4_f64 lane layout: A operand lane l -> (m = l%16, k = l/16),
+// B operand lane l -> (k = l/16, n = l%16), accumulator register r of lane l
+// -> (m = l/16 + 4*r, n = l%16).
+#pragma once
+#include "common.h"
+
+template <int BM, int BN, int WM, int WN>
+struct ZTile {
+  static constexpr int BK = 16;
+  static constexpr int PAD = 2;
+  static constexpr int NT = WM * WN * 64;
+  static constexpr int TI = BM / WM / 16;
+  static constexpr int TJ = BN / WN / 16;
+  static_assert(TI >= 1 && TJ >= 1, "tile too small for the wave grid");
+
+  struct Smem {
+    double a_re[BK][BM + PAD], a_im[BK][BM + PAD];
+    double b_re[BK][BN + PAD], b_im[BK][BN + PAD];
+  };
+
+  d4 cr[TI][TJ], ci[TI][TJ];
+  int wm0, wn0, lane;
+
+  BSE_DEV void init() {
+    lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    wm0 = (wid % WM) * (BM / WM);
+    wn0 = (wid / WM) * (BN / WN);
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        cr[i][j] = d4{0, 0, 0, 0};
+        ci[i][j] = d4{0, 0, 0, 0};
+      }
+  }
+
+  // loadA(mm, k) / loadB(k, nn): element of the operand at tile-local row mm
+  // (column nn) and absolute k; must return 0 outside the operand.
+  template <class LA, class LB>
+  BSE_DEV void run(Smem& s, int k_lo, int k_hi, bool a_mfast, bool b_nfast, LA loadA, LB loadB) {
+    const int tid = threadIdx.x;
+    for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
+      for (int e = tid; e < BM * BK; e += NT) {
+        int mm, kk;
+        if (a_mfast) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
+        const int k = k0 + kk;
+        double2 v = (k < k_hi) ? loadA(mm, k) : make_double2(0.0, 0.0);
+        s.a_re[kk][mm] = v.x;
+        s.a_im[kk][mm] = v.y;
+      }
+      for (int e = tid; e < BN * BK; e += NT) {
+        int nn, kk;
+        if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+        const int k = k0 + kk;
+        double2 v = (k < k_hi) ? loadB(k, nn) : make_double2(0.0, 0.0);
+        s.b_re[kk][nn] = v.x;
+        s.b_im[kk][nn] = v.y;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        double ar[TI], ai[TI], nai[TI], br[TJ], bi[TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+          ar[i] = s.a_re[kr][wm0 + i * 16 + (lane & 15)];
+          ai[i] = s.a_im[kr][wm0 + i * 16 + (lane & 15)];
+          nai[i] = -ai[i];
+        }
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          br[j] = s.b_re[kr][wn0 + j * 16 + (lane & 15)];
+          bi[j] = s.b_im[kr][wn0 + j * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+    }
+  }
+
+  // store(m_local, n_local, value) for every accumulator element.
+  template <class ST>
+  BSE_DEV void store(ST st) {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          st(wm0 + i * 16 + (lane >> 4) + 4 * r, wn0 + j * 16 + (lane & 15),
+             make_double2(cr[i][j][r], ci[i][j][r]));
+  }
+};

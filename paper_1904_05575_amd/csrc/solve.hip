@@ -1,0 +1,1074 @@
+// FP64 eigensolver of the BSE (paper Sec. 4.3).
+//
+// Full problem (squared form): with A-B = U^H U (Cholesky),
+//   S = U (A+B) U^H  has the spectrum E^2 of (A-B)^1/2 (A+B) (A-B)^1/2,
+//   S Z = E^2 Z,  X+Y = U^H Z E^-1/2.
+// TDA: A X = E X.
+// The Hermitian matrix (S or A) is reduced to a real symmetric tridiagonal
+// T = Q^H S Q by Householder reflectors (blocked, lower), T is solved by
+// multisection bisection and inverse iteration, and the eigenvectors are
+// back-transformed with the reflectors in compact-WY form.  When only the
+// spectrum is wanted the back-transform is replaced by projecting the probe:
+//   t_l = E_l^-1/2 z_l^T (Q^H U p)      (full),   t_l = z_l^T (Q^H p)   (TDA).
+#include <math.h>
+
+#include "bse_internal.h"
+#include "common.h"
+#include "timing.h"
+#include "zgemm.h"
+
+namespace {
+
+constexpr int CH_NB = 32;   // Cholesky panel width
+constexpr int TRD_NB = 32;  // Householder panel width
+constexpr int ROWS_A = 256; // rows per block of the column kernel
+
+BSE_DEV double2 ld_acq(const double2* p) {
+  double2 v;
+  v.x = __hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v.y = __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
+
+__global__ void k_zero_ints(int32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// ------------------------------------------------------------------ Cholesky
+// Factor the jb x jb diagonal block (upper, A = U^H U) in LDS and form U^-1.
+__global__ __launch_bounds__(256) void k_potrf_diag(double2* __restrict__ A, int64_t ld, int j0,
+                                                    int jb, double2* __restrict__ Uinv,
+                                                    int32_t* info) {
+  __shared__ double2 a[CH_NB][CH_NB + 1];
+  __shared__ double2 x[CH_NB][CH_NB + 1];
+  __shared__ int bad;
+  if (failed(info)) return;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < jb * jb; e += blockDim.x) {
+    const int r = e % jb, c = e / jb;
+    a[r][c] = (r <= c) ? A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * ld] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < jb; ++j) {
+    if (tid == 0) {
+      const double dj = a[j][j].x;
+      if (!(dj > 0.0) || !isfinite(dj)) {
+        bad = 1;
+        set_info(info, j0 + j + 1);
+      } else {
+        a[j][j] = make_double2(sqrt(dj), 0.0);
+      }
+    }
+    __syncthreads();
+    if (bad) return;
+    const double s = 1.0 / a[j][j].x;
+    for (int c = j + 1 + tid; c < jb; c += blockDim.x) a[j][c] = cscale(a[j][c], s);
+    __syncthreads();
+    for (int e = tid; e < jb * jb; e += blockDim.x) {
+      const int r = e % jb, c = e / jb;
+      if (r > j && c >= r) a[r][c] = csub(a[r][c], cmulc(a[j][r], a[j][c]));
+    }
+    __syncthreads();
+  }
+  if (tid < jb) {
+    const int c = tid;
+    for (int r = 0; r < jb; ++r) x[r][c] = make_double2(0.0, 0.0);
+    x[c][c] = make_double2(1.0 / a[c][c].x, 0.0);
+    for (int r = c - 1; r >= 0; --r) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int k = r + 1; k <= c; ++k) s = cadd(s, cmul(a[r][k], x[k][c]));
+      x[r][c] = cscale(s, -1.0 / a[r][r].x);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < jb * jb; e += blockDim.x) {
+    const int r = e % jb, c = e / jb;
+    if (r <= c) A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * ld] = a[r][c];
+    Uinv[r + (int64_t)c * jb] = x[r][c];
+  }
+}
+
+// Mirror one triangle onto the other: from_lower ? upper = conj(lower) :
+// lower = conj(upper); the diagonal is made real.
+__global__ __launch_bounds__(256) void k_hermitize(double2* __restrict__ M, int64_t n, int64_t ld,
+                                                   int from_lower, const int32_t* info) {
+  __shared__ double2 tile[32][33];
+  if (failed(info)) return;
+  const int bi = blockIdx.x, bj = blockIdx.y;  // destination tile (row, column)
+  const bool dst_upper = from_lower;
+  if (dst_upper ? (bi > bj) : (bi < bj)) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // source tile is the transpose position
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t row = (int64_t)bj * 32 + tx, col = (int64_t)bi * 32 + r;
+    if (row < n && col < n) tile[r][tx] = M[row + col * ld];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t row = (int64_t)bi * 32 + tx, col = (int64_t)bj * 32 + r;
+    if (row >= n || col >= n) continue;
+    const bool write = dst_upper ? (row < col) : (row > col);
+    if (write) {
+      const double2 u = tile[tx][r];
+      M[row + col * ld] = make_double2(u.x, -u.y);
+    } else if (row == col) {
+      M[row + col * ld] = make_double2(M[row + col * ld].x, 0.0);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ tridiagonalisation
+// Small shared state of the column kernels (complex slots):
+//   [0] scal = 1/(alpha_x - beta) of the current reflector, [1] tau,
+//   [2] alpha = -|tau|^2 (y^H v) / 2 from the hemv of the current column,
+//   [4 .. 4+NB) V^H v,  [4+NB .. 4+2NB) W^H v  (corrections of the hemv)
+constexpr int HS_SCAL = 0, HS_TAU = 1, HS_ALPHA = 2, HS_VV = 4, HS_WV = 4 + TRD_NB;
+constexpr int NPART = 1 + 2 * TRD_NB;
+
+// Column kernel for column c = j0 + i of the panel (rows r >= c, one thread per row):
+//  0. finishes the previous column: stores its scaled reflector v and its W column;
+//  1. applies the panel's earlier reflectors to column c;
+//  2. block partial sums of |x|^2 and of V^H x, W^H x over rows >= c+2;
+//  3. the last block to finish forms the reflector (beta, tau, scale) and the
+//     hemv corrections V^H v, W^H v.
+// With has_new = 0 only step 0 runs (end of a panel).
+__global__ __launch_bounds__(ROWS_A) void k_trd_col(double2* __restrict__ M, int64_t ld, int n,
+                                                    double2* __restrict__ Wp, int j0, int i,
+                                                    int has_new, double2* __restrict__ hs,
+                                                    const double2* __restrict__ ybuf,
+                                                    double2* __restrict__ part, int32_t* counter,
+                                                    double* __restrict__ dd, double* __restrict__ ee,
+                                                    double2* __restrict__ tau, const int32_t* info) {
+  __shared__ double2 red[ROWS_A / 64][NPART];
+  __shared__ double2 sums[NPART];
+  __shared__ double2 sh_scal;
+  __shared__ int is_last;
+  if (failed(info)) return;
+  const int c = j0 + i;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int r = c + blockIdx.x * ROWS_A + tid;
+  const bool act = r < n;
+
+  double2 vprev_r = make_double2(0.0, 0.0), wprev_r = make_double2(0.0, 0.0);
+  double2 wprev_c = make_double2(0.0, 0.0);
+  if (i > 0) {
+    const int cp = c - 1;
+    const double2 scal = hs[HS_SCAL], tc = hs[HS_TAU], al = hs[HS_ALPHA];
+    if (act) {
+      const double2 xv = M[r + (int64_t)cp * ld];
+      vprev_r = (r == c) ? make_double2(1.0, 0.0) : cmul(scal, xv);
+      M[r + (int64_t)cp * ld] = vprev_r;
+      wprev_r = cadd(cmul(tc, ybuf[r]), cmul(al, vprev_r));
+      Wp[r + (int64_t)(i - 1) * n] = wprev_r;
+    }
+    wprev_c = cadd(cmul(tc, ybuf[c]), al);
+  }
+  if (!has_new) return;
+
+  // 1. update of column c
+  double2 x = make_double2(0.0, 0.0);
+  if (act) {
+    x = M[r + (int64_t)c * ld];
+    for (int ip = 0; ip < i; ++ip) {
+      double2 vr, wr, vc, wc;
+      if (ip == i - 1) {
+        vr = vprev_r;
+        wr = wprev_r;
+        vc = make_double2(1.0, 0.0);
+        wc = wprev_c;
+      } else {
+        vr = M[r + (int64_t)(j0 + ip) * ld];
+        wr = Wp[r + (int64_t)ip * n];
+        vc = M[c + (int64_t)(j0 + ip) * ld];
+        wc = Wp[c + (int64_t)ip * n];
+      }
+      // x -= v_ip[r] conj(w_ip[c]) + w_ip[r] conj(v_ip[c])
+      x = csub(x, cadd(make_double2(vr.x * wc.x + vr.y * wc.y, vr.y * wc.x - vr.x * wc.y),
+                       make_double2(wr.x * vc.x + wr.y * vc.y, wr.y * vc.x - wr.x * vc.y)));
+    }
+    if (r == c) x.y = 0.0;
+    M[r + (int64_t)c * ld] = x;
+  }
+
+  // 2. partial sums over rows r >= c+2, compact layout [|x|^2, V^H x (i), W^H x (i)]
+  const bool tail = act && (r >= c + 2);
+  const int nvals = 1 + 2 * i;
+  for (int t = 0; t < nvals; ++t) {
+    double2 val = make_double2(0.0, 0.0);
+    if (tail) {
+      if (t == 0) {
+        val.x = cabs2(x);
+      } else if (t <= i) {
+        const int ip = t - 1;
+        const double2 vr = (ip == i - 1) ? vprev_r : M[r + (int64_t)(j0 + ip) * ld];
+        val = cmulc(vr, x);
+      } else {
+        const int ip = t - 1 - i;
+        const double2 wr = (ip == i - 1) ? wprev_r : Wp[r + (int64_t)ip * n];
+        val = cmulc(wr, x);
+      }
+    }
+    const double2 sw = wave_sum2(val);
+    if (lane == 0) red[wid][t] = sw;
+  }
+  __syncthreads();
+  for (int t = tid; t < nvals; t += ROWS_A) {
+    double2 sb = make_double2(0.0, 0.0);
+    for (int w = 0; w < ROWS_A / 64; ++w) sb = cadd(sb, red[w][t]);
+    part[(int64_t)blockIdx.x * NPART + t] = sb;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+
+  // 3. last block: reflector of column c
+  for (int t = tid; t < nvals; t += ROWS_A) {
+    double2 sb = make_double2(0.0, 0.0);
+    for (int b = 0; b < (int)gridDim.x; ++b) sb = cadd(sb, ld_acq(part + (int64_t)b * NPART + t));
+    sums[t] = sb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double2 ax = ld_acq(M + (c + 1) + (int64_t)c * ld);
+    const double xn2 = sums[0].x;
+    double2 tv, scal;
+    double beta;
+    if (xn2 == 0.0 && ax.y == 0.0) {
+      tv = make_double2(0.0, 0.0);
+      beta = ax.x;
+      scal = make_double2(0.0, 0.0);
+    } else {
+      beta = -copysign(sqrt(ax.x * ax.x + ax.y * ax.y + xn2), ax.x);
+      tv = make_double2((beta - ax.x) / beta, -ax.y / beta);
+      const double2 dnm = make_double2(ax.x - beta, ax.y);
+      const double q = 1.0 / cabs2(dnm);
+      scal = make_double2(dnm.x * q, -dnm.y * q);
+    }
+    ee[c] = beta;
+    tau[c] = tv;
+    dd[c] = ld_acq(M + c + (int64_t)c * ld).x;
+    hs[HS_SCAL] = scal;
+    hs[HS_TAU] = tv;
+    sh_scal = scal;
+  }
+  __syncthreads();
+  const double2 scal = sh_scal;
+  for (int ip = tid; ip < i; ip += ROWS_A) {
+    const double2 v1 = ld_acq(M + (c + 1) + (int64_t)(j0 + ip) * ld);
+    const double2 w1 = ld_acq(Wp + (c + 1) + (int64_t)ip * n);
+    hs[HS_VV + ip] = cadd(cconj(v1), cmul(scal, sums[1 + ip]));
+    hs[HS_WV + ip] = cadd(cconj(w1), cmul(scal, sums[1 + i + ip]));
+  }
+  if (tid == 0) *counter = 0;
+}
+
+// y[r] = sum_j S[r, j] v[j] - V[r,:] (W^H v) - W[r,:] (V^H v) for r in (c, n),
+// one wavefront per row r reading column r of the (Hermitian, full) trailing
+// matrix; the last block forms alpha = -|tau|^2 (y^H v) / 2.
+__global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ M, int64_t ld, int n,
+                                                  const double2* __restrict__ Wp, int j0, int i,
+                                                  double2* __restrict__ hs,
+                                                  double2* __restrict__ ybuf,
+                                                  double2* __restrict__ part, int32_t* counter,
+                                                  const int32_t* info) {
+  __shared__ double2 red[4];
+  __shared__ int is_last;
+  if (failed(info)) return;
+  const int c = j0 + i;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r = c + 1 + blockIdx.x * 4 + wid;
+  const double2 scal = hs[HS_SCAL];
+  const double2* vcol = M + (int64_t)c * ld;
+  double2 contrib = make_double2(0.0, 0.0);
+  if (r < n) {
+    const double2* col = M + (int64_t)r * ld;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = c + 1 + lane; j < n; j += 64) {
+      const double2 vj = (j == c + 1) ? make_double2(1.0, 0.0) : cmul(scal, vcol[j]);
+      acc = cadd(acc, cmulc(col[j], vj));  // conj(S[j, r]) v[j] = S[r, j] v[j]
+    }
+    // corrections, one panel column per lane
+    if (lane < i) {
+      const double2 vr = M[r + (int64_t)(j0 + lane) * ld];
+      const double2 wr = Wp[r + (int64_t)lane * n];
+      acc = csub(acc, cadd(cmul(vr, hs[HS_WV + lane]), cmul(wr, hs[HS_VV + lane])));
+    }
+    acc = wave_sum2(acc);
+    if (lane == 0) {
+      ybuf[r] = acc;
+      const double2 vr = (r == c + 1) ? make_double2(1.0, 0.0) : cmul(scal, vcol[r]);
+      contrib = cmulc(acc, vr);  // conj(y[r]) v[r]
+    }
+  }
+  if (lane == 0) red[wid] = contrib;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = cadd(cadd(red[0], red[1]), cadd(red[2], red[3]));
+    __threadfence();
+    is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  // deterministic final sum by one wavefront
+  if (wid == 0) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int b = lane; b < (int)gridDim.x; b += 64) s = cadd(s, ld_acq(part + b));
+    s = wave_sum2(s);
+    if (lane == 0) {
+      const double2 tv = hs[HS_TAU];
+      const double t2 = cabs2(tv);
+      hs[HS_ALPHA] = make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
+      *counter = 0;
+    }
+  }
+}
+
+__global__ void k_trd_last(const double2* M, int64_t ld, int n, double* dd, const int32_t* info) {
+  if (failed(info)) return;
+  if (threadIdx.x == 0) dd[n - 1] = M[(n - 1) + (int64_t)(n - 1) * ld].x;
+}
+
+// ------------------------------------------------------------------ tridiagonal eigensolver
+// e2, Gershgorin bounds, pivmin and the norm of T.  stat[0]=gl, [1]=gu, [2]=pivmin, [3]=tnorm
+__global__ __launch_bounds__(1024) void k_tri_prep(const double* __restrict__ d,
+                                                   const double* __restrict__ e, int n,
+                                                   double* __restrict__ e2, double* stat,
+                                                   const int32_t* info) {
+  __shared__ double slo[16], shi[16], sem[16];
+  if (failed(info)) return;
+  double lo = INFINITY, hi = -INFINITY, emax = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double em = (k > 0) ? fabs(e[k - 1]) : 0.0, ep = (k < n - 1) ? fabs(e[k]) : 0.0;
+    lo = fmin(lo, d[k] - em - ep);
+    hi = fmax(hi, d[k] + em + ep);
+    if (k < n - 1) {
+      e2[k] = e[k] * e[k];
+      emax = fmax(emax, e2[k]);
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+    emax = fmax(emax, __shfl_xor(emax, off, 64));
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    slo[w] = lo;
+    shi[w] = hi;
+    sem[w] = emax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+      lo = fmin(lo, slo[i]);
+      hi = fmax(hi, shi[i]);
+      emax = fmax(emax, sem[i]);
+    }
+    const double tnorm = fmax(fabs(lo), fabs(hi));
+    const double eps = 2.220446049250313e-16;
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
+    stat[0] = lo - 2.0 * eps * tnorm * n - 2.0 * pivmin;
+    stat[1] = hi + 2.0 * eps * tnorm * n + 2.0 * pivmin;
+    stat[2] = pivmin;
+    stat[3] = tnorm;
+  }
+}
+
+BSE_DEV int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n, double x,
+                        double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// Eigenvalue k (ascending) by multisection: the 64 lanes of a wavefront probe
+// 64 interior points of the bracket per round.
+__global__ __launch_bounds__(256) void k_bisect(const double* __restrict__ d,
+                                                const double* __restrict__ e2, int n,
+                                                const double* __restrict__ stat,
+                                                double* __restrict__ w, const int32_t* info) {
+  if (failed(info)) return;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= n) return;
+  double lo = stat[0], hi = stat[1];
+  const double pivmin = stat[2];
+  const double eps = 2.220446049250313e-16;
+  for (int it = 0; it < 40; ++it) {
+    const double width = hi - lo;
+    if (width <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
+    const double x = lo + width * (double)(lane + 1) / 65.0;
+    const int cnt = sturm_count(d, e2, n, x, pivmin);
+    const unsigned long long mask = __ballot(cnt > k);
+    double nlo, nhi;
+    if (mask == 0ull) {
+      nlo = lo + width * 64.0 / 65.0;
+      nhi = hi;
+    } else {
+      const int f = __ffsll((long long)mask) - 1;
+      nhi = lo + width * (double)(f + 1) / 65.0;
+      nlo = (f > 0) ? lo + width * (double)f / 65.0 : lo;
+    }
+    if (nlo == lo && nhi == hi) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) w[k] = 0.5 * (lo + hi);
+}
+
+BSE_DEV double hash_uniform(uint32_t a, uint32_t b) {
+  uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  return 2.0 * ((double)h / 4294967296.0) - 1.0;
+}
+
+// Inverse iteration for every eigenvalue (one thread per cluster of close
+// eigenvalues; members of a cluster are orthogonalised against each other).
+// Z and the LU scratch are stored [component i][eigenvalue j] (coalesced).
+__global__ __launch_bounds__(256) void k_inviter(const double* __restrict__ d,
+                                                 const double* __restrict__ e, int n,
+                                                 const double* __restrict__ w,
+                                                 const double* __restrict__ stat, double ortol_rel,
+                                                 double* __restrict__ Z, double* __restrict__ U0,
+                                                 double* __restrict__ U1, double* __restrict__ U2,
+                                                 int32_t* info) {
+  if (failed(info)) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double tnorm = stat[3];
+  const double ortol = ortol_rel * tnorm;
+  if (k > 0 && w[k] - w[k - 1] <= ortol) return;  // not the first member of its cluster
+  int kend = k;
+  while (kend + 1 < n && w[kend + 1] - w[kend] <= ortol) ++kend;
+  const double eps = 2.220446049250313e-16;
+  const double tiny = eps * fmax(tnorm, 1e-300);
+  const int64_t N = n;
+  for (int j = k; j <= kend; ++j) {
+    const double lam = w[j];
+    for (int i = 0; i < n; ++i) Z[i * N + j] = hash_uniform((uint32_t)i, (uint32_t)j);
+    for (int it = 0; it < 3; ++it) {
+      // LU with partial pivoting of T - lam I, forward elimination on the rhs in Z
+      double di = d[0] - lam, dui = (n > 1) ? e[0] : 0.0, rin = Z[j];
+      for (int i = 0; i < n - 1; ++i) {
+        const double dl = e[i];
+        double d1 = d[i + 1] - lam;
+        double du1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+        double r1 = Z[(i + 1) * N + j];
+        double Ud, Uu, Uu2, ri;
+        if (fabs(di) >= fabs(dl)) {
+          const double f = (di != 0.0) ? dl / di : 0.0;
+          Ud = di;
+          Uu = dui;
+          Uu2 = 0.0;
+          ri = rin;
+          d1 -= f * dui;
+          r1 -= f * rin;
+        } else {
+          const double f = di / dl;
+          Ud = dl;
+          Uu = d1;
+          Uu2 = du1;
+          ri = r1;
+          const double nd1 = dui - f * d1;
+          du1 = -f * du1;
+          r1 = rin - f * r1;
+          d1 = nd1;
+        }
+        U0[i * N + j] = Ud;
+        U1[i * N + j] = Uu;
+        U2[i * N + j] = Uu2;
+        Z[i * N + j] = ri;
+        di = d1;
+        dui = du1;
+        rin = r1;
+      }
+      U0[(N - 1) * N + j] = di;
+      Z[(N - 1) * N + j] = rin;
+      // back substitution with tiny pivots perturbed
+      double x1 = 0.0, x2 = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        double p = U0[i * N + j];
+        if (fabs(p) < tiny) p = (p >= 0.0) ? tiny : -tiny;
+        double s = Z[i * N + j];
+        if (i < n - 1) s -= U1[i * N + j] * x1;
+        if (i < n - 2) s -= U2[i * N + j] * x2;
+        const double xi = s / p;
+        Z[i * N + j] = xi;
+        x2 = x1;
+        x1 = xi;
+      }
+      // orthogonalise against earlier members of the cluster, then normalise
+      for (int jp = k; jp < j; ++jp) {
+        double dot = 0.0;
+        for (int i = 0; i < n; ++i) dot += Z[i * N + jp] * Z[i * N + j];
+        for (int i = 0; i < n; ++i) Z[i * N + j] -= dot * Z[i * N + jp];
+      }
+      double nrm = 0.0, big = 0.0;
+      for (int i = 0; i < n; ++i) big = fmax(big, fabs(Z[i * N + j]));
+      if (!(big > 0.0) || !isfinite(big)) {
+        set_info(info, BSE_INFO_NO_CONVERGE);
+        return;
+      }
+      const double sb = 1.0 / big;
+      for (int i = 0; i < n; ++i) {
+        const double v = Z[i * N + j] * sb;
+        nrm += v * v;
+      }
+      const double s = sb / sqrt(nrm);
+      for (int i = 0; i < n; ++i) Z[i * N + j] *= s;
+    }
+    // fixed sign: largest component positive
+    double big = 0.0;
+    int ib = 0;
+    for (int i = 0; i < n; ++i)
+      if (fabs(Z[i * N + j]) > big) {
+        big = fabs(Z[i * N + j]);
+        ib = i;
+      }
+    if (Z[ib * N + j] < 0.0)
+      for (int i = 0; i < n; ++i) Z[i * N + j] = -Z[i * N + j];
+  }
+}
+
+// E = sqrt(mu) (full) and the column scale of Z (E^-1/2), or E = mu (TDA).
+__global__ void k_eigvals(const double* __restrict__ mu, int n, int full, double* __restrict__ E,
+                          double* __restrict__ colscale, int32_t* info) {
+  if (failed(info)) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double m = mu[k];
+  if (full) {
+    if (!(m > 0.0)) {
+      set_info(info, BSE_INFO_NOT_PD_PLUS);
+      return;
+    }
+    const double ek = sqrt(m);
+    E[k] = ek;
+    colscale[k] = 1.0 / sqrt(ek);
+  } else {
+    E[k] = m;
+    colscale[k] = 1.0;
+  }
+}
+
+// Z (complex, column-major, ldz)[i, j] = Ztri[i][j] * scale[j]
+__global__ __launch_bounds__(256) void k_ztri_to_complex(const double* __restrict__ Zt, int n,
+                                                         const double* __restrict__ scale,
+                                                         double2* __restrict__ Z, int64_t ldz,
+                                                         const int32_t* info) {
+  __shared__ double tile[32][33];
+  if (failed(info)) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    tile[r][tx] = (i < n && j < n) ? Zt[i * n + j] * scale[j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + r, i = i0 + tx;
+    if (i < n && j < n) Z[i + j * ldz] = make_double2(tile[tx][r], 0.0);
+  }
+}
+
+// ------------------------------------------------------------------ reflector blocks
+// T factor (I - V T V^H = H_j0 ... H_j0+jb-1) of every panel; one block per panel.
+// Vcol(r, a) = M[r, j0+a] for r >= j0+a+1 (the unit entry is stored), else 0.
+__global__ __launch_bounds__(256) void k_larft(const double2* __restrict__ M, int64_t ld, int n,
+                                               const double2* __restrict__ tau,
+                                               double2* __restrict__ Tall,
+                                               const int32_t* info) {
+  __shared__ double2 vs[64][TRD_NB + 1];
+  __shared__ double2 G[TRD_NB][TRD_NB + 1];
+  __shared__ double2 T[TRD_NB][TRD_NB + 1];
+  if (failed(info)) return;
+  const int pnl = blockIdx.x;
+  const int j0 = pnl * TRD_NB;
+  const int jb = min(TRD_NB, n - 1 - j0);
+  if (jb <= 0) return;
+  const int tid = threadIdx.x;
+  double2 acc[4];
+  for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int r0 = j0 + 1; r0 < n; r0 += 64) {
+    for (int e = tid; e < 64 * TRD_NB; e += 256) {
+      const int rr = e % 64, a = e / 64;
+      const int r = r0 + rr;
+      double2 v = make_double2(0.0, 0.0);
+      if (a < jb && r < n && r >= j0 + a + 1) v = M[r + (int64_t)(j0 + a) * ld];
+      vs[rr][a] = v;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int pidx = tid + q * 256;  // (a, b) = (pidx % 32, pidx / 32)
+      const int a = pidx % TRD_NB, b = pidx / TRD_NB;
+      double2 s = acc[q];
+      for (int rr = 0; rr < 64; ++rr) s = cadd(s, cmulc(vs[rr][a], vs[rr][b]));
+      acc[q] = s;
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 4; ++q) {
+    const int pidx = tid + q * 256;
+    G[pidx % TRD_NB][pidx / TRD_NB] = acc[q];
+  }
+  for (int e = tid; e < TRD_NB * TRD_NB; e += 256) T[e % TRD_NB][e / TRD_NB] = make_double2(0.0, 0.0);
+  __syncthreads();
+  // T[:i, i] = -tau_i T[:i, :i] G[:i, i];  T[i, i] = tau_i
+  for (int i = 0; i < jb; ++i) {
+    const double2 ti = tau[j0 + i];
+    if (tid < i) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int k = tid; k < i; ++k) s = cadd(s, cmul(T[tid][k], G[k][i]));
+      T[tid][i] = make_double2(-(ti.x * s.x - ti.y * s.y), -(ti.x * s.y + ti.y * s.x));
+    }
+    if (tid == 0) T[i][i] = ti;
+    __syncthreads();
+  }
+  double2* To = Tall + (int64_t)pnl * TRD_NB * TRD_NB;
+  for (int e = tid; e < TRD_NB * TRD_NB; e += 256) To[e] = T[e % TRD_NB][e / TRD_NB];
+}
+
+// y := Q^H y = (H_n-2^H ... H_0^H) y over every panel in order (one block).
+__global__ __launch_bounds__(1024) void k_apply_qh_vec(const double2* __restrict__ M, int64_t ld,
+                                                       int n, const double2* __restrict__ Tall,
+                                                       double2* __restrict__ y,
+                                                       const int32_t* info) {
+  __shared__ double2 red[16][TRD_NB];
+  __shared__ double2 w1[TRD_NB], w2[TRD_NB];
+  if (failed(info)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int j0 = 0; j0 < n - 1; j0 += TRD_NB) {
+    const int jb = min(TRD_NB, n - 1 - j0);
+    const double2* T = Tall + (int64_t)(j0 / TRD_NB) * TRD_NB * TRD_NB;
+    double2 acc[TRD_NB];
+    for (int a = 0; a < TRD_NB; ++a) acc[a] = make_double2(0.0, 0.0);
+    for (int r = j0 + 1 + tid; r < n; r += 1024) {
+      const double2 yr = y[r];
+      for (int a = 0; a < jb; ++a)
+        if (r >= j0 + a + 1) acc[a] = cadd(acc[a], cmulc(M[r + (int64_t)(j0 + a) * ld], yr));
+    }
+    for (int a = 0; a < TRD_NB; ++a) {
+      const double2 s = wave_sum2(acc[a]);
+      if (lane == 0) red[wid][a] = s;
+    }
+    __syncthreads();
+    if (tid < TRD_NB) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int w = 0; w < 16; ++w) s = cadd(s, red[w][tid]);
+      w1[tid] = s;
+    }
+    __syncthreads();
+    // w2 = T^H w1
+    if (tid < jb) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int k = 0; k <= tid; ++k) s = cadd(s, cmulc(T[k + tid * TRD_NB], w1[k]));
+      w2[tid] = s;
+    }
+    __syncthreads();
+    for (int r = j0 + 1 + tid; r < n; r += 1024) {
+      double2 s = y[r];
+      for (int a = 0; a < jb; ++a)
+        if (r >= j0 + a + 1) s = csub(s, cmul(M[r + (int64_t)(j0 + a) * ld], w2[a]));
+      y[r] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// osc[l] = |sum_i Ztri[i][l] y[i]|^2 * scale2[l]
+__global__ __launch_bounds__(256) void k_osc_tri(const double* __restrict__ Zt, int n,
+                                                 const double2* __restrict__ y,
+                                                 const double* __restrict__ colscale,
+                                                 double* __restrict__ osc, const int32_t* info) {
+  if (failed(info)) return;
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n) return;
+  double2 s = make_double2(0.0, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    const double z = Zt[i * n + l];
+    const double2 yi = y[i];
+    s.x += z * yi.x;
+    s.y += z * yi.y;
+  }
+  const double cs = colscale[l];
+  osc[l] = cabs2(s) * cs * cs;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+namespace {
+struct SolveWs {
+  double2* Wk;    // n x n complex (T1 of the squared form, then Z)
+  double* Ztri;   // n x n real
+  double* U0;
+  double* U1;
+  double* U2;
+  double2* Wp;    // n x TRD_NB panel W
+  double2* W1;    // TRD_NB x n (back-transform)
+  double2* W2;    // TRD_NB x n
+  double2* ybuf;  // n
+  double2* yvec;  // n (probe projection)
+  double2* hs;    // small state
+  double2* part;  // partial sums
+  double2* Tall;  // T factors
+  double2* Uinv;  // CH_NB^2
+  double2* tau;   // n
+  double* dd;
+  double* ee;
+  double* e2;
+  double* mu;
+  double* colscale;
+  double* stat;
+  int32_t* counters;
+  size_t total;
+};
+
+SolveWs carve(const bse_desc* d, void* base) {
+  const int64_t n = (int64_t)d->nk * d->nv * d->nc;
+  const int64_t npnl = (n + TRD_NB - 1) / TRD_NB + 1;
+  const int64_t nblk_a = (n + ROWS_A - 1) / ROWS_A + 1;
+  const int64_t nblk_b = (n + 3) / 4 + 1;
+  WsLayout L(base);
+  SolveWs w;
+  w.Wk = (double2*)L.add(n * n * 16);
+  w.Ztri = (double*)L.add(n * n * 8);
+  w.U0 = (double*)L.add(n * n * 8);
+  w.U1 = (double*)L.add(n * n * 8);
+  w.U2 = (double*)L.add(n * n * 8);
+  w.Wp = (double2*)L.add(n * TRD_NB * 16);
+  w.W1 = (double2*)L.add(n * TRD_NB * 16);
+  w.W2 = (double2*)L.add(n * TRD_NB * 16);
+  w.ybuf = (double2*)L.add(n * 16);
+  w.yvec = (double2*)L.add(n * 16);
+  w.hs = (double2*)L.add((4 + 2 * TRD_NB) * 16);
+  w.part = (double2*)L.add(std::max(nblk_a * NPART, nblk_b) * 16);
+  w.Tall = (double2*)L.add(npnl * TRD_NB * TRD_NB * 16);
+  w.Uinv = (double2*)L.add(CH_NB * CH_NB * 16);
+  w.tau = (double2*)L.add(n * 16);
+  w.dd = (double*)L.add(n * 8);
+  w.ee = (double*)L.add(n * 8);
+  w.e2 = (double*)L.add(n * 8);
+  w.mu = (double*)L.add(n * 8);
+  w.colscale = (double*)L.add(n * 8);
+  w.stat = (double*)L.add(8 * 8);
+  w.counters = (int32_t*)L.add(64 * 4);
+  w.total = L.total;
+  return w;
+}
+
+bool cholesky(double2* H1, int64_t n, int64_t ld, double2* Uinv, int32_t* info, hipStream_t s) {
+  for (int64_t j0 = 0; j0 < n; j0 += CH_NB) {
+    const int jb = (int)std::min<int64_t>(CH_NB, n - j0);
+    BSE_LAUNCH(k_potrf_diag, dim3(1), dim3(256), 0, s, H1, ld, (int)j0, jb, Uinv, info);
+    const int64_t rest = n - j0 - jb;
+    if (rest <= 0) break;
+    double2* A12 = H1 + j0 + (j0 + jb) * ld;
+    ZgemmParams g;  // U12 = U11^-H A12 (in place: one row tile covers all jb rows)
+    g.M = jb;
+    g.N = (int)rest;
+    g.K = jb;
+    g.A = Uinv;
+    g.a_rs = jb;
+    g.a_cs = 1;
+    g.conjA = 1;
+    g.a_tri = 2;
+    g.B = A12;
+    g.b_rs = 1;
+    g.b_cs = ld;
+    g.C = A12;
+    g.c_rs = 1;
+    g.c_cs = ld;
+    g.info = info;
+    g.tag = "zgemm_potrf_trsm";
+    if (zgemm(g, 1, s) != hipSuccess) return false;
+    ZgemmParams h;  // A22 -= U12^H U12 (upper)
+    h.M = (int)rest;
+    h.N = (int)rest;
+    h.K = jb;
+    h.A = A12;
+    h.a_rs = ld;
+    h.a_cs = 1;
+    h.conjA = 1;
+    h.B = A12;
+    h.b_rs = 1;
+    h.b_cs = ld;
+    h.C = H1 + (j0 + jb) + (j0 + jb) * ld;
+    h.c_rs = 1;
+    h.c_cs = ld;
+    h.alpha = make_double2(-1.0, 0.0);
+    h.beta = 1.0;
+    h.c_uplo = 1;
+    h.info = info;
+    h.tag = "zgemm_potrf_herk";
+    if (zgemm(h, 1, s) != hipSuccess) return false;
+  }
+  return true;
+}
+
+bool tridiagonalise(double2* M, int64_t n, int64_t ld, SolveWs& w, int32_t* info, hipStream_t s) {
+  for (int64_t j0 = 0; j0 < n - 1; j0 += TRD_NB) {
+    const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
+    for (int i = 0; i < jb; ++i) {
+      const int64_t c = j0 + i;
+      const int ga = cdiv(n - c, ROWS_A);
+      BSE_LAUNCH(k_trd_col, dim3(ga), dim3(ROWS_A), 0, s, M, ld, (int)n, w.Wp, (int)j0,
+                         i, 1, w.hs, w.ybuf, w.part, w.counters + 0, w.dd, w.ee, w.tau, info);
+      const int gb = cdiv(n - c - 1, 4);
+      BSE_LAUNCH(k_trd_hemv, dim3(gb), dim3(256), 0, s, M, ld, (int)n, w.Wp, (int)j0, i,
+                         w.hs, w.ybuf, w.part, w.counters + 1, info);
+    }
+    // finish the panel's last column
+    BSE_LAUNCH(k_trd_col, dim3(cdiv(n - (j0 + jb), ROWS_A)), dim3(ROWS_A), 0, s, M, ld,
+                       (int)n, w.Wp, (int)j0, jb, 0, w.hs, w.ybuf, w.part, w.counters + 0, w.dd,
+                       w.ee, w.tau, info);
+    const int64_t t = j0 + jb;
+    if (t < n) {
+      ZgemmParams g;  // M[t:, t:] -= V W^H
+      g.M = (int)(n - t);
+      g.N = (int)(n - t);
+      g.K = jb;
+      g.A = M + t + j0 * ld;
+      g.a_rs = 1;
+      g.a_cs = ld;
+      g.B = w.Wp + t;
+      g.b_rs = n;
+      g.b_cs = 1;
+      g.conjB = 1;
+      g.C = M + t + t * ld;
+      g.c_rs = 1;
+      g.c_cs = ld;
+      g.alpha = make_double2(-1.0, 0.0);
+      g.beta = 1.0;
+      g.info = info;
+      g.tag = "zgemm_her2k";
+      if (zgemm(g, 1, s) != hipSuccess) return false;
+      ZgemmParams h = g;  // M[t:, t:] -= W V^H
+      h.A = w.Wp + t;
+      h.a_rs = 1;
+      h.a_cs = n;
+      h.B = M + t + j0 * ld;
+      h.b_rs = ld;
+      h.b_cs = 1;
+      h.conjB = 1;
+      if (zgemm(h, 1, s) != hipSuccess) return false;
+    }
+  }
+  BSE_LAUNCH(k_trd_last, dim3(1), dim3(64), 0, s, M, ld, (int)n, w.dd, info);
+  return hipGetLastError() == hipSuccess;
+}
+
+// Z := Q Z for the n x ncols complex matrix Z (column-major, ldz).
+bool apply_q(const double2* M, int64_t n, int64_t ld, double2* Z, int64_t ldz, int64_t ncols,
+             SolveWs& w, int32_t* info, hipStream_t s) {
+  const int64_t npnl = (n - 1 + TRD_NB - 1) / TRD_NB;
+  double2* W1 = w.W1;  // jb x ncols
+  double2* W2 = w.W2;  // jb x ncols
+  for (int64_t pnl = npnl - 1; pnl >= 0; --pnl) {
+    const int64_t j0 = pnl * TRD_NB;
+    const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
+    const int64_t m = n - j0 - 1;
+    const double2* V = M + (j0 + 1) + j0 * ld;
+    ZgemmParams a;  // W1 = V^H Z[j0+1:, :]
+    a.M = jb;
+    a.N = (int)ncols;
+    a.K = (int)m;
+    a.A = V;
+    a.a_rs = ld;
+    a.a_cs = 1;
+    a.conjA = 1;
+    a.a_tri = 1;
+    a.B = Z + (j0 + 1);
+    a.b_rs = 1;
+    a.b_cs = ldz;
+    a.C = W1;
+    a.c_rs = 1;
+    a.c_cs = jb;
+    a.info = info;
+    a.tag = "zgemm_bt_vhz";
+    if (zgemm(a, 1, s) != hipSuccess) return false;
+    ZgemmParams b;  // W2 = T W1
+    b.M = jb;
+    b.N = (int)ncols;
+    b.K = jb;
+    b.A = w.Tall + pnl * TRD_NB * TRD_NB;
+    b.a_rs = 1;
+    b.a_cs = TRD_NB;
+    b.a_tri = 1;
+    b.B = W1;
+    b.b_rs = 1;
+    b.b_cs = jb;
+    b.C = W2;
+    b.c_rs = 1;
+    b.c_cs = jb;
+    b.info = info;
+    b.tag = "zgemm_bt_tw";
+    if (zgemm(b, 1, s) != hipSuccess) return false;
+    ZgemmParams c;  // Z[j0+1:, :] -= V W2
+    c.M = (int)m;
+    c.N = (int)ncols;
+    c.K = jb;
+    c.A = V;
+    c.a_rs = 1;
+    c.a_cs = ld;
+    c.a_tri = 2;
+    c.B = W2;
+    c.b_rs = 1;
+    c.b_cs = jb;
+    c.C = Z + (j0 + 1);
+    c.c_rs = 1;
+    c.c_cs = ldz;
+    c.alpha = make_double2(-1.0, 0.0);
+    c.beta = 1.0;
+    c.info = info;
+    c.tag = "zgemm_bt_update";
+    if (zgemm(c, 1, s) != hipSuccess) return false;
+  }
+  return true;
+}
+}  // namespace
+
+size_t solve_workspace(const bse_desc* d) { return carve(d, nullptr).total; }
+
+bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* XpYv, int64_t ldx,
+                     const void* probev, double* osc, void* ws, int32_t* info, hipStream_t s) {
+  const int64_t n = (int64_t)d->nk * d->nv * d->nc, ld = d->ld;
+  const bool full = d->coupling == BSE_FULL;
+  double2* H0 = (double2*)H0v;
+  double2* H1 = (double2*)H1v;
+  double2* XpY = (double2*)XpYv;
+  const double2* probe = (const double2*)probev;
+  SolveWs w = carve(d, ws);
+  BSE_LAUNCH(k_zero_ints, dim3(1), dim3(64), 0, s, w.counters, 64);
+
+  double2* Hm = H0;  // Hermitian matrix handed to the tridiagonalisation
+  if (full) {
+    if (!cholesky(H1, n, ld, w.Uinv, info, s)) return BSE_ERR_HIP;
+    ZgemmParams a;  // T1 = (A+B) U^H
+    a.M = (int)n;
+    a.N = (int)n;
+    a.K = (int)n;
+    a.A = H0;
+    a.a_rs = 1;
+    a.a_cs = ld;
+    a.B = H1;
+    a.b_rs = ld;
+    a.b_cs = 1;
+    a.conjB = 1;
+    a.b_tri = 2;
+    a.C = w.Wk;
+    a.c_rs = 1;
+    a.c_cs = n;
+    a.info = info;
+    a.tag = "zgemm_sq_t1";
+    if (zgemm(a, 1, s) != hipSuccess) return BSE_ERR_HIP;
+    ZgemmParams b;  // S (lower) = U T1  -> H0
+    b.M = (int)n;
+    b.N = (int)n;
+    b.K = (int)n;
+    b.A = H1;
+    b.a_rs = 1;
+    b.a_cs = ld;
+    b.a_tri = 1;
+    b.B = w.Wk;
+    b.b_rs = 1;
+    b.b_cs = n;
+    b.C = H0;
+    b.c_rs = 1;
+    b.c_cs = ld;
+    b.c_uplo = 2;
+    b.info = info;
+    b.tag = "zgemm_sq_s";
+    if (zgemm(b, 1, s) != hipSuccess) return BSE_ERR_HIP;
+    const int nt = cdiv(n, 32);
+    BSE_LAUNCH(k_hermitize, dim3(nt, nt), dim3(256), 0, s, H0, n, ld, 1, info);
+  }
+
+  if (!tridiagonalise(Hm, n, ld, w, info, s)) return BSE_ERR_HIP;
+  BSE_LAUNCH(k_tri_prep, dim3(1), dim3(1024), 0, s, w.dd, w.ee, (int)n, w.e2, w.stat, info);
+  BSE_LAUNCH(k_bisect, dim3(cdiv(n, 4)), dim3(256), 0, s, w.dd, w.e2, (int)n, w.stat, w.mu,
+                     info);
+  BSE_LAUNCH(k_inviter, dim3(cdiv(n, 256)), dim3(256), 0, s, w.dd, w.ee, (int)n, w.mu,
+                     w.stat, 1e-5, w.Ztri, w.U0, w.U1, w.U2, info);
+  BSE_LAUNCH(k_eigvals, dim3(cdiv(n, 256)), dim3(256), 0, s, w.mu, (int)n, full ? 1 : 0, E,
+                     w.colscale, info);
+  const int64_t npnl = (n - 1 + TRD_NB - 1) / TRD_NB;
+  if (npnl > 0)
+    BSE_LAUNCH(k_larft, dim3((unsigned)npnl), dim3(256), 0, s, Hm, ld, (int)n, w.tau,
+                       w.Tall, info);
+
+  if (XpY) {
+    const int nt = cdiv(n, 32);
+    double2* Z = full ? w.Wk : XpY;
+    const int64_t ldz = full ? n : ldx;
+    BSE_LAUNCH(k_ztri_to_complex, dim3(nt, nt), dim3(256), 0, s, w.Ztri, (int)n,
+                       w.colscale, Z, ldz, info);
+    if (n > 1 && !apply_q(Hm, n, ld, Z, ldz, n, w, info, s)) return BSE_ERR_HIP;
+    if (full) {
+      ZgemmParams g;  // X+Y = U^H Z (columns already scaled by E^-1/2)
+      g.M = (int)n;
+      g.N = (int)n;
+      g.K = (int)n;
+      g.A = H1;
+      g.a_rs = ld;
+      g.a_cs = 1;
+      g.conjA = 1;
+      g.a_tri = 2;
+      g.B = w.Wk;
+      g.b_rs = 1;
+      g.b_cs = n;
+      g.C = XpY;
+      g.c_rs = 1;
+      g.c_cs = ldx;
+      g.info = info;
+      g.tag = "zgemm_recon";
+      if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
+    }
+    if (probe && osc && launch_oscillator(n, XpY, ldx, probe, osc, s) != hipSuccess)
+      return BSE_ERR_HIP;
+  } else if (probe && osc) {
+    if (full) {
+      ZgemmParams g;  // y = U p
+      g.M = (int)n;
+      g.N = 1;
+      g.K = (int)n;
+      g.A = H1;
+      g.a_rs = 1;
+      g.a_cs = ld;
+      g.a_tri = 1;
+      g.B = probe;
+      g.b_rs = 1;
+      g.b_cs = n;
+      g.C = w.yvec;
+      g.c_rs = 1;
+      g.c_cs = n;
+      g.info = info;
+      g.tag = "zgemm_probe_up";
+      if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
+    } else {
+      if (hipMemcpyAsync(w.yvec, probe, n * 16, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return BSE_ERR_HIP;
+    }
+    if (n > 1)
+      BSE_LAUNCH(k_apply_qh_vec, dim3(1), dim3(1024), 0, s, Hm, ld, (int)n, w.Tall, w.yvec,
+                         info);
+    BSE_LAUNCH(k_osc_tri, dim3(cdiv(n, 256)), dim3(256), 0, s, w.Ztri, (int)n, w.yvec,
+                       w.colscale, osc, info);
+  }
+  return hipGetLastError() == hipSuccess ? BSE_OK : BSE_ERR_HIP;
+}

@@ -1,0 +1,87 @@
+// Event-based kernel timing registry (see timing.h).
+#include "timing.h"
+
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bse_internal.h"
+
+namespace {
+struct Rec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex mu;
+bool enabled = false;
+std::vector<Rec> recs;
+std::vector<hipEvent_t> pool;
+
+hipEvent_t get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+bool timing_on() { return enabled; }
+
+void timing_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> g(mu);
+  Rec r{name, get_event(), get_event()};
+  if (r.a) hipEventRecord(r.a, s);
+  recs.push_back(r);
+}
+
+void timing_end(hipStream_t s) {
+  std::lock_guard<std::mutex> g(mu);
+  if (!recs.empty() && recs.back().b) hipEventRecord(recs.back().b, s);
+}
+
+extern "C" {
+
+void bse_timing_enable(int32_t on) {
+  std::lock_guard<std::mutex> g(mu);
+  enabled = on != 0;
+}
+
+int64_t bse_timing_report(char* buf, int64_t len) {
+  std::lock_guard<std::mutex> g(mu);
+  std::map<std::string, std::pair<long, double>> acc;
+  for (auto& r : recs) {
+    float ms = 0.0f;
+    if (r.a && r.b && hipEventSynchronize(r.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& e = acc[r.name];
+      e.first += 1;
+      e.second += ms;
+    }
+    if (r.a) pool.push_back(r.a);
+    if (r.b) pool.push_back(r.b);
+  }
+  recs.clear();
+  std::string out;
+  char line[256];
+  for (auto& kv : acc) {
+    snprintf(line, sizeof(line), "%s %ld %.6f\n", kv.first.c_str(), kv.second.first,
+             kv.second.second);
+    out += line;
+  }
+  if (buf && len > 0) {
+    const int64_t n = (int64_t)out.size() < len - 1 ? (int64_t)out.size() : len - 1;
+    memcpy(buf, out.data(), (size_t)n);
+    buf[n] = 0;
+  }
+  return (int64_t)out.size();
+}
+
+}  // extern "C"

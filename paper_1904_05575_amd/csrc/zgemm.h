@@ -1,0 +1,34 @@
+// Complex FP64 GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+//   C(m, n) = alpha * sum_k opA(m, k) opB(k, n) + beta * C(m, n)
+//
+// Operands are addressed through element strides (complex units), so one
+// kernel covers row- and column-major layouts, conjugate transposes and
+// batched products.  Triangular operands and triangular outputs skip the
+// zero tiles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+struct ZgemmParams {
+  int M = 0, N = 0, K = 0;
+  const double2* A = nullptr;
+  int64_t a_rs = 0, a_cs = 0, a_bs = 0;  // A(m,k) = A[b*a_bs + m*a_rs + k*a_cs]
+  const double2* B = nullptr;
+  int64_t b_rs = 0, b_cs = 0, b_bs = 0;  // B(k,n) = B[bb*b_bs + k*b_rs + n*b_cs]
+  double2* C = nullptr;
+  int64_t c_rs = 0, c_cs = 0, c_bs = 0;  // C(m,n) = C[b*c_bs + m*c_rs + n*c_cs]
+  const int32_t* b_batch_idx = nullptr;  // bb = b_batch_idx[b] (else bb = b)
+  double2 alpha = {1.0, 0.0};
+  double beta = 0.0;  // beta == 0: C is not read
+  int conjA = 0, conjB = 0;
+  int c_uplo = 0;  // 0 all; 1 store only m <= n; 2 store only m >= n
+  int a_tri = 0;   // 1: A(m,k) = 0 for k < m; 2: A(m,k) = 0 for k > m
+  int b_tri = 0;   // 1: B(k,n) = 0 for k > n; 2: B(k,n) = 0 for k < n
+  const double* kscale = nullptr;  // A(m,k) *= kscale[k]
+  const int32_t* info = nullptr;   // skip all work when *info != 0
+  const char* tag = "zgemm";        // name under which the launch is timed
+};
+
+// Enqueue `batch` products on `stream`.
+hipError_t zgemm(const ZgemmParams& p, int batch, hipStream_t stream);

@@ -1,0 +1,94 @@
+// Strided / batched complex FP64 GEMM on MFMA (see zgemm.h).
+#include "common.h"
+#include "mfma_tile.h"
+#include "timing.h"
+#include "zgemm.h"
+
+namespace {
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b_off) {
+  using T = ZTile<BM, BN, WM, WN>;
+  __shared__ typename T::Smem sm;
+  if (failed(p.info)) return;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  if (p.c_uplo == 1 && m0 > n0 + BN - 1) return;
+  if (p.c_uplo == 2 && n0 > m0 + BM - 1) return;
+  const int b = blockIdx.z + b_off;
+  const int64_t bb = p.b_batch_idx ? (int64_t)p.b_batch_idx[b] : (int64_t)b;
+  const double2* __restrict__ A = p.A + b * p.a_bs;
+  const double2* __restrict__ B = p.B + bb * p.b_bs;
+
+  int k_lo = 0, k_hi = p.K;
+  if (p.a_tri == 1) k_lo = max(k_lo, m0);
+  if (p.a_tri == 2) k_hi = min(k_hi, m0 + BM);
+  if (p.b_tri == 1) k_hi = min(k_hi, n0 + BN);
+  if (p.b_tri == 2) k_lo = max(k_lo, n0);
+
+  const double asgn = p.conjA ? -1.0 : 1.0, bsgn = p.conjB ? -1.0 : 1.0;
+  auto loadA = [&](int mm, int k) -> double2 {
+    const int m = m0 + mm;
+    bool ok = m < p.M;
+    if (p.a_tri == 1) ok = ok && (k >= m);
+    if (p.a_tri == 2) ok = ok && (k <= m);
+    if (!ok) return make_double2(0.0, 0.0);
+    double2 v = A[(int64_t)m * p.a_rs + (int64_t)k * p.a_cs];
+    v.y *= asgn;
+    if (p.kscale) {
+      const double s = p.kscale[k];
+      v.x *= s;
+      v.y *= s;
+    }
+    return v;
+  };
+  auto loadB = [&](int k, int nn) -> double2 {
+    const int n = n0 + nn;
+    bool ok = n < p.N;
+    if (p.b_tri == 1) ok = ok && (k <= n);
+    if (p.b_tri == 2) ok = ok && (k >= n);
+    if (!ok) return make_double2(0.0, 0.0);
+    double2 v = B[(int64_t)k * p.b_rs + (int64_t)n * p.b_cs];
+    v.y *= bsgn;
+    return v;
+  };
+  T t;
+  t.init();
+  t.run(sm, k_lo, k_hi, p.a_rs == 1, p.b_cs == 1, loadA, loadB);
+
+  double2* C = p.C + b * p.c_bs;
+  t.store([&](int mm, int nn, double2 acc) {
+    const int m = m0 + mm, n = n0 + nn;
+    if (m >= p.M || n >= p.N) return;
+    if (p.c_uplo == 1 && m > n) return;
+    if (p.c_uplo == 2 && m < n) return;
+    double2 v = cmul(p.alpha, acc);
+    double2* dst = C + (int64_t)m * p.c_rs + (int64_t)n * p.c_cs;
+    if (p.beta != 0.0) {
+      const double2 o = *dst;
+      v.x += p.beta * o.x;
+      v.y += p.beta * o.y;
+    }
+    *dst = v;
+  });
+}
+
+template <int BM, int BN, int WM, int WN>
+hipError_t launch(const ZgemmParams& p, int batch, hipStream_t s) {
+  TimedLaunch tl(p.tag, s);
+  for (int b0 = 0; b0 < batch; b0 += 65535) {
+    const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
+    dim3 grid(cdiv(p.M, BM), cdiv(p.N, BN), nb);
+    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, b0);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t zgemm(const ZgemmParams& p, int batch, hipStream_t s) {
+  if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
+  if (p.M <= 16 && p.N <= 16) return launch<16, 16, 1, 1>(p, batch, s);
+  if (p.M <= 32 || p.N <= 32 || (int64_t)cdiv(p.M, 64) * cdiv(p.N, 64) * batch < 512)
+    return launch<32, 32, 2, 2>(p, batch, s);
+  return launch<64, 64, 2, 2>(p, batch, s);
+}

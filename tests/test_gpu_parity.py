@@ -1,0 +1,140 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (FP64 path):
+  assembled matrices  max|H - H_or| <= 1e-12 max|H_or|   (sums of <= 2 NG products)
+  eigenvalues         max|E - E_or| / |E_or| <= 1e-10
+  spectrum            max|eps - eps_or| / max|eps_or - 1| <= 1e-10
+Eigenvectors are compared only through gauge-free quantities (oscillator
+strengths, the spectrum, residuals and the normalisation).
+"""
+import numpy as np
+import pytest
+
+from oracle import bse_oracle as O
+from tests._cache import inputs, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+SMALL = ["tiny_tda_k2_v2c2_g9", "tiny_full_k2_v2c3_g15", "small_full_k3_v3c4_g27",
+         "mid_full_k4_v3c4_g59", "tda_q0_k4_v2c3_g59"]
+
+
+def _problem(name, bse_type="singlet"):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_05575_amd.bse import Problem
+    print(f"[gpu] {name} {bse_type}", flush=True)
+    return Problem(inputs(name), bse_type)
+
+
+def _mat(H):
+    return H.T.cpu().numpy()  # column-major device storage
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_build_matches_oracle(name):
+    P = _problem(name)
+    H0, H1 = P.build()
+    P.check_info()
+    r = oracle_run(name)
+    if r["B"] is None:
+        assert _rel(_mat(H0), r["A"]) < 1e-12
+    else:
+        assert _rel(_mat(H0), r["A"] + r["B"]) < 1e-12
+        assert _rel(_mat(H1), r["A"] - r["B"]) < 1e-12
+    # Hermitian with a real diagonal, exactly
+    M = _mat(H0)
+    assert np.array_equal(M, M.conj().T)
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("vectors", [False, True])
+def test_solve_and_spectrum_match_oracle(name, vectors):
+    P = _problem(name)
+    out = P.run(vectors=vectors)
+    r = oracle_run(name)
+    assert np.all(np.diff(out["E"]) >= 0)
+    assert np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min() < 1e-10
+    spec = np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max()
+    assert spec < 1e-10, spec
+    # f-sum rule from the GPU's own E and oscillator strengths
+    A, B = r["A"], r["B"]
+    AmB = A if B is None else A - B
+    p = r["p"]
+    fs = np.vdot(p, AmB @ p).real
+    assert abs(np.sum(out["E"] * out["osc"]) - fs) < 1e-10 * fs
+
+
+@pytest.mark.parametrize("name", ["small_full_k3_v3c4_g27", "tda_q0_k4_v2c3_g59"])
+def test_eigenvectors_residual_and_normalisation(name):
+    P = _problem(name)
+    out = P.run(vectors=True)
+    r = oracle_run(name)
+    A, B, E, XpY = r["A"], r["B"], out["E"], out["XpY"]
+    if B is None:
+        res = np.abs(A @ XpY - XpY * E).max()
+        assert res < 1e-11 * E.max()
+        assert np.abs(XpY.conj().T @ XpY - np.eye(len(E))).max() < 1e-11
+    else:
+        # (A-B)(A+B)(X+Y) = E^2 (X+Y);  E (X+Y)^H (A-B)^-1 (X+Y) = I
+        res = np.abs((A - B) @ ((A + B) @ XpY) - XpY * E ** 2).max()
+        assert res < 1e-10 * E.max() ** 2
+        G = (XpY.conj().T @ np.linalg.solve(A - B, XpY)) * E[None, :]
+        assert np.abs(G - np.eye(len(E))).max() < 1e-10
+
+
+@pytest.mark.parametrize("name", ["tiny_full_k2_v2c3_g15", "tda_q0_k4_v2c3_g59"])
+def test_spectrum_kernel_alone(name):
+    """bse_spectrum fed with the oracle's E and |t|^2."""
+    torch = pytest.importorskip("torch")
+    P = _problem(name)
+    r = oracle_run(name)
+    E = torch.tensor(r["E"], device="cuda")
+    osc = torch.tensor(r["t2"], device="cuda")
+    eps = P.spectrum(E, osc).cpu().numpy()
+    assert np.abs(eps - r["eps"]).max() / np.abs(r["eps"] - 1).max() < 1e-13
+
+
+@pytest.mark.parametrize("bse_type", ["triplet", "rpa", "ip"])
+def test_other_bse_types(bse_type):
+    name = "small_full_k3_v3c4_g27"
+    P = _problem(name, bse_type)
+    out = P.run()
+    r = oracle_run(name, bse_type)
+    assert np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min() < 1e-10
+    assert np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max() < 1e-10
+
+
+def test_not_positive_definite_is_reported():
+    """A kernel scale far above the calibrated one breaks A-B: the Cholesky
+    reports the column in `info` (the oracle raises on the same input)."""
+    from dataclasses import replace
+    from bse_synth import get, make_inputs
+    from paper_1904_05575_amd._lib import BseError
+    from paper_1904_05575_amd.bse import Problem
+    w = replace(get("tiny_full_k2_v2c3_g15"), kernel_scale=4.0, name="bad")
+    d = make_inputs(w)
+    with pytest.raises(O.NotPositiveDefinite):
+        A, B = O.assemble(d)
+        O.solve_full(A, B)
+    torch = pytest.importorskip("torch")
+    P = Problem(d)
+    H0, H1 = P.build()
+    P.solve(H0, H1)
+    torch.cuda.synchronize()
+    code = int(P.info.item())
+    assert code != 0
+    with pytest.raises(BseError):
+        P.check_info()
+
+
+def test_repeat_is_bitwise_deterministic():
+    P = _problem("mid_full_k4_v3c4_g59")
+    a = P.run()
+    b = P.run()
+    assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["eps"], b["eps"])

@@ -1,0 +1,65 @@
+"""Host-side checks of the C-ABI library (no GPU needed): every function that
+include/bse.h declares is exported, workspace sizing and argument checks."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1904_05575_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bse.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bse_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libbse.so is not built (run `python -m paper_1904_05575_amd.build`)")
+    return L.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert set(L.EXPORTS) <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _desc(**kw):
+    d = dict(nk=8, nv=2, nc=3, ng=15, coupling=L.BSE_FULL, type=L.BSE_SINGLET,
+             prec=L.BSE_PREC_FP64, reserved=0, kappa=0.01, scissor=0.0, ld=48)
+    d.update(kw)
+    return L.BseDesc(**d)
+
+
+def test_workspace_sizes(lib):
+    assert L.bse_workspace_size(_desc(), L.BSE_STAGE_BUILD) > 0
+    assert L.bse_workspace_size(_desc(), L.BSE_STAGE_SOLVE) > 0
+    tda = L.bse_workspace_size(_desc(coupling=L.BSE_TDA), L.BSE_STAGE_BUILD)
+    assert 0 < tda < L.bse_workspace_size(_desc(), L.BSE_STAGE_BUILD)
+    for bad in (dict(nk=0), dict(ld=47), dict(coupling=7), dict(type=9), dict(prec=5),
+                dict(kappa=float("nan"))):
+        assert L.bse_workspace_size(_desc(**bad), L.BSE_STAGE_BUILD) == 0, bad
+    assert L.bse_workspace_size(_desc(), 9) == 0
+
+
+def test_argument_errors_are_reported_without_launching(lib):
+    d = _desc()
+    inp = L.BseInputs()
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+        L.bse_build(d, inp, 1, 1, 1, 1 << 30, 1, 0)       # null input pointers
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+        L.bse_solve(d, 1, 0, 1, 0, 48, 0, 0, 1, 1 << 30, 1, 0)   # full needs H1
+    with pytest.raises(L.BseError, match="BSE_ERR_WORKSPACE"):
+        L.bse_solve(d, 1, 1, 1, 1, 48, 0, 0, 1, 16, 1, 0)
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+        L.bse_spectrum(10, 1, 1, 1.0, 0.0, 5, 1, 1, 0)      # eta must be > 0
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+        L.bse_oscillator(10, 1, 5, 1, 1, 0)                 # ldx < n
+    assert lib.bse_status_string(2) == b"workspace too small"
