@@ -79,7 +79,7 @@ def cpu_baseline(inputs, w, budget_s: float = 20.0) -> dict:
         t0 = time.perf_counter()
         O.kernel_blocks(inputs, sel)
         dt = time.perf_counter() - t0
-        if dt > 2.0 or stride == 1:
+        if dt > 8.0 or stride == 1:
             break
         stride = max(1, stride // 4)
     # scale the sample to ~budget if it was quick

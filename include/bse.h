@@ -143,7 +143,8 @@ bse_status bse_spectrum(int64_t n, const double* E, const double* osc, double pr
  * bse_timing_report synchronises on those events, writes one line per kernel
  * name "<name> <launches> <total milliseconds>" into the HOST buffer `buf`
  * (truncated to len-1 bytes, NUL-terminated), clears the records and returns
- * the full length of the report. */
+ * the full length of the report.  With buf == NULL it only returns the length
+ * and keeps the records. */
 void bse_timing_enable(int32_t on);
 int64_t bse_timing_report(char* buf, int64_t len);
 

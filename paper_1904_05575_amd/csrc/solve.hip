@@ -14,20 +14,24 @@
 
 #include "bse_internal.h"
 #include "common.h"
+#include "solve_internal.h"
 #include "timing.h"
 #include "zgemm.h"
 
 namespace {
 
 constexpr int CH_NB = 32;   // Cholesky panel width
-constexpr int TRD_NB = 32;  // Householder panel width
-constexpr int ROWS_A = 256; // rows per block of the column kernel
 
 BSE_DEV double2 ld_acq(const double2* p) {
   double2 v;
   v.x = __hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   v.y = __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return v;
+}
+
+__global__ void k_copy_c(const double2* __restrict__ src, double2* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 __global__ void k_zero_ints(int32_t* p, int n) {
@@ -118,221 +122,6 @@ __global__ __launch_bounds__(256) void k_hermitize(double2* __restrict__ M, int6
   }
 }
 
-// ------------------------------------------------------------------ tridiagonalisation
-// Small shared state of the column kernels (complex slots):
-//   [0] scal = 1/(alpha_x - beta) of the current reflector, [1] tau,
-//   [2] alpha = -|tau|^2 (y^H v) / 2 from the hemv of the current column,
-//   [4 .. 4+NB) V^H v,  [4+NB .. 4+2NB) W^H v  (corrections of the hemv)
-constexpr int HS_SCAL = 0, HS_TAU = 1, HS_ALPHA = 2, HS_VV = 4, HS_WV = 4 + TRD_NB;
-constexpr int NPART = 1 + 2 * TRD_NB;
-
-// Column kernel for column c = j0 + i of the panel (rows r >= c, one thread per row):
-//  0. finishes the previous column: stores its scaled reflector v and its W column;
-//  1. applies the panel's earlier reflectors to column c;
-//  2. block partial sums of |x|^2 and of V^H x, W^H x over rows >= c+2;
-//  3. the last block to finish forms the reflector (beta, tau, scale) and the
-//     hemv corrections V^H v, W^H v.
-// With has_new = 0 only step 0 runs (end of a panel).
-__global__ __launch_bounds__(ROWS_A) void k_trd_col(double2* __restrict__ M, int64_t ld, int n,
-                                                    double2* __restrict__ Wp, int j0, int i,
-                                                    int has_new, double2* __restrict__ hs,
-                                                    const double2* __restrict__ ybuf,
-                                                    double2* __restrict__ part, int32_t* counter,
-                                                    double* __restrict__ dd, double* __restrict__ ee,
-                                                    double2* __restrict__ tau, const int32_t* info) {
-  __shared__ double2 red[ROWS_A / 64][NPART];
-  __shared__ double2 sums[NPART];
-  __shared__ double2 sh_scal;
-  __shared__ int is_last;
-  if (failed(info)) return;
-  const int c = j0 + i;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int r = c + blockIdx.x * ROWS_A + tid;
-  const bool act = r < n;
-
-  double2 vprev_r = make_double2(0.0, 0.0), wprev_r = make_double2(0.0, 0.0);
-  double2 wprev_c = make_double2(0.0, 0.0);
-  if (i > 0) {
-    const int cp = c - 1;
-    const double2 scal = hs[HS_SCAL], tc = hs[HS_TAU], al = hs[HS_ALPHA];
-    if (act) {
-      const double2 xv = M[r + (int64_t)cp * ld];
-      vprev_r = (r == c) ? make_double2(1.0, 0.0) : cmul(scal, xv);
-      M[r + (int64_t)cp * ld] = vprev_r;
-      wprev_r = cadd(cmul(tc, ybuf[r]), cmul(al, vprev_r));
-      Wp[r + (int64_t)(i - 1) * n] = wprev_r;
-    }
-    wprev_c = cadd(cmul(tc, ybuf[c]), al);
-  }
-  if (!has_new) return;
-
-  // 1. update of column c
-  double2 x = make_double2(0.0, 0.0);
-  if (act) {
-    x = M[r + (int64_t)c * ld];
-    for (int ip = 0; ip < i; ++ip) {
-      double2 vr, wr, vc, wc;
-      if (ip == i - 1) {
-        vr = vprev_r;
-        wr = wprev_r;
-        vc = make_double2(1.0, 0.0);
-        wc = wprev_c;
-      } else {
-        vr = M[r + (int64_t)(j0 + ip) * ld];
-        wr = Wp[r + (int64_t)ip * n];
-        vc = M[c + (int64_t)(j0 + ip) * ld];
-        wc = Wp[c + (int64_t)ip * n];
-      }
-      // x -= v_ip[r] conj(w_ip[c]) + w_ip[r] conj(v_ip[c])
-      x = csub(x, cadd(make_double2(vr.x * wc.x + vr.y * wc.y, vr.y * wc.x - vr.x * wc.y),
-                       make_double2(wr.x * vc.x + wr.y * vc.y, wr.y * vc.x - wr.x * vc.y)));
-    }
-    if (r == c) x.y = 0.0;
-    M[r + (int64_t)c * ld] = x;
-  }
-
-  // 2. partial sums over rows r >= c+2, compact layout [|x|^2, V^H x (i), W^H x (i)]
-  const bool tail = act && (r >= c + 2);
-  const int nvals = 1 + 2 * i;
-  for (int t = 0; t < nvals; ++t) {
-    double2 val = make_double2(0.0, 0.0);
-    if (tail) {
-      if (t == 0) {
-        val.x = cabs2(x);
-      } else if (t <= i) {
-        const int ip = t - 1;
-        const double2 vr = (ip == i - 1) ? vprev_r : M[r + (int64_t)(j0 + ip) * ld];
-        val = cmulc(vr, x);
-      } else {
-        const int ip = t - 1 - i;
-        const double2 wr = (ip == i - 1) ? wprev_r : Wp[r + (int64_t)ip * n];
-        val = cmulc(wr, x);
-      }
-    }
-    const double2 sw = wave_sum2(val);
-    if (lane == 0) red[wid][t] = sw;
-  }
-  __syncthreads();
-  for (int t = tid; t < nvals; t += ROWS_A) {
-    double2 sb = make_double2(0.0, 0.0);
-    for (int w = 0; w < ROWS_A / 64; ++w) sb = cadd(sb, red[w][t]);
-    part[(int64_t)blockIdx.x * NPART + t] = sb;
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-
-  // 3. last block: reflector of column c
-  for (int t = tid; t < nvals; t += ROWS_A) {
-    double2 sb = make_double2(0.0, 0.0);
-    for (int b = 0; b < (int)gridDim.x; ++b) sb = cadd(sb, ld_acq(part + (int64_t)b * NPART + t));
-    sums[t] = sb;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const double2 ax = ld_acq(M + (c + 1) + (int64_t)c * ld);
-    const double xn2 = sums[0].x;
-    double2 tv, scal;
-    double beta;
-    if (xn2 == 0.0 && ax.y == 0.0) {
-      tv = make_double2(0.0, 0.0);
-      beta = ax.x;
-      scal = make_double2(0.0, 0.0);
-    } else {
-      beta = -copysign(sqrt(ax.x * ax.x + ax.y * ax.y + xn2), ax.x);
-      tv = make_double2((beta - ax.x) / beta, -ax.y / beta);
-      const double2 dnm = make_double2(ax.x - beta, ax.y);
-      const double q = 1.0 / cabs2(dnm);
-      scal = make_double2(dnm.x * q, -dnm.y * q);
-    }
-    ee[c] = beta;
-    tau[c] = tv;
-    dd[c] = ld_acq(M + c + (int64_t)c * ld).x;
-    hs[HS_SCAL] = scal;
-    hs[HS_TAU] = tv;
-    sh_scal = scal;
-  }
-  __syncthreads();
-  const double2 scal = sh_scal;
-  for (int ip = tid; ip < i; ip += ROWS_A) {
-    const double2 v1 = ld_acq(M + (c + 1) + (int64_t)(j0 + ip) * ld);
-    const double2 w1 = ld_acq(Wp + (c + 1) + (int64_t)ip * n);
-    hs[HS_VV + ip] = cadd(cconj(v1), cmul(scal, sums[1 + ip]));
-    hs[HS_WV + ip] = cadd(cconj(w1), cmul(scal, sums[1 + i + ip]));
-  }
-  if (tid == 0) *counter = 0;
-}
-
-// y[r] = sum_j S[r, j] v[j] - V[r,:] (W^H v) - W[r,:] (V^H v) for r in (c, n),
-// one wavefront per row r reading column r of the (Hermitian, full) trailing
-// matrix; the last block forms alpha = -|tau|^2 (y^H v) / 2.
-__global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ M, int64_t ld, int n,
-                                                  const double2* __restrict__ Wp, int j0, int i,
-                                                  double2* __restrict__ hs,
-                                                  double2* __restrict__ ybuf,
-                                                  double2* __restrict__ part, int32_t* counter,
-                                                  const int32_t* info) {
-  __shared__ double2 red[4];
-  __shared__ int is_last;
-  if (failed(info)) return;
-  const int c = j0 + i;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int r = c + 1 + blockIdx.x * 4 + wid;
-  const double2 scal = hs[HS_SCAL];
-  const double2* vcol = M + (int64_t)c * ld;
-  double2 contrib = make_double2(0.0, 0.0);
-  if (r < n) {
-    const double2* col = M + (int64_t)r * ld;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int j = c + 1 + lane; j < n; j += 64) {
-      const double2 vj = (j == c + 1) ? make_double2(1.0, 0.0) : cmul(scal, vcol[j]);
-      acc = cadd(acc, cmulc(col[j], vj));  // conj(S[j, r]) v[j] = S[r, j] v[j]
-    }
-    // corrections, one panel column per lane
-    if (lane < i) {
-      const double2 vr = M[r + (int64_t)(j0 + lane) * ld];
-      const double2 wr = Wp[r + (int64_t)lane * n];
-      acc = csub(acc, cadd(cmul(vr, hs[HS_WV + lane]), cmul(wr, hs[HS_VV + lane])));
-    }
-    acc = wave_sum2(acc);
-    if (lane == 0) {
-      ybuf[r] = acc;
-      const double2 vr = (r == c + 1) ? make_double2(1.0, 0.0) : cmul(scal, vcol[r]);
-      contrib = cmulc(acc, vr);  // conj(y[r]) v[r]
-    }
-  }
-  if (lane == 0) red[wid] = contrib;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = cadd(cadd(red[0], red[1]), cadd(red[2], red[3]));
-    __threadfence();
-    is_last = (atomicAdd(counter, 1) == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  // deterministic final sum by one wavefront
-  if (wid == 0) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int b = lane; b < (int)gridDim.x; b += 64) s = cadd(s, ld_acq(part + b));
-    s = wave_sum2(s);
-    if (lane == 0) {
-      const double2 tv = hs[HS_TAU];
-      const double t2 = cabs2(tv);
-      hs[HS_ALPHA] = make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
-      *counter = 0;
-    }
-  }
-}
-
-__global__ void k_trd_last(const double2* M, int64_t ld, int n, double* dd, const int32_t* info) {
-  if (failed(info)) return;
-  if (threadIdx.x == 0) dd[n - 1] = M[(n - 1) + (int64_t)(n - 1) * ld].x;
-}
-
 // ------------------------------------------------------------------ tridiagonal eigensolver
 // e2, Gershgorin bounds, pivmin and the norm of T.  stat[0]=gl, [1]=gu, [2]=pivmin, [3]=tnorm
 __global__ __launch_bounds__(1024) void k_tri_prep(const double* __restrict__ d,
@@ -393,7 +182,8 @@ BSE_DEV int sturm_count(const double* __restrict__ d, const double* __restrict__
 }
 
 // Eigenvalue k (ascending) by multisection: the 64 lanes of a wavefront probe
-// 64 interior points of the bracket per round.
+// 128 interior points of the bracket per round, two independent Sturm
+// sequences per lane.
 __global__ __launch_bounds__(256) void k_bisect(const double* __restrict__ d,
                                                 const double* __restrict__ e2, int n,
                                                 const double* __restrict__ stat,
@@ -405,20 +195,37 @@ __global__ __launch_bounds__(256) void k_bisect(const double* __restrict__ d,
   double lo = stat[0], hi = stat[1];
   const double pivmin = stat[2];
   const double eps = 2.220446049250313e-16;
+  constexpr double NP = 129.0;
   for (int it = 0; it < 40; ++it) {
     const double width = hi - lo;
     if (width <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
-    const double x = lo + width * (double)(lane + 1) / 65.0;
-    const int cnt = sturm_count(d, e2, n, x, pivmin);
-    const unsigned long long mask = __ballot(cnt > k);
+    const double xa = lo + width * (double)(2 * lane + 1) / NP;
+    const double xb = lo + width * (double)(2 * lane + 2) / NP;
+    double qa = d[0] - xa, qb = d[0] - xb;
+    if (fabs(qa) < pivmin) qa = -pivmin;
+    if (fabs(qb) < pivmin) qb = -pivmin;
+    int ca = qa < 0.0, cb = qb < 0.0;
+    for (int i = 1; i < n; ++i) {
+      const double di = d[i], ei = e2[i - 1];
+      qa = (di - xa) - ei / qa;
+      qb = (di - xb) - ei / qb;
+      if (fabs(qa) < pivmin) qa = -pivmin;
+      if (fabs(qb) < pivmin) qb = -pivmin;
+      ca += qa < 0.0;
+      cb += qb < 0.0;
+    }
+    const unsigned long long ma = __ballot(ca > k), mb = __ballot(cb > k);
+    // first point (in order a0 b0 a1 b1 ...) whose count exceeds k
+    int f = 1 << 30;
+    if (ma) f = min(f, 2 * (__ffsll((long long)ma) - 1));
+    if (mb) f = min(f, 2 * (__ffsll((long long)mb) - 1) + 1);
     double nlo, nhi;
-    if (mask == 0ull) {
-      nlo = lo + width * 64.0 / 65.0;
+    if (f == (1 << 30)) {
+      nlo = lo + width * 128.0 / NP;
       nhi = hi;
     } else {
-      const int f = __ffsll((long long)mask) - 1;
-      nhi = lo + width * (double)(f + 1) / 65.0;
-      nlo = (f > 0) ? lo + width * (double)f / 65.0 : lo;
+      nhi = lo + width * (double)(f + 1) / NP;
+      nlo = (f > 0) ? lo + width * (double)f / NP : lo;
     }
     if (nlo == lo && nhi == hi) break;
     lo = nlo;
@@ -437,16 +244,96 @@ BSE_DEV double hash_uniform(uint32_t a, uint32_t b) {
   return 2.0 * ((double)h / 4294967296.0) - 1.0;
 }
 
-// Inverse iteration for every eigenvalue (one thread per cluster of close
-// eigenvalues; members of a cluster are orthogonalised against each other).
-// Z and the LU scratch are stored [component i][eigenvalue j] (coalesced).
+// One inverse-iteration solve (T - lam I) x = s * b with partial pivoting:
+// the forward sweep writes U (U0 diagonal, U1, U2 super-diagonals) and the
+// eliminated rhs R; the backward sweep writes x into X and returns max |x|,
+// sum x^2 and the index of the largest |x|.  The rhs b is X (scaled by s) or,
+// when X_in_is_random, the start vector.  Arrays are [component i][eigenvalue j].
+struct SolveStats {
+  double big, nrm2;
+  int ibig;
+};
+
+BSE_DEV SolveStats inv_solve(const double* __restrict__ d, const double* __restrict__ e, int n,
+                             double lam, double tiny, int j, int64_t N, bool random_rhs,
+                             double scale, double* __restrict__ X, double* __restrict__ U0,
+                             double* __restrict__ U1, double* __restrict__ U2,
+                             double* __restrict__ R) {
+  double di = d[0] - lam, dui = (n > 1) ? e[0] : 0.0;
+  double rin = random_rhs ? hash_uniform(0u, (uint32_t)j) : X[j] * scale;
+  double nxt = (n > 1) ? (random_rhs ? hash_uniform(1u, (uint32_t)j) : X[N + j] * scale) : 0.0;
+  for (int i = 0; i < n - 1; ++i) {
+    double r1 = nxt;
+    if (i + 2 < n) nxt = random_rhs ? hash_uniform((uint32_t)(i + 2), (uint32_t)j)
+                                    : X[(int64_t)(i + 2) * N + j] * scale;
+    const double dl = e[i];
+    double d1 = d[i + 1] - lam;
+    double du1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+    double Ud, Uu, Uu2, ri;
+    if (fabs(di) >= fabs(dl)) {
+      const double f = (di != 0.0) ? dl / di : 0.0;
+      Ud = di;
+      Uu = dui;
+      Uu2 = 0.0;
+      ri = rin;
+      d1 -= f * dui;
+      r1 -= f * rin;
+    } else {
+      const double f = di / dl;
+      Ud = dl;
+      Uu = d1;
+      Uu2 = du1;
+      ri = r1;
+      const double nd1 = dui - f * d1;
+      du1 = -f * du1;
+      r1 = rin - f * r1;
+      d1 = nd1;
+    }
+    const int64_t o = (int64_t)i * N + j;
+    U0[o] = Ud;
+    U1[o] = Uu;
+    U2[o] = Uu2;
+    R[o] = ri;
+    di = d1;
+    dui = du1;
+    rin = r1;
+  }
+  U0[(int64_t)(n - 1) * N + j] = di;
+  R[(int64_t)(n - 1) * N + j] = rin;
+  SolveStats st{0.0, 0.0, 0};
+  double x1 = 0.0, x2 = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    const int64_t o = (int64_t)i * N + j;
+    double p = U0[o];
+    if (fabs(p) < tiny) p = (p >= 0.0) ? tiny : -tiny;
+    double s = R[o];
+    if (i < n - 1) s -= U1[o] * x1;
+    if (i < n - 2) s -= U2[o] * x2;
+    const double xi = s / p;
+    X[o] = xi;
+    const double ax = fabs(xi);
+    if (ax > st.big) {
+      st.big = ax;
+      st.ibig = i;
+    }
+    st.nrm2 += xi * xi;
+    x2 = x1;
+    x1 = xi;
+  }
+  return st;
+}
+
+// Inverse iteration for every eigenvalue: one thread per cluster of close
+// eigenvalues (gap <= ortol_rel * |T|); cluster members are orthogonalised
+// against the earlier ones.  Two solves per eigenvalue from a pseudo-random
+// start, then normalisation with the largest component made positive.
 __global__ __launch_bounds__(256) void k_inviter(const double* __restrict__ d,
                                                  const double* __restrict__ e, int n,
                                                  const double* __restrict__ w,
                                                  const double* __restrict__ stat, double ortol_rel,
                                                  double* __restrict__ Z, double* __restrict__ U0,
                                                  double* __restrict__ U1, double* __restrict__ U2,
-                                                 int32_t* info) {
+                                                 double* __restrict__ R, int32_t* info) {
   if (failed(info)) return;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -460,88 +347,44 @@ __global__ __launch_bounds__(256) void k_inviter(const double* __restrict__ d,
   const int64_t N = n;
   for (int j = k; j <= kend; ++j) {
     const double lam = w[j];
-    for (int i = 0; i < n; ++i) Z[i * N + j] = hash_uniform((uint32_t)i, (uint32_t)j);
-    for (int it = 0; it < 3; ++it) {
-      // LU with partial pivoting of T - lam I, forward elimination on the rhs in Z
-      double di = d[0] - lam, dui = (n > 1) ? e[0] : 0.0, rin = Z[j];
-      for (int i = 0; i < n - 1; ++i) {
-        const double dl = e[i];
-        double d1 = d[i + 1] - lam;
-        double du1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;
-        double r1 = Z[(i + 1) * N + j];
-        double Ud, Uu, Uu2, ri;
-        if (fabs(di) >= fabs(dl)) {
-          const double f = (di != 0.0) ? dl / di : 0.0;
-          Ud = di;
-          Uu = dui;
-          Uu2 = 0.0;
-          ri = rin;
-          d1 -= f * dui;
-          r1 -= f * rin;
-        } else {
-          const double f = di / dl;
-          Ud = dl;
-          Uu = d1;
-          Uu2 = du1;
-          ri = r1;
-          const double nd1 = dui - f * d1;
-          du1 = -f * du1;
-          r1 = rin - f * r1;
-          d1 = nd1;
-        }
-        U0[i * N + j] = Ud;
-        U1[i * N + j] = Uu;
-        U2[i * N + j] = Uu2;
-        Z[i * N + j] = ri;
-        di = d1;
-        dui = du1;
-        rin = r1;
-      }
-      U0[(N - 1) * N + j] = di;
-      Z[(N - 1) * N + j] = rin;
-      // back substitution with tiny pivots perturbed
-      double x1 = 0.0, x2 = 0.0;
-      for (int i = n - 1; i >= 0; --i) {
-        double p = U0[i * N + j];
-        if (fabs(p) < tiny) p = (p >= 0.0) ? tiny : -tiny;
-        double s = Z[i * N + j];
-        if (i < n - 1) s -= U1[i * N + j] * x1;
-        if (i < n - 2) s -= U2[i * N + j] * x2;
-        const double xi = s / p;
-        Z[i * N + j] = xi;
-        x2 = x1;
-        x1 = xi;
-      }
-      // orthogonalise against earlier members of the cluster, then normalise
+    SolveStats st = inv_solve(d, e, n, lam, tiny, j, N, true, 1.0, Z, U0, U1, U2, R);
+    if (!(st.big > 0.0) || !isfinite(st.big)) {
+      set_info(info, BSE_INFO_NO_CONVERGE);
+      return;
+    }
+    st = inv_solve(d, e, n, lam, tiny, j, N, false, 1.0 / st.big, Z, U0, U1, U2, R);
+    if (!(st.big > 0.0) || !isfinite(st.big)) {
+      set_info(info, BSE_INFO_NO_CONVERGE);
+      return;
+    }
+    double s = 1.0 / sqrt(st.nrm2);
+    if (j > k) {
+      // orthogonalise against the earlier members of the cluster, renormalise
+      for (int i = 0; i < n; ++i) Z[(int64_t)i * N + j] *= s;
       for (int jp = k; jp < j; ++jp) {
         double dot = 0.0;
-        for (int i = 0; i < n; ++i) dot += Z[i * N + jp] * Z[i * N + j];
-        for (int i = 0; i < n; ++i) Z[i * N + j] -= dot * Z[i * N + jp];
+        for (int i = 0; i < n; ++i) dot += Z[(int64_t)i * N + jp] * Z[(int64_t)i * N + j];
+        for (int i = 0; i < n; ++i) Z[(int64_t)i * N + j] -= dot * Z[(int64_t)i * N + jp];
       }
-      double nrm = 0.0, big = 0.0;
-      for (int i = 0; i < n; ++i) big = fmax(big, fabs(Z[i * N + j]));
-      if (!(big > 0.0) || !isfinite(big)) {
+      double nrm2 = 0.0, big = 0.0;
+      int ib = 0;
+      for (int i = 0; i < n; ++i) {
+        const double v = Z[(int64_t)i * N + j];
+        nrm2 += v * v;
+        if (fabs(v) > big) {
+          big = fabs(v);
+          ib = i;
+        }
+      }
+      if (!(nrm2 > 0.0)) {
         set_info(info, BSE_INFO_NO_CONVERGE);
         return;
       }
-      const double sb = 1.0 / big;
-      for (int i = 0; i < n; ++i) {
-        const double v = Z[i * N + j] * sb;
-        nrm += v * v;
-      }
-      const double s = sb / sqrt(nrm);
-      for (int i = 0; i < n; ++i) Z[i * N + j] *= s;
+      s = 1.0 / sqrt(nrm2);
+      st.ibig = ib;
     }
-    // fixed sign: largest component positive
-    double big = 0.0;
-    int ib = 0;
-    for (int i = 0; i < n; ++i)
-      if (fabs(Z[i * N + j]) > big) {
-        big = fabs(Z[i * N + j]);
-        ib = i;
-      }
-    if (Z[ib * N + j] < 0.0)
-      for (int i = 0; i < n; ++i) Z[i * N + j] = -Z[i * N + j];
+    if (Z[(int64_t)st.ibig * N + j] < 0.0) s = -s;
+    for (int i = 0; i < n; ++i) Z[(int64_t)i * N + j] *= s;
   }
 }
 
@@ -643,53 +486,6 @@ __global__ __launch_bounds__(256) void k_larft(const double2* __restrict__ M, in
   for (int e = tid; e < TRD_NB * TRD_NB; e += 256) To[e] = T[e % TRD_NB][e / TRD_NB];
 }
 
-// y := Q^H y = (H_n-2^H ... H_0^H) y over every panel in order (one block).
-__global__ __launch_bounds__(1024) void k_apply_qh_vec(const double2* __restrict__ M, int64_t ld,
-                                                       int n, const double2* __restrict__ Tall,
-                                                       double2* __restrict__ y,
-                                                       const int32_t* info) {
-  __shared__ double2 red[16][TRD_NB];
-  __shared__ double2 w1[TRD_NB], w2[TRD_NB];
-  if (failed(info)) return;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int j0 = 0; j0 < n - 1; j0 += TRD_NB) {
-    const int jb = min(TRD_NB, n - 1 - j0);
-    const double2* T = Tall + (int64_t)(j0 / TRD_NB) * TRD_NB * TRD_NB;
-    double2 acc[TRD_NB];
-    for (int a = 0; a < TRD_NB; ++a) acc[a] = make_double2(0.0, 0.0);
-    for (int r = j0 + 1 + tid; r < n; r += 1024) {
-      const double2 yr = y[r];
-      for (int a = 0; a < jb; ++a)
-        if (r >= j0 + a + 1) acc[a] = cadd(acc[a], cmulc(M[r + (int64_t)(j0 + a) * ld], yr));
-    }
-    for (int a = 0; a < TRD_NB; ++a) {
-      const double2 s = wave_sum2(acc[a]);
-      if (lane == 0) red[wid][a] = s;
-    }
-    __syncthreads();
-    if (tid < TRD_NB) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int w = 0; w < 16; ++w) s = cadd(s, red[w][tid]);
-      w1[tid] = s;
-    }
-    __syncthreads();
-    // w2 = T^H w1
-    if (tid < jb) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int k = 0; k <= tid; ++k) s = cadd(s, cmulc(T[k + tid * TRD_NB], w1[k]));
-      w2[tid] = s;
-    }
-    __syncthreads();
-    for (int r = j0 + 1 + tid; r < n; r += 1024) {
-      double2 s = y[r];
-      for (int a = 0; a < jb; ++a)
-        if (r >= j0 + a + 1) s = csub(s, cmul(M[r + (int64_t)(j0 + a) * ld], w2[a]));
-      y[r] = s;
-    }
-    __syncthreads();
-  }
-}
-
 // osc[l] = |sum_i Ztri[i][l] y[i]|^2 * scale2[l]
 __global__ __launch_bounds__(256) void k_osc_tri(const double* __restrict__ Zt, int n,
                                                  const double2* __restrict__ y,
@@ -719,7 +515,9 @@ struct SolveWs {
   double* U0;
   double* U1;
   double* U2;
-  double2* Wp;    // n x TRD_NB panel W
+  double* U3;
+  double2* VW;    // n x 2 TRD_NB panel [V | W]
+  double2* WV;    // n x 2 TRD_NB panel [W | V]
   double2* W1;    // TRD_NB x n (back-transform)
   double2* W2;    // TRD_NB x n
   double2* ybuf;  // n
@@ -742,8 +540,6 @@ struct SolveWs {
 SolveWs carve(const bse_desc* d, void* base) {
   const int64_t n = (int64_t)d->nk * d->nv * d->nc;
   const int64_t npnl = (n + TRD_NB - 1) / TRD_NB + 1;
-  const int64_t nblk_a = (n + ROWS_A - 1) / ROWS_A + 1;
-  const int64_t nblk_b = (n + 3) / 4 + 1;
   WsLayout L(base);
   SolveWs w;
   w.Wk = (double2*)L.add(n * n * 16);
@@ -751,13 +547,15 @@ SolveWs carve(const bse_desc* d, void* base) {
   w.U0 = (double*)L.add(n * n * 8);
   w.U1 = (double*)L.add(n * n * 8);
   w.U2 = (double*)L.add(n * n * 8);
-  w.Wp = (double2*)L.add(n * TRD_NB * 16);
+  w.U3 = (double*)L.add(n * n * 8);
+  w.VW = (double2*)L.add(n * 2 * TRD_NB * 16);
+  w.WV = (double2*)L.add(n * 2 * TRD_NB * 16);
   w.W1 = (double2*)L.add(n * TRD_NB * 16);
   w.W2 = (double2*)L.add(n * TRD_NB * 16);
   w.ybuf = (double2*)L.add(n * 16);
   w.yvec = (double2*)L.add(n * 16);
-  w.hs = (double2*)L.add((4 + 2 * TRD_NB) * 16);
-  w.part = (double2*)L.add(std::max(nblk_a * NPART, nblk_b) * 16);
+  w.hs = (double2*)L.add(HS_SIZE * 16);
+  w.part = (double2*)L.add(trd_part_elems(n) * 16);
   w.Tall = (double2*)L.add(npnl * TRD_NB * TRD_NB * 16);
   w.Uinv = (double2*)L.add(CH_NB * CH_NB * 16);
   w.tau = (double2*)L.add(n * 16);
@@ -819,58 +617,6 @@ bool cholesky(double2* H1, int64_t n, int64_t ld, double2* Uinv, int32_t* info, 
     if (zgemm(h, 1, s) != hipSuccess) return false;
   }
   return true;
-}
-
-bool tridiagonalise(double2* M, int64_t n, int64_t ld, SolveWs& w, int32_t* info, hipStream_t s) {
-  for (int64_t j0 = 0; j0 < n - 1; j0 += TRD_NB) {
-    const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
-    for (int i = 0; i < jb; ++i) {
-      const int64_t c = j0 + i;
-      const int ga = cdiv(n - c, ROWS_A);
-      BSE_LAUNCH(k_trd_col, dim3(ga), dim3(ROWS_A), 0, s, M, ld, (int)n, w.Wp, (int)j0,
-                         i, 1, w.hs, w.ybuf, w.part, w.counters + 0, w.dd, w.ee, w.tau, info);
-      const int gb = cdiv(n - c - 1, 4);
-      BSE_LAUNCH(k_trd_hemv, dim3(gb), dim3(256), 0, s, M, ld, (int)n, w.Wp, (int)j0, i,
-                         w.hs, w.ybuf, w.part, w.counters + 1, info);
-    }
-    // finish the panel's last column
-    BSE_LAUNCH(k_trd_col, dim3(cdiv(n - (j0 + jb), ROWS_A)), dim3(ROWS_A), 0, s, M, ld,
-                       (int)n, w.Wp, (int)j0, jb, 0, w.hs, w.ybuf, w.part, w.counters + 0, w.dd,
-                       w.ee, w.tau, info);
-    const int64_t t = j0 + jb;
-    if (t < n) {
-      ZgemmParams g;  // M[t:, t:] -= V W^H
-      g.M = (int)(n - t);
-      g.N = (int)(n - t);
-      g.K = jb;
-      g.A = M + t + j0 * ld;
-      g.a_rs = 1;
-      g.a_cs = ld;
-      g.B = w.Wp + t;
-      g.b_rs = n;
-      g.b_cs = 1;
-      g.conjB = 1;
-      g.C = M + t + t * ld;
-      g.c_rs = 1;
-      g.c_cs = ld;
-      g.alpha = make_double2(-1.0, 0.0);
-      g.beta = 1.0;
-      g.info = info;
-      g.tag = "zgemm_her2k";
-      if (zgemm(g, 1, s) != hipSuccess) return false;
-      ZgemmParams h = g;  // M[t:, t:] -= W V^H
-      h.A = w.Wp + t;
-      h.a_rs = 1;
-      h.a_cs = n;
-      h.B = M + t + j0 * ld;
-      h.b_rs = ld;
-      h.b_cs = 1;
-      h.conjB = 1;
-      if (zgemm(h, 1, s) != hipSuccess) return false;
-    }
-  }
-  BSE_LAUNCH(k_trd_last, dim3(1), dim3(64), 0, s, M, ld, (int)n, w.dd, info);
-  return hipGetLastError() == hipSuccess;
 }
 
 // Z := Q Z for the n x ncols complex matrix Z (column-major, ldz).
@@ -999,25 +745,52 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
     BSE_LAUNCH(k_hermitize, dim3(nt, nt), dim3(256), 0, s, H0, n, ld, 1, info);
   }
 
-  if (!tridiagonalise(Hm, n, ld, w, info, s)) return BSE_ERR_HIP;
+  // spectrum-only: the probe is carried through the reduction, y = Q^H (U p)
+  const bool project = (XpY == nullptr) && probe && osc;
+  if (project) {
+    if (full) {
+      ZgemmParams g;  // y = U p
+      g.M = (int)n;
+      g.N = 1;
+      g.K = (int)n;
+      g.A = H1;
+      g.a_rs = 1;
+      g.a_cs = ld;
+      g.a_tri = 1;
+      g.B = probe;
+      g.b_rs = 1;
+      g.b_cs = n;
+      g.C = w.yvec;
+      g.c_rs = 1;
+      g.c_cs = n;
+      g.info = info;
+      g.tag = "zgemm_probe_up";
+      if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
+    } else {
+      BSE_LAUNCH(k_copy_c, dim3(cdiv(n, 256)), dim3(256), 0, s, probe, w.yvec, n);
+    }
+  }
+  TrdBufs tb{w.VW, w.WV, w.ybuf, w.hs, w.part, w.counters, w.dd, w.ee, w.tau,
+             project ? w.yvec : nullptr};
+  if (!tridiagonalise(Hm, n, ld, tb, info, s)) return BSE_ERR_HIP;
   BSE_LAUNCH(k_tri_prep, dim3(1), dim3(1024), 0, s, w.dd, w.ee, (int)n, w.e2, w.stat, info);
   BSE_LAUNCH(k_bisect, dim3(cdiv(n, 4)), dim3(256), 0, s, w.dd, w.e2, (int)n, w.stat, w.mu,
-                     info);
-  BSE_LAUNCH(k_inviter, dim3(cdiv(n, 256)), dim3(256), 0, s, w.dd, w.ee, (int)n, w.mu,
-                     w.stat, 1e-5, w.Ztri, w.U0, w.U1, w.U2, info);
+             info);
+  BSE_LAUNCH(k_inviter, dim3(cdiv(n, 256)), dim3(256), 0, s, w.dd, w.ee, (int)n, w.mu, w.stat,
+             1e-5, w.Ztri, w.U0, w.U1, w.U2, w.U3, info);
   BSE_LAUNCH(k_eigvals, dim3(cdiv(n, 256)), dim3(256), 0, s, w.mu, (int)n, full ? 1 : 0, E,
-                     w.colscale, info);
-  const int64_t npnl = (n - 1 + TRD_NB - 1) / TRD_NB;
-  if (npnl > 0)
-    BSE_LAUNCH(k_larft, dim3((unsigned)npnl), dim3(256), 0, s, Hm, ld, (int)n, w.tau,
-                       w.Tall, info);
+             w.colscale, info);
 
   if (XpY) {
+    const int64_t npnl = (n - 1 + TRD_NB - 1) / TRD_NB;
+    if (npnl > 0)
+      BSE_LAUNCH(k_larft, dim3((unsigned)npnl), dim3(256), 0, s, Hm, ld, (int)n, w.tau, w.Tall,
+                 info);
     const int nt = cdiv(n, 32);
     double2* Z = full ? w.Wk : XpY;
     const int64_t ldz = full ? n : ldx;
-    BSE_LAUNCH(k_ztri_to_complex, dim3(nt, nt), dim3(256), 0, s, w.Ztri, (int)n,
-                       w.colscale, Z, ldz, info);
+    BSE_LAUNCH(k_ztri_to_complex, dim3(nt, nt), dim3(256), 0, s, w.Ztri, (int)n, w.colscale, Z,
+               ldz, info);
     if (n > 1 && !apply_q(Hm, n, ld, Z, ldz, n, w, info, s)) return BSE_ERR_HIP;
     if (full) {
       ZgemmParams g;  // X+Y = U^H Z (columns already scaled by E^-1/2)
@@ -1041,34 +814,9 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
     }
     if (probe && osc && launch_oscillator(n, XpY, ldx, probe, osc, s) != hipSuccess)
       return BSE_ERR_HIP;
-  } else if (probe && osc) {
-    if (full) {
-      ZgemmParams g;  // y = U p
-      g.M = (int)n;
-      g.N = 1;
-      g.K = (int)n;
-      g.A = H1;
-      g.a_rs = 1;
-      g.a_cs = ld;
-      g.a_tri = 1;
-      g.B = probe;
-      g.b_rs = 1;
-      g.b_cs = n;
-      g.C = w.yvec;
-      g.c_rs = 1;
-      g.c_cs = n;
-      g.info = info;
-      g.tag = "zgemm_probe_up";
-      if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
-    } else {
-      if (hipMemcpyAsync(w.yvec, probe, n * 16, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return BSE_ERR_HIP;
-    }
-    if (n > 1)
-      BSE_LAUNCH(k_apply_qh_vec, dim3(1), dim3(1024), 0, s, Hm, ld, (int)n, w.Tall, w.yvec,
-                         info);
+  } else if (project) {
     BSE_LAUNCH(k_osc_tri, dim3(cdiv(n, 256)), dim3(256), 0, s, w.Ztri, (int)n, w.yvec,
-                       w.colscale, osc, info);
+               w.colscale, osc, info);
   }
   return hipGetLastError() == hipSuccess ? BSE_OK : BSE_ERR_HIP;
 }

@@ -65,10 +65,7 @@ int64_t bse_timing_report(char* buf, int64_t len) {
       e.first += 1;
       e.second += ms;
     }
-    if (r.a) pool.push_back(r.a);
-    if (r.b) pool.push_back(r.b);
   }
-  recs.clear();
   std::string out;
   char line[256];
   for (auto& kv : acc) {
@@ -80,6 +77,12 @@ int64_t bse_timing_report(char* buf, int64_t len) {
     const int64_t n = (int64_t)out.size() < len - 1 ? (int64_t)out.size() : len - 1;
     memcpy(buf, out.data(), (size_t)n);
     buf[n] = 0;
+    // a report written into a buffer consumes the records
+    for (auto& r : recs) {
+      if (r.a) pool.push_back(r.a);
+      if (r.b) pool.push_back(r.b);
+    }
+    recs.clear();
   }
   return (int64_t)out.size();
 }
