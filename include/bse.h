@@ -139,13 +139,14 @@ bse_status bse_spectrum(int64_t n, const double* E, const double* osc, double pr
                         int64_t nw, const double* omega, void* eps, hipStream_t stream);
 
 /* Measurement hook: while enabled (on != 0), every kernel launch of the
- * library is bracketed by two HIP events recorded on the launch stream.
+ * library (or, when `name` is not NULL, every launch of the kernel with that
+ * name) is bracketed by two HIP events recorded on the launch stream.
  * bse_timing_report synchronises on those events, writes one line per kernel
  * name "<name> <launches> <total milliseconds>" into the HOST buffer `buf`
  * (truncated to len-1 bytes, NUL-terminated), clears the records and returns
  * the full length of the report.  With buf == NULL it only returns the length
  * and keeps the records. */
-void bse_timing_enable(int32_t on);
+void bse_timing_enable(int32_t on, const char* name);
 int64_t bse_timing_report(char* buf, int64_t len);
 
 /* Human-readable name of a status. */

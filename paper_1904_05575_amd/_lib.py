@@ -65,7 +65,7 @@ def lib() -> ctypes.CDLL:
         L.bse_oscillator.restype = ctypes.c_int
         L.bse_spectrum.argtypes = [i64, vp, vp, dbl, dbl, i64, vp, vp, vp]
         L.bse_spectrum.restype = ctypes.c_int
-        L.bse_timing_enable.argtypes = [i32]
+        L.bse_timing_enable.argtypes = [i32, ctypes.c_char_p]
         L.bse_timing_enable.restype = None
         L.bse_timing_report.argtypes = [ctypes.c_char_p, i64]
         L.bse_timing_report.restype = i64
@@ -107,8 +107,8 @@ def bse_spectrum(n: int, E: int, osc: int, pref: float, eta: float, nw: int, ome
            "bse_spectrum")
 
 
-def bse_timing_enable(on: bool) -> None:
-    lib().bse_timing_enable(1 if on else 0)
+def bse_timing_enable(on: bool, name: str | None = None) -> None:
+    lib().bse_timing_enable(1 if on else 0, name.encode() if name else None)
 
 
 def bse_timing_report() -> dict:

@@ -287,10 +287,13 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   // direct terms, stage 1 (grouped by class) and stage 2 (batched by pair)
   auto direct = [&](const void* left, int R, const void* right, int N2, const int32_t* perm,
                     const int32_t* cls, double2* T, double2* blk) -> bool {
-    const int tiles = cdiv((int64_t)nk * R, S1_BM);  // a class holds at most nk pairs
-    dim3 grid((unsigned)(nq * tiles), (unsigned)cdiv(ng, S1_BN));
-    BSE_LAUNCH(k_stage1, grid, dim3(256), 0, s, (const double2*)left, R, ng,
-                       (const double2*)in->W, perm, cls, tiles, T, info);
+    if (!launch_stage1((const double2*)left, R, ng, (const double2*)in->W, perm, cls, nq, nk, T,
+                       info, s)) {
+      const int tiles = cdiv((int64_t)nk * R, S1_BM);  // a class holds at most nk pairs
+      dim3 grid((unsigned)(nq * tiles), (unsigned)cdiv(ng, S1_BN));
+      BSE_LAUNCH(k_stage1, grid, dim3(256), 0, s, (const double2*)left, R, ng,
+                 (const double2*)in->W, perm, cls, tiles, T, info);
+    }
     ZgemmParams g;
     g.M = R;
     g.N = N2;

@@ -45,6 +45,11 @@ size_t build_workspace_fp64(const bse_desc* d);
 bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void* out1, void* ws,
                       int32_t* info, hipStream_t s);
 
+// stage1.hip: class-grouped T = conj(L) W(q) on the real view of the complex data
+bool launch_stage1(const double2* left, int R, int ng, const double2* W, const int32_t* perm,
+                   const int32_t* cls, int nq, int nk, double2* T, const int32_t* info,
+                   hipStream_t s);
+
 // solve.hip
 size_t solve_workspace(const bse_desc* d);
 bse_status solve_run(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, int64_t ldx,

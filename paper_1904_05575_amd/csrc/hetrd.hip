@@ -20,7 +20,7 @@
 
 namespace {
 
-constexpr int ROWS_A = 128;     // rows per block of the column kernel
+constexpr int ROWS_A = 256;     // rows per block of the column kernel
 constexpr int HEMV_WAVES = 8;   // output rows per hemv block
 constexpr int VCHUNK = 2048;    // v staged in LDS in chunks of this many entries
 constexpr int NVAL = 2 + 2 * TRD_NB;  // |x|^2, conj(x) y_probe, V^H x (i), W^H x (i)
@@ -43,7 +43,10 @@ __global__ __launch_bounds__(ROWS_A) void k_trd_col(
     double2* __restrict__ part, int32_t* counter, double* __restrict__ dd,
     double* __restrict__ ee, double2* __restrict__ tau, double2* __restrict__ yp,
     const int32_t* info) {
-  __shared__ double2 red[ROWS_A / 64][NVAL];
+  constexpr int NG = ROWS_A / 64;
+  __shared__ double2 xs[ROWS_A], vps[ROWS_A], wps[ROWS_A];
+  __shared__ double2 vcs[TRD_NB], wcs[TRD_NB];
+  __shared__ double2 red[NG][2 * TRD_NB + 2];
   __shared__ double2 sums[NVAL];
   __shared__ double2 sh_scal;
   __shared__ int is_last;
@@ -51,7 +54,8 @@ __global__ __launch_bounds__(ROWS_A) void k_trd_col(
   const int c = j0 + i;
   const int64_t N = n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int r = c + blockIdx.x * ROWS_A + tid;
+  const int rbase = c + blockIdx.x * ROWS_A;
+  const int r = rbase + tid;
   const bool act = r < n;
 
   // ---- 0. finish reflector c-1
@@ -79,65 +83,85 @@ __global__ __launch_bounds__(ROWS_A) void k_trd_col(
   }
   if (!has_new) return;
 
-  // ---- 1. apply the panel's earlier reflectors to column c
-  double2 vr[TRD_NB], wr[TRD_NB];
-  double2 x = make_double2(0.0, 0.0);
-  if (act) x = M[r + (int64_t)c * ld];
-#pragma unroll
-  for (int ip = 0; ip < TRD_NB; ++ip) {
-    vr[ip] = make_double2(0.0, 0.0);
-    wr[ip] = make_double2(0.0, 0.0);
-    if (ip < i && act) {
-      double2 vc, wc;
-      if (ip == i - 1) {
-        vr[ip] = vprev_r;
-        wr[ip] = wprev_r;
-        vc = make_double2(1.0, 0.0);
-        wc = wprev_c;
-      } else {
-        vr[ip] = VW[r + (int64_t)ip * N];
-        wr[ip] = VW[r + (int64_t)(TRD_NB + ip) * N];
-        vc = VW[c + (int64_t)ip * N];
-        wc = VW[c + (int64_t)(TRD_NB + ip) * N];
-      }
-      x = sub_mulc(x, vr[ip], wc);
-      x = sub_mulc(x, wr[ip], vc);
-    }
+  // ---- 1. apply the panel's earlier reflectors to column c (one row per thread);
+  // row c of the panel is the same for every thread and is staged in LDS
+  for (int ip = tid; ip < i - 1; ip += ROWS_A) {
+    vcs[ip] = VW[c + (int64_t)ip * N];
+    wcs[ip] = VW[c + (int64_t)(TRD_NB + ip) * N];
   }
+  __syncthreads();
+  double2 x = make_double2(0.0, 0.0);
   if (act) {
+    x = M[r + (int64_t)c * ld];
+    for (int ip0 = 0; ip0 < i - 1; ip0 += 8) {
+      double2 vr[8], wr[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (ip0 + u < i - 1) {
+          vr[u] = VW[r + (int64_t)(ip0 + u) * N];
+          wr[u] = VW[r + (int64_t)(TRD_NB + ip0 + u) * N];
+        }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (ip0 + u < i - 1) {
+          x = sub_mulc(x, vr[u], wcs[ip0 + u]);
+          x = sub_mulc(x, wr[u], vcs[ip0 + u]);
+        }
+    }
+    if (i > 0) {
+      x = sub_mulc(x, vprev_r, wprev_c);
+      x = sub_mulc(x, wprev_r, make_double2(1.0, 0.0));
+    }
     if (r == c) x.y = 0.0;
     M[r + (int64_t)c * ld] = x;
   }
-
-  // ---- 2. block partial sums over rows r >= c+2 (compact layout)
   const bool tail = act && (r >= c + 2);
-  const int nvals = 2 + 2 * i;
+  xs[tid] = tail ? x : make_double2(0.0, 0.0);
+  vps[tid] = vprev_r;  // column i-1 of the panel, just formed by this thread
+  wps[tid] = wprev_r;
   {
-    double2 v0 = make_double2(tail ? cabs2(x) : 0.0, 0.0);
-    double2 s0 = wave_sum2(v0);
-    double2 v1 = (tail && yp) ? cmulc(x, yp[r]) : make_double2(0.0, 0.0);
-    double2 s1 = wave_sum2(v1);
+    const double2 s0 = wave_sum2(make_double2(tail ? cabs2(x) : 0.0, 0.0));
+    const double2 s1 = wave_sum2((tail && yp) ? cmulc(x, yp[r]) : make_double2(0.0, 0.0));
     if (lane == 0) {
-      red[wid][0] = s0;
-      red[wid][1] = s1;
-    }
-  }
-#pragma unroll
-  for (int ip = 0; ip < TRD_NB; ++ip) {
-    if (ip < i) {
-      const double2 pv = tail ? cmulc(vr[ip], x) : make_double2(0.0, 0.0);
-      const double2 pw = tail ? cmulc(wr[ip], x) : make_double2(0.0, 0.0);
-      const double2 sv = wave_sum2(pv), sw = wave_sum2(pw);
-      if (lane == 0) {
-        red[wid][2 + ip] = sv;
-        red[wid][2 + i + ip] = sw;
-      }
+      red[wid][2 * TRD_NB] = s0;
+      red[wid][2 * TRD_NB + 1] = s1;
     }
   }
   __syncthreads();
+
+  // ---- 2. V^H x and W^H x over this block's rows: thread = (panel column, row group)
+  {
+    const int col = tid & 63;  // 0..31 -> V column, 32..63 -> W column
+    const int ip = col & (TRD_NB - 1);
+    double2 acc = make_double2(0.0, 0.0);
+    const int r0 = rbase + wid * 64;
+    const int rlim = min(n, r0 + 64);
+    if (ip < i - 1) {
+      const double2* src = VW + (int64_t)col * N;
+      for (int rr0 = max(r0, c + 2); rr0 < rlim; rr0 += 16) {
+        double2 sv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (rr0 + u < rlim) sv[u] = src[rr0 + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (rr0 + u < rlim) acc = cadd(acc, cmulc(sv[u], xs[rr0 + u - rbase]));
+      }
+    } else if (ip == i - 1) {
+      const double2* src = (col < TRD_NB) ? vps : wps;
+      for (int rr = max(r0, c + 2); rr < rlim; ++rr)
+        acc = cadd(acc, cmulc(src[rr - rbase], xs[rr - rbase]));
+    }
+    red[wid][col] = acc;
+  }
+  __syncthreads();
+  // block partials, compact layout [|x|^2, conj(x) y, V^H x (i), W^H x (i)]
+  const int nvals = 2 + 2 * i;
   for (int t = tid; t < nvals; t += ROWS_A) {
+    const int src = (t == 0) ? 2 * TRD_NB : (t == 1) ? 2 * TRD_NB + 1
+                  : (t < 2 + i) ? (t - 2) : (TRD_NB + t - 2 - i);
     double2 sb = make_double2(0.0, 0.0);
-    for (int w = 0; w < ROWS_A / 64; ++w) sb = cadd(sb, red[w][t]);
+    for (int g = 0; g < NG; ++g) sb = cadd(sb, red[g][src]);
     part[(int64_t)blockIdx.x * NVAL + t] = sb;
   }
   __threadfence();
@@ -148,9 +172,18 @@ __global__ __launch_bounds__(ROWS_A) void k_trd_col(
   __threadfence();
 
   // ---- 3. last block: reflector c
+  const int nb = gridDim.x;
   for (int t = tid; t < nvals; t += ROWS_A) {
     double2 sb = make_double2(0.0, 0.0);
-    for (int b = 0; b < (int)gridDim.x; ++b) sb = cadd(sb, ld_acq(part + (int64_t)b * NVAL + t));
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = ld_acq(part + (int64_t)(b + u) * NVAL + t);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sb = cadd(sb, v[u]);
+    }
+    for (; b < nb; ++b) sb = cadd(sb, ld_acq(part + (int64_t)b * NVAL + t));
     sums[t] = sb;
   }
   __syncthreads();

@@ -181,9 +181,17 @@ BSE_DEV int sturm_count(const double* __restrict__ d, const double* __restrict__
   return cnt;
 }
 
+// 1/q to full double precision: hardware reciprocal refined by two Newton steps.
+BSE_DEV double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(fma(-q, r, 1.0), r, r);
+  r = fma(fma(-q, r, 1.0), r, r);
+  return r;
+}
+
 // Eigenvalue k (ascending) by multisection: the 64 lanes of a wavefront probe
-// 128 interior points of the bracket per round, two independent Sturm
-// sequences per lane.
+// 64 interior points of the bracket per round with Sturm counts of the
+// LDL^T factorisation of T - x I.
 __global__ __launch_bounds__(256) void k_bisect(const double* __restrict__ d,
                                                 const double* __restrict__ e2, int n,
                                                 const double* __restrict__ stat,
@@ -195,35 +203,43 @@ __global__ __launch_bounds__(256) void k_bisect(const double* __restrict__ d,
   double lo = stat[0], hi = stat[1];
   const double pivmin = stat[2];
   const double eps = 2.220446049250313e-16;
-  constexpr double NP = 129.0;
+  constexpr double NP = 65.0;
   for (int it = 0; it < 40; ++it) {
     const double width = hi - lo;
     if (width <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
-    const double xa = lo + width * (double)(2 * lane + 1) / NP;
-    const double xb = lo + width * (double)(2 * lane + 2) / NP;
-    double qa = d[0] - xa, qb = d[0] - xb;
-    if (fabs(qa) < pivmin) qa = -pivmin;
-    if (fabs(qb) < pivmin) qb = -pivmin;
-    int ca = qa < 0.0, cb = qb < 0.0;
-    for (int i = 1; i < n; ++i) {
-      const double di = d[i], ei = e2[i - 1];
-      qa = (di - xa) - ei / qa;
-      qb = (di - xb) - ei / qb;
-      if (fabs(qa) < pivmin) qa = -pivmin;
-      if (fabs(qb) < pivmin) qb = -pivmin;
-      ca += qa < 0.0;
-      cb += qb < 0.0;
+    const double x = lo + width * (double)(lane + 1) / NP;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+    int i = 1;
+    for (; i + 4 <= n; i += 4) {
+      const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
+      const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+      q = (d0 - x) - f0 * recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+      q = (d1 - x) - f1 * recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+      q = (d2 - x) - f2 * recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+      q = (d3 - x) - f3 * recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
     }
-    const unsigned long long ma = __ballot(ca > k), mb = __ballot(cb > k);
-    // first point (in order a0 b0 a1 b1 ...) whose count exceeds k
-    int f = 1 << 30;
-    if (ma) f = min(f, 2 * (__ffsll((long long)ma) - 1));
-    if (mb) f = min(f, 2 * (__ffsll((long long)mb) - 1) + 1);
+    for (; i < n; ++i) {
+      q = (d[i] - x) - e2[i - 1] * recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+    const unsigned long long mask = __ballot(cnt > k);
     double nlo, nhi;
-    if (f == (1 << 30)) {
-      nlo = lo + width * 128.0 / NP;
+    if (mask == 0ull) {
+      nlo = lo + width * 64.0 / NP;
       nhi = hi;
     } else {
+      const int f = __ffsll((long long)mask) - 1;
       nhi = lo + width * (double)(f + 1) / NP;
       nlo = (f > 0) ? lo + width * (double)f / NP : lo;
     }
@@ -259,66 +275,94 @@ BSE_DEV SolveStats inv_solve(const double* __restrict__ d, const double* __restr
                              double scale, double* __restrict__ X, double* __restrict__ U0,
                              double* __restrict__ U1, double* __restrict__ U2,
                              double* __restrict__ R) {
+  constexpr int CH = 16;  // rows whose loads are issued together
   double di = d[0] - lam, dui = (n > 1) ? e[0] : 0.0;
   double rin = random_rhs ? hash_uniform(0u, (uint32_t)j) : X[j] * scale;
-  double nxt = (n > 1) ? (random_rhs ? hash_uniform(1u, (uint32_t)j) : X[N + j] * scale) : 0.0;
-  for (int i = 0; i < n - 1; ++i) {
-    double r1 = nxt;
-    if (i + 2 < n) nxt = random_rhs ? hash_uniform((uint32_t)(i + 2), (uint32_t)j)
-                                    : X[(int64_t)(i + 2) * N + j] * scale;
-    const double dl = e[i];
-    double d1 = d[i + 1] - lam;
-    double du1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;
-    double Ud, Uu, Uu2, ri;
-    if (fabs(di) >= fabs(dl)) {
-      const double f = (di != 0.0) ? dl / di : 0.0;
-      Ud = di;
-      Uu = dui;
-      Uu2 = 0.0;
-      ri = rin;
-      d1 -= f * dui;
-      r1 -= f * rin;
-    } else {
-      const double f = di / dl;
-      Ud = dl;
-      Uu = d1;
-      Uu2 = du1;
-      ri = r1;
-      const double nd1 = dui - f * d1;
-      du1 = -f * du1;
-      r1 = rin - f * r1;
-      d1 = nd1;
+  for (int i0 = 0; i0 < n - 1; i0 += CH) {
+    double rb[CH], db[CH], eb[CH], fb[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i0 + u;
+      if (i < n - 1) {
+        rb[u] = random_rhs ? hash_uniform((uint32_t)(i + 1), (uint32_t)j)
+                           : X[(int64_t)(i + 1) * N + j] * scale;
+        db[u] = d[i + 1];
+        eb[u] = e[i];
+        fb[u] = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+      }
     }
-    const int64_t o = (int64_t)i * N + j;
-    U0[o] = Ud;
-    U1[o] = Uu;
-    U2[o] = Uu2;
-    R[o] = ri;
-    di = d1;
-    dui = du1;
-    rin = r1;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i0 + u;
+      if (i < n - 1) {
+        const double dl = eb[u];
+        double d1 = db[u] - lam, du1 = fb[u], r1 = rb[u];
+        double Ud, Uu, Uu2, ri;
+        if (fabs(di) >= fabs(dl)) {
+          const double f = (di != 0.0) ? dl / di : 0.0;
+          Ud = di;
+          Uu = dui;
+          Uu2 = 0.0;
+          ri = rin;
+          d1 -= f * dui;
+          r1 -= f * rin;
+        } else {
+          const double f = di / dl;
+          Ud = dl;
+          Uu = d1;
+          Uu2 = du1;
+          ri = r1;
+          const double nd1 = dui - f * d1;
+          du1 = -f * du1;
+          r1 = rin - f * r1;
+          d1 = nd1;
+        }
+        const int64_t o = (int64_t)i * N + j;
+        U0[o] = Ud;
+        U1[o] = Uu;
+        U2[o] = Uu2;
+        R[o] = ri;
+        di = d1;
+        dui = du1;
+        rin = r1;
+      }
+    }
   }
   U0[(int64_t)(n - 1) * N + j] = di;
   R[(int64_t)(n - 1) * N + j] = rin;
   SolveStats st{0.0, 0.0, 0};
   double x1 = 0.0, x2 = 0.0;
-  for (int i = n - 1; i >= 0; --i) {
-    const int64_t o = (int64_t)i * N + j;
-    double p = U0[o];
-    if (fabs(p) < tiny) p = (p >= 0.0) ? tiny : -tiny;
-    double s = R[o];
-    if (i < n - 1) s -= U1[o] * x1;
-    if (i < n - 2) s -= U2[o] * x2;
-    const double xi = s / p;
-    X[o] = xi;
-    const double ax = fabs(xi);
-    if (ax > st.big) {
-      st.big = ax;
-      st.ibig = i;
+  for (int i1 = n - 1; i1 >= 0; i1 -= CH) {
+    double p0[CH], p1[CH], p2[CH], rr[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i1 - u;
+      if (i >= 0) {
+        const int64_t o = (int64_t)i * N + j;
+        p0[u] = U0[o];
+        p1[u] = (i < n - 1) ? U1[o] : 0.0;
+        p2[u] = (i < n - 2) ? U2[o] : 0.0;
+        rr[u] = R[o];
+      }
     }
-    st.nrm2 += xi * xi;
-    x2 = x1;
-    x1 = xi;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i1 - u;
+      if (i >= 0) {
+        double p = p0[u];
+        if (fabs(p) < tiny) p = (p >= 0.0) ? tiny : -tiny;
+        const double xi = (rr[u] - p1[u] * x1 - p2[u] * x2) / p;
+        X[(int64_t)i * N + j] = xi;
+        const double ax = fabs(xi);
+        if (ax > st.big) {
+          st.big = ax;
+          st.ibig = i;
+        }
+        st.nrm2 += xi * xi;
+        x2 = x1;
+        x1 = xi;
+      }
+    }
   }
   return st;
 }

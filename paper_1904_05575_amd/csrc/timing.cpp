@@ -18,6 +18,7 @@ struct Rec {
 };
 std::mutex mu;
 bool enabled = false;
+std::string only;  // when non-empty, only launches with this name are timed
 std::vector<Rec> recs;
 std::vector<hipEvent_t> pool;
 
@@ -37,6 +38,10 @@ bool timing_on() { return enabled; }
 
 void timing_begin(const char* name, hipStream_t s) {
   std::lock_guard<std::mutex> g(mu);
+  if (!only.empty() && only != name) {
+    recs.push_back(Rec{name, nullptr, nullptr});
+    return;
+  }
   Rec r{name, get_event(), get_event()};
   if (r.a) hipEventRecord(r.a, s);
   recs.push_back(r);
@@ -49,9 +54,10 @@ void timing_end(hipStream_t s) {
 
 extern "C" {
 
-void bse_timing_enable(int32_t on) {
+void bse_timing_enable(int32_t on, const char* name) {
   std::lock_guard<std::mutex> g(mu);
   enabled = on != 0;
+  only = name ? name : "";
 }
 
 int64_t bse_timing_report(char* buf, int64_t len) {
