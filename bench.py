@@ -100,6 +100,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="full_q0_k8_v3c4_g113")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precisions", default="fp32,bf16x6",
+                    help="assembly precisions timed after the FP64 steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -152,26 +154,34 @@ def main() -> int:
     dom = max(cands, key=lambda k: cands[k][1]) if cands else None
     print(f"[bench] profiling step done; dominant kernel {dom}", file=sys.stderr, flush=True)
 
-    # timed region: HIP events around each stage, and around every launch of
-    # the dominant kernel on the stream it runs on
+    # timed region: HIP events around each stage of every step
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    if dom:
-        L.bse_timing_enable(True, dom)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         E, osc, eps = step(evs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    L.bse_timing_enable(False)
     P.check_info()
-    kern = L.bse_timing_report()
     build_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     solve_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     spec_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
     step_ms = float(np.mean([e[0].elapsed_time(e[3]) for e in evs]))
     flops = build_flops(w)
     value = flops["total"] / (build_ms * 1e-3) / 1e12
+
+    # the same steps again with HIP events around every launch of the dominant
+    # kernel, recorded on the stream it runs on (the events add host overhead,
+    # so these steps do not enter ms_per_step)
+    if dom:
+        L.bse_timing_enable(True, dom)
+    evr = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    for i in range(args.steps):
+        step(evr[i])
+    torch.cuda.synchronize()
+    L.bse_timing_enable(False)
+    kern = L.bse_timing_report()
+    roof_step_ms = float(np.mean([e[0].elapsed_time(e[3]) for e in evr]))
 
     roof = None
     if dom and dom in kern:
@@ -186,9 +196,35 @@ def main() -> int:
         roof = {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": u,
                 "frac": ach / peak, "traffic": None, "launches_per_step": launches / args.steps,
                 "avg_launch_us": total_ms / launches * 1e3,
+                "ms_per_step_with_events": roof_step_ms,
                 "per_launch_" + ("bytes" if bound == "hbm" else "flop"): per_launch}
     kernels_ms = {k: round(v[1], 3) for k, v in
                   sorted(breakdown.items(), key=lambda kv: -kv[1][1])}
+
+    # precision form of the assembly: same inputs, FP32 and split-BF16 (6 products);
+    # errors are against the FP64 path of the same run
+    E64, eps64 = E.cpu().numpy(), eps.cpu().numpy()
+    t2e = {"fp64": step_ms}
+    b_ms = {"fp64": build_ms}
+    mixed_err = {}
+    for prec in args.precisions.split(","):
+        if not prec:
+            continue
+        P.set_precision(prec)
+        step()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for i in range(args.steps):
+            Ep, _, epsp = step(ev[i])
+        torch.cuda.synchronize()
+        P.check_info()
+        t2e[prec] = float(np.mean([e[0].elapsed_time(e[3]) for e in ev]))
+        b_ms[prec] = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        Ep, epsp = Ep.cpu().numpy(), epsp.cpu().numpy()
+        mixed_err[prec] = {"eig_rel": float(np.abs(Ep - E64).max() / np.abs(E64).min()),
+                           "spec_err": float(np.abs(epsp - eps64).max() / np.abs(eps64 - 1).max())}
+        print(f"[bench] precision {prec}: {t2e[prec]:.1f} ms/step", file=sys.stderr, flush=True)
+    P.set_precision("fp64")
 
     out = {
         "metric": "kernel-build TFLOP/s + time-to-eps_M at N=6144 full BSE, FP64 vs split-BF16",
@@ -206,7 +242,10 @@ def main() -> int:
         "config": {"workload": w.name, "n": w.n, "nk": w.nk, "nv": w.nv, "nc": w.nc,
                    "ng": w.ng, "coupling": w.coupling, "nw": w.nw,
                    "assembly_precision": "fp64"},
-        "time_to_eps_M_ms": {"fp64": step_ms},
+        "time_to_eps_M_ms": t2e,
+        "build_ms": b_ms,
+        "build_tflops": {k: flops["total"] / (v * 1e-3) / 1e12 for k, v in b_ms.items()},
+        "mixed_error_vs_fp64_path": mixed_err,
         "stage_ms": {"build": build_ms, "solve": solve_ms, "spectrum": spec_ms},
         "wall_ms_per_step": wall / args.steps * 1e3,
         "build_gflop": flops["total"] / 1e9,

@@ -61,8 +61,16 @@ typedef enum { BSE_TDA = 0, BSE_FULL = 1 } bse_coupling;
  * singlet (1,1), triplet (0,1), RPA (1,0), independent particles (0,0). */
 typedef enum { BSE_SINGLET = 0, BSE_TRIPLET = 1, BSE_RPA = 2, BSE_IP = 3 } bse_type;
 
-/* Arithmetic of the kernel assembly.  The solve is always FP64. */
-typedef enum { BSE_PREC_FP64 = 0 } bse_precision;
+/* Arithmetic of the kernel assembly (exchange and both direct terms); the
+ * solve is always FP64.
+ *  FP64   : FP64 matrix-core products.
+ *  FP32   : operands rounded to FP32, FP32 products and accumulation inside
+ *           chunks of 16 complex terms, FP64 accumulation across chunks.
+ *  BF16X3 : operands rounded to FP32 and split into three BF16 terms
+ *           (hi + mid + lo); split_terms = 6 (default) keeps the products
+ *           hi*hi, hi*mid, mid*hi, hi*lo, lo*hi, mid*mid, split_terms = 3 the
+ *           first three; FP32 accumulation inside chunks, FP64 across. */
+typedef enum { BSE_PREC_FP64 = 0, BSE_PREC_FP32 = 1, BSE_PREC_BF16X3 = 2 } bse_precision;
 
 typedef enum { BSE_STAGE_BUILD = 0, BSE_STAGE_SOLVE = 1 } bse_stage;
 
@@ -71,7 +79,7 @@ typedef struct {
   int32_t coupling;       /* bse_coupling */
   int32_t type;           /* bse_type */
   int32_t prec;           /* bse_precision */
-  int32_t reserved;
+  int32_t split_terms;    /* BSE_PREC_BF16X3 only: 3 or 6 products (0 = 6) */
   double kappa;           /* kernel prefactor: 1/V_c of eq. vft in energy units */
   double scissor;         /* rigid shift added to every transition energy */
   int64_t ld;             /* leading dimension of the N x N matrices, >= n */

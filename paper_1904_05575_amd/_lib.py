@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbse.so")
 
 BSE_TDA, BSE_FULL = 0, 1
 BSE_SINGLET, BSE_TRIPLET, BSE_RPA, BSE_IP = 0, 1, 2, 3
-BSE_PREC_FP64 = 0
+BSE_PREC_FP64, BSE_PREC_FP32, BSE_PREC_BF16X3 = 0, 1, 2
 BSE_STAGE_BUILD, BSE_STAGE_SOLVE = 0, 1
 STATUS = {0: "BSE_OK", 1: "BSE_ERR_ARG", 2: "BSE_ERR_WORKSPACE", 3: "BSE_ERR_HIP"}
 EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bse_spectrum",
@@ -24,7 +24,7 @@ EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bs
 class BseDesc(ctypes.Structure):
     _fields_ = [("nk", ctypes.c_int32), ("nv", ctypes.c_int32), ("nc", ctypes.c_int32),
                 ("ng", ctypes.c_int32), ("coupling", ctypes.c_int32), ("type", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("split_terms", ctypes.c_int32),
                 ("kappa", ctypes.c_double), ("scissor", ctypes.c_double),
                 ("ld", ctypes.c_int64)]
 

@@ -16,6 +16,8 @@ from . import _lib as L
 
 HARTREE_EV = 27.211386245988
 TYPES = {"singlet": L.BSE_SINGLET, "triplet": L.BSE_TRIPLET, "rpa": L.BSE_RPA, "ip": L.BSE_IP}
+PRECISIONS = {"fp64": (L.BSE_PREC_FP64, 0), "fp32": (L.BSE_PREC_FP32, 0),
+              "bf16x6": (L.BSE_PREC_BF16X3, 6), "bf16x3": (L.BSE_PREC_BF16X3, 3)}
 
 
 def g_index_of_q(gvec: np.ndarray, alat: float, q) -> int:
@@ -55,7 +57,8 @@ def _dev(a: np.ndarray, dtype, device) -> torch.Tensor:
 class Problem:
     """One BSE problem resident on the GPU."""
 
-    def __init__(self, inputs: dict, bse_type: str = "singlet", device: str = "cuda"):
+    def __init__(self, inputs: dict, bse_type: str = "singlet", device: str = "cuda",
+                 precision: str = "fp64"):
         w = inputs["workload"]
         self.workload = w
         self.device = torch.device(device)
@@ -87,7 +90,8 @@ class Problem:
         self.eta = w.eta
         self.desc = L.BseDesc(nk=w.nk, nv=w.nv, nc=w.nc, ng=w.ng,
                               coupling=L.BSE_FULL if self.full else L.BSE_TDA,
-                              type=TYPES[bse_type], prec=L.BSE_PREC_FP64, reserved=0,
+                              type=TYPES[bse_type], prec=PRECISIONS[precision][0],
+                              split_terms=PRECISIONS[precision][1],
                               kappa=self.kappa, scissor=w.scissor, ld=self.n)
         p = lambda k: self.t[k].data_ptr() if k in self.t else None  # noqa: E731
         self.inp = L.BseInputs(eps_v=p("eps_v"), eps_c=p("eps_c"), Mcv=p("Mcv"), Mvv=p("Mvv"),
@@ -99,6 +103,10 @@ class Problem:
                                     dtype=torch.uint8, device=dv)
         self.ws_solve = torch.empty(max(1, L.bse_workspace_size(self.desc, L.BSE_STAGE_SOLVE)),
                                     dtype=torch.uint8, device=dv)
+
+    def set_precision(self, precision: str) -> None:
+        """Switch the arithmetic of the assembly (same inputs and workspaces)."""
+        self.desc.prec, self.desc.split_terms = PRECISIONS[precision]
 
     @staticmethod
     def stream() -> int:

@@ -13,7 +13,9 @@ bool desc_ok(const bse_desc* d) {
   if (d->ld < n) return false;
   if (d->coupling != BSE_TDA && d->coupling != BSE_FULL) return false;
   if (d->type < BSE_SINGLET || d->type > BSE_IP) return false;
-  if (d->prec != BSE_PREC_FP64) return false;
+  if (d->prec != BSE_PREC_FP64 && d->prec != BSE_PREC_FP32 && d->prec != BSE_PREC_BF16X3)
+    return false;
+  if (d->split_terms != 0 && d->split_terms != 3 && d->split_terms != 6) return false;
   if (!isfinite(d->kappa) || !isfinite(d->scissor)) return false;
   return true;
 }

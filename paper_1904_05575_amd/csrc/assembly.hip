@@ -259,8 +259,15 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
     BSE_LAUNCH(k_class_sort, dim3(1), dim3(1024), 2 * nq * sizeof(int32_t), s, in->qramap,
                        nk, nq, perm_ra, cls_ra, inv_ra, info);
 
+  const int prec = d->prec;
+  const int nterms = d->split_terms == 0 ? 6 : d->split_terms;
   // exchange: out0 (upper) = alpha * conj(Mcv) diag(vbar) Mcv^T
-  {
+  const double ex_alpha = (full ? 4.0 : 2.0) * gx * kap;
+  if (prec != BSE_PREC_FP64) {
+    if (!launch_exchange_lp(prec, nterms, (const double2*)in->Mcv, (int)n, ng, in->vbar, ex_alpha,
+                            (double2*)out0, ld, info, s))
+      return BSE_ERR_HIP;
+  } else {
     ZgemmParams g;
     g.M = (int)n;
     g.N = (int)n;
@@ -276,7 +283,7 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
     g.C = (double2*)out0;
     g.c_rs = 1;
     g.c_cs = ld;
-    g.alpha = make_double2((full ? 4.0 : 2.0) * gx * kap, 0.0);
+    g.alpha = make_double2(ex_alpha, 0.0);
     g.beta = 0.0;
     g.c_uplo = 1;
     g.info = info;
@@ -287,6 +294,12 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   // direct terms, stage 1 (grouped by class) and stage 2 (batched by pair)
   auto direct = [&](const void* left, int R, const void* right, int N2, const int32_t* perm,
                     const int32_t* cls, double2* T, double2* blk) -> bool {
+    if (prec != BSE_PREC_FP64) {
+      return launch_stage1_lp(prec, nterms, (const double2*)left, R, ng, (const double2*)in->W,
+                              perm, cls, nq, nk, T, info, s) &&
+             launch_batched_lp(prec, nterms, T, R, ng, (const double2*)right, N2, perm, (int)P,
+                               blk, info, s);
+    }
     if (!launch_stage1((const double2*)left, R, ng, (const double2*)in->W, perm, cls, nq, nk, T,
                        info, s)) {
       const int tiles = cdiv((int64_t)nk * R, S1_BM);  // a class holds at most nk pairs

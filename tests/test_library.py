@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def _desc(**kw):
     d = dict(nk=8, nv=2, nc=3, ng=15, coupling=L.BSE_FULL, type=L.BSE_SINGLET,
-             prec=L.BSE_PREC_FP64, reserved=0, kappa=0.01, scissor=0.0, ld=48)
+             prec=L.BSE_PREC_FP64, split_terms=0, kappa=0.01, scissor=0.0, ld=48)
     d.update(kw)
     return L.BseDesc(**d)
 
