@@ -93,6 +93,46 @@ def cpu_baseline(inputs, w, budget_s: float = 20.0) -> dict:
                       f"{stride}-th k-pair ({len(sel)} of {P} pairs), {dt:.1f} s"}
 
 
+def batched_section(name: str, steps: int) -> dict:
+    """Many momentum transfers in one HIP graph (mixed-precision assembly,
+    concurrent branches) against the per-Q sequential FP64 path."""
+    import torch
+    from bse_synth import BATCHES, make_batch_inputs
+    from paper_1904_05575_amd.batch import Batch
+    bw = BATCHES[name]
+    members = make_batch_inputs(bw)
+    B = Batch(members, precision="fp64", nbranch=4)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    seq_ms = timed(B.run_sequential)
+    ref = B.results()
+    graph64_ms = timed(B.run)
+    B.set_precision("bf16x6")
+    graph_mixed_ms = timed(B.run)
+    mixed = B.results()
+    eig = max(float(np.abs(m["E"] - r["E"]).max() / np.abs(r["E"]).min())
+              for m, r in zip(mixed, ref))
+    spec = max(float(np.abs(m["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max())
+               for m, r in zip(mixed, ref))
+    B.close()
+    print(f"[bench] batch {name}: sequential fp64 {seq_ms:.1f} ms, graph fp64 {graph64_ms:.1f} ms, "
+          f"graph bf16x6 {graph_mixed_ms:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": name, "problems": len(members), "sizes": [m["workload"].n for m in members],
+            "sequential_fp64_ms": seq_ms, "graph_fp64_ms": graph64_ms,
+            "graph_bf16x6_ms": graph_mixed_ms, "speedup_vs_sequential_fp64": seq_ms / graph_mixed_ms,
+            "bf16x6_error_vs_fp64": {"eig_rel": eig, "spec_err": spec}, "branches": 4}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +140,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="full_q0_k8_v3c4_g113")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", default="batch16_k6_g89",
+                    help="batched finite-Q workload timed after the main steps ('' to skip)")
     ap.add_argument("--precisions", default="fp32,bf16x6",
                     help="assembly precisions timed after the FP64 steps")
     args = ap.parse_args()
@@ -253,6 +295,8 @@ def main() -> int:
         "roofline": roof,
         "kernels_ms_per_step": kernels_ms,
     }
+    if args.batch:
+        out["batched"] = batched_section(args.batch, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inputs, w)
     print(json.dumps(out), flush=True)

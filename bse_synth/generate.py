@@ -112,7 +112,7 @@ def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
         if w.coupling == "full":
             out["Ncv"] = _complex_rows(w.seed, "Ncv", (P, nc, nv, ng), env)
             out["Nvc"] = _complex_rows(w.seed, "Nvc", (P, nv, nc, ng), env)
-    out["W"] = screened_interaction(w)
+    out["W"] = screened_interaction(w) if want_pairs else None
     qmap, qramap = lattice.q_maps(w.mesh)
     out["qmap"], out["qramap"] = qmap, qramap
     out["gvec"] = lattice.gvectors(ng)
@@ -120,4 +120,25 @@ def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
     out["omega"] = np.linspace(w.wmin, w.wmax, w.nw)
     out["alat"] = lattice.A_LATT
     out["cell_volume"] = lattice.cell_volume()
+    return out
+
+
+def make_batch_inputs(bw) -> list:
+    """Inputs of every member of a BatchWorkload.  W(q), the q-maps and the
+    pair arrays come from the master (widest band window); member m takes the
+    first nv occupied and nc unoccupied bands of them (NumPy views)."""
+    master = make_inputs(bw.master)
+    out = []
+    for w in bw.members:
+        d = make_inputs(w, want_pairs=False)
+        d["W"] = master["W"]
+        d["qmap"], d["qramap"] = master["qmap"], master["qramap"]
+        nv, nc = w.nv, w.nc
+        d["Mvv"] = master["Mvv"][:, :nv, :nv, :]
+        d["Mcc"] = master["Mcc"][:, :nc, :nc, :]
+        if w.coupling == "full":
+            d["Ncv"] = master["Ncv"][:, :nc, :nv, :]
+            d["Nvc"] = master["Nvc"][:, :nv, :nc, :]
+        d["master"] = master
+        out.append(d)
     return out

@@ -92,6 +92,49 @@ TINY = {
 }
 
 
+@dataclass(frozen=True)
+class BatchWorkload:
+    """Many momentum transfers Q solved as one batch: W(q) and the pair
+    elements are shared (drawn once for the widest band window and sliced),
+    energies and M_cv are drawn per Q."""
+    name: str
+    members: tuple            # Workload per Q (own nv, nc, q, seed)
+    master: Workload          # widest band window; seed of the shared arrays
+
+    @property
+    def sizes(self) -> list:
+        return [m.n for m in self.members]
+
+
+def _batch(name, mesh, ng, nq, qmax, nvs, ncs, seed, kernel_scale, nw, wmax, coupling="full"):
+    members = []
+    for i in range(nq):
+        nv, nc = nvs[i % len(nvs)], ncs[i % len(ncs)]
+        q = (qmax * i / (nq - 1), 0.0, 0.0) if nq > 1 else (0.0, 0.0, 0.0)
+        members.append(Workload(name=f"{name}_q{i}", mesh=mesh, nv=nv, nc=nc, ng=ng,
+                                coupling=coupling, nw=nw, wmin=0.0, wmax=wmax, eta=0.05,
+                                seed=seed + 101 + i, kernel_scale=kernel_scale, q=q))
+    master = Workload(name=f"{name}_master", mesh=mesh, nv=max(nvs), nc=max(ncs), ng=ng,
+                      coupling=coupling, nw=nw, wmin=0.0, wmax=wmax, eta=0.05, seed=seed,
+                      kernel_scale=kernel_scale)
+    return BatchWorkload(name=name, members=tuple(members), master=master)
+
+
+BATCHES: dict[str, BatchWorkload] = {}
+# 16 momentum transfers Q = (0.1 i, 0, 0) bohr^-1 along Gamma-X, 6x6x6 mesh,
+# N_v = 2 + (i mod 3), N_c = 3 + (i mod 4): N from 1296 to 5184
+BATCHES["batch16_k6_g89"] = _batch("batch16_k6_g89", mesh=6, ng=89, nq=16, qmax=1.5,
+                                   nvs=(2, 3, 4), ncs=(3, 4, 5, 6), seed=3,
+                                   kernel_scale=0.125, nw=2000, wmax=10.0)
+# small batch for the parity tests (uneven sizes, several tiles, finite Q)
+BATCHES["batch4_k2_g15"] = _batch("batch4_k2_g15", mesh=2, ng=15, nq=4, qmax=1.5,
+                                  nvs=(1, 2, 3), ncs=(2, 3), seed=21, kernel_scale=0.015625,
+                                  nw=300, wmax=10.0)
+BATCHES["batch3_k3_g27"] = _batch("batch3_k3_g27", mesh=3, ng=27, nq=3, qmax=0.9,
+                                  nvs=(2, 3, 2), ncs=(3, 4, 2), seed=22, kernel_scale=0.03125,
+                                  nw=300, wmax=10.0)
+
+
 def get(name: str) -> Workload:
     return WORKLOADS[name]
 

@@ -146,6 +146,32 @@ bse_status bse_oscillator(int64_t n, const void* XpY, int64_t ldx, const void* p
 bse_status bse_spectrum(int64_t n, const double* E, const double* osc, double pref, double eta,
                         int64_t nw, const double* omega, void* eps, hipStream_t stream);
 
+/* ---- Batches of independent problems (one per momentum transfer Q; the BSE
+ * decouples per q, Sec. 2.3 eq. chimatrixq).  The whole pipeline of every
+ * problem (bse_build, the spectrum path of bse_solve, bse_spectrum) is
+ * recorded once into a HIP graph and replayed with one graph launch.
+ * Problems run on `nbranch` concurrent branches (streams the batch creates
+ * at default priority), largest N^3 first, each branch with its own slice of
+ * the workspace.  All pointers given to bse_batch_capture stay baked into the
+ * graph: they must stay valid until bse_batch_destroy.  `info` holds one
+ * int32 per problem and is cleared at the start of every replay.  Capture
+ * needs a created stream (not the NULL stream). */
+typedef struct bse_batch* bse_batch_t;
+
+size_t bse_batch_workspace_size(int32_t nprob, const bse_desc* descs, int32_t nbranch);
+bse_status bse_batch_create(int32_t nprob, const bse_desc* descs, int32_t nbranch,
+                            bse_batch_t* out);
+/* Per-problem arrays of length nprob: inputs, H0, H1 (full only), E, probe,
+ * osc, pref, eta, nw, omega, eps -- the arguments of bse_build / bse_solve /
+ * bse_spectrum for that problem (device pointers; pref/eta/nw host values). */
+bse_status bse_batch_capture(bse_batch_t batch, const bse_inputs* inputs, void* const* H0,
+                             void* const* H1, double* const* E, const void* const* probe,
+                             double* const* osc, const double* pref, const double* eta,
+                             const int64_t* nw, const double* const* omega, void* const* eps,
+                             void* ws, size_t ws_bytes, int32_t* info, hipStream_t stream);
+bse_status bse_batch_run(bse_batch_t batch, hipStream_t stream);
+void bse_batch_destroy(bse_batch_t batch);
+
 /* Measurement hook: while enabled (on != 0), every kernel launch of the
  * library (or, when `name` is not NULL, every launch of the kernel with that
  * name) is bracketed by two HIP events recorded on the launch stream.

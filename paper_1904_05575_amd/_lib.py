@@ -18,7 +18,9 @@ BSE_PREC_FP64, BSE_PREC_FP32, BSE_PREC_BF16X3 = 0, 1, 2
 BSE_STAGE_BUILD, BSE_STAGE_SOLVE = 0, 1
 STATUS = {0: "BSE_OK", 1: "BSE_ERR_ARG", 2: "BSE_ERR_WORKSPACE", 3: "BSE_ERR_HIP"}
 EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bse_spectrum",
-           "bse_status_string", "bse_timing_enable", "bse_timing_report")
+           "bse_status_string", "bse_timing_enable", "bse_timing_report",
+           "bse_batch_workspace_size", "bse_batch_create", "bse_batch_capture", "bse_batch_run",
+           "bse_batch_destroy")
 
 
 class BseDesc(ctypes.Structure):
@@ -69,6 +71,19 @@ def lib() -> ctypes.CDLL:
         L.bse_timing_enable.restype = None
         L.bse_timing_report.argtypes = [ctypes.c_char_p, i64]
         L.bse_timing_report.restype = i64
+        L.bse_batch_workspace_size.argtypes = [i32, ctypes.POINTER(BseDesc), i32]
+        L.bse_batch_workspace_size.restype = sz
+        L.bse_batch_create.argtypes = [i32, ctypes.POINTER(BseDesc), i32, ctypes.POINTER(vp)]
+        L.bse_batch_create.restype = ctypes.c_int
+        P = ctypes.POINTER(vp)
+        L.bse_batch_capture.argtypes = [vp, ctypes.POINTER(BseInputs), P, P, P, P, P,
+                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                        ctypes.POINTER(i64), P, P, vp, sz, vp, vp]
+        L.bse_batch_capture.restype = ctypes.c_int
+        L.bse_batch_run.argtypes = [vp, vp]
+        L.bse_batch_run.restype = ctypes.c_int
+        L.bse_batch_destroy.argtypes = [vp]
+        L.bse_batch_destroy.restype = None
         L.bse_status_string.argtypes = [ctypes.c_int]
         L.bse_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -121,3 +136,40 @@ def bse_timing_report() -> dict:
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+def _ptrs(vals):
+    arr = (ctypes.c_void_p * len(vals))(*[v or None for v in vals])
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), arr
+
+
+def bse_batch_workspace_size(descs, nbranch: int) -> int:
+    arr = (BseDesc * len(descs))(*descs)
+    return int(lib().bse_batch_workspace_size(len(descs), arr, nbranch))
+
+
+def bse_batch_create(descs, nbranch: int) -> int:
+    arr = (BseDesc * len(descs))(*descs)
+    h = ctypes.c_void_p()
+    _check(lib().bse_batch_create(len(descs), arr, nbranch, ctypes.byref(h)), "bse_batch_create")
+    return h.value
+
+
+def bse_batch_capture(batch: int, inputs, H0, H1, E, probe, osc, pref, eta, nw, omega, eps,
+                      ws: int, ws_bytes: int, info: int, stream: int) -> None:
+    n = len(inputs)
+    inarr = (BseInputs * n)(*inputs)
+    keep = [_ptrs(v) for v in (H0, H1, E, probe, osc, omega, eps)]
+    dbl = ctypes.c_double * n
+    _check(lib().bse_batch_capture(batch, inarr, keep[0][0], keep[1][0], keep[2][0], keep[3][0],
+                                   keep[4][0], dbl(*pref), dbl(*eta), (ctypes.c_int64 * n)(*nw),
+                                   keep[5][0], keep[6][0], ws, ws_bytes, info, stream or None),
+           "bse_batch_capture")
+
+
+def bse_batch_run(batch: int, stream: int) -> None:
+    _check(lib().bse_batch_run(batch, stream or None), "bse_batch_run")
+
+
+def bse_batch_destroy(batch: int) -> None:
+    lib().bse_batch_destroy(batch)

@@ -1,0 +1,174 @@
+// Batches of independent BSE problems (one per momentum transfer Q: the BSE
+// decouples per q, paper Sec. 2.3 eq. chimatrixq) recorded once into a HIP
+// graph and replayed with one launch.  Problems are spread over `nbranch`
+// concurrent branches (longest first, by N^3), each with its own slice of the
+// caller's workspace.
+#include <algorithm>
+#include <vector>
+
+#include "bse_internal.h"
+#include "timing.h"
+
+struct bse_batch {
+  int nprob = 0, nbranch = 0;
+  std::vector<bse_desc> descs;
+  std::vector<int> branch_of;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;  // [0] fork, [1 + b] join of branch b
+  size_t slice = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+bool batch_desc_ok(const bse_desc* d) { return bse_workspace_size(d, BSE_STAGE_BUILD) > 0; }
+
+size_t slice_bytes(int nprob, const bse_desc* descs) {
+  size_t s = 0;
+  for (int i = 0; i < nprob; ++i) {
+    s = std::max(s, bse_workspace_size(&descs[i], BSE_STAGE_BUILD));
+    s = std::max(s, bse_workspace_size(&descs[i], BSE_STAGE_SOLVE));
+  }
+  return (s + 255) & ~(size_t)255;
+}
+
+void release(bse_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bse_batch_workspace_size(int32_t nprob, const bse_desc* descs, int32_t nbranch) {
+  if (nprob <= 0 || !descs || nbranch <= 0) return 0;
+  for (int i = 0; i < nprob; ++i)
+    if (!batch_desc_ok(&descs[i])) return 0;
+  return slice_bytes(nprob, descs) * (size_t)std::min(nbranch, nprob);
+}
+
+bse_status bse_batch_create(int32_t nprob, const bse_desc* descs, int32_t nbranch,
+                            bse_batch_t* out) {
+  if (!out || nprob <= 0 || !descs || nbranch <= 0) return BSE_ERR_ARG;
+  for (int i = 0; i < nprob; ++i)
+    if (!batch_desc_ok(&descs[i])) return BSE_ERR_ARG;
+  bse_batch* b = new bse_batch;
+  b->nprob = nprob;
+  b->nbranch = std::min(nbranch, nprob);
+  b->descs.assign(descs, descs + nprob);
+  b->slice = slice_bytes(nprob, descs);
+  // longest processing time first: largest N^3 to the least loaded branch
+  std::vector<int> order(nprob);
+  for (int i = 0; i < nprob; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    const double n = (double)descs[i].nk * descs[i].nv * descs[i].nc;
+    return n * n * n;
+  };
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  std::vector<double> load(b->nbranch, 0.0);
+  b->branch_of.assign(nprob, 0);
+  for (int i : order) {
+    const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->branch_of[i] = br;
+    load[br] += cost(i);
+  }
+  b->streams.assign(b->nbranch, nullptr);
+  for (auto& s : b->streams)
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      bse_batch_destroy(b);
+      return BSE_ERR_HIP;
+    }
+  b->events.assign(1 + b->nbranch, nullptr);
+  for (auto& e : b->events)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      bse_batch_destroy(b);
+      return BSE_ERR_HIP;
+    }
+  *out = b;
+  return BSE_OK;
+}
+
+bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* const* H0,
+                             void* const* H1, double* const* E, const void* const* probe,
+                             double* const* osc, const double* pref, const double* eta,
+                             const int64_t* nw, const double* const* omega, void* const* eps,
+                             void* ws, size_t ws_bytes, int32_t* info, hipStream_t stream) {
+  if (!b || !inputs || !H0 || !E || !probe || !osc || !pref || !eta || !nw || !omega || !eps ||
+      !ws || !info)
+    return BSE_ERR_ARG;
+  if (stream == nullptr) return BSE_ERR_ARG;  // the legacy NULL stream cannot be captured
+  if (ws_bytes < b->slice * (size_t)b->nbranch) return BSE_ERR_WORKSPACE;
+  for (int i = 0; i < b->nprob; ++i) {
+    const bse_desc* d = &b->descs[i];
+    const bse_inputs* in = &inputs[i];
+    if (!H0[i] || !E[i] || !probe[i] || !osc[i] || !omega[i] || !eps[i] || nw[i] <= 0) return BSE_ERR_ARG;
+    if (d->coupling == BSE_FULL && (!H1 || !H1[i] || !in->Ncv || !in->Nvc || !in->qramap))
+      return BSE_ERR_ARG;
+    if (!in->eps_v || !in->eps_c || !in->Mcv || !in->Mvv || !in->Mcc || !in->W || !in->vbar ||
+        !in->qmap || in->nq <= 0 || in->nq > kMaxQ)
+      return BSE_ERR_ARG;
+    if (!(eta[i] > 0.0)) return BSE_ERR_ARG;
+  }
+  release(b);
+  const bool was_timing = timing_on();
+  if (was_timing) bse_timing_enable(0, nullptr);
+  bse_status st = BSE_OK;
+  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return BSE_ERR_HIP;
+  launch_zero_ints(info, b->nprob, stream);
+  hipEventRecord(b->events[0], stream);
+  for (int br = 0; br < b->nbranch; ++br) hipStreamWaitEvent(b->streams[br], b->events[0], 0);
+  for (int i = 0; i < b->nprob && st == BSE_OK; ++i) {
+    const bse_desc* d = &b->descs[i];
+    const int br = b->branch_of[i];
+    hipStream_t s = b->streams[br];
+    void* wsb = (char*)ws + b->slice * (size_t)br;
+    void* h1 = (d->coupling == BSE_FULL) ? H1[i] : nullptr;
+    const int64_t n = (int64_t)d->nk * d->nv * d->nc;
+    st = build_fp64(d, &inputs[i], H0[i], h1, wsb, info + i, s);
+    if (st == BSE_OK)
+      st = solve_run(d, H0[i], h1, E[i], nullptr, n, probe[i], osc[i], wsb, info + i, s);
+    if (st == BSE_OK &&
+        launch_spectrum(n, E[i], osc[i], pref[i], eta[i], nw[i], omega[i], (double2*)eps[i], s) !=
+            hipSuccess)
+      st = BSE_ERR_HIP;
+  }
+  for (int br = 0; br < b->nbranch; ++br) {
+    hipEventRecord(b->events[1 + br], b->streams[br]);
+    hipStreamWaitEvent(stream, b->events[1 + br], 0);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(stream, &g);
+  if (was_timing) bse_timing_enable(1, nullptr);
+  if (st != BSE_OK || ec != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    return st != BSE_OK ? st : BSE_ERR_HIP;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    release(b);
+    return BSE_ERR_HIP;
+  }
+  return BSE_OK;
+}
+
+bse_status bse_batch_run(bse_batch_t b, hipStream_t stream) {
+  if (!b || !b->exec) return BSE_ERR_ARG;
+  return hipGraphLaunch(b->exec, stream) == hipSuccess ? BSE_OK : BSE_ERR_HIP;
+}
+
+void bse_batch_destroy(bse_batch_t b) {
+  if (!b) return;
+  release(b);
+  for (auto s : b->streams)
+    if (s) hipStreamDestroy(s);
+  for (auto e : b->events)
+    if (e) hipEventDestroy(e);
+  delete b;
+}
+
+}  // extern "C"

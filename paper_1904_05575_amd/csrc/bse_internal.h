@@ -62,6 +62,7 @@ bool launch_exchange_lp(int prec, int nterms, const double2* Mcv, int n, int ng,
                         const int32_t* info, hipStream_t s);
 
 // solve.hip
+void launch_zero_ints(int32_t* p, int n, hipStream_t s);
 size_t solve_workspace(const bse_desc* d);
 bse_status solve_run(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, int64_t ldx,
                      const void* probe, double* osc, void* ws, int32_t* info, hipStream_t s);

@@ -37,6 +37,8 @@ __global__ void k_copy_c(const double2* __restrict__ src, double2* __restrict__ 
 __global__ void k_zero_ints(int32_t* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
+}  // namespace
+namespace {
 
 // ------------------------------------------------------------------ Cholesky
 // Factor the jb x jb diagonal block (upper, A = U^H U) in LDS and form U^-1.
@@ -734,6 +736,10 @@ bool apply_q(const double2* M, int64_t n, int64_t ld, double2* Z, int64_t ldz, i
 }  // namespace
 
 size_t solve_workspace(const bse_desc* d) { return carve(d, nullptr).total; }
+
+void launch_zero_ints(int32_t* p, int n, hipStream_t s) {
+  BSE_LAUNCH(k_zero_ints, dim3(1), dim3(64), 0, s, p, n);
+}
 
 bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* XpYv, int64_t ldx,
                      const void* probev, double* osc, void* ws, int32_t* info, hipStream_t s) {

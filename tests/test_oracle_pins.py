@@ -370,3 +370,54 @@ def test_sampled_blocks_match_full_assembly():
             iu = np.triu_indices(nvnc, 1)
             assert np.abs(ApB[p][iu] - FA[i, :, j, :][iu]).max() < 1e-12
             assert np.abs(ApB[p].diagonal().real - FA[i, :, j, :].diagonal().real).max() < 1e-12
+
+
+# ----------------------------------------------------------------- finite momentum transfer
+def _batch_members(name):
+    from bse_synth import BATCHES, make_batch_inputs
+    return make_batch_inputs(BATCHES[name])
+
+
+def test_finite_q_vbar_drops_g_of_q():
+    """At Q != 0, vbar removes exactly the G nearest to Q and is 4 pi/|G+q|^2
+    with q = Q - G_Q elsewhere (eq. vbar_def)."""
+    d = _batch_members("batch4_k2_g15")[-1]  # Q = (1.5, 0, 0)
+    Q = np.asarray(d["workload"].q)
+    G = lattice.gcart(15)
+    gq = O.g_of_q(d)
+    assert np.argmin(np.sum((G - Q) ** 2, axis=1)) == gq and gq != 0
+    v = O.coulomb_vbar(d)
+    q = Q - G[gq]
+    keep = np.arange(15) != gq
+    assert v[gq] == 0.0
+    assert np.allclose(v[keep], 4 * np.pi / np.sum((G[keep] + q) ** 2, axis=1))
+    assert np.isclose(O.coulomb_v0(d), 4 * np.pi / (Q @ Q))
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3])
+def test_finite_q_members_resolvent_and_2n(idx):
+    """Every member of a finite-Q batch: eigen-sum = resolvent, +-E pairs of
+    the 2N problem, f-sum rule."""
+    d = _batch_members("batch4_k2_g15")[idx]
+    r = O.run(d)
+    om = np.array([0.7, 2.1, 4.4, 8.0])
+    eta = d["workload"].eta
+    e1 = O.spectrum(r["E"], r["t2"], om, eta, r["pref"])
+    e2 = O.resolvent_spectrum(r["A"], r["B"], r["p"], om, eta, r["pref"])
+    assert _rel(e1, e2) < 1e-10
+    ev, _ = O.brute_force_2n(r["A"], r["B"])
+    n = len(r["E"])
+    assert _rel(ev[n:], r["E"]) < 1e-12
+    fs = np.vdot(r["p"], (r["A"] - r["B"]) @ r["p"]).real
+    assert abs(np.sum(r["E"] * r["t2"]) - fs) < 1e-11 * fs
+
+
+def test_batch_members_share_w_and_slice_pairs():
+    ms = _batch_members("batch4_k2_g15")
+    master = ms[0]["master"]
+    for d in ms:
+        w = d["workload"]
+        assert d["W"] is master["W"]
+        assert np.array_equal(d["Mvv"], master["Mvv"][:, :w.nv, :w.nv])
+        assert np.array_equal(d["Nvc"], master["Nvc"][:, :w.nv, :w.nc])
+    assert len({d["workload"].n for d in ms}) > 1  # uneven sizes
