@@ -55,4 +55,4 @@ BSE_DEV void set_info(int32_t* info, int32_t code) {
   if (info) atomicCAS(info, 0, code);
 }
 
-static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+__host__ __device__ static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

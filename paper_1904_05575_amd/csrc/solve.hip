@@ -370,7 +370,7 @@ BSE_DEV SolveStats inv_solve(const double* __restrict__ d, const double* __restr
 }
 
 // Inverse iteration for every eigenvalue: one thread per cluster of close
-// eigenvalues (gap <= ortol_rel * |T|); cluster members are orthogonalised
+// eigenvalues (gap <= ortol_rel * |lambda|); cluster members are orthogonalised
 // against the earlier ones.  Two solves per eigenvalue from a pseudo-random
 // start, then normalisation with the largest component made positive.
 __global__ __launch_bounds__(256) void k_inviter(const double* __restrict__ d,
@@ -384,10 +384,14 @@ __global__ __launch_bounds__(256) void k_inviter(const double* __restrict__ d,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const double tnorm = stat[3];
-  const double ortol = ortol_rel * tnorm;
-  if (k > 0 && w[k] - w[k - 1] <= ortol) return;  // not the first member of its cluster
+  // close eigenvalues: gap below ortol_rel times the local magnitude (a few
+  // outlying eigenvalues must not merge the rest of the spectrum into one cluster)
+  auto close = [&](int a) {  // eigenvalues a and a+1
+    return w[a + 1] - w[a] <= ortol_rel * fmax(fabs(w[a]), fabs(w[a + 1]));
+  };
+  if (k > 0 && close(k - 1)) return;  // not the first member of its cluster
   int kend = k;
-  while (kend + 1 < n && w[kend + 1] - w[kend] <= ortol) ++kend;
+  while (kend + 1 < n && close(kend)) ++kend;
   const double eps = 2.220446049250313e-16;
   const double tiny = eps * fmax(tnorm, 1e-300);
   const int64_t N = n;
@@ -820,8 +824,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
       BSE_LAUNCH(k_copy_c, dim3(cdiv(n, 256)), dim3(256), 0, s, probe, w.yvec, n);
     }
   }
-  TrdBufs tb{w.VW, w.WV, w.ybuf, w.hs, w.part, w.counters, w.dd, w.ee, w.tau,
-             project ? w.yvec : nullptr};
+  TrdBufs tb{w.VW, w.WV, w.ybuf, w.hs, w.part, w.dd, w.ee, w.tau, project ? w.yvec : nullptr};
   if (!tridiagonalise(Hm, n, ld, tb, info, s)) return BSE_ERR_HIP;
   BSE_LAUNCH(k_tri_prep, dim3(1), dim3(1024), 0, s, w.dd, w.ee, (int)n, w.e2, w.stat, info);
   BSE_LAUNCH(k_bisect, dim3(cdiv(n, 4)), dim3(256), 0, s, w.dd, w.e2, (int)n, w.stat, w.mu,

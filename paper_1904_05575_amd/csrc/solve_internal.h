@@ -7,11 +7,8 @@ constexpr int TRD_NB = 32;  // Householder panel width
 
 // Small shared state of the tridiagonalisation kernels (complex slots):
 //   [0] scal = 1/(alpha_x - beta) of the current reflector, [1] tau,
-//   [2] alpha = -|tau|^2 (y^H v) / 2 of the current column's hemv,
-//   [3] v^H y_probe of the current reflector,
-//   [4 .. 4+NB) V^H v,  [4+NB .. 4+2NB) W^H v  (hemv corrections)
-constexpr int HS_SCAL = 0, HS_TAU = 1, HS_ALPHA = 2, HS_PDOT = 3, HS_VV = 4,
-              HS_WV = 4 + TRD_NB, HS_SIZE = 4 + 2 * TRD_NB;
+//   [3] v^H y_probe of the current reflector
+constexpr int HS_SCAL = 0, HS_TAU = 1, HS_PDOT = 3, HS_SIZE = 4;
 
 struct TrdBufs {
   double2* VW;      // n x 2*TRD_NB, [V | W] of the current panel (column-major, ld n)
@@ -19,7 +16,6 @@ struct TrdBufs {
   double2* ybuf;    // n
   double2* hs;      // HS_SIZE
   double2* part;    // trd_part_elems(n)
-  int32_t* counters;
   double* dd;       // n   diagonal of T
   double* ee;       // n-1 off-diagonal of T
   double2* tau;     // n-1 reflector scalars
