@@ -51,16 +51,16 @@ def kernel_roofline_table(w) -> dict:
     f = build_flops(w)
     m = np.arange(1, n, dtype=np.float64)
     return {
-        # column-r reads of the trailing Hermitian matrix, one launch per reflector
-        "k_trd_hemv": ("hbm", float(np.sum(m * m) * 16.0), "B"),
-        "k_stage1": ("mfma", float(f["stage1"]), "flop"),
+        # lower triangle of the trailing Hermitian matrix (order m), one launch per reflector
+        "k_trd_hemv": ("hbm", float(np.sum(m * (m + 1) / 2) * 16.0), "B"),
+        "k_stage1_real": ("mfma", float(f["stage1"]), "flop"),
         "zgemm_direct_stage2": ("mfma", float(f["stage2"]), "flop"),
         "zgemm_exchange": ("mfma", float(f["exchange"]), "flop"),
         # triangular products of the squared form: n^3 / 2 complex MACs each
         "zgemm_sq_t1": ("mfma", n ** 3 / 2 * 8.0, "flop"),
         "zgemm_sq_s": ("mfma", n ** 3 / 4 * 8.0, "flop"),
-        # trailing updates of the tridiagonalisation: 2 x sum over panels of m^2 x 32
-        "zgemm_her2k": ("mfma", 2.0 * float(np.sum(m[::32] ** 2)) * 32 * 8.0, "flop"),
+        # trailing updates of the tridiagonalisation (lower triangle): m(m+1)/2 x 64 per panel
+        "zgemm_her2k": ("mfma", float(np.sum(m[::32] * (m[::32] + 1) / 2)) * 64 * 8.0, "flop"),
     }
 
 

@@ -32,8 +32,9 @@
  *      -2   a non-finite value on the diagonal of an assembled matrix
  *      -3   a squared-form eigenvalue E^2 <= 0: A+B is not positive definite
  *      -4   the tridiagonal eigensolver did not converge
- *    Once `info` is non-zero, later kernels of the same calls return at
- *    entry; outputs are then undefined.
+ *    Once `info` is non-zero, the later kernels of the same calls return at
+ *    entry, except the per-column kernels of the Householder sweep, which
+ *    index no memory by data and run on; outputs are then undefined.
  */
 #ifndef BSE_H
 #define BSE_H
@@ -174,7 +175,9 @@ void bse_batch_destroy(bse_batch_t batch);
 
 /* Measurement hook: while enabled (on != 0), every kernel launch of the
  * library (or, when `name` is not NULL, every launch of the kernel with that
- * name) is bracketed by two HIP events recorded on the launch stream.
+ * name) is bracketed by two HIP events recorded on the launch stream.  Kernel
+ * names carry no template arguments: the instances of one kernel template are
+ * timed and reported together.
  * bse_timing_report synchronises on those events, writes one line per kernel
  * name "<name> <launches> <total milliseconds>" into the HOST buffer `buf`
  * (truncated to len-1 bytes, NUL-terminated), clears the records and returns

@@ -7,13 +7,15 @@ constexpr int TRD_NB = 32;  // Householder panel width
 
 // Small shared state of the tridiagonalisation kernels (complex slots):
 //   [0] scal = 1/(alpha_x - beta) of the current reflector, [1] tau,
-//   [3] v^H y_probe of the current reflector
-constexpr int HS_SCAL = 0, HS_TAU = 1, HS_PDOT = 3, HS_SIZE = 4;
+//   [3] v^H y_probe of the current reflector,
+//   [4, 4 + TRD_NB) V^H v and [4 + TRD_NB, 4 + 2 TRD_NB) W^H v over the panel
+constexpr int HS_SCAL = 0, HS_TAU = 1, HS_PDOT = 3, HS_SVV = 4, HS_SWV = 4 + TRD_NB,
+              HS_SIZE = 4 + 2 * TRD_NB;
 
 struct TrdBufs {
   double2* VW;      // n x 2*TRD_NB, [V | W] of the current panel (column-major, ld n)
   double2* WV;      // n x 2*TRD_NB, [W | V]
-  double2* ybuf;    // n
+  double2* ybuf;    // n (unused by the lower-triangle sweep)
   double2* hs;      // HS_SIZE
   double2* part;    // trd_part_elems(n)
   double* dd;       // n   diagonal of T

@@ -13,7 +13,7 @@
 
 namespace {
 struct Rec {
-  const char* name;
+  std::string name;  // kernel name without template arguments
   hipEvent_t a, b;
 };
 std::mutex mu;
@@ -38,11 +38,12 @@ bool timing_on() { return enabled; }
 
 void timing_begin(const char* name, hipStream_t s) {
   std::lock_guard<std::mutex> g(mu);
-  if (!only.empty() && only != name) {
-    recs.push_back(Rec{name, nullptr, nullptr});
+  std::string base(name, strcspn(name, "<"));
+  if (!only.empty() && only != base) {
+    recs.push_back(Rec{std::move(base), nullptr, nullptr});
     return;
   }
-  Rec r{name, get_event(), get_event()};
+  Rec r{std::move(base), get_event(), get_event()};
   if (r.a) hipEventRecord(r.a, s);
   recs.push_back(r);
 }
