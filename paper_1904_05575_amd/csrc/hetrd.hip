@@ -57,18 +57,30 @@ BSE_DEV double2 block_sum2(double2 v, double2* sh) {
   return s;
 }
 
-// alpha of reflector c-1: -|tau|^2 / 2 times sum of the nb hemv partials of y^H v
-BSE_DEV double2 reduce_alpha(const double2* __restrict__ partB, int nb, double2 tc, double2* sh) {
-  double2 acc = make_double2(0.0, 0.0);
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc = cadd(acc, partB[b]);
-  const double2 s = block_sum2(acc, sh);
-  const double t2 = cabs2(tc);
-  return make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
-}
-
 // x -= a conj(b)
 BSE_DEV double2 sub_mulc(double2 x, double2 a, double2 b) {
   return make_double2(x.x - (a.x * b.x + a.y * b.y), x.y - (a.y * b.x - a.x * b.y));
+}
+
+// Full wavefront sum with DPP lane moves on the vector ALU (no LDS traffic);
+// the total lands in lane 63.  Steps: quad swaps, half-row and row mirrors,
+// then row 0 + 1 and row 2 + 3 through row_bcast:15, all four through
+// row_bcast:31.  Lanes outside a step's row mask add zero.
+template <int CTRL, int ROWS = 0xf>
+BSE_DEV double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+BSE_DEV double wave_total63(double v) {
+  v += dpp_d<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);       // row_half_mirror
+  v += dpp_d<0x140>(v);       // row_mirror
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
 }
 
 __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
@@ -77,15 +89,14 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     int ycs, int tprev, double2* __restrict__ partA, const double2* __restrict__ partB,
     double2* __restrict__ yp) {
   constexpr int QP = COL_THREADS / ROWS_A;        // threads sharing one row
-  constexpr int RG = COL_THREADS / 64;            // row groups of step 2
-  constexpr int RPG = ROWS_A / RG;                // rows per group
   constexpr int PER = TRD_NB / QP;                // panel columns per thread
   constexpr int YCH = 8;                          // y slots loaded per round
-  __shared__ double2 xs[ROWS_A], vps[ROWS_A], wps[ROWS_A], x0s[ROWS_A];
+  constexpr int HW = ROWS_A / 64;                 // wavefronts per thread group qq
+  __shared__ double2 vps[ROWS_A], wps[ROWS_A], x0s[ROWS_A], xs[ROWS_A];
   __shared__ double2 xpart[QP][ROWS_A];
   __shared__ double2 vcs[TRD_NB], wcs[TRD_NB];
-  __shared__ double2 red[RG][2 * TRD_NB];
-  __shared__ double2 red0[ROWS_A / 64][2];
+  __shared__ double2 red[QP][HW][2 * PER];
+  __shared__ double2 red0[HW][2];
   __shared__ double2 shb[COL_THREADS / 64];
   __shared__ double2 yc_s;
   __shared__ double2 svw[2 * TRD_NB];  // V^H v | W^H v of reflector c-1
@@ -93,18 +104,18 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   const int64_t N = n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int rbase = c + blockIdx.x * ROWS_A;
-  const int rr = tid % ROWS_A, qq = tid / ROWS_A;
+  const int rr = tid % ROWS_A, qq = tid / ROWS_A;  // qq is uniform in a wavefront
   const int r = rbase + rr;
   const bool act = r < n;
 
-  // ---- 0. issue every load of the first phase
+  // ---- 0. issue every global load of the kernel
   double2 x0 = make_double2(0.0, 0.0), xv = x0, ypr = x0;
   if (qq == 0 && act) {
     if (has_new) x0 = M[r + (int64_t)c * ld];
     if (yp) ypr = yp[r];
     if (i > 0) xv = M[r + (int64_t)(c - 1) * ld];
   }
-  // panel reflectors 0..i-2 on this row: the correction of y_{c-1} and step 1
+  // panel reflectors 0..i-2 on this row: the correction of y_{c-1}, step 2, step 3
   double2 vr[PER], wr[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -130,7 +141,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
         if (k0 + u * QP <= nIp) yq = cadd(yq, t[u]);
     }
   }
-  // row c of the panel's earlier reflectors, and y_{c-1}[c] (wave 2)
+  // row c of the panel's earlier reflectors, and the slots of y_{c-1}[c] (wave 2)
   double2 vcl = make_double2(0.0, 0.0), wcl = vcl;
   if (qq == 1 && rr < i - 1) {
     vcl = VW[c + (int64_t)rr * N];
@@ -139,9 +150,21 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   double2 ycq = make_double2(0.0, 0.0);
   if (wid == 2 && i > 0)
     for (int k = lane; k <= nIp; k += 64) ycq = cadd(ycq, Y[yslot(k, 0, ycs, N, c)]);
-  __syncthreads();  // svw staged
+  // the hemv blocks' partials of y^H v
+  double2 pa = make_double2(0.0, 0.0);
+  if (i > 0)
+    for (int b = tid; b < nIp * (nIp + 1) / 2; b += COL_THREADS) pa = cadd(pa, partB[b]);
+  double2 tc = make_double2(0.0, 0.0), scal_p = tc, pdot = tc;
   if (i > 0) {
-    // y = S v - V (W^H v) - W (V^H v): this thread's panel columns
+    tc = hs[HS_TAU];
+    scal_p = hs[HS_SCAL];
+    pdot = hs[HS_PDOT];
+  }
+  __syncthreads();  // svw staged
+
+  // ---- 1. y_{c-1} = S v - V (W^H v) - W (V^H v) and alpha
+  double2 al = make_double2(0.0, 0.0);
+  if (i > 0) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int ip = qq + u * QP;
@@ -154,17 +177,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
       ycq = wave_sum2(ycq);
       if (lane == 0) yc_s = ycq;
     }
-  }
-  xpart[qq][rr] = yq;
-  double2 tc = make_double2(0.0, 0.0), al = tc, scal_p = tc, pdot = tc;
-  if (i > 0) {
-    tc = hs[HS_TAU];
-    scal_p = hs[HS_SCAL];
-    pdot = hs[HS_PDOT];
-    al = reduce_alpha(partB, nIp * (nIp + 1) / 2, tc, shb);  // synchronises the block
+    xpart[qq][rr] = yq;
+    const double2 s = block_sum2(pa, shb);  // y^H v; synchronises the block
+    const double t2 = cabs2(tc);
+    al = make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
   }
 
-  // ---- 1. finish reflector c-1 (row threads) and stage row c of the panel
+  // ---- finish reflector c-1 (row threads) and stage row c of the panel
   if (qq == 0) {
     double2 vprev_r = make_double2(0.0, 0.0), wprev_r = make_double2(0.0, 0.0);
     if (i > 0 && act) {
@@ -236,28 +255,30 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   }
   __syncthreads();
 
-  // ---- 3. V^H x and W^H x over this block's rows: thread = (panel column, row group)
+  // ---- 3. V^H x and W^H x over this block's rows from the panel values each
+  // thread holds (column ip = qq + u QP; column i-1 from LDS), wavefront sums
   {
-    const int col = tid & 63;  // 0..31 -> V column, 32..63 -> W column
-    const int ip = col & (TRD_NB - 1);
-    const int g = tid >> 6;
-    double2 acc = make_double2(0.0, 0.0);
-    if (ip < i) {
-      const int lo = g * RPG, hi = lo + RPG;
-      if (ip < i - 1) {
-        const double2* src = VW + (int64_t)col * N + rbase;
-        double2 sv2[RPG];
+    const double2 x = xs[rr];
 #pragma unroll
-        for (int u = 0; u < RPG; ++u)
-          sv2[u] = (rbase + lo + u < n) ? src[lo + u] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int u = 0; u < RPG; ++u) acc = cadd(acc, cmulc(sv2[u], xs[lo + u]));
-      } else {
-        const double2* src = (col < TRD_NB) ? vps : wps;
-        for (int u = lo; u < hi; ++u) acc = cadd(acc, cmulc(src[u], xs[u]));
+    for (int u = 0; u < PER; ++u) {
+      const int ip = qq + u * QP;
+      if (ip < i) {  // uniform in the wavefront
+        double2 v = vr[u], w = wr[u];
+        if (ip == i - 1) {
+          v = vps[rr];
+          w = wps[rr];
+        }
+        double2 pv = cmulc(v, x), pw = cmulc(w, x);
+        pv.x = wave_total63(pv.x);
+        pv.y = wave_total63(pv.y);
+        pw.x = wave_total63(pw.x);
+        pw.y = wave_total63(pw.y);
+        if (lane == 63) {
+          red[qq][wid % HW][2 * u] = pv;
+          red[qq][wid % HW][2 * u + 1] = pw;
+        }
       }
     }
-    red[g][col] = acc;
   }
   __syncthreads();
   // block partials, compact layout [|x|^2, conj(x) y, V^H x (i), W^H x (i)]
@@ -266,34 +287,14 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     const int t = tid;
     double2 sb = make_double2(0.0, 0.0);
     if (t < 2) {
-      for (int w = 0; w < ROWS_A / 64; ++w) sb = cadd(sb, red0[w][t]);
+      for (int w = 0; w < HW; ++w) sb = cadd(sb, red0[w][t]);
     } else {
-      const int src = (t < 2 + i) ? (t - 2) : (TRD_NB + t - 2 - i);
-      for (int g = 0; g < RG; ++g) sb = cadd(sb, red[g][src]);
+      const bool isw = t >= 2 + i;
+      const int ip = isw ? t - 2 - i : t - 2;
+      for (int h = 0; h < HW; ++h) sb = cadd(sb, red[ip % QP][h][2 * (ip / QP) + (isw ? 1 : 0)]);
     }
     partA[(int64_t)blockIdx.x * NVAL + t] = sb;
   }
-}
-
-// Full wavefront sum with DPP lane moves on the vector ALU (no LDS traffic);
-// the total lands in lane 63.  Steps: quad swaps, half-row and row mirrors,
-// then row 0 + 1 and row 2 + 3 through row_bcast:15, all four through
-// row_bcast:31.  Lanes outside a step's row mask add zero.
-template <int CTRL, int ROWS = 0xf>
-BSE_DEV double dpp_d(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-BSE_DEV double wave_total63(double v) {
-  v += dpp_d<0xB1>(v);        // quad_perm [1,0,3,2]
-  v += dpp_d<0x4E>(v);        // quad_perm [2,3,0,1]
-  v += dpp_d<0x141>(v);       // row_half_mirror
-  v += dpp_d<0x140>(v);       // row_mirror
-  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
 }
 
 // Reflector c from the column kernel's partials, then the Hermitian product

@@ -28,7 +28,7 @@ struct S1Smem {
 };
 
 template <int BN2>
-__global__ __launch_bounds__(NTHR) void k_stage1_real(const double2* __restrict__ Left, int R,
+__global__ __launch_bounds__(NTHR, (BN2 == 240 || BN2 == 192) ? 4 : 2) void k_stage1_real(const double2* __restrict__ Left, int R,
                                                       int ng, const double2* __restrict__ W,
                                                       const int32_t* __restrict__ perm,
                                                       const int32_t* __restrict__ cls,
