@@ -27,21 +27,28 @@
 
 namespace {
 
-constexpr int ROWS_A = 128;     // rows per block of the column kernel
+constexpr int ROWS_A = 64;      // rows per block of the column kernel
 constexpr int COL_THREADS = 1024;
-constexpr int HEMV_THREADS = 256;
+constexpr int HT = 64;          // square tile of the hemv kernel
+constexpr int HV_THREADS = 1024; // hemv block: 16 wavefronts, 4 tile columns each
 constexpr int NVAL = 2 + 2 * TRD_NB;  // |x|^2, conj(x) y_probe, V^H x (i), W^H x (i)
 
-// Square tile of the hemv kernel for a trailing matrix of order m.
-__host__ __device__ inline int hemv_tile(int64_t m) { return m < 4096 ? 64 : (m < 12288 ? 128 : 256); }
-
 // Partial sums of y = S v for a trailing matrix of order m starting at row b0,
-// cut into nI x nI tiles of size t (lower triangle, tile-row I >= tile-column J):
-// row r (tile index Ir) collects nI + 1 slots,
-//   slot k <= Ir : Y[k][r]          = (S_{Ir,k} v_k)[r]
-//   slot k >  Ir : Y[ycs + k-1][r]  = (S_{k-1,Ir}^H v_{k-1})[r]
-BSE_DEV int64_t yslot(int k, int Ir, int ycs, int64_t n, int r) {
-  return (int64_t)(k <= Ir ? k : ycs + k - 1) * n + r;
+// cut into nI x nI tiles of order HT (lower triangle: tile-row I >= tile-column
+// J).  The hemv kernel's work unit is tile-row I over the panels
+// J = kK .. min(I, kK + K - 1) (chunk k).  Row r, in tile-row Ir, collects
+//   Y[k][r]        k = 0 .. cdiv(Ir + 1, K) - 1  (unit (k, Ir): S v over its panels)
+//   Y[ycs + I][r]  I = Ir .. nI - 1              (tile (I, Ir): S_{I,Ir}^H v_I)
+// i.e. nrs + nI - Ir slots with nrs = cdiv(Ir + 1, K).
+__host__ __device__ inline int hemv_k(int nI) { return nI >= 48 ? 4 : (nI >= 24 ? 2 : 1); }
+__host__ __device__ inline int hemv_punits(int j, int nI, int K) {
+  return j * nI - K * (j * (j - 1) / 2);
+}
+__host__ __device__ inline int hemv_units(int nI, int K) {
+  return hemv_punits((nI + K - 1) / K, nI, K);
+}
+BSE_DEV int64_t yslot(int q, int Ir, int nrs, int ycs, int64_t n, int r) {
+  return (int64_t)(q < nrs ? q : ycs + Ir + (q - nrs)) * n + r;
 }
 
 // Deterministic block-wide complex sum (wavefront butterflies, then waves in
@@ -86,7 +93,7 @@ BSE_DEV double wave_total63(double v) {
 __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     double2* __restrict__ M, int64_t ld, int n, double2* __restrict__ VW, double2* __restrict__ WV,
     int j0, int i, int has_new, const double2* __restrict__ hs, const double2* __restrict__ Y,
-    int ycs, int tprev, double2* __restrict__ partA, const double2* __restrict__ partB,
+    int ycs, double2* __restrict__ partA, const double2* __restrict__ partB,
     double2* __restrict__ yp) {
   constexpr int QP = COL_THREADS / ROWS_A;        // threads sharing one row
   constexpr int PER = TRD_NB / QP;                // panel columns per thread
@@ -128,32 +135,34 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   }
   if (tid < 2 * TRD_NB && tid % TRD_NB < i - 1) svw[tid] = hs[HS_SVV + tid];
   // y_{c-1}[r]: the previous hemv kernel's slots, QP threads per row
-  const int nIp = i > 0 ? cdiv(n - c, tprev) : 0;
+  const int nIp = i > 0 ? cdiv(n - c, HT) : 0;
+  const int Kp = i > 0 ? hemv_k(nIp) : 1;
   double2 yq = make_double2(0.0, 0.0);
   if (i > 0 && act) {
-    const int Ir = (r - c) / tprev;
-    for (int k0 = qq; k0 <= nIp; k0 += YCH * QP) {
+    const int Ir = (r - c) / HT, nrs = cdiv(Ir + 1, Kp), tot = nrs + nIp - Ir;
+    for (int q0 = qq; q0 < tot; q0 += YCH * QP) {
       double2 t[YCH];
 #pragma unroll
-      for (int u = 0; u < YCH; ++u) t[u] = Y[yslot(min(k0 + u * QP, nIp), Ir, ycs, N, r)];
+      for (int u = 0; u < YCH; ++u) t[u] = Y[yslot(min(q0 + u * QP, tot - 1), Ir, nrs, ycs, N, r)];
 #pragma unroll
       for (int u = 0; u < YCH; ++u)
-        if (k0 + u * QP <= nIp) yq = cadd(yq, t[u]);
+        if (q0 + u * QP < tot) yq = cadd(yq, t[u]);
     }
   }
-  // row c of the panel's earlier reflectors, and the slots of y_{c-1}[c] (wave 2)
+  // row c of the panel's earlier reflectors (threads qq = 1, lane = rr) and, in their
+  // first wavefront, the slots of y_{c-1}[c]
   double2 vcl = make_double2(0.0, 0.0), wcl = vcl;
   if (qq == 1 && rr < i - 1) {
     vcl = VW[c + (int64_t)rr * N];
     wcl = VW[c + (int64_t)(TRD_NB + rr) * N];
   }
   double2 ycq = make_double2(0.0, 0.0);
-  if (wid == 2 && i > 0)
-    for (int k = lane; k <= nIp; k += 64) ycq = cadd(ycq, Y[yslot(k, 0, ycs, N, c)]);
-  // the hemv blocks' partials of y^H v
+  if (wid == ROWS_A / 64 && i > 0)
+    for (int q = lane; q <= nIp; q += 64) ycq = cadd(ycq, Y[yslot(q, 0, 1, ycs, N, c)]);
+  // the hemv units' partials of y^H v and the panel's correction (last slot)
   double2 pa = make_double2(0.0, 0.0);
   if (i > 0)
-    for (int b = tid; b < nIp * (nIp + 1) / 2; b += COL_THREADS) pa = cadd(pa, partB[b]);
+    for (int b = tid; b <= hemv_units(nIp, Kp); b += COL_THREADS) pa = cadd(pa, partB[b]);
   double2 tc = make_double2(0.0, 0.0), scal_p = tc, pdot = tc;
   if (i > 0) {
     tc = hs[HS_TAU];
@@ -171,7 +180,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
       if (ip < i - 1 && act)
         yq = csub(yq, cadd(cmul(vr[u], svw[TRD_NB + ip]), cmul(wr[u], svw[ip])));
     }
-    if (wid == 2) {
+    if (wid == ROWS_A / 64) {
       if (lane < i - 1)
         ycq = csub(ycq, cadd(cmul(vcl, svw[TRD_NB + lane]), cmul(wcl, svw[lane])));
       ycq = wave_sum2(ycq);
@@ -297,92 +306,137 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   }
 }
 
+// Unit u (numbered chunk-major: chunk k holds tile-rows kK .. nI-1) of the
+// hemv tiling: the largest k with hemv_punits(k) <= u, from the root of that
+// quadratic corrected by one step either way, and its tile-row I.
+BSE_DEV void unit_of(int u, int nI, int K, int& k, int& I) {
+  const int nK = (nI + K - 1) / K;
+  const double a = nI + 0.5 * K;
+  int j = (int)floor((a - sqrt(a * a - 2.0 * K * u)) / K);
+  j = max(0, min(j, nK - 1));
+  j = (j + 1 <= nK - 1 && hemv_punits(j + 1, nI, K) <= u) ? j + 1 : j;
+  j = (hemv_punits(j, nI, K) > u) ? j - 1 : j;
+  k = j;
+  I = j * K + (u - hemv_punits(j, nI, K));
+}
+
+// Sum over the 16 lanes of each row of the wavefront (DPP within rows); every
+// lane of a row gets its row's total.
+BSE_DEV double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+
 // Reflector c from the column kernel's partials, then the Hermitian product
 // S v over the lower triangle of the trailing matrix (rows and columns c+1..n-1)
-// in t x t tiles, one block per tile (I >= J), tiles numbered column-major.
-// Wavefront w reads columns w, w+4, ... of the tile, lane l rows l, l+64, ...:
-// each load is a contiguous 1 KB column segment.  The first two load batches
-// of the tile are issued before the reflector is formed (every thread forms it
-// from the same reduced |x|^2, so no broadcast round trip is needed).  Block 0
-// also stores the reflector, V^H v and W^H v for the next column kernel.
-template <int TT>
-__global__ __launch_bounds__(HEMV_THREADS) void k_trd_hemv(
+// in HT x HT tiles, grouped into units (tile-row I, up to K consecutive
+// panels).  Persistent blocks (one per compute unit) take units b, b + G, ...;
+// every result is stored per unit or per tile, never per block.  Tiles stream
+// through three register buffers (two in flight while one is used) and their
+// loads carry no conditions, so the wait for one tile never covers the next.
+// Within a unit no barrier is taken: each lane keeps its rows' partial sums
+// in registers, and each tile's column sums go from the lanes straight to
+// the slots.  A unit ends with one LDS reduction of its row sums.  Block 0
+// also stores the reflector, V^H v and W^H v for the next column kernel, and
+// the panel's share of y^H v in the slot after the units'.
+//
+// Wavefront w owns tile column 4w + l / 16 (lane l); load s of lane l reads
+// row 16 s + l % 16: four contiguous 256-byte column segments per
+// instruction.  A column's sum over the tile's rows is lane-local over s plus
+// one 16-lane DPP reduction serving four columns.
+__global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     const double2* __restrict__ M, int64_t ld, int n, const double2* __restrict__ VW, int j0,
     int i, double2* __restrict__ hs, const double2* __restrict__ partA,
     double2* __restrict__ partB, double2* __restrict__ Y, int ycs, double* __restrict__ dd,
     double* __restrict__ ee, double2* __restrict__ tau, const double2* __restrict__ yp) {
-  constexpr int U = TT / 64;              // rows per lane
-  constexpr int CPW = TT / 4;             // columns per wavefront
-  constexpr int CB = (8 / U) < CPW ? (8 / U) : CPW;  // columns per load batch
-  constexpr int SLC = HEMV_THREADS / 128;
+  constexpr int NW = HV_THREADS / 64;     // 16 wavefronts
+  constexpr int NL = 4;                   // matrix loads per lane per tile
+  constexpr int SLC = HV_THREADS / 128;
+  static_assert(NW * 4 == HT, "tile layout");
+  struct Rec {        // one tile's loads
+    double2 s[NL];    // elements (rows 16 s + lr, column jl)
+    double2 xj;       // x at column jl
+  };
+  struct Cur {        // position in this block's tile sequence
+    int u, t, k, I, nt, In;  // In: tile-row of the block's next unit
+  };
   __shared__ double2 sl[SLC][128];
   __shared__ double2 sums[NVAL];
-  __shared__ double2 vrow[TT], vcol[TT], csum[TT];
-  __shared__ double2 racc[HEMV_THREADS / 64][TT];
-  __shared__ double2 red[HEMV_THREADS / 64];
+  __shared__ double2 vrow[2][HT];
+  __shared__ double2 rpart[NW * 4][HT];  // [wavefront x lane group][row]
+  __shared__ double2 pred[NW];
   const int c = j0 + i, b0 = c + 1;
   const int64_t N = n;
   const int m = n - b0;
-  const int nI = cdiv(m, TT);
+  const int nI = cdiv(m, HT), K = hemv_k(nI), nunits = hemv_units(nI, K);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int bid = blockIdx.x;
+  const int lr = lane & 15, lg = lane >> 4;  // row in slab, column group
+  const int jl = 4 * wid + lg;               // this lane's tile column
+  const int nlast = n - 1, G = gridDim.x;
+  const double2* xcol = M + (int64_t)c * ld;
+  const double2 zero = make_double2(0.0, 0.0);
 
-  // ---- tile of this block: largest J with J*nI - J(J-1)/2 <= bid
-  int J = 0;
-  {
-    int lo = 0, hi = nI - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      const int64_t pre = (int64_t)mid * nI - (int64_t)mid * (mid - 1) / 2;
-      if (pre <= bid) lo = mid; else hi = mid - 1;
+  auto decode = [&](Cur& q) {
+    if (q.u < nunits) {
+      unit_of(q.u, nI, K, q.k, q.I);
+      q.nt = min(q.I, q.k * K + K - 1) - q.k * K + 1;
+    } else {
+      q.k = 0;
+      q.I = 0;
+      q.nt = 1;
     }
-    J = lo;
-  }
-  const int Ib = J + (bid - (J * nI - J * (J - 1) / 2));
-  const int cj0 = b0 + J * TT, rb0 = b0 + Ib * TT;
-  const bool diag = Ib == J;
-  const int nlast = n - 1;
-
-  auto load = [&](double2 (&s)[CB][U], int q0) {
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int jl = wid + 4 * (q0 + cb);
-      const int64_t jc = min(cj0 + jl, nlast);
-#pragma unroll
-      for (int u = 0; u < U; ++u) s[cb][u] = M[min(rb0 + lane + 64 * u, nlast) + jc * ld];
+    int kn = 0;
+    q.In = 0;
+    if (q.u + G < nunits) unit_of(q.u + G, nI, K, kn, q.In);
+  };
+  auto advance = [&](Cur& q) {
+    if (++q.t == q.nt) {
+      q.u += G;
+      q.t = 0;
+      decode(q);
     }
   };
+  // loads without conditions (indices clamped; past the end, values unused)
+  auto load = [&](Rec& rc, const Cur& q) {
+    const int rb0 = b0 + q.I * HT;
+    const int64_t j = min(b0 + (q.k * K + q.t) * HT + jl, nlast);
+#pragma unroll
+    for (int s = 0; s < NL; ++s) rc.s[s] = M[min(rb0 + 16 * s + lr, nlast) + j * ld];
+    rc.xj = xcol[j];
+  };
 
-  // ---- issue the first tile batches and every load of the reflector
-  double2 ba[CB][U], bb[CB][U];
-  load(ba, 0);
-  if (CB < CPW) load(bb, CB);
-  const double2* xcol = M + (int64_t)c * ld;
+  // ---- first two tiles and every load of the reflector
+  Cur C{(int)blockIdx.x, 0, 0, 0, 1, 0};
+  decode(C);
+  Cur Lq = C;
+  Rec r0, r1, r2;
+  load(r0, Lq);
+  advance(Lq);
+  load(r1, Lq);
+  advance(Lq);
   const double2 ax = xcol[b0];
-  double2 xc = make_double2(0.0, 0.0), xr = xc;
-  if (tid < TT) {
-    if (cj0 + tid < n) xc = xcol[cj0 + tid];
-    if (rb0 + tid < n) xr = xcol[rb0 + tid];
-  }
   const int nbA = cdiv(n - c, ROWS_A);
   const int nvals = 2 + 2 * i;
   if (wid == 0) {
-    double2 a = make_double2(0.0, 0.0);
+    double2 a = zero;
     for (int b = lane; b < nbA; b += 64) a = cadd(a, partA[(int64_t)b * NVAL]);
     a = wave_sum2(a);
     if (lane == 0) sums[0] = a;
   }
-  if (bid == 0) {
+  if (blockIdx.x == 0) {
     const int t = tid & 127, slice = tid >> 7;
     if (t >= 1 && t < nvals) {
-      double2 sb = make_double2(0.0, 0.0);
+      double2 sb = zero;
       for (int b = slice; b < nbA; b += SLC) sb = cadd(sb, partA[(int64_t)b * NVAL + t]);
       sl[slice][t] = sb;
     }
   }
   __syncthreads();
-  if (bid == 0 && tid >= 1 && tid < nvals) {
-    double2 sb = make_double2(0.0, 0.0);
+  if (blockIdx.x == 0 && tid >= 1 && tid < nvals) {
+    double2 sb = zero;
     for (int q = 0; q < SLC; ++q) sb = cadd(sb, sl[q][tid]);
     sums[tid] = sb;
   }
@@ -393,9 +447,9 @@ __global__ __launch_bounds__(HEMV_THREADS) void k_trd_hemv(
   double2 tv, scal;
   double beta;
   if (xn2 == 0.0 && ax.y == 0.0) {
-    tv = make_double2(0.0, 0.0);
+    tv = zero;
     beta = ax.x;
-    scal = make_double2(0.0, 0.0);
+    scal = zero;
   } else {
     beta = -copysign(sqrt(ax.x * ax.x + ax.y * ax.y + xn2), ax.x);
     tv = make_double2((beta - ax.x) / beta, -ax.y / beta);
@@ -403,10 +457,10 @@ __global__ __launch_bounds__(HEMV_THREADS) void k_trd_hemv(
     const double q = 1.0 / cabs2(dnm);
     scal = make_double2(dnm.x * q, -dnm.y * q);
   }
-  // block 0: the reflector, V^H v and W^H v of the panel, and their share of
-  // y^H v: sum_r conj(V (W^H v) + W (V^H v))[r] v[r] = sum_ip conj(sWv) sVv + conj(sVv) sWv
-  double2 corr = make_double2(0.0, 0.0);
-  if (bid == 0) {
+  if (blockIdx.x == 0) {
+    // block 0: the reflector, V^H v and W^H v of the panel, and their share of
+    // y^H v: sum_r conj(V (W^H v) + W (V^H v))[r] v[r] = sum_ip conj(sWv) sVv + conj(sVv) sWv
+    double2 corr = zero;
     if (tid == 0) {
       ee[c] = beta;
       tau[c] = tv;
@@ -425,77 +479,98 @@ __global__ __launch_bounds__(HEMV_THREADS) void k_trd_hemv(
       hs[HS_SWV + tid] = swv;
       corr = cadd(cmulc(swv, svv), cmulc(svv, swv));
     }
-  }
-  // ---- v on the tile's rows and columns
-  if (tid < TT) {
-    const int j = cj0 + tid, r = rb0 + tid;
-    vcol[tid] = (j < n) ? ((j == b0) ? make_double2(1.0, 0.0) : cmul(scal, xc)) : make_double2(0.0, 0.0);
-    vrow[tid] = (r < n) ? ((r == b0) ? make_double2(1.0, 0.0) : cmul(scal, xr)) : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-
-  // ---- tile product: rows S_IJ v_J (lane-local), columns S_IJ^H v_I (wave sums)
-  double2 vr[U], racc_l[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    vr[u] = vrow[lane + 64 * u];
-    racc_l[u] = make_double2(0.0, 0.0);
-  }
-  auto use = [&](const double2 (&s)[CB][U], int q0) {
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int jl = wid + 4 * (q0 + cb);
-      const bool jok = cj0 + jl < n;
-      const double2 vj = vcol[jl];
-      double2 cacc = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int rl = lane + 64 * u;
-        const bool ok = jok && (rb0 + rl < n) && (!diag || rl >= jl);
-        const bool strict = !diag || rl > jl;
-        double2 sr = ok ? s[cb][u] : make_double2(0.0, 0.0);
-        if (diag && rl == jl) sr.y = 0.0;  // the diagonal of a Hermitian matrix is real
-        racc_l[u] = cadd(racc_l[u], cmul(sr, vj));
-        if (ok && strict) cacc = cadd(cacc, cmulc(s[cb][u], vr[u]));
-      }
-      cacc.x = wave_total63(cacc.x);
-      cacc.y = wave_total63(cacc.y);
-      if (lane == 63) csum[jl] = cacc;
+    if (wid == 0) {
+      corr.x = wave_total63(corr.x);
+      corr.y = wave_total63(corr.y);
+      if (lane == 63) partB[nunits] = make_double2(-corr.x, -corr.y);
     }
+  }
+  auto vval = [&](int e, double2 x) -> double2 {
+    return (e < n) ? ((e == b0) ? make_double2(1.0, 0.0) : cmul(scal, x)) : zero;
   };
-#pragma unroll 1
-  for (int q0 = 0; q0 < CPW; q0 += 2 * CB) {
-    use(ba, q0);
-    if (q0 + 2 * CB < CPW) load(ba, q0 + 2 * CB);
-    if (q0 + CB < CPW) {
-      use(bb, q0 + CB);
-      if (q0 + 3 * CB < CPW) load(bb, q0 + 3 * CB);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < U; ++u) racc[wid][lane + 64 * u] = racc_l[u];
+  int ub = 0;  // vrow buffer of the current unit
+  if (tid < HT) vrow[0][tid] = vval(b0 + C.I * HT + tid, xcol[min(b0 + C.I * HT + tid, nlast)]);
   __syncthreads();
 
-  // ---- slots and this block's share of y^H v
-  double2 pb = make_double2(0.0, 0.0);
-  if (tid < TT) {
-    const int r = rb0 + tid, j = cj0 + tid;
-    if (r < n) {
-      double2 rp = make_double2(0.0, 0.0);
+  double2 ra[NL] = {zero, zero, zero, zero};
+  double2 pbl = zero;
+  // cb: tile C; nb receives tile C + 2 (tile C + 1 is in flight in the third buffer)
+  auto tile = [&](const Rec& cb, Rec& nb) {
+    // x on the rows of the next unit (issued before the tile loads, so that
+    // waiting for it at the end of the unit leaves those in flight)
+    const double2 xnext = xcol[min(b0 + C.In * HT + lane, nlast)];
+    load(nb, Lq);
+    advance(Lq);
+    const int I = C.I, J = C.k * K + C.t;
+    const int rb0 = b0 + I * HT, cj0 = b0 + J * HT;
+    const double2 vj = vval(cj0 + jl, cb.xj);
+    const bool plain = J != I && rb0 + HT <= n && cj0 + HT <= n;  // uniform
+    double2 ca = zero;
 #pragma unroll
-      for (int w = 0; w < HEMV_THREADS / 64; ++w) rp = cadd(rp, racc[w][tid]);
-      Y[(int64_t)J * N + r] = rp;
-      pb = cadd(pb, cmulc(rp, vrow[tid]));
+    for (int s = 0; s < NL; ++s) {
+      const int rl = 16 * s + lr;
+      const double2 sv = cb.s[s];
+      const double2 vr = vrow[ub][rl];
+      if (plain) {
+        ra[s] = cadd(ra[s], cmul(sv, vj));
+        ca = cadd(ca, cmulc(sv, vr));
+      } else {
+        const bool ok = (rb0 + rl < n) && (cj0 + jl < n) && (J != I || rl >= jl);
+        const bool strict = J != I || rl > jl;
+        double2 sr = ok ? sv : zero;
+        if (J == I && rl == jl) sr.y = 0.0;  // the diagonal of a Hermitian matrix is real
+        ra[s] = cadd(ra[s], cmul(sr, vj));
+        if (ok && strict) ca = cadd(ca, cmulc(sv, vr));
+      }
     }
-    if (j < n) {
-      const double2 cp = csum[tid];
-      Y[(int64_t)(ycs + Ib) * N + j] = cp;
-      pb = cadd(pb, cmulc(cp, vcol[tid]));
+    ca.x = row16_sum(ca.x);
+    ca.y = row16_sum(ca.y);
+    if (lr == 0 && cj0 + jl < n) {
+      Y[(int64_t)(ycs + I) * N + cj0 + jl] = ca;
+      pbl = cadd(pbl, cmulc(ca, vj));
     }
+    if (C.t == C.nt - 1) {
+      // ---- end of unit: row sums over 64 partials (16 threads per row, then a
+      // 16-lane reduction), the next unit's v rows, and the unit's y^H v share
+#pragma unroll
+      for (int s = 0; s < NL; ++s) {
+        rpart[4 * wid + lg][16 * s + lr] = ra[s];
+        ra[s] = zero;
+      }
+      if (tid < HT) vrow[ub ^ 1][tid] = vval(b0 + C.In * HT + tid, xnext);
+      __syncthreads();
+      const int row = tid >> 4, part = tid & 15;
+      double2 rs = zero;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rs = cadd(rs, rpart[part + 16 * q][row]);
+      rs.x = row16_sum(rs.x);
+      rs.y = row16_sum(rs.y);
+      if (part == 0 && rb0 + row < n) {
+        Y[(int64_t)C.k * N + rb0 + row] = rs;
+        pbl = cadd(pbl, cmulc(rs, vrow[ub][row]));
+      }
+      pbl.x = wave_total63(pbl.x);
+      pbl.y = wave_total63(pbl.y);
+      if (lane == 63) pred[wid] = pbl;
+      pbl = zero;
+      __syncthreads();
+      if (tid == 0) {
+        double2 t = zero;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t = cadd(t, pred[w]);
+        partB[C.u] = t;
+      }
+      ub ^= 1;
+    }
+    advance(C);
+  };
+  while (C.u < nunits) {  // uniform
+    tile(r0, r2);
+    if (C.u >= nunits) break;
+    tile(r1, r0);
+    if (C.u >= nunits) break;
+    tile(r2, r1);
   }
-  pb = csub(pb, corr);
-  pb = block_sum2(pb, red);
-  if (tid == 0) partB[bid] = pb;
 }
 
 __global__ void k_trd_last(const double2* M, int64_t ld, int n, double* dd, const int32_t* info) {
@@ -516,40 +591,39 @@ __global__ void k_trd_zero_cols(double2* VW, double2* WV, int64_t n, int jb) {
   }
 }
 
-// Largest hemv grid over the sweep (tiles of the largest trailing order in
-// each tile-size range).
-int64_t hemv_blocks_max(int64_t n) {
-  int64_t best = 1;
-  for (int64_t m : {std::min<int64_t>(n - 1, 4095), std::min<int64_t>(n - 1, 12287), n - 1}) {
-    if (m < 1) continue;
-    const int64_t t = hemv_tile(m), nI = (m + t - 1) / t;
-    best = std::max(best, nI * (nI + 1) / 2);
-  }
-  return best;
+int64_t ycs_of(int64_t n) { return (n + 63) / 64; }
+int64_t hemv_tiles_max(int64_t n) {
+  const int64_t nI = (n - 1 + HT - 1) / HT;
+  return nI * (nI + 1) / 2;
 }
 
-int64_t ycs_of(int64_t n) { return (n + 63) / 64; }
-
-template <int TT>
-void launch_hemv(int nb, double2* M, int64_t ld, int64_t n, const TrdBufs& w, int j0, int i,
-                 double2* partA, double2* partB, double2* Y, int ycs, hipStream_t s) {
-  BSE_LAUNCH(k_trd_hemv<TT>, dim3(nb), dim3(HEMV_THREADS), 0, s, M, ld, (int)n, w.VW, j0, i, w.hs,
-             partA, partB, Y, ycs, w.dd, w.ee, w.tau, w.yproj);
+int hemv_grid(int64_t m) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  const int nI = (int)((m + HT - 1) / HT);
+  return std::min(hemv_units(nI, hemv_k(nI)), cus);
 }
 
 }  // namespace
 
-// [partA: column-kernel partials | partB: hemv partials of y^H v | Y: hemv slots]
+// [partA: column-kernel partials | partB: hemv tile partials of y^H v + one |
+//  Y: hemv slots]
 int64_t trd_part_elems(int64_t n) {
   const int64_t a = ((n + ROWS_A - 1) / ROWS_A + 1) * NVAL;
-  return a + hemv_blocks_max(n) + 2 * ycs_of(n) * n;
+  return a + hemv_tiles_max(n) + 1 + 2 * ycs_of(n) * n;
 }
 
 bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t* info,
                     hipStream_t s) {
   double2* partA = w.part;
   double2* partB = w.part + ((n + ROWS_A - 1) / ROWS_A + 1) * NVAL;
-  double2* Y = partB + hemv_blocks_max(n);
+  double2* Y = partB + hemv_tiles_max(n) + 1;
   const int ycs = (int)ycs_of(n);
   for (int64_t j0 = 0; j0 < n - 1; j0 += TRD_NB) {
     const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
@@ -558,17 +632,14 @@ bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t
     for (int i = 0; i < jb; ++i) {
       const int64_t c = j0 + i, m = n - c - 1;
       BSE_LAUNCH(k_trd_col, dim3(cdiv(n - c, ROWS_A)), dim3(COL_THREADS), 0, s, M, ld, (int)n, w.VW,
-                 w.WV, (int)j0, i, 1, w.hs, Y, ycs, hemv_tile(n - c), partA, partB, w.yproj);
-      const int tt = hemv_tile(m);
-      const int nI = cdiv(m, tt), nb = nI * (nI + 1) / 2;
-      if (tt == 64) launch_hemv<64>(nb, M, ld, n, w, (int)j0, i, partA, partB, Y, ycs, s);
-      else if (tt == 128) launch_hemv<128>(nb, M, ld, n, w, (int)j0, i, partA, partB, Y, ycs, s);
-      else launch_hemv<256>(nb, M, ld, n, w, (int)j0, i, partA, partB, Y, ycs, s);
+                 w.WV, (int)j0, i, 1, w.hs, Y, ycs, partA, partB, w.yproj);
+      BSE_LAUNCH(k_trd_hemv, dim3(hemv_grid(m)), dim3(HV_THREADS), 0, s, M, ld, (int)n, w.VW,
+                 (int)j0, i, w.hs, partA, partB, Y, ycs, w.dd, w.ee, w.tau, w.yproj);
     }
     // finish the panel's last reflector
     const int64_t cl = j0 + jb;
     BSE_LAUNCH(k_trd_col, dim3(cdiv(n - cl, ROWS_A)), dim3(COL_THREADS), 0, s, M, ld, (int)n,
-               w.VW, w.WV, (int)j0, jb, 0, w.hs, Y, ycs, hemv_tile(n - cl), partA, partB, w.yproj);
+               w.VW, w.WV, (int)j0, jb, 0, w.hs, Y, ycs, partA, partB, w.yproj);
     const int64_t t = j0 + jb;
     if (t < n) {
       ZgemmParams g;  // S[t:, t:] -= [V W] [W V]^H
