@@ -41,58 +41,65 @@ __global__ void k_zero_ints(int32_t* p, int n) {
 namespace {
 
 // ------------------------------------------------------------------ Cholesky
-// Factor the jb x jb diagonal block (upper, A = U^H U) in LDS and form U^-1.
-__global__ __launch_bounds__(256) void k_potrf_diag(double2* __restrict__ A, int64_t ld, int j0,
-                                                    int jb, double2* __restrict__ Uinv,
-                                                    int32_t* info) {
+// One panel of the blocked Cholesky A - B = U^H U (Sec. 4.3): every block
+// factors the jb x jb diagonal block A11 = U11^H U11 in LDS (right-looking, one
+// barrier per column: the update uses the unscaled pivot row divided by the
+// pivot, so the row itself is never rewritten within its step), then solves
+// U11^H X = A12 for its own PCOLS columns of the panel row by forward
+// substitution, one column per thread held in registers.  Block 0 stores U11.
+constexpr int PCOLS = 256;
+__global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, int64_t ld,
+                                                       int64_t n, int j0, int jb,
+                                                       int32_t* info) {
   __shared__ double2 a[CH_NB][CH_NB + 1];
-  __shared__ double2 x[CH_NB][CH_NB + 1];
-  __shared__ int bad;
+  __shared__ double2 u[CH_NB][CH_NB + 1];
   if (failed(info)) return;
   const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
+  const int64_t c0 = (int64_t)j0 + jb + (int64_t)blockIdx.x * PCOLS;
+  const bool solve = jb == CH_NB && c0 + tid < n;
+  // this thread's column of A12 (rows j0 .. j0 + jb - 1)
+  double2 x[CH_NB];
+#pragma unroll
+  for (int r = 0; r < CH_NB; ++r)
+    x[r] = solve ? A[(int64_t)(j0 + r) + (c0 + tid) * ld] : make_double2(0.0, 0.0);
+  for (int e = tid; e < jb * jb; e += PCOLS) {
     const int r = e % jb, c = e / jb;
     a[r][c] = (r <= c) ? A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * ld] : make_double2(0.0, 0.0);
   }
   __syncthreads();
   for (int j = 0; j < jb; ++j) {
-    if (tid == 0) {
-      const double dj = a[j][j].x;
-      if (!(dj > 0.0) || !isfinite(dj)) {
-        bad = 1;
-        set_info(info, j0 + j + 1);
-      } else {
-        a[j][j] = make_double2(sqrt(dj), 0.0);
-      }
+    const double d = a[j][j].x;  // the same value in every thread: uniform exit
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0 && blockIdx.x == 0) set_info(info, j0 + j + 1);
+      return;
     }
-    __syncthreads();
-    if (bad) return;
-    const double s = 1.0 / a[j][j].x;
-    for (int c = j + 1 + tid; c < jb; c += blockDim.x) a[j][c] = cscale(a[j][c], s);
-    __syncthreads();
-    for (int e = tid; e < jb * jb; e += blockDim.x) {
+    const double rs = 1.0 / sqrt(d), rd = 1.0 / d;
+    for (int e = tid; e < jb * jb; e += PCOLS) {
       const int r = e % jb, c = e / jb;
-      if (r > j && c >= r) a[r][c] = csub(a[r][c], cmulc(a[j][r], a[j][c]));
+      if (r == j && c >= j)
+        u[j][c] = (c == j) ? make_double2(d * rs, 0.0) : cscale(a[j][c], rs);
+      else if (r > j && c >= r)
+        a[r][c] = csub(a[r][c], cscale(cmulc(a[j][r], a[j][c]), rd));
     }
     __syncthreads();
   }
-  if (tid < jb) {
-    const int c = tid;
-    for (int r = 0; r < jb; ++r) x[r][c] = make_double2(0.0, 0.0);
-    x[c][c] = make_double2(1.0 / a[c][c].x, 0.0);
-    for (int r = c - 1; r >= 0; --r) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int k = r + 1; k <= c; ++k) s = cadd(s, cmul(a[r][k], x[k][c]));
-      x[r][c] = cscale(s, -1.0 / a[r][r].x);
+  if (blockIdx.x == 0)
+    for (int e = tid; e < jb * jb; e += PCOLS) {
+      const int r = e % jb, c = e / jb;
+      if (r <= c) A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * ld] = u[r][c];
     }
+  if (jb != CH_NB) return;  // the last panel has no panel row
+  // U11^H X = A12: x[r] = (a12[r] - sum_{k<r} conj(U[k][r]) x[k]) / U[r][r]
+#pragma unroll
+  for (int r = 0; r < CH_NB; ++r) {
+    double2 s = x[r];
+#pragma unroll
+    for (int k = 0; k < r; ++k) s = csub(s, cmulc(u[k][r], x[k]));
+    x[r] = cscale(s, 1.0 / u[r][r].x);
   }
-  __syncthreads();
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    const int r = e % jb, c = e / jb;
-    if (r <= c) A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * ld] = a[r][c];
-    Uinv[r + (int64_t)c * jb] = x[r][c];
-  }
+  if (solve)
+#pragma unroll
+    for (int r = 0; r < CH_NB; ++r) A[(int64_t)(j0 + r) + (c0 + tid) * ld] = x[r];
 }
 
 // Mirror one triangle onto the other: from_lower ? upper = conj(lower) :
@@ -575,7 +582,6 @@ struct SolveWs {
   double2* hs;    // small state
   double2* part;  // partial sums
   double2* Tall;  // T factors
-  double2* Uinv;  // CH_NB^2
   double2* tau;   // n
   double* dd;
   double* ee;
@@ -607,7 +613,6 @@ SolveWs carve(const bse_desc* d, void* base) {
   w.hs = (double2*)L.add(HS_SIZE * 16);
   w.part = (double2*)L.add(trd_part_elems(n) * 16);
   w.Tall = (double2*)L.add(npnl * TRD_NB * TRD_NB * 16);
-  w.Uinv = (double2*)L.add(CH_NB * CH_NB * 16);
   w.tau = (double2*)L.add(n * 16);
   w.dd = (double*)L.add(n * 8);
   w.ee = (double*)L.add(n * 8);
@@ -620,31 +625,14 @@ SolveWs carve(const bse_desc* d, void* base) {
   return w;
 }
 
-bool cholesky(double2* H1, int64_t n, int64_t ld, double2* Uinv, int32_t* info, hipStream_t s) {
+bool cholesky(double2* H1, int64_t n, int64_t ld, int32_t* info, hipStream_t s) {
   for (int64_t j0 = 0; j0 < n; j0 += CH_NB) {
     const int jb = (int)std::min<int64_t>(CH_NB, n - j0);
-    BSE_LAUNCH(k_potrf_diag, dim3(1), dim3(256), 0, s, H1, ld, (int)j0, jb, Uinv, info);
     const int64_t rest = n - j0 - jb;
+    BSE_LAUNCH(k_potrf_panel, dim3((unsigned)std::max<int64_t>(1, cdiv(rest, PCOLS))),
+               dim3(PCOLS), 0, s, H1, ld, n, (int)j0, jb, info);
     if (rest <= 0) break;
     double2* A12 = H1 + j0 + (j0 + jb) * ld;
-    ZgemmParams g;  // U12 = U11^-H A12 (in place: one row tile covers all jb rows)
-    g.M = jb;
-    g.N = (int)rest;
-    g.K = jb;
-    g.A = Uinv;
-    g.a_rs = jb;
-    g.a_cs = 1;
-    g.conjA = 1;
-    g.a_tri = 2;
-    g.B = A12;
-    g.b_rs = 1;
-    g.b_cs = ld;
-    g.C = A12;
-    g.c_rs = 1;
-    g.c_cs = ld;
-    g.info = info;
-    g.tag = "zgemm_potrf_trsm";
-    if (zgemm(g, 1, s) != hipSuccess) return false;
     ZgemmParams h;  // A22 -= U12^H U12 (upper)
     h.M = (int)rest;
     h.N = (int)rest;
@@ -758,7 +746,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
 
   double2* Hm = H0;  // Hermitian matrix handed to the tridiagonalisation
   if (full) {
-    if (!cholesky(H1, n, ld, w.Uinv, info, s)) return BSE_ERR_HIP;
+    if (!cholesky(H1, n, ld, info, s)) return BSE_ERR_HIP;
     ZgemmParams a;  // T1 = (A+B) U^H
     a.M = (int)n;
     a.N = (int)n;
