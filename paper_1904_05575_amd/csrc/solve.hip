@@ -42,17 +42,19 @@ namespace {
 
 // ------------------------------------------------------------------ Cholesky
 // One panel of the blocked Cholesky A - B = U^H U (Sec. 4.3): every block
-// factors the jb x jb diagonal block A11 = U11^H U11 in LDS (right-looking, one
-// barrier per column: the update uses the unscaled pivot row divided by the
-// pivot, so the row itself is never rewritten within its step), then solves
-// U11^H X = A12 for its own PCOLS columns of the panel row by forward
-// substitution, one column per thread held in registers.  Block 0 stores U11.
+// factors the jb x jb diagonal block A11 = U11^H U11 (right-looking; each
+// thread keeps four fixed elements in registers and only the pivot row goes
+// through LDS, one barrier per column), then solves U11^H X = A12 for its own
+// PCOLS columns of the panel row by forward substitution (one column per
+// thread, in registers; the updates of one step are independent).  Block 0
+// stores U11.
 constexpr int PCOLS = 256;
+constexpr int PEL = CH_NB * CH_NB / PCOLS;  // diagonal-block elements per thread
 __global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, int64_t ld,
                                                        int64_t n, int j0, int jb,
                                                        int32_t* info) {
-  __shared__ double2 a[CH_NB][CH_NB + 1];
-  __shared__ double2 u[CH_NB][CH_NB + 1];
+  __shared__ double2 u[CH_NB][CH_NB + 1];  // rows of U11 as they are finished
+  __shared__ double dsh[CH_NB];
   if (failed(info)) return;
   const int tid = threadIdx.x;
   const int64_t c0 = (int64_t)j0 + jb + (int64_t)blockIdx.x * PCOLS;
@@ -62,40 +64,55 @@ __global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, 
 #pragma unroll
   for (int r = 0; r < CH_NB; ++r)
     x[r] = solve ? A[(int64_t)(j0 + r) + (c0 + tid) * ld] : make_double2(0.0, 0.0);
-  for (int e = tid; e < jb * jb; e += PCOLS) {
-    const int r = e % jb, c = e / jb;
-    a[r][c] = (r <= c) ? A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * ld] : make_double2(0.0, 0.0);
+  // elements e = tid + PCOLS q of the diagonal block: row e % 32, column e / 32
+  double2 ae[PEL];
+  int er[PEL], ec[PEL];
+#pragma unroll
+  for (int q = 0; q < PEL; ++q) {
+    const int e = tid + PCOLS * q;
+    er[q] = e % CH_NB;
+    ec[q] = e / CH_NB;
+    const bool in = er[q] < jb && ec[q] < jb && er[q] <= ec[q];
+    ae[q] = in ? A[(int64_t)(j0 + er[q]) + (int64_t)(j0 + ec[q]) * ld] : make_double2(0.0, 0.0);
   }
-  __syncthreads();
   for (int j = 0; j < jb; ++j) {
-    const double d = a[j][j].x;  // the same value in every thread: uniform exit
+    // the owners of row j publish it (column >= j), then every thread updates
+#pragma unroll
+    for (int q = 0; q < PEL; ++q)
+      if (er[q] == j && ec[q] >= j && ec[q] < jb) u[j][ec[q]] = ae[q];
+    __syncthreads();
+    const double d = u[j][j].x;  // the same value in every thread: uniform exit
     if (!(d > 0.0) || !isfinite(d)) {
       if (tid == 0 && blockIdx.x == 0) set_info(info, j0 + j + 1);
       return;
     }
-    const double rs = 1.0 / sqrt(d), rd = 1.0 / d;
-    for (int e = tid; e < jb * jb; e += PCOLS) {
-      const int r = e % jb, c = e / jb;
-      if (r == j && c >= j)
-        u[j][c] = (c == j) ? make_double2(d * rs, 0.0) : cscale(a[j][c], rs);
-      else if (r > j && c >= r)
-        a[r][c] = csub(a[r][c], cscale(cmulc(a[j][r], a[j][c]), rd));
-    }
-    __syncthreads();
+    const double rd = 1.0 / d;
+#pragma unroll
+    for (int q = 0; q < PEL; ++q)
+      if (er[q] > j && ec[q] >= er[q] && ec[q] < jb)
+        ae[q] = csub(ae[q], cscale(cmulc(u[j][er[q]], u[j][ec[q]]), rd));
+    if (tid == 0) dsh[j] = sqrt(d);
   }
+  __syncthreads();
+  // u holds the unscaled rows: U[j][c] = u[j][c] / sqrt(u[j][j])
+  for (int e = tid; e < CH_NB * CH_NB; e += PCOLS) {
+    const int r = e % CH_NB, c = e / CH_NB;
+    if (r < jb && c < jb && r <= c)
+      u[r][c] = (r == c) ? make_double2(dsh[r], 0.0) : cscale(u[r][c], 1.0 / dsh[r]);
+  }
+  __syncthreads();
   if (blockIdx.x == 0)
     for (int e = tid; e < jb * jb; e += PCOLS) {
       const int r = e % jb, c = e / jb;
       if (r <= c) A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * ld] = u[r][c];
     }
   if (jb != CH_NB) return;  // the last panel has no panel row
-  // U11^H X = A12: x[r] = (a12[r] - sum_{k<r} conj(U[k][r]) x[k]) / U[r][r]
+  // U11^H X = A12, right-looking: x[k] /= U[k][k]; x[r] -= conj(U[k][r]) x[k], r > k
 #pragma unroll
-  for (int r = 0; r < CH_NB; ++r) {
-    double2 s = x[r];
+  for (int k = 0; k < CH_NB; ++k) {
+    x[k] = cscale(x[k], 1.0 / u[k][k].x);
 #pragma unroll
-    for (int k = 0; k < r; ++k) s = csub(s, cmulc(u[k][r], x[k]));
-    x[r] = cscale(s, 1.0 / u[r][r].x);
+    for (int r = k + 1; r < CH_NB; ++r) x[r] = csub(x[r], cmulc(u[k][r], x[k]));
   }
   if (solve)
 #pragma unroll
