@@ -96,6 +96,108 @@ struct ZTile {
     }
   }
 
+  // Main loop with register prefetch: while one K slice is multiplied from
+  // LDS, the next one is in flight in registers; two LDS buffers, one barrier
+  // per slice.  addrA(mm, k, ok) / addrB(k, nn, ok) return the address of an
+  // element for any index (clamped inside the operand) and set ok when the
+  // element exists, so that every load is issued without a condition;
+  // fixA(v, k) / fixB(v, k) apply conjugation or scaling to an existing one.
+  struct Smem2 {
+    Smem buf[2];
+  };
+  template <class AA, class AB, class FA, class FB>
+  BSE_DEV void run_pf(Smem2& s, int k_lo, int k_hi, bool a_mfast, bool b_nfast, AA addrA,
+                      AB addrB, FA fixA, FB fixB) {
+    constexpr int NA = BM * BK / NT, NB = BN * BK / NT;
+    static_assert(NA * NT == BM * BK && NB * NT == BN * BK, "slice not divisible");
+    const int tid = threadIdx.x;
+    double2 ra[NA], rb[NB];
+    bool oa[NA], ob[NB];
+    auto a_at = [&](int e, int& mm, int& kk) {
+      if (a_mfast) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
+    };
+    auto b_at = [&](int e, int& kk, int& nn) {
+      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+    };
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        int mm, kk;
+        a_at(tid + NT * q, mm, kk);
+        bool ok;
+        const double2* p = addrA(mm, k0 + kk, ok);
+        ra[q] = *p;
+        oa[q] = ok && k0 + kk < k_hi;
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        int kk, nn;
+        b_at(tid + NT * q, kk, nn);
+        bool ok;
+        const double2* p = addrB(k0 + kk, nn, ok);
+        rb[q] = *p;
+        ob[q] = ok && k0 + kk < k_hi;
+      }
+    };
+    auto put = [&](Smem& sm, int k0) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        int mm, kk;
+        a_at(tid + NT * q, mm, kk);
+        const double2 v = oa[q] ? fixA(ra[q], k0 + kk) : make_double2(0.0, 0.0);
+        sm.a_re[kk][mm] = v.x;
+        sm.a_im[kk][mm] = v.y;
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        int kk, nn;
+        b_at(tid + NT * q, kk, nn);
+        const double2 v = ob[q] ? fixB(rb[q], k0 + kk) : make_double2(0.0, 0.0);
+        sm.b_re[kk][nn] = v.x;
+        sm.b_im[kk][nn] = v.y;
+      }
+    };
+    if (k_lo >= k_hi) return;
+    fetch(k_lo);
+    int buf = 0;
+    for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
+      put(s.buf[buf], k0);
+      __syncthreads();
+      if (k0 + BK < k_hi) fetch(k0 + BK);
+      slice(s.buf[buf]);
+      buf ^= 1;
+    }
+  }
+
+  // acc += the BK-deep slice staged in sm
+  BSE_DEV void slice(const Smem& sm) {
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kr = ks * 4 + (lane >> 4);
+      double ar[TI], ai[TI], nai[TI], br[TJ], bi[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        ar[i] = sm.a_re[kr][wm0 + i * 16 + (lane & 15)];
+        ai[i] = sm.a_im[kr][wm0 + i * 16 + (lane & 15)];
+        nai[i] = -ai[i];
+      }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        br[j] = sm.b_re[kr][wn0 + j * 16 + (lane & 15)];
+        bi[j] = sm.b_im[kr][wn0 + j * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+        }
+    }
+  }
+
   // store(m_local, n_local, value) for every accumulator element.
   template <class ST>
   BSE_DEV void store(ST st) {

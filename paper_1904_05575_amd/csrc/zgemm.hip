@@ -9,7 +9,7 @@ namespace {
 template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b_off) {
   using T = ZTile<BM, BN, WM, WN>;
-  __shared__ typename T::Smem sm;
+  __shared__ typename T::Smem2 sm;
   if (failed(p.info)) return;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   if (p.c_uplo == 1 && m0 > n0 + BN - 1) return;
@@ -26,13 +26,22 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
   if (p.b_tri == 2) k_lo = max(k_lo, n0);
 
   const double asgn = p.conjA ? -1.0 : 1.0, bsgn = p.conjB ? -1.0 : 1.0;
-  auto loadA = [&](int mm, int k) -> double2 {
+  const int mlast = p.M - 1, nlast = p.N - 1, klast = p.K - 1;
+  auto addrA = [&](int mm, int k, bool& ok) -> const double2* {
     const int m = m0 + mm;
-    bool ok = m < p.M;
+    ok = m < p.M && k < p.K;
     if (p.a_tri == 1) ok = ok && (k >= m);
     if (p.a_tri == 2) ok = ok && (k <= m);
-    if (!ok) return make_double2(0.0, 0.0);
-    double2 v = A[(int64_t)m * p.a_rs + (int64_t)k * p.a_cs];
+    return A + (int64_t)min(m, mlast) * p.a_rs + (int64_t)min(k, klast) * p.a_cs;
+  };
+  auto addrB = [&](int k, int nn, bool& ok) -> const double2* {
+    const int n = n0 + nn;
+    ok = n < p.N && k < p.K;
+    if (p.b_tri == 1) ok = ok && (k <= n);
+    if (p.b_tri == 2) ok = ok && (k >= n);
+    return B + (int64_t)min(k, klast) * p.b_rs + (int64_t)min(n, nlast) * p.b_cs;
+  };
+  auto fixA = [&](double2 v, int k) -> double2 {
     v.y *= asgn;
     if (p.kscale) {
       const double s = p.kscale[k];
@@ -41,19 +50,13 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
     }
     return v;
   };
-  auto loadB = [&](int k, int nn) -> double2 {
-    const int n = n0 + nn;
-    bool ok = n < p.N;
-    if (p.b_tri == 1) ok = ok && (k <= n);
-    if (p.b_tri == 2) ok = ok && (k >= n);
-    if (!ok) return make_double2(0.0, 0.0);
-    double2 v = B[(int64_t)k * p.b_rs + (int64_t)n * p.b_cs];
+  auto fixB = [&](double2 v, int) -> double2 {
     v.y *= bsgn;
     return v;
   };
   T t;
   t.init();
-  t.run(sm, k_lo, k_hi, p.a_rs == 1, p.b_cs == 1, loadA, loadB);
+  t.run_pf(sm, k_lo, k_hi, p.a_rs == 1, p.b_cs == 1, addrA, addrB, fixA, fixB);
 
   double2* C = p.C + b * p.c_bs;
   t.store([&](int mm, int nn, double2 acc) {
