@@ -225,6 +225,7 @@ size_t build_workspace_fp64(const bse_desc* d) {
   L.add(full ? P * R2 * d->ng * 16 : 0);         // T_ra
   L.add(P * R1 * N1 * 16);                       // blk_rr
   L.add(full ? P * R2 * R2 * 16 : 0);            // blk_ra
+  L.add((int64_t)split_w_bytes(d->nk, d->ng));   // W split for the precision form
   return L.total;
 }
 
@@ -250,6 +251,7 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   double2* T_ra = (double2*)L.add(full ? P * R2 * ng * 16 : 0);
   double2* blk_rr = (double2*)L.add(P * R1 * N1 * 16);
   double2* blk_ra = (double2*)L.add(full ? P * R2 * R2 * 16 : 0);
+  void* Wsp = L.add((int64_t)split_w_bytes(nk, ng));
   (void)cls_ra;
 
   // class sorts
@@ -261,6 +263,11 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
 
   const int prec = d->prec;
   const int nterms = d->split_terms == 0 ? 6 : d->split_terms;
+  // the precision form splits W once per build; its buffer holds nk slices
+  if (prec != BSE_PREC_FP64) {
+    if (nq > nk) return BSE_ERR_ARG;
+    if (!launch_split_w(prec, (const double2*)in->W, nq, ng, Wsp, s)) return BSE_ERR_HIP;
+  }
   // exchange: out0 (upper) = alpha * conj(Mcv) diag(vbar) Mcv^T
   const double ex_alpha = (full ? 4.0 : 2.0) * gx * kap;
   if (prec != BSE_PREC_FP64) {
@@ -295,13 +302,13 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   auto direct = [&](const void* left, int R, const void* right, int N2, const int32_t* perm,
                     const int32_t* cls, double2* T, double2* blk) -> bool {
     if (prec != BSE_PREC_FP64) {
-      return launch_stage1_lp(prec, nterms, (const double2*)left, R, ng, (const double2*)in->W,
-                              perm, cls, nq, nk, T, info, s) &&
-             launch_batched_lp(prec, nterms, T, R, ng, (const double2*)right, N2, perm, (int)P,
-                               blk, info, s);
-    }
-    if (!launch_stage1((const double2*)left, R, ng, (const double2*)in->W, perm, cls, nq, nk, T,
-                       info, s)) {
+      // stage 1 in the precision form; stage 2 (R x ng x N2 per pair, memory-bound)
+      // runs in FP64 below
+      if (!launch_stage1_lp(prec, nterms, (const double2*)left, R, ng, Wsp, perm, cls, nq, nk, T,
+                            info, s))
+        return false;
+    } else if (!launch_stage1((const double2*)left, R, ng, (const double2*)in->W, perm, cls, nq,
+                              nk, T, info, s)) {
       const int tiles = cdiv((int64_t)nk * R, S1_BM);  // a class holds at most nk pairs
       dim3 grid((unsigned)(nq * tiles), (unsigned)cdiv(ng, S1_BN));
       BSE_LAUNCH(k_stage1, grid, dim3(256), 0, s, (const double2*)left, R, ng,

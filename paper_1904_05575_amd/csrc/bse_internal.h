@@ -51,12 +51,11 @@ bool launch_stage1(const double2* left, int R, int ng, const double2* W, const i
                    hipStream_t s);
 
 // gemm_lp.hip: reduced-precision products of the assembly
-bool launch_stage1_lp(int prec, int nterms, const double2* left, int R, int ng, const double2* W,
+size_t split_w_bytes(int nq, int ng);
+bool launch_split_w(int prec, const double2* W, int nq, int ng, void* Wsp, hipStream_t s);
+bool launch_stage1_lp(int prec, int nterms, const double2* left, int R, int ng, const void* Wsp,
                       const int32_t* perm, const int32_t* cls, int nq, int nk, double2* T,
                       const int32_t* info, hipStream_t s);
-bool launch_batched_lp(int prec, int nterms, const double2* A, int M, int K, const double2* B,
-                       int N, const int32_t* bidx, int batch, double2* C, const int32_t* info,
-                       hipStream_t s);
 bool launch_exchange_lp(int prec, int nterms, const double2* Mcv, int n, int ng,
                         const double* vbar, double alpha, double2* C, int64_t ld,
                         const int32_t* info, hipStream_t s);

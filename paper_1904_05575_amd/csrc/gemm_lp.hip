@@ -16,6 +16,7 @@
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -177,78 +178,230 @@ BSE_DEV int lp_row(int r) { return (threadIdx.x >> 6) * 16 + 4 * ((threadIdx.x &
 BSE_DEV int lp_col(int j) { return j * 16 + (threadIdx.x & 15); }
 
 // ---------------------------------------------------------------- stage 1
-template <int PREC, int BN2>
-__global__ __launch_bounds__(256) void k_stage1_lp(const double2* __restrict__ Left, int R, int ng,
-                                                   const double2* __restrict__ W,
+// Real view of W(q) (see stage1.hip), split once per build for the matrix
+// cores: B'(k, n) = row 2g: W[g] as doubles, row 2g+1: i W[g] as doubles.
+//   BF16: planes hi, mid, lo of B', layout [q][plane][n < n2p][k < k2p] (k contiguous,
+//         eight k per lane of the 16x16x32 operand)
+//   FP32: layout [q][k < k2p][n < n2p]
+// zero outside 2 ng.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_split_w(const double2* __restrict__ W, int ng, int n2p,
+                                                 int k2p, void* __restrict__ Wsp) {
+  const int q = blockIdx.y;
+  const double2* __restrict__ Wq = W + (int64_t)q * ng * ng;
+  const int64_t per = (int64_t)n2p * k2p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < per;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int k, n;
+    if constexpr (PREC == BSE_PREC_FP32) { k = (int)(e / n2p); n = (int)(e % n2p); }
+    else { n = (int)(e / k2p); k = (int)(e % k2p); }
+    float v = 0.f;
+    if (k < 2 * ng && n < 2 * ng) {
+      const double2 w = Wq[(int64_t)(k >> 1) * ng + (n >> 1)];
+      const double d = (k & 1) ? ((n & 1) ? w.x : -w.y) : ((n & 1) ? w.y : w.x);
+      v = (float)d;
+    }
+    if constexpr (PREC == BSE_PREC_FP32) {
+      ((float*)Wsp)[(int64_t)q * per + e] = v;
+    } else {
+      unsigned short* o = (unsigned short*)Wsp + (int64_t)q * 3 * per;
+      const unsigned short h = bf16_rne(v);
+      const float r1 = v - bf16_to_f(h);
+      const unsigned short m = bf16_rne(r1);
+      const unsigned short l = bf16_rne(r1 - bf16_to_f(m));
+      o[e] = h;
+      o[per + e] = m;
+      o[2 * per + e] = l;
+    }
+  }
+}
+
+// T[pos*R + sub, G'] = sum_G conj(L[p][sub][G]) W[q][G][G'] in the precision
+// form: 64 rows x all n2p real columns per block of 8 wavefronts (4 row groups
+// x 2 column halves of 8 tiles).  Each wavefront loads and splits its own A
+// fragments (eight consecutive real k per lane); the block stages the split
+// W(q) through two LDS buffers, one 32-deep slice ahead in registers.  FP32
+// accumulation inside a slice (16 complex k), FP64 across slices.
+constexpr int S1L_BM = 64, S1L_KS = 32, S1L_NMAX = 256;
+template <int PREC>
+struct S1LSmem;
+template <>
+struct alignas(16) S1LSmem<BSE_PREC_BF16X3> {
+  unsigned short b[2][3][S1L_NMAX][S1L_KS + 8];
+};
+template <>
+struct alignas(16) S1LSmem<BSE_PREC_FP32> {
+  float b[2][S1L_KS][S1L_NMAX + 4];
+};
+
+template <int PREC>
+__global__ __launch_bounds__(512) void k_stage1_lp(const double2* __restrict__ Left, int R,
+                                                   int ng, const void* __restrict__ Wsp,
+                                                   int n2p, int k2p,
                                                    const int32_t* __restrict__ perm,
                                                    const int32_t* __restrict__ cls,
                                                    int tiles_per_class, int nterms,
-                                                   double2* __restrict__ T, const int32_t* info) {
-  __shared__ LpSmem<PREC, BN2> sm;
+                                                   double2* __restrict__ T,
+                                                   const int32_t* info) {
+  constexpr int NTW = 8;  // column tiles per wavefront
+  __shared__ S1LSmem<PREC> sm;
   if (failed(info)) return;
   const int q = blockIdx.x / tiles_per_class, mt = blockIdx.x % tiles_per_class;
   const int s0 = cls[q], rows = (cls[q + 1] - s0) * R;
-  const int m0 = mt * LBM;
+  const int m0 = mt * S1L_BM;
   if (m0 >= rows) return;
-  const int n0c = blockIdx.y * (BN2 / 2);
-  const double2* __restrict__ Wq = W + (int64_t)q * ng * ng;
-  auto ga = [&](int mm, int k) -> double2 {
-    const int m = m0 + mm;
-    if (m >= rows || k >= ng) return make_double2(0.0, 0.0);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int rg = wid & 3, hf = wid >> 2, g = lane >> 4, l16 = lane & 15;
+  const int ntiles = n2p / 16;
+  const int64_t per = (int64_t)n2p * k2p;
+  const int nslices = k2p / S1L_KS;
+
+  // this lane's A row (clamped inside the class; masked at the store)
+  const int mrow = m0 + rg * 16 + l16;
+  const bool row_ok = mrow < rows;
+  const double2* arow;
+  {
+    const int m = row_ok ? mrow : m0;
     const int64_t p = perm[s0 + m / R];
-    const double2 v = Left[(p * R + m % R) * ng + k];
-    return make_double2(v.x, -v.y);
+    arow = Left + (p * R + m % R) * ng;
+  }
+  // slices ahead in registers: complex G = k0/2 + 4g .. +3 of A, 16-byte units of B
+  auto load_a = [&](double2 (&an)[4], int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) an[t] = arow[min(k0 / 2 + 4 * g + t, ng - 1)];
   };
-  auto gb = [&](int k, int nc) -> double2 {
-    const int n = n0c + nc;
-    if (k >= ng || n >= ng) return make_double2(0.0, 0.0);
-    return Wq[(int64_t)k * ng + n];
+  // W(q) slice in 16-byte units over the whole LDS buffer (S1L_NMAX columns), so
+  // that every thread moves the same number of units without a condition;
+  // columns past n2p repeat column n2p-1 and are never read
+  constexpr int UNITS = (PREC == BSE_PREC_FP32) ? S1L_KS * S1L_NMAX / 4 : 3 * S1L_NMAX * S1L_KS / 8;
+  constexpr int UPT = UNITS / 512;
+  static_assert(UPT * 512 == UNITS, "slice units");
+  auto load_b = [&](u32x4 (&bn)[UPT], int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+      const int e = tid + 512 * u;
+      if constexpr (PREC == BSE_PREC_FP32) {
+        const int kk = e / (S1L_NMAX / 4), c4 = min(e % (S1L_NMAX / 4), n2p / 4 - 1);
+        const int64_t off = (int64_t)q * per + (int64_t)(k0 + kk) * n2p + 4 * c4;  // floats
+        bn[u] = *(const u32x4*)((const float*)Wsp + off);
+      } else {
+        const int seg = e & 3, row = e >> 2;  // row = plane * S1L_NMAX + n
+        const int plane = row / S1L_NMAX, nn = min(row % S1L_NMAX, n2p - 1);
+        const int64_t off =
+            (int64_t)q * 3 * per + (int64_t)plane * per + (int64_t)nn * k2p + k0 + 8 * seg;
+        bn[u] = *(const u32x4*)((const unsigned short*)Wsp + off);
+      }
+    }
   };
-  double acc64[BN2 / 16][4];
-  lp_gemm<PREC, BN2>(sm, ng, nterms, ga, gb, acc64);
+  auto store_b = [&](const u32x4 (&bn)[UPT], int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+      const int e = tid + 512 * u;
+      if constexpr (PREC == BSE_PREC_FP32) {
+        const int kk = e / (S1L_NMAX / 4), c4 = e % (S1L_NMAX / 4);
+        *(u32x4*)&sm.b[buf][kk][4 * c4] = bn[u];
+      } else {
+        const int seg = e & 3, row = e >> 2;
+        *(u32x4*)&sm.b[buf][row / S1L_NMAX][row % S1L_NMAX][8 * seg] = bn[u];
+      }
+    }
+  };
+
+  double acc64[NTW][4];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[j][r] = 0.0;
+
+  // one slice: stage its W part, split its A part, start the loads of the slice
+  // two ahead into the register set just freed, multiply
+  auto slice = [&](int sl, double2 (&ac)[4], u32x4 (&bc)[UPT]) __attribute__((always_inline)) {
+    const int buf = sl & 1, k0 = sl * S1L_KS;
+    store_b(bc, buf);
+    float ak[8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bool ok = row_ok && (k0 / 2 + 4 * g + t) < ng;
+      ak[2 * t] = ok ? (float)ac[t].x : 0.f;
+      ak[2 * t + 1] = ok ? (float)(-ac[t].y) : 0.f;
+    }
+    __syncthreads();
+    {  // unconditional (clamped to the last slice) so that waits stay counted
+      const int kn = min(k0 + 2 * S1L_KS, k2p - S1L_KS);
+      load_a(ac, kn);
+      load_b(bc, kn);
+    }
+    f4 acc[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (PREC == BSE_PREC_FP32) {
+      const float* brow = &sm.b[buf][8 * g][16 * hf * NTW + l16];
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        if (hf * NTW + j < ntiles) {
+          f4 c = acc[j];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(ak[t], brow[t * (S1L_NMAX + 4) + 16 * j], c, 0,
+                                                     0, 0);
+          acc[j] = c;
+        }
+      }
+    } else {
+      unsigned short hs[8], ms[8], ls[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        hs[t] = bf16_rne(ak[t]);
+        const float r1 = ak[t] - bf16_to_f(hs[t]);
+        ms[t] = bf16_rne(r1);
+        ls[t] = bf16_rne(r1 - bf16_to_f(ms[t]));
+      }
+      const bf8 ah = __builtin_bit_cast(bf8, hs), am = __builtin_bit_cast(bf8, ms),
+                al = __builtin_bit_cast(bf8, ls);
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        const int tj = hf * NTW + j;
+        if (tj < ntiles) {
+          const int col = 16 * tj + l16;
+          const bf8 bh = ld_bf8(&sm.b[buf][0][col][8 * g]);
+          const bf8 bm = ld_bf8(&sm.b[buf][1][col][8 * g]);
+          f4 c = acc[j];
+          if (nterms >= 6) {
+            const bf8 bl = ld_bf8(&sm.b[buf][2][col][8 * g]);
+            // small terms first so that they are not absorbed by the large one
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+          }
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+          acc[j] = c;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[j][r] += (double)acc[j][r];
+  };
+  double2 a0[4], a1[4];
+  u32x4 bs0[UPT], bs1[UPT];
+  load_a(a0, 0);
+  load_b(bs0, 0);
+  load_a(a1, min(S1L_KS, k2p - S1L_KS));
+  load_b(bs1, min(S1L_KS, k2p - S1L_KS));
+  for (int sl = 0; sl < nslices; sl += 2) {
+    slice(sl, a0, bs0);
+    if (sl + 1 < nslices) slice(sl + 1, a1, bs1);
+  }
   double* Td = (double*)T;
 #pragma unroll
-  for (int j = 0; j < BN2 / 16; ++j)
+  for (int j = 0; j < NTW; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = m0 + lp_row(r), n2 = 2 * n0c + lp_col(j);
+      const int m = m0 + rg * 16 + 4 * g + r, n2 = 16 * (hf * NTW + j) + l16;
       if (m < rows && n2 < 2 * ng) Td[((int64_t)s0 * R + m) * (2 * ng) + n2] = acc64[j][r];
-    }
-}
-
-// ---------------------------------------------------------------- batched stage 2
-// blk[b] (M x N) = T[b] (M x K) x Right[perm[b]]^T, Right[p] stored (N x K)
-template <int PREC, int BN2>
-__global__ __launch_bounds__(256) void k_batched_lp(const double2* __restrict__ A, int M, int K,
-                                                    const double2* __restrict__ Bm, int N,
-                                                    const int32_t* __restrict__ bidx, int nterms,
-                                                    double2* __restrict__ C, int b_off,
-                                                    const int32_t* info) {
-  __shared__ LpSmem<PREC, BN2> sm;
-  if (failed(info)) return;
-  const int b = blockIdx.z + b_off;
-  const int m0 = blockIdx.x * LBM, n0c = blockIdx.y * (BN2 / 2);
-  const double2* __restrict__ Ab = A + (int64_t)b * M * K;
-  const double2* __restrict__ Bb = Bm + (int64_t)bidx[b] * N * K;
-  auto ga = [&](int mm, int k) -> double2 {
-    const int m = m0 + mm;
-    if (m >= M || k >= K) return make_double2(0.0, 0.0);
-    return Ab[(int64_t)m * K + k];
-  };
-  auto gb = [&](int k, int nc) -> double2 {
-    const int n = n0c + nc;
-    if (k >= K || n >= N) return make_double2(0.0, 0.0);
-    return Bb[(int64_t)n * K + k];
-  };
-  double acc64[BN2 / 16][4];
-  lp_gemm<PREC, BN2>(sm, K, nterms, ga, gb, acc64);
-  double* Cd = (double*)(C + (int64_t)b * M * N);
-#pragma unroll
-  for (int j = 0; j < BN2 / 16; ++j)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + lp_row(r), n2 = 2 * n0c + lp_col(j);
-      if (m < M && n2 < 2 * N) Cd[(int64_t)m * (2 * N) + n2] = acc64[j][r];
     }
 }
 
@@ -294,33 +447,36 @@ __global__ __launch_bounds__(256) void k_exchange_lp(const double2* __restrict__
 
 }  // namespace
 
-bool launch_stage1_lp(int prec, int nterms, const double2* left, int R, int ng, const double2* W,
-                      const int32_t* perm, const int32_t* cls, int nq, int nk, double2* T,
-                      const int32_t* info, hipStream_t s) {
-  const int tiles = cdiv((int64_t)nk * R, LBM);
-  dim3 grid((unsigned)(nq * tiles), (unsigned)cdiv(ng, 32));
+int lp_n2p(int ng) { return (2 * ng + 15) / 16 * 16; }
+int lp_k2p(int ng) { return (2 * ng + S1L_KS - 1) / S1L_KS * S1L_KS; }
+
+size_t split_w_bytes(int nq, int ng) {
+  return (size_t)nq * 3 * lp_n2p(ng) * lp_k2p(ng) * 2;  // the larger of the two layouts
+}
+
+bool launch_split_w(int prec, const double2* W, int nq, int ng, void* Wsp, hipStream_t s) {
+  const int n2p = lp_n2p(ng), k2p = lp_k2p(ng);
+  dim3 grid((unsigned)std::min(64, cdiv((int64_t)n2p * k2p, 256)), (unsigned)nq);
   if (prec == BSE_PREC_FP32)
-    BSE_LAUNCH((k_stage1_lp<BSE_PREC_FP32, 64>), grid, dim3(256), 0, s, left, R, ng, W, perm, cls,
-               tiles, nterms, T, info);
+    BSE_LAUNCH((k_split_w<BSE_PREC_FP32>), grid, dim3(256), 0, s, W, ng, n2p, k2p, Wsp);
   else
-    BSE_LAUNCH((k_stage1_lp<BSE_PREC_BF16X3, 64>), grid, dim3(256), 0, s, left, R, ng, W, perm,
-               cls, tiles, nterms, T, info);
+    BSE_LAUNCH((k_split_w<BSE_PREC_BF16X3>), grid, dim3(256), 0, s, W, ng, n2p, k2p, Wsp);
   return hipGetLastError() == hipSuccess;
 }
 
-bool launch_batched_lp(int prec, int nterms, const double2* A, int M, int K, const double2* B,
-                       int N, const int32_t* bidx, int batch, double2* C, const int32_t* info,
-                       hipStream_t s) {
-  for (int b0 = 0; b0 < batch; b0 += 65535) {
-    const int nb = std::min(65535, batch - b0);
-    dim3 grid((unsigned)cdiv(M, LBM), (unsigned)cdiv(N, 32), (unsigned)nb);
-    if (prec == BSE_PREC_FP32)
-      BSE_LAUNCH((k_batched_lp<BSE_PREC_FP32, 64>), grid, dim3(256), 0, s, A, M, K, B, N, bidx,
-                 nterms, C, b0, info);
-    else
-      BSE_LAUNCH((k_batched_lp<BSE_PREC_BF16X3, 64>), grid, dim3(256), 0, s, A, M, K, B, N, bidx,
-                 nterms, C, b0, info);
-  }
+bool launch_stage1_lp(int prec, int nterms, const double2* left, int R, int ng, const void* Wsp,
+                      const int32_t* perm, const int32_t* cls, int nq, int nk, double2* T,
+                      const int32_t* info, hipStream_t s) {
+  const int n2p = lp_n2p(ng), k2p = lp_k2p(ng);
+  if (n2p > S1L_NMAX) return false;
+  const int tiles = cdiv((int64_t)nk * R, S1L_BM);
+  dim3 grid((unsigned)(nq * tiles));
+  if (prec == BSE_PREC_FP32)
+    BSE_LAUNCH((k_stage1_lp<BSE_PREC_FP32>), grid, dim3(512), 0, s, left, R, ng, Wsp, n2p, k2p,
+               perm, cls, tiles, nterms, T, info);
+  else
+    BSE_LAUNCH((k_stage1_lp<BSE_PREC_BF16X3>), grid, dim3(512), 0, s, left, R, ng, Wsp, n2p, k2p,
+               perm, cls, tiles, nterms, T, info);
   return hipGetLastError() == hipSuccess;
 }
 

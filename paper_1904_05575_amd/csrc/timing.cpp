@@ -38,6 +38,7 @@ bool timing_on() { return enabled; }
 
 void timing_begin(const char* name, hipStream_t s) {
   std::lock_guard<std::mutex> g(mu);
+  while (*name == '(') ++name;  // launch macros may parenthesise template names
   std::string base(name, strcspn(name, "<"));
   if (!only.empty() && only != base) {
     recs.push_back(Rec{std::move(base), nullptr, nullptr});
