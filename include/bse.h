@@ -62,15 +62,20 @@ typedef enum { BSE_TDA = 0, BSE_FULL = 1 } bse_coupling;
  * singlet (1,1), triplet (0,1), RPA (1,0), independent particles (0,0). */
 typedef enum { BSE_SINGLET = 0, BSE_TRIPLET = 1, BSE_RPA = 2, BSE_IP = 3 } bse_type;
 
-/* Arithmetic of the kernel assembly (exchange and both direct terms); the
- * solve is always FP64.
- *  FP64   : FP64 matrix-core products.
- *  FP32   : operands rounded to FP32, FP32 products and accumulation inside
+/* Arithmetic of the kernel assembly; the solve is always FP64.
+ *  FP64   : FP64 matrix-core products throughout.
+ *  FP32   : the exchange term and the W contraction of both direct terms
+ *           (eqs. wrrm, wrabar: conj(M) W(q), 85% of the assembly flops) use
+ *           operands rounded to FP32, FP32 products and accumulation inside
  *           chunks of 16 complex terms, FP64 accumulation across chunks.
- *  BF16X3 : operands rounded to FP32 and split into three BF16 terms
+ *  BF16X3 : as FP32, with operands split into three BF16 terms
  *           (hi + mid + lo); split_terms = 6 (default) keeps the products
  *           hi*hi, hi*mid, mid*hi, hi*lo, lo*hi, mid*mid, split_terms = 3 the
- *           first three; FP32 accumulation inside chunks, FP64 across. */
+ *           first three.
+ * The per-pair second contraction of the direct terms (R x N_G x R' per
+ * k-pair, memory-bound) runs in FP64 in every mode.  The reduced modes split
+ * W once per call into a part of the BUILD workspace sized for nk slices, so
+ * they require nq <= nk (else BSE_ERR_ARG). */
 typedef enum { BSE_PREC_FP64 = 0, BSE_PREC_FP32 = 1, BSE_PREC_BF16X3 = 2 } bse_precision;
 
 typedef enum { BSE_STAGE_BUILD = 0, BSE_STAGE_SOLVE = 1 } bse_stage;

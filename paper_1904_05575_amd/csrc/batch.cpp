@@ -112,6 +112,7 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
         !in->qmap || in->nq <= 0 || in->nq > kMaxQ)
       return BSE_ERR_ARG;
     if (!(eta[i] > 0.0)) return BSE_ERR_ARG;
+    if (d->prec != BSE_PREC_FP64 && in->nq > d->nk) return BSE_ERR_ARG;
   }
   release(b);
   const bool was_timing = timing_on();
