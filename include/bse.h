@@ -191,6 +191,41 @@ void bse_batch_destroy(bse_batch_t batch);
 void bse_timing_enable(int32_t on, const char* name);
 int64_t bse_timing_report(char* buf, int64_t len);
 
+/* Tuning table: the output of the project's autotuner
+ * (paper_1904_05575_amd/tune.py, run on the GPU).  Each entry selects, for one
+ * call site and for sizes up to size_max, a tile choice:
+ *   BSE_TUNE_HEMV_UNIT     size = trailing order m of a Householder step;
+ *                          choice = panels of 64 columns per work unit of the
+ *                          Hermitian matrix-vector kernel: 1, 2, 4 or 8
+ *   BSE_TUNE_GEMM_*        size = problem order n; choice = GEMM tile edge
+ *                          16, 32 or 64 (squared form S = U (A+B) U^H; Cholesky
+ *                          trailing updates; Householder panel updates; the
+ *                          second contraction of the direct terms; exchange)
+ * Among the entries of a site, the one with the smallest size_max >= size
+ * applies; sizes no entry covers use built-in rules.  Every choice gives the
+ * same results up to rounding order.  The table is read on the host when work
+ * is enqueued (a captured graph keeps the choices of its capture).
+ * bse_tune_set copies `count` entries from HOST memory (count 0 clears the
+ * table; BSE_ERR_ARG for an unknown site or choice, nothing changed).
+ * bse_tune_get copies at most `cap` entries into HOST memory `out` (may be
+ * NULL) and returns the number in the table. */
+enum {
+  BSE_TUNE_HEMV_UNIT = 0,
+  BSE_TUNE_GEMM_SQUARED = 1,
+  BSE_TUNE_GEMM_POTRF = 2,
+  BSE_TUNE_GEMM_HER2K = 3,
+  BSE_TUNE_GEMM_STAGE2 = 4,
+  BSE_TUNE_GEMM_EXCHANGE = 5
+};
+typedef struct {
+  int32_t site;
+  int32_t size_max;
+  int32_t choice;
+  int32_t reserved;
+} bse_tune_entry;
+bse_status bse_tune_set(const bse_tune_entry* entries, int32_t count);
+int32_t bse_tune_get(bse_tune_entry* out, int32_t cap);
+
 /* Human-readable name of a status. */
 const char* bse_status_string(bse_status status);
 

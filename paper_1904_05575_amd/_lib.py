@@ -20,7 +20,9 @@ STATUS = {0: "BSE_OK", 1: "BSE_ERR_ARG", 2: "BSE_ERR_WORKSPACE", 3: "BSE_ERR_HIP
 EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bse_spectrum",
            "bse_status_string", "bse_timing_enable", "bse_timing_report",
            "bse_batch_workspace_size", "bse_batch_create", "bse_batch_capture", "bse_batch_run",
-           "bse_batch_destroy")
+           "bse_batch_destroy", "bse_tune_set", "bse_tune_get")
+TUNE_SITES = {"hemv_unit": 0, "gemm_squared": 1, "gemm_potrf": 2, "gemm_her2k": 3,
+              "gemm_stage2": 4, "gemm_exchange": 5}
 
 
 class BseDesc(ctypes.Structure):
@@ -37,6 +39,11 @@ class BseInputs(ctypes.Structure):
                 ("Ncv", ctypes.c_void_p), ("Nvc", ctypes.c_void_p), ("W", ctypes.c_void_p),
                 ("vbar", ctypes.c_void_p), ("qmap", ctypes.c_void_p), ("qramap", ctypes.c_void_p),
                 ("nq", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BseTuneEntry(ctypes.Structure):
+    _fields_ = [("site", ctypes.c_int32), ("size_max", ctypes.c_int32),
+                ("choice", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BseError(RuntimeError):
@@ -84,6 +91,10 @@ def lib() -> ctypes.CDLL:
         L.bse_batch_run.restype = ctypes.c_int
         L.bse_batch_destroy.argtypes = [vp]
         L.bse_batch_destroy.restype = None
+        L.bse_tune_set.argtypes = [ctypes.POINTER(BseTuneEntry), i32]
+        L.bse_tune_set.restype = ctypes.c_int
+        L.bse_tune_get.argtypes = [ctypes.POINTER(BseTuneEntry), i32]
+        L.bse_tune_get.restype = i32
         L.bse_status_string.argtypes = [ctypes.c_int]
         L.bse_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -173,3 +184,17 @@ def bse_batch_run(batch: int, stream: int) -> None:
 
 def bse_batch_destroy(batch: int) -> None:
     lib().bse_batch_destroy(batch)
+
+
+def bse_tune_set(entries) -> None:
+    """entries: iterable of (site, size_max, choice); an empty list clears the table."""
+    entries = list(entries)
+    arr = (BseTuneEntry * max(1, len(entries)))(*[BseTuneEntry(s, m, c, 0) for s, m, c in entries])
+    _check(lib().bse_tune_set(arr, len(entries)), "bse_tune_set")
+
+
+def bse_tune_get() -> list:
+    n = int(lib().bse_tune_get(None, 0))
+    arr = (BseTuneEntry * max(1, n))()
+    lib().bse_tune_get(arr, n)
+    return [(arr[i].site, arr[i].size_max, arr[i].choice) for i in range(n)]

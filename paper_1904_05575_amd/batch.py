@@ -14,6 +14,8 @@ from .bse import (PRECISIONS, TYPES, _dev, coulomb_v0, coulomb_vbar, g_index_of_
 class Batch:
     def __init__(self, members: list, precision: str = "fp64", nbranch: int = 4,
                  bse_type: str = "singlet", device: str = "cuda"):
+        from . import tune
+        tune.load()  # the autotuner's tile choices, when a table is present
         dv = self.device = torch.device(device)
         c128, f64 = torch.complex128, torch.float64
         self.members = members

@@ -59,6 +59,8 @@ class Problem:
 
     def __init__(self, inputs: dict, bse_type: str = "singlet", device: str = "cuda",
                  precision: str = "fp64"):
+        from . import tune
+        tune.load()  # the autotuner's tile choices, when a table is present
         w = inputs["workload"]
         self.workload = w
         self.device = torch.device(device)

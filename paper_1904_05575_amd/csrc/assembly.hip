@@ -295,6 +295,7 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
     g.c_uplo = 1;
     g.info = info;
     g.tag = "zgemm_exchange";
+    g.tile = tune_choice(BSE_TUNE_GEMM_EXCHANGE, n, 0);
     if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
   }
 
@@ -333,6 +334,7 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
     g.c_bs = (int64_t)R * N2;
     g.info = info;
     g.tag = "zgemm_direct_stage2";
+    g.tile = tune_choice(BSE_TUNE_GEMM_STAGE2, n, 0);
     return zgemm(g, (int)P, s) == hipSuccess;
   };
   if (!direct(in->Mvv, (int)R1, in->Mcc, (int)N1, perm_rr, cls_rr, T_rr, blk_rr)) return BSE_ERR_HIP;

@@ -60,6 +60,9 @@ bool launch_exchange_lp(int prec, int nterms, const double2* Mcv, int n, int ng,
                         const double* vbar, double alpha, double2* C, int64_t ld,
                         const int32_t* info, hipStream_t s);
 
+// tune.cpp: tile choice for a call site and size (deflt when no entry applies)
+int tune_choice(int site, int64_t size, int deflt);
+
 // solve.hip
 void launch_zero_ints(int32_t* p, int n, hipStream_t s);
 size_t solve_workspace(const bse_desc* d);

@@ -40,7 +40,8 @@ constexpr int NVAL = 2 + 2 * TRD_NB;  // |x|^2, conj(x) y_probe, V^H x (i), W^H 
 //   Y[k][r]        k = 0 .. cdiv(Ir + 1, K) - 1  (unit (k, Ir): S v over its panels)
 //   Y[ycs + I][r]  I = Ir .. nI - 1              (tile (I, Ir): S_{I,Ir}^H v_I)
 // i.e. nrs + nI - Ir slots with nrs = cdiv(Ir + 1, K).
-__host__ __device__ inline int hemv_k(int nI) { return nI >= 48 ? 4 : (nI >= 24 ? 2 : 1); }
+// Built-in unit width (panels per unit) for nI tile-rows; a tuning table entry may replace it.
+inline int hemv_k_default(int nI) { return nI >= 48 ? 4 : (nI >= 24 ? 2 : 1); }
 __host__ __device__ inline int hemv_punits(int j, int nI, int K) {
   return j * nI - K * (j * (j - 1) / 2);
 }
@@ -93,7 +94,7 @@ BSE_DEV double wave_total63(double v) {
 __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     double2* __restrict__ M, int64_t ld, int n, double2* __restrict__ VW, double2* __restrict__ WV,
     int j0, int i, int has_new, const double2* __restrict__ hs, const double2* __restrict__ Y,
-    int ycs, double2* __restrict__ partA, const double2* __restrict__ partB,
+    int ycs, int kprev, double2* __restrict__ partA, const double2* __restrict__ partB,
     double2* __restrict__ yp) {
   constexpr int QP = COL_THREADS / ROWS_A;        // threads sharing one row
   constexpr int PER = TRD_NB / QP;                // panel columns per thread
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   if (tid < 2 * TRD_NB && tid % TRD_NB < i - 1) svw[tid] = hs[HS_SVV + tid];
   // y_{c-1}[r]: the previous hemv kernel's slots, QP threads per row
   const int nIp = i > 0 ? cdiv(n - c, HT) : 0;
-  const int Kp = i > 0 ? hemv_k(nIp) : 1;
+  const int Kp = kprev;  // unit width of the hemv launch that produced the slots
   double2 yq = make_double2(0.0, 0.0);
   if (i > 0 && act) {
     const int Ir = (r - c) / HT, nrs = cdiv(Ir + 1, Kp), tot = nrs + nIp - Ir;
@@ -350,8 +351,9 @@ BSE_DEV double row16_sum(double v) {
 __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     const double2* __restrict__ M, int64_t ld, int n, const double2* __restrict__ VW, int j0,
     int i, double2* __restrict__ hs, const double2* __restrict__ partA,
-    double2* __restrict__ partB, double2* __restrict__ Y, int ycs, double* __restrict__ dd,
-    double* __restrict__ ee, double2* __restrict__ tau, const double2* __restrict__ yp) {
+    double2* __restrict__ partB, double2* __restrict__ Y, int ycs, int K,
+    double* __restrict__ dd, double* __restrict__ ee, double2* __restrict__ tau,
+    const double2* __restrict__ yp) {
   constexpr int NW = HV_THREADS / 64;     // 16 wavefronts
   constexpr int NL = 4;                   // matrix loads per lane per tile
   constexpr int SLC = HV_THREADS / 128;
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   const int c = j0 + i, b0 = c + 1;
   const int64_t N = n;
   const int m = n - b0;
-  const int nI = cdiv(m, HT), K = hemv_k(nI), nunits = hemv_units(nI, K);
+  const int nI = cdiv(m, HT), nunits = hemv_units(nI, K);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;  // row in slab, column group
   const int jl = 4 * wid + lg;               // this lane's tile column
@@ -597,7 +599,13 @@ int64_t hemv_tiles_max(int64_t n) {
   return nI * (nI + 1) / 2;
 }
 
-int hemv_grid(int64_t m) {
+// Units per hemv work item for a trailing matrix of order m.
+int hemv_unit(int64_t m) {
+  const int nI = (int)((m + HT - 1) / HT);
+  return tune_choice(BSE_TUNE_HEMV_UNIT, m, hemv_k_default(nI));
+}
+
+int hemv_grid(int64_t m, int K) {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
@@ -607,7 +615,7 @@ int hemv_grid(int64_t m) {
       cus = 256;
   }
   const int nI = (int)((m + HT - 1) / HT);
-  return std::min(hemv_units(nI, hemv_k(nI)), cus);
+  return std::min(hemv_units(nI, K), cus);
 }
 
 }  // namespace
@@ -625,6 +633,7 @@ bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t
   double2* partB = w.part + ((n + ROWS_A - 1) / ROWS_A + 1) * NVAL;
   double2* Y = partB + hemv_tiles_max(n) + 1;
   const int ycs = (int)ycs_of(n);
+  int kprev = 1;  // unit width of the last hemv launch (read by the next column kernel)
   for (int64_t j0 = 0; j0 < n - 1; j0 += TRD_NB) {
     const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
     if (jb < TRD_NB)
@@ -632,14 +641,16 @@ bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t
     for (int i = 0; i < jb; ++i) {
       const int64_t c = j0 + i, m = n - c - 1;
       BSE_LAUNCH(k_trd_col, dim3(cdiv(n - c, ROWS_A)), dim3(COL_THREADS), 0, s, M, ld, (int)n, w.VW,
-                 w.WV, (int)j0, i, 1, w.hs, Y, ycs, partA, partB, w.yproj);
-      BSE_LAUNCH(k_trd_hemv, dim3(hemv_grid(m)), dim3(HV_THREADS), 0, s, M, ld, (int)n, w.VW,
-                 (int)j0, i, w.hs, partA, partB, Y, ycs, w.dd, w.ee, w.tau, w.yproj);
+                 w.WV, (int)j0, i, 1, w.hs, Y, ycs, kprev, partA, partB, w.yproj);
+      const int K = hemv_unit(m);
+      BSE_LAUNCH(k_trd_hemv, dim3(hemv_grid(m, K)), dim3(HV_THREADS), 0, s, M, ld, (int)n, w.VW,
+                 (int)j0, i, w.hs, partA, partB, Y, ycs, K, w.dd, w.ee, w.tau, w.yproj);
+      kprev = K;
     }
     // finish the panel's last reflector
     const int64_t cl = j0 + jb;
     BSE_LAUNCH(k_trd_col, dim3(cdiv(n - cl, ROWS_A)), dim3(COL_THREADS), 0, s, M, ld, (int)n,
-               w.VW, w.WV, (int)j0, jb, 0, w.hs, Y, ycs, partA, partB, w.yproj);
+               w.VW, w.WV, (int)j0, jb, 0, w.hs, Y, ycs, kprev, partA, partB, w.yproj);
     const int64_t t = j0 + jb;
     if (t < n) {
       ZgemmParams g;  // S[t:, t:] -= [V W] [W V]^H
@@ -661,6 +672,7 @@ bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t
       g.beta = 1.0;
       g.info = info;
       g.tag = "zgemm_her2k";
+      g.tile = tune_choice(BSE_TUNE_GEMM_HER2K, n, 0);
       if (zgemm(g, 1, s) != hipSuccess) return false;
     }
   }

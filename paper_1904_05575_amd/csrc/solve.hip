@@ -669,6 +669,7 @@ bool cholesky(double2* H1, int64_t n, int64_t ld, int32_t* info, hipStream_t s) 
     h.c_uplo = 1;
     h.info = info;
     h.tag = "zgemm_potrf_herk";
+    h.tile = tune_choice(BSE_TUNE_GEMM_POTRF, n, 0);
     if (zgemm(h, 1, s) != hipSuccess) return false;
   }
   return true;
@@ -781,6 +782,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
     a.c_cs = n;
     a.info = info;
     a.tag = "zgemm_sq_t1";
+    a.tile = tune_choice(BSE_TUNE_GEMM_SQUARED, n, 0);
     if (zgemm(a, 1, s) != hipSuccess) return BSE_ERR_HIP;
     ZgemmParams b;  // S (lower) = U T1  -> H0
     b.M = (int)n;
@@ -799,6 +801,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
     b.c_uplo = 2;
     b.info = info;
     b.tag = "zgemm_sq_s";
+    b.tile = tune_choice(BSE_TUNE_GEMM_SQUARED, n, 0);
     if (zgemm(b, 1, s) != hipSuccess) return BSE_ERR_HIP;
     const int nt = cdiv(n, 32);
     BSE_LAUNCH(k_hermitize, dim3(nt, nt), dim3(256), 0, s, H0, n, ld, 1, info);

@@ -28,6 +28,7 @@ struct ZgemmParams {
   const double* kscale = nullptr;  // A(m,k) *= kscale[k]
   const int32_t* info = nullptr;   // skip all work when *info != 0
   const char* tag = "zgemm";        // name under which the launch is timed
+  int tile = 0;                     // 16, 32 or 64: tile edge; 0: chosen from the shape
 };
 
 // Enqueue `batch` products on `stream`.

@@ -90,6 +90,9 @@ hipError_t launch(const ZgemmParams& p, int batch, hipStream_t s) {
 
 hipError_t zgemm(const ZgemmParams& p, int batch, hipStream_t s) {
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
+  if (p.tile == 16) return launch<16, 16, 1, 1>(p, batch, s);
+  if (p.tile == 32) return launch<32, 32, 2, 2>(p, batch, s);
+  if (p.tile == 64) return launch<64, 64, 2, 2>(p, batch, s);
   if (p.M <= 16 && p.N <= 16) return launch<16, 16, 1, 1>(p, batch, s);
   if (p.M <= 32 || p.N <= 32 || (int64_t)cdiv(p.M, 64) * cdiv(p.N, 64) * batch < 512)
     return launch<32, 32, 2, 2>(p, batch, s);

@@ -1,0 +1,142 @@
+"""Autotuner of the library's tile choices (run on the GPU; writes a JSON table).
+
+    python -m paper_1904_05575_amd.tune [--out PATH] [--reps 2]
+
+For every tunable call site of the FP64 path (see bse_tune_entry in
+include/bse.h) the tuner builds and solves seeded synthetic problems of the
+batched and single-problem workloads, times the site's kernels with the
+library's per-kernel events under each candidate choice, and keeps the
+fastest:
+  * GEMM tile edge (32 or 64; 16 or 32 for the per-pair second contraction)
+    for the squared form, the Cholesky and Householder trailing updates, the
+    per-pair contraction and the exchange term, per problem order n;
+  * panels per work unit of the Householder hemv kernel (1, 2, 4, 8), per
+    bucket of the trailing order m, on the largest problem.
+`load()` installs the table in the library (Problem and Batch call it once).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+from . import _lib as L
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
+
+GEMM_SITES = {  # site -> (candidates, kernel tags timed)
+    "gemm_squared": ((32, 64), ("zgemm_sq_t1", "zgemm_sq_s")),
+    "gemm_potrf": ((32, 64), ("zgemm_potrf_herk",)),
+    "gemm_her2k": ((32, 64), ("zgemm_her2k",)),
+    "gemm_stage2": ((16, 32), ("zgemm_direct_stage2",)),
+    "gemm_exchange": ((32, 64), ("zgemm_exchange",)),
+}
+HEMV_BUCKETS = (1024, 2048, 3072, 4096, 8192)  # upper bounds of the trailing order m
+HEMV_UNITS = (1, 2, 4, 8)
+HEMV_TAGS = ("k_trd_hemv", "k_trd_col")
+
+_loaded = False
+
+
+def load(path: str | None = None, force: bool = False) -> int:
+    """Install the tuning table (if the file exists); returns the number of entries."""
+    global _loaded
+    if _loaded and not force:
+        return len(L.bse_tune_get())
+    path = path or TABLE
+    _loaded = True
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        tab = json.load(f)
+    entries = [(L.TUNE_SITES[e["site"]], int(e["size_max"]), int(e["choice"]))
+               for e in tab["entries"]]
+    L.bse_tune_set(entries)
+    return len(entries)
+
+
+def _time_sites(P, tags, reps):
+    """Best-of-reps total event time (ms) of the kernels named in tags for build + solve."""
+    import torch
+    best = None
+    for _ in range(reps):
+        H0, H1 = P.alloc_matrices()
+        torch.cuda.synchronize()
+        L.bse_timing_enable(True)
+        P.build(H0, H1)
+        E, _, osc = P.solve(H0, H1)
+        torch.cuda.synchronize()
+        L.bse_timing_enable(False)
+        P.check_info()
+        k = L.bse_timing_report()
+        t = sum(k[name][1] for name in tags if name in k)
+        best = t if best is None else min(best, t)
+        del H0, H1
+    return best
+
+
+def run(out: str, reps: int = 2) -> dict:
+    import torch
+    from bse_synth import BATCHES, get, make_batch_inputs, make_inputs
+    from .bse import Problem
+
+    problems = {}
+    for d in make_batch_inputs(BATCHES["batch16_k6_g89"]):
+        problems.setdefault(d["workload"].n, d)
+    big = make_inputs(get("full_q0_k8_v3c4_g113"))
+    problems[big["workload"].n] = big
+    sizes = sorted(problems)
+    entries, measured = [], {}
+    t0 = time.time()
+    L.bse_tune_set([])
+    for n in sizes:
+        P = Problem(problems[n])
+        for site, (cands, tags) in GEMM_SITES.items():
+            times = {}
+            for c in cands:
+                L.bse_tune_set([(L.TUNE_SITES[site], n, c)])
+                times[c] = _time_sites(P, tags, reps)
+            best = min(times, key=times.get)
+            entries.append({"site": site, "size_max": n, "choice": best})
+            measured[f"{site}@{n}"] = {str(c): round(v, 4) for c, v in times.items()}
+            print(f"[tune] n={n} {site}: {times} -> {best}", file=sys.stderr, flush=True)
+        del P
+        torch.cuda.empty_cache()
+    L.bse_tune_set([])
+    P = Problem(big)
+    lo = 0
+    for hi in HEMV_BUCKETS:
+        if lo >= big["workload"].n:
+            break
+        times = {}
+        for K in HEMV_UNITS:
+            L.bse_tune_set([(L.TUNE_SITES["hemv_unit"], hi, K)])
+            times[K] = _time_sites(P, HEMV_TAGS, reps)
+        best = min(times, key=times.get)
+        entries.append({"site": "hemv_unit", "size_max": hi, "choice": best})
+        measured[f"hemv_unit@m<={hi}"] = {str(k): round(v, 4) for k, v in times.items()}
+        print(f"[tune] m<={hi} hemv_unit: {times} -> {best}", file=sys.stderr, flush=True)
+        lo = hi
+    L.bse_tune_set([])
+    tab = {"device": torch.cuda.get_device_name(0), "entries": entries,
+           "measured_ms": measured, "seconds": round(time.time() - t0, 1),
+           "workloads": {"sizes": sizes, "hemv": big["workload"].name}}
+    with open(out, "w") as f:
+        json.dump(tab, f, indent=1)
+    return tab
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--reps", type=int, default=2)
+    args = ap.parse_args()
+    tab = run(args.out, args.reps)
+    print(json.dumps({"entries": len(tab["entries"]), "seconds": tab["seconds"], "out": args.out}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

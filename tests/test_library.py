@@ -69,3 +69,18 @@ def test_argument_errors_are_reported_without_launching(lib):
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
         L.bse_oscillator(10, 1, 5, 1, 1, 0)                 # ldx < n
     assert lib.bse_status_string(2) == b"workspace too small"
+
+
+def test_tuning_table_round_trip_and_validation(lib):
+    old = L.bse_tune_get()
+    try:
+        L.bse_tune_set([(0, 4096, 4), (1, 6144, 64), (4, 2000, 16)])
+        assert L.bse_tune_get() == [(0, 4096, 4), (1, 6144, 64), (4, 2000, 16)]
+        for bad in ([(0, 4096, 3)], [(1, 6144, 48)], [(9, 10, 32)], [(2, 0, 32)]):
+            with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+                L.bse_tune_set(bad)
+            assert len(L.bse_tune_get()) == 3  # a rejected table changes nothing
+        L.bse_tune_set([])
+        assert L.bse_tune_get() == []
+    finally:
+        L.bse_tune_set(old)
