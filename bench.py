@@ -94,14 +94,18 @@ def cpu_baseline(inputs, w, budget_s: float = 20.0) -> dict:
 
 
 def batched_section(name: str, steps: int) -> dict:
-    """Many momentum transfers in one HIP graph (mixed-precision assembly,
-    concurrent branches) against the per-Q sequential FP64 path."""
+    """Many momentum transfers in one HIP graph (concurrent branches, the
+    autotuner's tile choices, FP64 and mixed-precision assembly) against the
+    per-Q sequential FP64 path with the built-in tile rules."""
     import torch
     from bse_synth import BATCHES, make_batch_inputs
+    from paper_1904_05575_amd import _lib as L
+    from paper_1904_05575_amd import tune
     from paper_1904_05575_amd.batch import Batch
     bw = BATCHES[name]
     members = make_batch_inputs(bw)
     B = Batch(members, precision="fp64", nbranch=4)
+    tuned = L.bse_tune_get()
 
     def timed(fn):
         fn()
@@ -114,8 +118,13 @@ def batched_section(name: str, steps: int) -> dict:
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
+    L.bse_tune_set([])                       # built-in tile rules
     seq_ms = timed(B.run_sequential)
     ref = B.results()
+    graph_builtin_ms = timed(B.run)
+    L.bse_tune_set(tuned)                    # the autotuner's table (captured anew)
+    B.set_precision("fp64")
+    seq_tuned_ms = timed(B.run_sequential)
     graph64_ms = timed(B.run)
     B.set_precision("bf16x6")
     graph_mixed_ms = timed(B.run)
@@ -125,11 +134,15 @@ def batched_section(name: str, steps: int) -> dict:
     spec = max(float(np.abs(m["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max())
                for m, r in zip(mixed, ref))
     B.close()
-    print(f"[bench] batch {name}: sequential fp64 {seq_ms:.1f} ms, graph fp64 {graph64_ms:.1f} ms, "
-          f"graph bf16x6 {graph_mixed_ms:.1f} ms", file=sys.stderr, flush=True)
+    print(f"[bench] batch {name}: sequential fp64 {seq_ms:.1f} ms (tuned {seq_tuned_ms:.1f}), "
+          f"graph fp64 {graph_builtin_ms:.1f} ms (tuned {graph64_ms:.1f}), graph bf16x6 tuned "
+          f"{graph_mixed_ms:.1f} ms", file=sys.stderr, flush=True)
     return {"workload": name, "problems": len(members), "sizes": [m["workload"].n for m in members],
-            "sequential_fp64_ms": seq_ms, "graph_fp64_ms": graph64_ms,
-            "graph_bf16x6_ms": graph_mixed_ms, "speedup_vs_sequential_fp64": seq_ms / graph_mixed_ms,
+            "tuning_entries": len(tuned), "tuning_table": os.path.basename(tune.TABLE),
+            "sequential_fp64_builtin_tiles_ms": seq_ms, "sequential_fp64_tuned_ms": seq_tuned_ms,
+            "graph_fp64_builtin_tiles_ms": graph_builtin_ms, "graph_fp64_tuned_ms": graph64_ms,
+            "graph_bf16x6_tuned_ms": graph_mixed_ms,
+            "speedup_vs_sequential_fp64": seq_ms / graph_mixed_ms,
             "bf16x6_error_vs_fp64": {"eig_rel": eig, "spec_err": spec}, "branches": 4}
 
 
@@ -294,9 +307,10 @@ def main() -> int:
         "build_frac_fp64_peak": value / FP64_PEAK_TFLOPS,
         "roofline": roof,
         "kernels_ms_per_step": kernels_ms,
+        "tile_choices": f"{len(L.bse_tune_get())} autotuner entries (paper_1904_05575_amd/tuning_gfx950.json)",
     }
     if args.batch:
-        out["batched"] = batched_section(args.batch, args.steps)
+        out["batched"] = batched_section(args.batch, min(args.steps, 3))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inputs, w)
     print(json.dumps(out), flush=True)
