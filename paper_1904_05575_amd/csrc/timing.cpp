@@ -36,22 +36,21 @@ hipEvent_t get_event() {
 
 bool timing_on() { return enabled; }
 
-void timing_begin(const char* name, hipStream_t s) {
+void timing_begin(const char* name, hipEvent_t* a, hipEvent_t* b) {
   std::lock_guard<std::mutex> g(mu);
   while (*name == '(') ++name;  // launch macros may parenthesise template names
   std::string base(name, strcspn(name, "<"));
+  *a = *b = nullptr;
   if (!only.empty() && only != base) {
     recs.push_back(Rec{std::move(base), nullptr, nullptr});
     return;
   }
   Rec r{std::move(base), get_event(), get_event()};
-  if (r.a) hipEventRecord(r.a, s);
+  if (r.a && r.b) {
+    *a = r.a;
+    *b = r.b;
+  }
   recs.push_back(r);
-}
-
-void timing_end(hipStream_t s) {
-  std::lock_guard<std::mutex> g(mu);
-  if (!recs.empty() && recs.back().b) hipEventRecord(recs.back().b, s);
 }
 
 extern "C" {

@@ -1,26 +1,29 @@
-// Opt-in per-kernel timing with HIP events recorded on the launch stream.
-// Disabled by default; when enabled every instrumented launch is bracketed
-// by two events and bse_timing_report() sums their elapsed times by name.
+// Opt-in per-kernel timing with HIP events on the launch stream.  Disabled by
+// default.  When enabled, instrumented launches go through hipExtLaunchKernel
+// with a start and a stop event, which the runtime stamps at the kernel's own
+// start and end (no separate event packets around it); bse_timing_report()
+// sums the elapsed times by kernel name.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 bool timing_on();
-void timing_begin(const char* name, hipStream_t s);
-void timing_end(hipStream_t s);
+// Registers a launch of `name`; *a / *b receive the events to launch with, or
+// nullptr when this launch is not timed.
+void timing_begin(const char* name, hipEvent_t* a, hipEvent_t* b);
 
 struct TimedLaunch {
-  hipStream_t s;
-  bool on;
-  TimedLaunch(const char* name, hipStream_t st) : s(st), on(timing_on()) {
-    if (on) timing_begin(name, s);
-  }
-  ~TimedLaunch() {
-    if (on) timing_end(s);
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(const char* name, hipStream_t) {
+    if (timing_on()) timing_begin(name, &a, &b);
   }
 };
 
-#define BSE_LAUNCH(kern, grid, block, shmem, stream, ...)            \
-  do {                                                               \
-    TimedLaunch _tl(#kern, stream);                                  \
-    hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__); \
+#define BSE_LAUNCH(kern, grid, block, shmem, stream, ...)                                 \
+  do {                                                                                    \
+    TimedLaunch _tl(#kern, stream);                                                       \
+    if (_tl.a)                                                                            \
+      hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, _tl.a, _tl.b, 0, __VA_ARGS__); \
+    else                                                                                  \
+      hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                  \
   } while (0)

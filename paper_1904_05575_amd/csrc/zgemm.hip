@@ -78,10 +78,16 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
 template <int BM, int BN, int WM, int WN>
 hipError_t launch(const ZgemmParams& p, int batch, hipStream_t s) {
   TimedLaunch tl(p.tag, s);
+  // a timed product spans its first and last chunk of at most 65535 batch entries
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
     dim3 grid(cdiv(p.M, BM), cdiv(p.N, BN), nb);
-    hipLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, b0);
+    const bool first = b0 == 0, last = b0 + nb >= batch;
+    if (tl.a)
+      hipExtLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s,
+                            first ? tl.a : nullptr, last ? tl.b : nullptr, 0, p, b0);
+    else
+      hipLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, b0);
   }
   return hipGetLastError();
 }
