@@ -6,7 +6,7 @@
 // TDA: A X = E X.
 // The Hermitian matrix (S or A) is reduced to a real symmetric tridiagonal
 // T = Q^H S Q by Householder reflectors (blocked, lower), T is solved by
-// multisection bisection and inverse iteration, and the eigenvectors are
+// multisection on Sturm counts and twisted factorisations, and the eigenvectors are
 // back-transformed with the reflectors in compact-WY form.  When only the
 // spectrum is wanted the back-transform is replaced by projecting the probe:
 //   t_l = E_l^-1/2 z_l^T (Q^H U p)      (full),   t_l = z_l^T (Q^H p)   (TDA).
@@ -149,62 +149,73 @@ __global__ __launch_bounds__(256) void k_hermitize(double2* __restrict__ M, int6
 }
 
 // ------------------------------------------------------------------ tridiagonal eigensolver
-// e2, Gershgorin bounds, pivmin and the norm of T.  stat[0]=gl, [1]=gu, [2]=pivmin, [3]=tnorm
+// T (diagonal d, off-diagonal e) is solved through a copy scaled by a power of
+// two sigma that brings its Gershgorin norm into [1/2, 1).  The leading and
+// trailing principal minors of T - x I then grow by at most a factor 3 per row
+// and are carried as plain numbers, renormalised by a power of two every MR
+// rows (exact, ratios unchanged): no division sits on their recurrence.
+//
+// stat: [0] gl, [1] gu  Gershgorin bounds of the scaled T, widened by the
+//                       rounding of the counts
+//       [2] pivmin      smallest pivot magnitude kept in the ratio forms
+//       [3] tnorm       Gershgorin norm of T (unscaled)
+//       [4] sigma       the scale
+constexpr int MR = 8;                  // rows between renormalisations of the minors
+constexpr double E2_FLOOR = 0x1p-600;  // floor of e^2 in the minor recurrences
+constexpr int BS_G = 16384;            // points of the shared Sturm-count grid
+constexpr int BS_L = 8;                // probe points per eigenvalue and round
+constexpr int TB = 8;                  // rows prefetched per block in the vector sweeps
+
 __global__ __launch_bounds__(1024) void k_tri_prep(const double* __restrict__ d,
                                                    const double* __restrict__ e, int n,
-                                                   double* __restrict__ e2, double* stat,
+                                                   double* __restrict__ ds, double* __restrict__ es,
+                                                   double* __restrict__ e2s, double* stat,
                                                    const int32_t* info) {
-  __shared__ double slo[16], shi[16], sem[16];
+  __shared__ double slo[16], shi[16];
+  __shared__ double ssig;
   if (failed(info)) return;
-  double lo = INFINITY, hi = -INFINITY, emax = 0.0;
+  double lo = INFINITY, hi = -INFINITY;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     const double em = (k > 0) ? fabs(e[k - 1]) : 0.0, ep = (k < n - 1) ? fabs(e[k]) : 0.0;
     lo = fmin(lo, d[k] - em - ep);
     hi = fmax(hi, d[k] + em + ep);
-    if (k < n - 1) {
-      e2[k] = e[k] * e[k];
-      emax = fmax(emax, e2[k]);
-    }
   }
   for (int off = 32; off >= 1; off >>= 1) {
     lo = fmin(lo, __shfl_xor(lo, off, 64));
     hi = fmax(hi, __shfl_xor(hi, off, 64));
-    emax = fmax(emax, __shfl_xor(emax, off, 64));
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) {
     slo[w] = lo;
     shi[w] = hi;
-    sem[w] = emax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
       lo = fmin(lo, slo[i]);
       hi = fmax(hi, shi[i]);
-      emax = fmax(emax, sem[i]);
     }
     const double tnorm = fmax(fabs(lo), fabs(hi));
+    const double sigma =
+        (tnorm > 0.0 && tnorm < INFINITY) ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(tnorm)) : 1.0;
     const double eps = 2.220446049250313e-16;
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
-    stat[0] = lo - 2.0 * eps * tnorm * n - 2.0 * pivmin;
-    stat[1] = hi + 2.0 * eps * tnorm * n + 2.0 * pivmin;
+    const double pivmin = 2.2250738585072014e-308;  // e^2 <= 1 after scaling
+    const double tn = tnorm * sigma;
+    stat[0] = lo * sigma - 2.0 * eps * tn * n - 2.0 * pivmin;
+    stat[1] = hi * sigma + 2.0 * eps * tn * n + 2.0 * pivmin;
     stat[2] = pivmin;
     stat[3] = tnorm;
+    stat[4] = sigma;
+    ssig = sigma;
   }
-}
-
-BSE_DEV int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n, double x,
-                        double pivmin) {
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int cnt = q < 0.0;
-  for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
+  __syncthreads();
+  const double sigma = ssig;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    ds[k] = d[k] * sigma;
+    const double v = (k < n - 1) ? e[k] * sigma : 0.0;  // es, e2s carry a zero at n-1
+    es[k] = v;
+    e2s[k] = (k < n - 1) ? fmax(v * v, E2_FLOOR) : 0.0;
   }
-  return cnt;
 }
 
 // 1/q to full double precision: hardware reciprocal refined by two Newton steps.
@@ -215,65 +226,148 @@ BSE_DEV double recip(double q) {
   return r;
 }
 
-// Eigenvalue k (ascending) by multisection: the 64 lanes of a wavefront probe
-// 64 interior points of the bracket per round with Sturm counts of the
-// LDL^T factorisation of T - x I.
-__global__ __launch_bounds__(256) void k_bisect(const double* __restrict__ d,
-                                                const double* __restrict__ e2, int n,
+BSE_DEV uint32_t hi_word(double v) { return (uint32_t)((uint64_t)__double_as_longlong(v) >> 32); }
+
+// Brings the larger of two consecutive minors to [1/2, 1) by a power of two.
+BSE_DEV void renorm(double& a, double& b) {
+  const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(a), fabs(b)));
+  a = __builtin_amdgcn_ldexp(a, -ex);
+  b = __builtin_amdgcn_ldexp(b, -ex);
+}
+
+// Number of eigenvalues of the scaled T below x: the sign changes along the
+// leading principal minors p_{-1} = 1, p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}
+// of T - x I, i.e. the negative pivots of its LDL^T factorisation (Sturm).  Each
+// computed ratio p_i / p_{i-1} is the pivot recurrence of T with relative
+// perturbations of a few ulps in d_i - x and e_{i-1}^2.  Sign bits are packed
+// 32 rows to a word (newest in bit 0) and the changes counted per word.
+BSE_DEV int count_below(const double* __restrict__ ds, const double* __restrict__ e2s, int n,
+                        double x) {
+  double p2 = 1.0, p1 = ds[0] - x;
+  uint32_t prev = hi_word(p1) >> 31;
+  int cnt = (int)prev;
+  int i = 1;
+  for (; i + 32 <= n; i += 32) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const double pn = fma(ds[i + u] - x, p1, -(e2s[i + u - 1] * p2));
+      p2 = p1;
+      p1 = pn;
+      w = __builtin_amdgcn_alignbit(w, hi_word(pn), 31);
+      if (u % MR == MR - 1) renorm(p1, p2);
+    }
+    cnt += __popc(w ^ ((w >> 1) | (prev << 31)));
+    prev = w & 1u;
+  }
+  for (int u = 0; i < n; ++i, ++u) {
+    const double pn = fma(ds[i] - x, p1, -(e2s[i - 1] * p2));
+    p2 = p1;
+    p1 = pn;
+    const uint32_t sg = hi_word(pn) >> 31;
+    cnt += (int)(sg ^ prev);
+    prev = sg;
+    if (u % MR == MR - 1) renorm(p1, p2);
+  }
+  return cnt;
+}
+
+// Point g of the shared grid; g = -1 and g = BS_G are the ends gl and gu.
+BSE_DEV double grid_x(double gl, double gu, int g) {
+  if (g < 0) return gl;
+  if (g >= BS_G) return gu;
+  return gl + (gu - gl) * ((double)(g + 1) / (double)(BS_G + 1));
+}
+
+// Sturm counts on BS_G interior points of the Gershgorin interval, one per lane.
+__global__ __launch_bounds__(64) void k_sturm_grid(const double* __restrict__ ds,
+                                                   const double* __restrict__ e2s, int n,
+                                                   const double* __restrict__ stat,
+                                                   int32_t* __restrict__ counts,
+                                                   const int32_t* info) {
+  if (failed(info)) return;
+  const int g = blockIdx.x * 64 + threadIdx.x;
+  if (g >= BS_G) return;
+  counts[g] = count_below(ds, e2s, n, grid_x(stat[0], stat[1], g));
+}
+
+BSE_DEV double probe_x(double lo, double width, int q) {
+  return lo + width * ((double)q / (double)(BS_L + 1));
+}
+
+// Eigenvalue k (ascending) by multisection.  Its starting bracket is the grid
+// cell where the shared counts pass k; then BS_L lanes probe BS_L interior
+// points per round (eight eigenvalues per wavefront) and the bracket shrinks to
+// the sub-interval where the count passes k, until it is below
+// max(2 eps |lambda|, eps tnorm).  Results are unscaled.
+__global__ __launch_bounds__(256) void k_bisect(const double* __restrict__ ds,
+                                                const double* __restrict__ e2s, int n,
                                                 const double* __restrict__ stat,
+                                                const int32_t* __restrict__ counts,
                                                 double* __restrict__ w, const int32_t* info) {
   if (failed(info)) return;
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (k >= n) return;
-  double lo = stat[0], hi = stat[1];
-  const double pivmin = stat[2];
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wv * (64 / BS_L) >= n) return;  // the whole wavefront is past the end
+  const int lane = threadIdx.x & 63, grp = lane / BS_L, s = lane % BS_L;
+  const int k = wv * (64 / BS_L) + grp;
+  const double gl = stat[0], gu = stat[1], pivmin = stat[2], sigma = stat[4];
+  const double tn = stat[3] * sigma;
   const double eps = 2.220446049250313e-16;
-  constexpr double NP = 65.0;
-  for (int it = 0; it < 40; ++it) {
-    const double width = hi - lo;
-    if (width <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
-    const double x = lo + width * (double)(lane + 1) / NP;
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int cnt = q < 0.0;
-    int i = 1;
-    for (; i + 4 <= n; i += 4) {
-      const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
-      const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
-      q = (d0 - x) - f0 * recip(q);
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-      q = (d1 - x) - f1 * recip(q);
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-      q = (d2 - x) - f2 * recip(q);
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-      q = (d3 - x) - f3 * recip(q);
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-    }
-    for (; i < n; ++i) {
-      q = (d[i] - x) - e2[i - 1] * recip(q);
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-    }
-    const unsigned long long mask = __ballot(cnt > k);
-    double nlo, nhi;
-    if (mask == 0ull) {
-      nlo = lo + width * 64.0 / NP;
-      nhi = hi;
-    } else {
-      const int f = __ffsll((long long)mask) - 1;
-      nhi = lo + width * (double)(f + 1) / NP;
-      nlo = (f > 0) ? lo + width * (double)f / NP : lo;
-    }
-    if (nlo == lo && nhi == hi) break;
-    lo = nlo;
-    hi = nhi;
+  int a = 0, b = BS_G;  // first grid point whose count exceeds k (counts[BS_G] = n)
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (counts[m] > k) b = m;
+    else a = m + 1;
   }
-  if (lane == 0) w[k] = 0.5 * (lo + hi);
+  double lo = grid_x(gl, gu, a - 1), hi = grid_x(gl, gu, a);
+  bool done = k >= n;
+  for (int it = 0; it < 96; ++it) {
+    const double width = hi - lo;
+    const double tol = fmax(2.0 * eps * fmax(fabs(lo), fabs(hi)), eps * tn) + 4.0 * pivmin;
+    done = done || !(width > tol);
+    if (__ballot(!done) == 0ull) break;
+    const int c = count_below(ds, e2s, n, probe_x(lo, width, s + 1));
+    const uint32_t gb = (uint32_t)(__ballot(c > k) >> (BS_L * grp)) & ((1u << BS_L) - 1u);
+    if (!done) {
+      double nlo = lo, nhi = hi;
+      if (gb == 0u) {
+        nlo = probe_x(lo, width, BS_L);
+      } else {
+        const int f = __ffs(gb) - 1;
+        nhi = probe_x(lo, width, f + 1);
+        if (f > 0) nlo = probe_x(lo, width, f);
+      }
+      if (nlo == lo && nhi == hi) done = true;
+      lo = nlo;
+      hi = nhi;
+    }
+  }
+  if (k < n && s == 0) w[k] = 0.5 * (lo + hi) / sigma;
+}
+
+// Independent brackets can leave two nearly equal eigenvalues out of order by
+// an ulp: a running maximum restores the ascending order.
+__global__ __launch_bounds__(1024) void k_monotone(double* __restrict__ w, int n,
+                                                   const int32_t* info) {
+  __shared__ double sm[1024];
+  if (failed(info)) return;
+  const int t = threadIdx.x, per = cdiv(n, 1024);
+  const int a = min(n, t * per), b = min(n, a + per);
+  double m = -INFINITY;
+  for (int i = a; i < b; ++i) m = fmax(m, w[i]);
+  sm[t] = m;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const double v = (t >= off) ? sm[t - off] : -INFINITY;
+    __syncthreads();
+    sm[t] = fmax(sm[t], v);
+    __syncthreads();
+  }
+  double run = (t > 0) ? sm[t - 1] : -INFINITY;
+  for (int i = a; i < b; ++i) {
+    run = fmax(run, w[i]);
+    if (w[i] != run) w[i] = run;
+  }
 }
 
 BSE_DEV double hash_uniform(uint32_t a, uint32_t b) {
@@ -286,185 +380,297 @@ BSE_DEV double hash_uniform(uint32_t a, uint32_t b) {
   return 2.0 * ((double)h / 4294967296.0) - 1.0;
 }
 
-// One inverse-iteration solve (T - lam I) x = s * b with partial pivoting:
-// the forward sweep writes U (U0 diagonal, U1, U2 super-diagonals) and the
-// eliminated rhs R; the backward sweep writes x into X and returns max |x|,
-// sum x^2 and the index of the largest |x|.  The rhs b is X (scaled by s) or,
-// when X_in_is_random, the start vector.  Arrays are [component i][eigenvalue j].
-struct SolveStats {
-  double big, nrm2;
-  int ibig;
-};
-
-BSE_DEV SolveStats inv_solve(const double* __restrict__ d, const double* __restrict__ e, int n,
-                             double lam, double tiny, int j, int64_t N, bool random_rhs,
-                             double scale, double* __restrict__ X, double* __restrict__ U0,
-                             double* __restrict__ U1, double* __restrict__ U2,
-                             double* __restrict__ R) {
-  constexpr int CH = 16;  // rows whose loads are issued together
-  double di = d[0] - lam, dui = (n > 1) ? e[0] : 0.0;
-  double rin = random_rhs ? hash_uniform(0u, (uint32_t)j) : X[j] * scale;
-  for (int i0 = 0; i0 < n - 1; i0 += CH) {
-    double rb[CH], db[CH], eb[CH], fb[CH];
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int i = i0 + u;
-      if (i < n - 1) {
-        rb[u] = random_rhs ? hash_uniform((uint32_t)(i + 1), (uint32_t)j)
-                           : X[(int64_t)(i + 1) * N + j] * scale;
-        db[u] = d[i + 1];
-        eb[u] = e[i];
-        fb[u] = (i + 1 < n - 1) ? e[i + 1] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int i = i0 + u;
-      if (i < n - 1) {
-        const double dl = eb[u];
-        double d1 = db[u] - lam, du1 = fb[u], r1 = rb[u];
-        double Ud, Uu, Uu2, ri;
-        if (fabs(di) >= fabs(dl)) {
-          const double f = (di != 0.0) ? dl / di : 0.0;
-          Ud = di;
-          Uu = dui;
-          Uu2 = 0.0;
-          ri = rin;
-          d1 -= f * dui;
-          r1 -= f * rin;
-        } else {
-          const double f = di / dl;
-          Ud = dl;
-          Uu = d1;
-          Uu2 = du1;
-          ri = r1;
-          const double nd1 = dui - f * d1;
-          du1 = -f * du1;
-          r1 = rin - f * r1;
-          d1 = nd1;
-        }
-        const int64_t o = (int64_t)i * N + j;
-        U0[o] = Ud;
-        U1[o] = Uu;
-        U2[o] = Uu2;
-        R[o] = ri;
-        di = d1;
-        dui = du1;
-        rin = r1;
-      }
-    }
-  }
-  U0[(int64_t)(n - 1) * N + j] = di;
-  R[(int64_t)(n - 1) * N + j] = rin;
-  SolveStats st{0.0, 0.0, 0};
-  double x1 = 0.0, x2 = 0.0;
-  for (int i1 = n - 1; i1 >= 0; i1 -= CH) {
-    double p0[CH], p1[CH], p2[CH], rr[CH];
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int i = i1 - u;
-      if (i >= 0) {
-        const int64_t o = (int64_t)i * N + j;
-        p0[u] = U0[o];
-        p1[u] = (i < n - 1) ? U1[o] : 0.0;
-        p2[u] = (i < n - 2) ? U2[o] : 0.0;
-        rr[u] = R[o];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int i = i1 - u;
-      if (i >= 0) {
-        double p = p0[u];
-        if (fabs(p) < tiny) p = (p >= 0.0) ? tiny : -tiny;
-        const double xi = (rr[u] - p1[u] * x1 - p2[u] * x2) / p;
-        X[(int64_t)i * N + j] = xi;
-        const double ax = fabs(xi);
-        if (ax > st.big) {
-          st.big = ax;
-          st.ibig = i;
-        }
-        st.nrm2 += xi * xi;
-        x2 = x1;
-        x1 = xi;
-      }
-    }
-  }
-  return st;
+// A zero the compiler cannot see through: added to a pointer it makes the
+// accesses per-lane (vector) loads, so that rows that are the same for every
+// lane are prefetched into registers like the per-lane ones.
+BSE_DEV int lane_zero() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
 }
 
-// Inverse iteration for every eigenvalue: one thread per cluster of close
-// eigenvalues (gap <= ortol_rel * |lambda|); cluster members are orthogonalised
-// against the earlier ones.  Two solves per eigenvalue from a pseudo-random
-// start, then normalisation with the largest component made positive.
-__global__ __launch_bounds__(256) void k_inviter(const double* __restrict__ d,
-                                                 const double* __restrict__ e, int n,
-                                                 const double* __restrict__ w,
-                                                 const double* __restrict__ stat, double ortol_rel,
-                                                 double* __restrict__ Z, double* __restrict__ U0,
-                                                 double* __restrict__ U1, double* __restrict__ U2,
-                                                 double* __restrict__ R, int32_t* info) {
+// Runs body(t, v_0, ..., v_{NA-1}) for t = 0 .. count-1, where
+// v_q = A[q][row(t) * ld[q]] and row(t) = r0 + dir * t.  Rows are fetched TB
+// ahead into registers (two buffers); whole blocks run without bounds tests,
+// the last one or two with them (a fetch past the end repeats the last row).
+template <int NA, typename F>
+BSE_DEV void stream_rows(const double* const (&A)[NA], const int64_t (&ld)[NA], int r0, int dir,
+                         int count, F&& body) {
+  if (count <= 0) return;
+  double b0[NA][TB], b1[NA][TB];
+  auto fetch = [&](double(&buf)[NA][TB], int blk) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int64_t row = r0 + dir * min(blk * TB + u, count - 1);
+#pragma unroll
+      for (int q = 0; q < NA; ++q) buf[q][u] = A[q][row * ld[q]];
+    }
+  };
+  auto run = [&](double(&buf)[NA][TB], int blk, bool guarded) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int t = blk * TB + u;
+      if (guarded && t >= count) break;
+      if constexpr (NA == 2) body(t, buf[0][u], buf[1][u]);
+      else body(t, buf[0][u], buf[1][u], buf[2][u]);
+    }
+  };
+  const int nfull = count / TB, nblk = cdiv(count, TB);
+  fetch(b0, 0);
+  int blk = 0;
+  for (; blk + 2 <= nfull; blk += 2) {
+    fetch(b1, blk + 1);
+    run(b0, blk, false);
+    fetch(b0, blk + 2);
+    run(b1, blk + 1, false);
+  }
+  if (blk < nblk) {
+    fetch(b1, blk + 1);
+    run(b0, blk, true);
+    if (blk + 1 < nblk) run(b1, blk + 1, true);
+  }
+}
+
+// Eigenvectors of T, one lane per eigenvalue; Z, Dp and Dm are [row i][eigenvalue j].
+//
+// Isolated eigenvalues (blocks 0 .. nb-1): the twisted factorisation of
+// T - lambda I.  The top-down pivots D+_i = p_i / p_{i-1} (leading minors) and
+// the bottom-up pivots D-_i = q_i / q_{i+1} (trailing minors) give
+// gamma_i = D+_i + D-_i - (d_i - lambda); with r = argmin |gamma_i| the vector
+// z_r = 1, z_i = -(e_i / D+_i) z_{i+1} (i < r), z_{i+1} = -(e_i / D-_{i+1}) z_i
+// (i >= r) solves (T - lambda I) z = gamma_r e_r, i.e. one step of inverse
+// iteration from the unit vector that the factorisation marks as largest.  Z
+// keeps z unnormalised; zs[j] = +-1 / |z| makes it unit length with its
+// largest component positive.
+//
+// Eigenvalues of a cluster (gap <= ortol_rel |lambda|, blocks nb .. 2nb-1): two
+// solves of (T - lambda I) x = b through the top-down LDL^T factorisation
+// (pivots kept at least eps tnorm in magnitude) from a pseudo-random start,
+// the second from the normalised first; k_cluster_orth then orthonormalises
+// the cluster.
+__global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
+                                               const double* __restrict__ es,
+                                               const double* __restrict__ e2s, int n,
+                                               const double* __restrict__ w,
+                                               const double* __restrict__ stat, double ortol_rel,
+                                               double* __restrict__ Z, double* __restrict__ Dp,
+                                               double* __restrict__ Dm, double* __restrict__ zs,
+                                               int32_t* info) {
   if (failed(info)) return;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const double tnorm = stat[3];
-  // close eigenvalues: gap below ortol_rel times the local magnitude (a few
-  // outlying eigenvalues must not merge the rest of the spectrum into one cluster)
+  const int nb = cdiv(n, 64);
+  const bool cl_role = (int)blockIdx.x >= nb;
+  const int j = ((int)blockIdx.x - (cl_role ? nb : 0)) * 64 + (int)threadIdx.x;
+  const bool valid = j < n;
   auto close = [&](int a) {  // eigenvalues a and a+1
     return w[a + 1] - w[a] <= ortol_rel * fmax(fabs(w[a]), fabs(w[a + 1]));
   };
-  if (k > 0 && close(k - 1)) return;  // not the first member of its cluster
-  int kend = k;
-  while (kend + 1 < n && close(kend)) ++kend;
-  const double eps = 2.220446049250313e-16;
-  const double tiny = eps * fmax(tnorm, 1e-300);
+  const bool member = valid && ((j > 0 && close(j - 1)) || (j + 1 < n && close(j)));
+  const bool act = valid && (member == cl_role);
+  if (__ballot(act) == 0ull) return;
   const int64_t N = n;
+  const double pivmin = stat[2], sigma = stat[4];
+  const double lam = w[valid ? j : n - 1] * sigma;
+  auto guard = [&](double v) { return fabs(v) >= pivmin ? v : -pivmin; };
+
+  // top-down pivots D+ (both roles)
+  {
+    double p2 = 1.0, p1 = ds[0] - lam;
+    if (act) Dp[j] = guard(p1);
+    int i = 1;
+    for (; i + MR <= n; i += MR) {
+#pragma unroll
+      for (int u = 0; u < MR; ++u) {
+        const double pn = fma(ds[i + u] - lam, p1, -(e2s[i + u - 1] * p2));
+        const double dq = guard(pn * recip(p1));
+        if (act) Dp[(int64_t)(i + u) * N + j] = dq;
+        p2 = p1;
+        p1 = pn;
+      }
+      renorm(p1, p2);
+    }
+    for (; i < n; ++i) {
+      const double pn = fma(ds[i] - lam, p1, -(e2s[i - 1] * p2));
+      const double dq = guard(pn * recip(p1));
+      if (act) Dp[(int64_t)i * N + j] = dq;
+      p2 = p1;
+      p1 = pn;
+    }
+  }
+
+  const int zl = lane_zero();
+  const double* dsv = ds + zl;  // rows shared by the lanes, read as vector loads
+  const double* esv = es + zl;
+  const double* e2v = e2s + zl;
+  const double* Dpc = Dp + (valid ? j : 0);
+  const double* Dmc = Dm + (valid ? j : 0);
+  const double* Zc = Z + (valid ? j : 0);
+
+  if (!cl_role) {
+    // bottom-up pivots D- and the twist index
+    double q2 = 1.0, q1 = ds[n - 1] - lam;
+    double best = INFINITY;
+    int r = n - 1;
+    stream_rows<3>({Dpc, dsv, e2v}, {N, 1, 1}, n - 1, -1, n,
+                   [&](int t, double dp, double dk, double e2k) __attribute__((always_inline)) {
+                     const int k = n - 1 - t;
+                     double dm, g;
+                     if (t == 0) {
+                       dm = guard(q1);
+                       g = dp;
+                     } else {
+                       const double a = dk - lam;
+                       const double qn = fma(a, q1, -(e2k * q2));
+                       dm = guard(qn * recip(q1));
+                       g = dp + dm - a;
+                       q2 = q1;
+                       q1 = qn;
+                       if (t % MR == 0) renorm(q1, q2);
+                     }
+                     if (act) Dm[(int64_t)k * N + j] = dm;
+                     const bool nb = fabs(g) < best;
+                     best = nb ? fabs(g) : best;
+                     r = nb ? k : r;
+                   });
+    // z below r (descending), then above r (ascending); branch-free bodies so
+    // that the ratios are formed ahead of the product chain
+    double nrm = 1.0, big = 1.0;
+    bool neg = false;
+    double z = 1.0;
+    auto track = [&](bool on) __attribute__((always_inline)) {
+      const double az = on ? fabs(z) : 0.0;
+      nrm = fma(az, az, nrm);
+      const bool nbig = az > big;
+      big = nbig ? az : big;
+      neg = nbig ? (z < 0.0) : neg;
+    };
+    stream_rows<2>({Dpc, esv}, {N, 1}, n - 2, -1, n - 1,
+                   [&](int t, double dp, double ek) __attribute__((always_inline)) {
+                     const int k = n - 2 - t;
+                     const double l = ek * recip(dp);
+                     const bool on = k < r;
+                     z = on ? -l * z : z;
+                     if (act && on) Z[(int64_t)k * N + j] = z;
+                     track(on);
+                   });
+    if (act) Z[(int64_t)r * N + j] = 1.0;
+    z = 1.0;
+    // row k + 1 from row k: D-_{k+1} and e_k
+    stream_rows<2>({Dmc, esv - 1}, {N, 1}, 1, 1, n - 1,
+                   [&](int t, double dm, double ek) __attribute__((always_inline)) {
+                     const int k = t;
+                     const double l = ek * recip(dm);
+                     const bool on = k >= r;
+                     z = on ? -l * z : z;
+                     if (act && on) Z[(int64_t)(k + 1) * N + j] = z;
+                     track(on);
+                   });
+    if (act) zs[j] = (neg ? -1.0 : 1.0) / sqrt(nrm);
+    return;
+  }
+
+  // cluster members: inverse iteration through L D+ L^T (e_{n-1} is stored as 0)
+  const double tiny = 2.220446049250313e-16 * stat[3] * sigma;
+  auto piv = [&](double v) { return fabs(v) >= tiny ? v : (v >= 0.0 ? tiny : -tiny); };
+  double scale = 1.0;
+  for (int it = 0; it < 2; ++it) {
+    double lprev = 0.0, yprev = 0.0;
+    stream_rows<3>({Dpc, Zc, esv}, {N, N, 1}, 0, 1, n,
+                   [&](int i, double dp, double zv, double ei) __attribute__((always_inline)) {
+                     const double b =
+                         (it == 0) ? hash_uniform((uint32_t)i, (uint32_t)j) : zv * scale;
+                     const double y = fma(-lprev, yprev, b);
+                     if (act) Z[(int64_t)i * N + j] = y;
+                     lprev = ei * recip(piv(dp));
+                     yprev = y;
+                   });
+    double xprev = 0.0, big = 0.0;
+    stream_rows<3>({Dpc, Zc, esv}, {N, N, 1}, n - 1, -1, n,
+                   [&](int t, double dp, double y, double ei) __attribute__((always_inline)) {
+                     const int i = n - 1 - t;
+                     const double rp = recip(piv(dp));
+                     const double x = fma(-(ei * rp), xprev, y * rp);
+                     if (act) Z[(int64_t)i * N + j] = x;
+                     xprev = x;
+                     big = fmax(big, fabs(x));
+                   });
+    if (act && (!(big > 0.0) || !(big < INFINITY))) set_info(info, BSE_INFO_NO_CONVERGE);
+    scale = 1.0 / big;
+  }
+  if (act) zs[j] = 1.0;
+}
+
+// Largest |v| with its value (ties: lower index).
+struct ArgMax {
+  double a, v;
+  int i;
+};
+BSE_DEV ArgMax argmax_merge(ArgMax x, ArgMax y) {
+  if (y.a > x.a || (y.a == x.a && y.i < x.i)) return y;
+  return x;
+}
+
+// Orthonormalises each cluster (one block per cluster, led by its first
+// eigenvalue): modified Gram-Schmidt, two passes, over the members in order,
+// then unit length with the largest component positive.
+__global__ __launch_bounds__(256) void k_cluster_orth(const double* __restrict__ w, int n,
+                                                      double ortol_rel, double* __restrict__ Z,
+                                                      int32_t* info) {
+  __shared__ double sh[4];
+  __shared__ double sa[4], sv[4];
+  __shared__ int si[4];
+  if (failed(info)) return;
+  const int k = blockIdx.x;
+  auto close = [&](int a) {
+    return w[a + 1] - w[a] <= ortol_rel * fmax(fabs(w[a]), fabs(w[a + 1]));
+  };
+  if (k + 1 >= n || !close(k) || (k > 0 && close(k - 1))) return;
+  int kend = k + 1;
+  while (kend + 1 < n && close(kend)) ++kend;
+  const int64_t N = n;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int j = k; j <= kend; ++j) {
-    const double lam = w[j];
-    SolveStats st = inv_solve(d, e, n, lam, tiny, j, N, true, 1.0, Z, U0, U1, U2, R);
-    if (!(st.big > 0.0) || !isfinite(st.big)) {
-      set_info(info, BSE_INFO_NO_CONVERGE);
-      return;
-    }
-    st = inv_solve(d, e, n, lam, tiny, j, N, false, 1.0 / st.big, Z, U0, U1, U2, R);
-    if (!(st.big > 0.0) || !isfinite(st.big)) {
-      set_info(info, BSE_INFO_NO_CONVERGE);
-      return;
-    }
-    double s = 1.0 / sqrt(st.nrm2);
-    if (j > k) {
-      // orthogonalise against the earlier members of the cluster, renormalise
-      for (int i = 0; i < n; ++i) Z[(int64_t)i * N + j] *= s;
+    for (int pass = 0; pass < 2; ++pass) {
       for (int jp = k; jp < j; ++jp) {
         double dot = 0.0;
-        for (int i = 0; i < n; ++i) dot += Z[(int64_t)i * N + jp] * Z[(int64_t)i * N + j];
-        for (int i = 0; i < n; ++i) Z[(int64_t)i * N + j] -= dot * Z[(int64_t)i * N + jp];
+        for (int i = tid; i < n; i += 256) dot += Z[(int64_t)i * N + jp] * Z[(int64_t)i * N + j];
+        dot = block_sum(dot, sh);
+        for (int i = tid; i < n; i += 256) Z[(int64_t)i * N + j] -= dot * Z[(int64_t)i * N + jp];
       }
-      double nrm2 = 0.0, big = 0.0;
-      int ib = 0;
-      for (int i = 0; i < n; ++i) {
-        const double v = Z[(int64_t)i * N + j];
-        nrm2 += v * v;
-        if (fabs(v) > big) {
-          big = fabs(v);
-          ib = i;
-        }
-      }
-      if (!(nrm2 > 0.0)) {
-        set_info(info, BSE_INFO_NO_CONVERGE);
-        return;
-      }
-      s = 1.0 / sqrt(nrm2);
-      st.ibig = ib;
     }
-    if (Z[(int64_t)st.ibig * N + j] < 0.0) s = -s;
-    for (int i = 0; i < n; ++i) Z[(int64_t)i * N + j] *= s;
+    double nrm = 0.0;
+    ArgMax m{-1.0, 0.0, 0};
+    for (int i = tid; i < n; i += 256) {
+      const double v = Z[(int64_t)i * N + j];
+      nrm += v * v;
+      m = argmax_merge(m, ArgMax{fabs(v), v, i});
+    }
+    nrm = block_sum(nrm, sh);
+    for (int off = 32; off >= 1; off >>= 1) {
+      ArgMax o{__shfl_xor(m.a, off, 64), __shfl_xor(m.v, off, 64), __shfl_xor(m.i, off, 64)};
+      m = argmax_merge(m, o);
+    }
+    __syncthreads();
+    if (lane == 0) {
+      sa[wv] = m.a;
+      sv[wv] = m.v;
+      si[wv] = m.i;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) m = argmax_merge(m, ArgMax{sa[q], sv[q], si[q]});
+    if (!(nrm > 0.0) || !(nrm < INFINITY)) {
+      if (tid == 0) set_info(info, BSE_INFO_NO_CONVERGE);
+      return;
+    }
+    const double s = (m.v < 0.0 ? -1.0 : 1.0) / sqrt(nrm);
+    for (int i = tid; i < n; i += 256) Z[(int64_t)i * N + j] *= s;
   }
 }
 
-// E = sqrt(mu) (full) and the column scale of Z (E^-1/2), or E = mu (TDA).
-__global__ void k_eigvals(const double* __restrict__ mu, int n, int full, double* __restrict__ E,
-                          double* __restrict__ colscale, int32_t* info) {
+// E = sqrt(mu) (full) and the column scale of Z (E^-1/2), or E = mu (TDA); the
+// column scale also carries the normalisation zs of the tridiagonal eigenvectors.
+__global__ void k_eigvals(const double* __restrict__ mu, const double* __restrict__ zs, int n,
+                          int full, double* __restrict__ E, double* __restrict__ colscale,
+                          int32_t* info) {
   if (failed(info)) return;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -476,10 +682,10 @@ __global__ void k_eigvals(const double* __restrict__ mu, int n, int full, double
     }
     const double ek = sqrt(m);
     E[k] = ek;
-    colscale[k] = 1.0 / sqrt(ek);
+    colscale[k] = zs[k] / sqrt(ek);
   } else {
     E[k] = m;
-    colscale[k] = 1.0;
+    colscale[k] = zs[k];
   }
 }
 
@@ -585,11 +791,9 @@ __global__ __launch_bounds__(256) void k_osc_tri(const double* __restrict__ Zt, 
 namespace {
 struct SolveWs {
   double2* Wk;    // n x n complex (T1 of the squared form, then Z)
-  double* Ztri;   // n x n real
-  double* U0;
-  double* U1;
-  double* U2;
-  double* U3;
+  double* Ztri;   // n x n real, [row][eigenvalue]
+  double* Dp;     // n x n top-down pivots, [row][eigenvalue]
+  double* Dm;     // n x n bottom-up pivots, [row][eigenvalue]
   double2* VW;    // n x 2 TRD_NB panel [V | W]
   double2* WV;    // n x 2 TRD_NB panel [W | V]
   double2* W1;    // TRD_NB x n (back-transform)
@@ -602,10 +806,14 @@ struct SolveWs {
   double2* tau;   // n
   double* dd;
   double* ee;
-  double* e2;
+  double* ds;     // scaled T: diagonal, off-diagonal, squared off-diagonal
+  double* es;
+  double* e2s;
   double* mu;
+  double* zs;     // eigenvector normalisation
   double* colscale;
   double* stat;
+  int32_t* grid;  // shared Sturm counts
   int32_t* counters;
   size_t total;
 };
@@ -617,10 +825,8 @@ SolveWs carve(const bse_desc* d, void* base) {
   SolveWs w;
   w.Wk = (double2*)L.add(n * n * 16);
   w.Ztri = (double*)L.add(n * n * 8);
-  w.U0 = (double*)L.add(n * n * 8);
-  w.U1 = (double*)L.add(n * n * 8);
-  w.U2 = (double*)L.add(n * n * 8);
-  w.U3 = (double*)L.add(n * n * 8);
+  w.Dp = (double*)L.add(n * n * 8);
+  w.Dm = (double*)L.add(n * n * 8);
   w.VW = (double2*)L.add(n * 2 * TRD_NB * 16);
   w.WV = (double2*)L.add(n * 2 * TRD_NB * 16);
   w.W1 = (double2*)L.add(n * TRD_NB * 16);
@@ -633,10 +839,14 @@ SolveWs carve(const bse_desc* d, void* base) {
   w.tau = (double2*)L.add(n * 16);
   w.dd = (double*)L.add(n * 8);
   w.ee = (double*)L.add(n * 8);
-  w.e2 = (double*)L.add(n * 8);
+  w.ds = (double*)L.add(n * 8);
+  w.es = (double*)L.add(n * 8);
+  w.e2s = (double*)L.add(n * 8);
   w.mu = (double*)L.add(n * 8);
+  w.zs = (double*)L.add(n * 8);
   w.colscale = (double*)L.add(n * 8);
   w.stat = (double*)L.add(8 * 8);
+  w.grid = (int32_t*)L.add(BS_G * 4);
   w.counters = (int32_t*)L.add(64 * 4);
   w.total = L.total;
   return w;
@@ -834,12 +1044,19 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
   }
   TrdBufs tb{w.VW, w.WV, w.ybuf, w.hs, w.part, w.dd, w.ee, w.tau, project ? w.yvec : nullptr};
   if (!tridiagonalise(Hm, n, ld, tb, info, s)) return BSE_ERR_HIP;
-  BSE_LAUNCH(k_tri_prep, dim3(1), dim3(1024), 0, s, w.dd, w.ee, (int)n, w.e2, w.stat, info);
-  BSE_LAUNCH(k_bisect, dim3(cdiv(n, 4)), dim3(256), 0, s, w.dd, w.e2, (int)n, w.stat, w.mu,
+  BSE_LAUNCH(k_tri_prep, dim3(1), dim3(1024), 0, s, w.dd, w.ee, (int)n, w.ds, w.es, w.e2s,
+             w.stat, info);
+  BSE_LAUNCH(k_sturm_grid, dim3(BS_G / 64), dim3(64), 0, s, w.ds, w.e2s, (int)n, w.stat, w.grid,
              info);
-  BSE_LAUNCH(k_inviter, dim3(cdiv(n, 256)), dim3(256), 0, s, w.dd, w.ee, (int)n, w.mu, w.stat,
-             1e-5, w.Ztri, w.U0, w.U1, w.U2, w.U3, info);
-  BSE_LAUNCH(k_eigvals, dim3(cdiv(n, 256)), dim3(256), 0, s, w.mu, (int)n, full ? 1 : 0, E,
+  BSE_LAUNCH(k_bisect, dim3(cdiv(n, 4 * (64 / BS_L))), dim3(256), 0, s, w.ds, w.e2s, (int)n,
+             w.stat, w.grid, w.mu, info);
+  BSE_LAUNCH(k_monotone, dim3(1), dim3(1024), 0, s, w.mu, (int)n, info);
+  constexpr double ortol_rel = 1e-5;  // relative gap below which eigenvalues form a cluster
+  BSE_LAUNCH(k_eigvec, dim3(2 * cdiv(n, 64)), dim3(64), 0, s, w.ds, w.es, w.e2s, (int)n, w.mu,
+             w.stat, ortol_rel, w.Ztri, w.Dp, w.Dm, w.zs, info);
+  BSE_LAUNCH(k_cluster_orth, dim3((unsigned)n), dim3(256), 0, s, w.mu, (int)n, ortol_rel, w.Ztri,
+             info);
+  BSE_LAUNCH(k_eigvals, dim3(cdiv(n, 256)), dim3(256), 0, s, w.mu, w.zs, (int)n, full ? 1 : 0, E,
              w.colscale, info);
 
   if (XpY) {
