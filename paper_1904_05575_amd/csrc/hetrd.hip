@@ -52,24 +52,6 @@ BSE_DEV int64_t yslot(int q, int Ir, int nrs, int ycs, int64_t n, int r) {
   return (int64_t)(q < nrs ? q : ycs + Ir + (q - nrs)) * n + r;
 }
 
-// Deterministic block-wide complex sum (wavefront butterflies, then waves in
-// order); every thread gets the result.  sh needs blockDim.x / 64 entries.
-BSE_DEV double2 block_sum2(double2 v, double2* sh) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = wave_sum2(v);
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double2 s = make_double2(0.0, 0.0);
-  for (int k = 0; k < nw; ++k) s = cadd(s, sh[k]);
-  return s;
-}
-
-// x -= a conj(b)
-BSE_DEV double2 sub_mulc(double2 x, double2 a, double2 b) {
-  return make_double2(x.x - (a.x * b.x + a.y * b.y), x.y - (a.y * b.x - a.x * b.y));
-}
-
 // Full wavefront sum with DPP lane moves on the vector ALU (no LDS traffic);
 // the total lands in lane 63.  Steps: quad swaps, half-row and row mirrors,
 // then row 0 + 1 and row 2 + 3 through row_bcast:15, all four through
@@ -89,6 +71,40 @@ BSE_DEV double wave_total63(double v) {
   v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
   v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
   return v;
+}
+
+// Wavefront sum of a complex value, every lane gets it (DPP, then lane 63
+// broadcast).
+BSE_DEV double bcast63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+BSE_DEV double2 wave_sum2_dpp(double2 v) {
+  return make_double2(bcast63(wave_total63(v.x)), bcast63(wave_total63(v.y)));
+}
+
+// Deterministic block-wide complex sum (wavefront butterflies, then waves in
+// order); every thread gets the result.  sh needs blockDim.x / 64 entries.
+BSE_DEV double2 block_sum2(double2 v, double2* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum2_dpp(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+  for (int k = 0; k < nw; ++k) s = cadd(s, sh[k]);
+  return s;
+}
+
+// v where ok, else 0 (component selects: a select of the whole vector type
+// would send register arrays to scratch)
+BSE_DEV double2 keep(bool ok, double2 v) { return make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0); }
+
+// x -= a conj(b)
+BSE_DEV double2 sub_mulc(double2 x, double2 a, double2 b) {
+  return make_double2(x.x - (a.x * b.x + a.y * b.y), x.y - (a.y * b.x - a.x * b.y));
 }
 
 __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
@@ -116,60 +132,86 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   const int r = rbase + rr;
   const bool act = r < n;
 
-  // ---- 0. issue every global load of the kernel
-  double2 x0 = make_double2(0.0, 0.0), xv = x0, ypr = x0;
-  if (qq == 0 && act) {
-    if (has_new) x0 = M[r + (int64_t)c * ld];
-    if (yp) ypr = yp[r];
-    if (i > 0) xv = M[r + (int64_t)(c - 1) * ld];
+  // ---- 0. issue every global load of the kernel before any arithmetic on
+  // them: addresses are clamped and the values masked afterwards, so that the
+  // loads go out together and are waited for once
+  const double2 zero = make_double2(0.0, 0.0);
+  const int rc = min(r, n - 1);
+  static_assert(2 * TRD_NB == 64, "one wavefront stages V^H v | W^H v");
+  double2 svl = zero, x0 = zero, xv = zero, ypr = zero;
+  if (wid == 0) {
+    svl = hs[HS_SVV + lane];
+    x0 = M[rc + (int64_t)c * ld];
+    xv = M[rc + (int64_t)max(c - 1, 0) * ld];
+    ypr = (yp ? yp : (const double2*)M)[rc];
   }
   // panel reflectors 0..i-2 on this row: the correction of y_{c-1}, step 2, step 3
+  const int ipmax = max(i - 2, 0);
   double2 vr[PER], wr[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int ip = qq + u * QP;
-    vr[u] = wr[u] = make_double2(0.0, 0.0);
-    if (ip < i - 1 && act) {
-      vr[u] = VW[r + (int64_t)ip * N];
-      wr[u] = VW[r + (int64_t)(TRD_NB + ip) * N];
-    }
+    const int ip = min(qq + u * QP, ipmax);
+    vr[u] = VW[rc + (int64_t)ip * N];
+    wr[u] = VW[rc + (int64_t)(TRD_NB + ip) * N];
   }
-  if (tid < 2 * TRD_NB && tid % TRD_NB < i - 1) svw[tid] = hs[HS_SVV + tid];
   // y_{c-1}[r]: the previous hemv kernel's slots, QP threads per row
   const int nIp = i > 0 ? cdiv(n - c, HT) : 0;
   const int Kp = kprev;  // unit width of the hemv launch that produced the slots
-  double2 yq = make_double2(0.0, 0.0);
+  const int Ir = (rc - c) / HT, nrs = cdiv(Ir + 1, Kp), tot = max(nrs + nIp - Ir, 1);
+  double2 ysl[YCH];
+#pragma unroll
+  for (int u = 0; u < YCH; ++u) ysl[u] = Y[yslot(min(qq + u * QP, tot - 1), Ir, nrs, ycs, N, rc)];
+  // the hemv units' partials of y^H v
+  constexpr int PB = 2;  // unit partials per thread issued together
+  const int nun = i > 0 ? hemv_units(nIp, Kp) : 0;
+  double2 pbl[PB];
+#pragma unroll
+  for (int u = 0; u < PB; ++u) pbl[u] = partB[min(tid + COL_THREADS * u, max(nun - 1, 0))];
+  const double2 tc = hs[HS_TAU], scal_p = hs[HS_SCAL], pdot = hs[HS_PDOT];
+  // row c of the panel's earlier reflectors and the slots of y_{c-1}[c] (wavefront 1)
+  constexpr int YC = 2;  // slots of row c per lane issued together
+  double2 vcl = zero, wcl = zero, ycl[YC];
+  if (wid == 1) {
+    const int ip = min(lane, ipmax);
+    vcl = VW[c + (int64_t)ip * N];
+    wcl = VW[c + (int64_t)(TRD_NB + ip) * N];
+#pragma unroll
+    for (int u = 0; u < YC; ++u) ycl[u] = Y[yslot(min(lane + 64 * u, nIp), 0, 1, ycs, N, c)];
+  }
+
+  // ---- masks and sums
+  if (wid == 0 && lane % TRD_NB < i - 1) svw[lane] = svl;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const bool ok = qq + u * QP < i - 1 && act;
+    vr[u] = keep(ok, vr[u]);
+    wr[u] = keep(ok, wr[u]);
+  }
+  double2 yq = zero;
   if (i > 0 && act) {
-    const int Ir = (r - c) / HT, nrs = cdiv(Ir + 1, Kp), tot = nrs + nIp - Ir;
-    for (int q0 = qq; q0 < tot; q0 += YCH * QP) {
-      double2 t[YCH];
 #pragma unroll
-      for (int u = 0; u < YCH; ++u) t[u] = Y[yslot(min(q0 + u * QP, tot - 1), Ir, nrs, ycs, N, r)];
+    for (int u = 0; u < YCH; ++u)
+      if (qq + u * QP < tot) yq = cadd(yq, ysl[u]);
+    for (int q0 = qq + YCH * QP; q0 < tot; q0 += QP)  // beyond the first round (very large n)
+      yq = cadd(yq, Y[yslot(q0, Ir, nrs, ycs, N, r)]);
+  }
+  double2 ycq = zero;
+  if (wid == 1) {
+    const bool ok = lane < i - 1;
+    vcl = keep(ok, vcl);
+    wcl = keep(ok, wcl);
+    if (i > 0) {
 #pragma unroll
-      for (int u = 0; u < YCH; ++u)
-        if (q0 + u * QP < tot) yq = cadd(yq, t[u]);
+      for (int u = 0; u < YC; ++u)
+        if (lane + 64 * u <= nIp) ycq = cadd(ycq, ycl[u]);
+      for (int q = lane + 64 * YC; q <= nIp; q += 64) ycq = cadd(ycq, Y[yslot(q, 0, 1, ycs, N, c)]);
     }
   }
-  // row c of the panel's earlier reflectors (threads qq = 1, lane = rr) and, in their
-  // first wavefront, the slots of y_{c-1}[c]
-  double2 vcl = make_double2(0.0, 0.0), wcl = vcl;
-  if (qq == 1 && rr < i - 1) {
-    vcl = VW[c + (int64_t)rr * N];
-    wcl = VW[c + (int64_t)(TRD_NB + rr) * N];
-  }
-  double2 ycq = make_double2(0.0, 0.0);
-  if (wid == ROWS_A / 64 && i > 0)
-    for (int q = lane; q <= nIp; q += 64) ycq = cadd(ycq, Y[yslot(q, 0, 1, ycs, N, c)]);
-  // the hemv units' partials of y^H v and the panel's correction (last slot)
-  double2 pa = make_double2(0.0, 0.0);
-  if (i > 0)
-    for (int b = tid; b <= hemv_units(nIp, Kp); b += COL_THREADS) pa = cadd(pa, partB[b]);
-  double2 tc = make_double2(0.0, 0.0), scal_p = tc, pdot = tc;
-  if (i > 0) {
-    tc = hs[HS_TAU];
-    scal_p = hs[HS_SCAL];
-    pdot = hs[HS_PDOT];
-  }
+  double2 pa = zero;
+#pragma unroll
+  for (int u = 0; u < PB; ++u)
+    if (tid + COL_THREADS * u < nun) pa = cadd(pa, pbl[u]);
+  for (int b = tid + COL_THREADS * PB; b < nun; b += COL_THREADS) pa = cadd(pa, partB[b]);
   __syncthreads();  // svw staged
 
   // ---- 1. y_{c-1} = S v - V (W^H v) - W (V^H v) and alpha
@@ -184,10 +226,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     if (wid == ROWS_A / 64) {
       if (lane < i - 1)
         ycq = csub(ycq, cadd(cmul(vcl, svw[TRD_NB + lane]), cmul(wcl, svw[lane])));
-      ycq = wave_sum2(ycq);
+      ycq = wave_sum2_dpp(ycq);
       if (lane == 0) yc_s = ycq;
     }
     xpart[qq][rr] = yq;
+    // the panel's share of y^H v: -sum_ip conj(W^H v) V^H v + conj(V^H v) W^H v
+    if (tid < i - 1) {
+      const double2 sv = svw[tid], sw = svw[TRD_NB + tid];
+      pa = csub(pa, cadd(cmulc(sw, sv), cmulc(sv, sw)));
+    }
     const double2 s = block_sum2(pa, shb);  // y^H v; synchronises the block
     const double t2 = cabs2(tc);
     al = make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
@@ -256,8 +303,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
       tail = r >= c + 2;
     }
     xs[rr] = tail ? x : make_double2(0.0, 0.0);
-    const double2 s0 = wave_sum2(make_double2(tail ? cabs2(x) : 0.0, 0.0));
-    const double2 s1 = wave_sum2((tail && yp) ? cmulc(x, ypr) : make_double2(0.0, 0.0));
+    const double2 s0 = wave_sum2_dpp(make_double2(tail ? cabs2(x) : 0.0, 0.0));
+    const double2 s1 = wave_sum2_dpp((tail && yp) ? cmulc(x, ypr) : make_double2(0.0, 0.0));
     if (lane == 0) {
       red0[wid][0] = s0;
       red0[wid][1] = s1;
@@ -341,8 +388,11 @@ BSE_DEV double row16_sum(double v) {
 // Within a unit no barrier is taken: each lane keeps its rows' partial sums
 // in registers, and each tile's column sums go from the lanes straight to
 // the slots.  A unit ends with one LDS reduction of its row sums.  Block 0
-// also stores the reflector, V^H v and W^H v for the next column kernel, and
-// the panel's share of y^H v in the slot after the units'.
+// also stores the reflector; V^H v, W^H v and conj(v) y_probe for the next
+// column kernel are spread over the blocks, one value each (the panel's share
+// of y^H v follows from them in that kernel).  The column kernel's partial
+// sums are loaded before the tile prefetch so that the reflector is not held
+// up behind it.
 //
 // Wavefront w owns tile column 4w + l / 16 (lane l); load s of lane l reads
 // row 16 s + l % 16: four contiguous 256-byte column segments per
@@ -356,7 +406,6 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     const double2* __restrict__ yp) {
   constexpr int NW = HV_THREADS / 64;     // 16 wavefronts
   constexpr int NL = 4;                   // matrix loads per lane per tile
-  constexpr int SLC = HV_THREADS / 128;
   static_assert(NW * 4 == HT, "tile layout");
   struct Rec {        // one tile's loads
     double2 s[NL];    // elements (rows 16 s + lr, column jl)
@@ -365,8 +414,7 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   struct Cur {        // position in this block's tile sequence
     int u, t, k, I, nt, In;  // In: tile-row of the block's next unit
   };
-  __shared__ double2 sl[SLC][128];
-  __shared__ double2 sums[NVAL];
+  __shared__ double2 sums[1];
   __shared__ double2 vrow[2][HT];
   __shared__ double2 rpart[NW * 4][HT];  // [wavefront x lane group][row]
   __shared__ double2 pred[NW];
@@ -410,37 +458,54 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     rc.xj = xcol[j];
   };
 
-  // ---- first two tiles and every load of the reflector
+  // ---- the small loads first, so that they are not queued behind the tile
+  // prefetch of every block: the column kernel's |x|^2 partials (wavefront 0),
+  // this block's share of the other partial sums (wavefront 1: value
+  // t = 1 + blockIdx.x, + G, ...), and x on the first unit's rows
+  const int nbA = cdiv(n - c, ROWS_A);
+  const int nvals = 2 + 2 * i;
   Cur C{(int)blockIdx.x, 0, 0, 0, 1, 0};
   decode(C);
+  const double2 ax = xcol[b0];
+  const double2 xv0 = xcol[min(b0 + C.I * HT + (tid & (HT - 1)), nlast)];
+  constexpr int PQ = 4;  // partial sums per lane issued together
+  double2 pq[PQ];
+  const int t0 = 1 + (int)blockIdx.x;  // first value of wavefront 1
+  double2 vw1 = zero, yb0 = zero;
+  if (wid <= 1) {
+    const int col = (wid == 0) ? 0 : min(t0, NVAL - 1);
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) pq[q] = partA[(int64_t)min(lane + 64 * q, nbA - 1) * NVAL + col];
+    if (wid == 1 && t0 < nvals) {
+      if (t0 >= 2) {
+        const int ip = (t0 - 2) % max(i, 1), w = (t0 - 2) / max(i, 1);
+        vw1 = VW[b0 + (int64_t)(w * TRD_NB + ip) * N];
+      } else if (yp) {
+        yb0 = yp[b0];
+      }
+    }
+  }
   Cur Lq = C;
   Rec r0, r1, r2;
   load(r0, Lq);
   advance(Lq);
   load(r1, Lq);
   advance(Lq);
-  const double2 ax = xcol[b0];
-  const int nbA = cdiv(n - c, ROWS_A);
-  const int nvals = 2 + 2 * i;
-  if (wid == 0) {
+  // sum over the column kernel's blocks of value col (lanes over blocks)
+  auto colsum = [&](int col) -> double2 {
     double2 a = zero;
-    for (int b = lane; b < nbA; b += 64) a = cadd(a, partA[(int64_t)b * NVAL]);
-    a = wave_sum2(a);
+#pragma unroll
+    for (int q = 0; q < PQ; ++q)
+      if (lane + 64 * q < nbA) a = cadd(a, pq[q]);
+    for (int b = lane + 64 * PQ; b < nbA; b += 64) a = cadd(a, partA[(int64_t)b * NVAL + col]);
+    return wave_sum2(a);
+  };
+  double2 s1 = zero;  // wavefront 1: the sum of value t0
+  if (wid == 0) {
+    const double2 a = colsum(0);
     if (lane == 0) sums[0] = a;
-  }
-  if (blockIdx.x == 0) {
-    const int t = tid & 127, slice = tid >> 7;
-    if (t >= 1 && t < nvals) {
-      double2 sb = zero;
-      for (int b = slice; b < nbA; b += SLC) sb = cadd(sb, partA[(int64_t)b * NVAL + t]);
-      sl[slice][t] = sb;
-    }
-  }
-  __syncthreads();
-  if (blockIdx.x == 0 && tid >= 1 && tid < nvals) {
-    double2 sb = zero;
-    for (int q = 0; q < SLC; ++q) sb = cadd(sb, sl[q][tid]);
-    sums[tid] = sb;
+  } else if (wid == 1 && t0 < nvals) {
+    s1 = colsum(t0);
   }
   __syncthreads();
 
@@ -459,39 +524,49 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     const double q = 1.0 / cabs2(dnm);
     scal = make_double2(dnm.x * q, -dnm.y * q);
   }
-  if (blockIdx.x == 0) {
-    // block 0: the reflector, V^H v and W^H v of the panel, and their share of
-    // y^H v: sum_r conj(V (W^H v) + W (V^H v))[r] v[r] = sum_ip conj(sWv) sVv + conj(sVv) sWv
-    double2 corr = zero;
-    if (tid == 0) {
-      ee[c] = beta;
-      tau[c] = tv;
-      dd[c] = M[c + (int64_t)c * ld].x;
-      hs[HS_SCAL] = scal;
-      hs[HS_TAU] = tv;
-      // v^H y = y[c+1] + conj(scal) sum_{r >= c+2} conj(x_r) y_r
-      if (yp) hs[HS_PDOT] = cadd(yp[b0], cmulc(scal, sums[1]));
-    }
-    if (tid < i) {
-      const double2 v1 = VW[b0 + (int64_t)tid * N];
-      const double2 w1 = VW[b0 + (int64_t)(TRD_NB + tid) * N];
-      const double2 svv = cadd(cconj(v1), cmul(scal, sums[2 + tid]));
-      const double2 swv = cadd(cconj(w1), cmul(scal, sums[2 + i + tid]));
-      hs[HS_SVV + tid] = svv;
-      hs[HS_SWV + tid] = swv;
-      corr = cadd(cmulc(swv, svv), cmulc(svv, swv));
-    }
-    if (wid == 0) {
-      corr.x = wave_total63(corr.x);
-      corr.y = wave_total63(corr.y);
-      if (lane == 63) partB[nunits] = make_double2(-corr.x, -corr.y);
+  // next column kernel's inputs: the reflector (block 0); V^H v, W^H v of the
+  // panel and conj(v) y_probe (one value per block and round of G)
+  if (blockIdx.x == 0 && tid == 0) {
+    ee[c] = beta;
+    tau[c] = tv;
+    dd[c] = M[c + (int64_t)c * ld].x;
+    hs[HS_SCAL] = scal;
+    hs[HS_TAU] = tv;
+  }
+  if (wid == 1) {
+    // lane k takes value t0 + k G (more than one only when there are fewer
+    // blocks than values, i.e. for small trailing matrices)
+    const int t = t0 + lane * G;
+    if (t < nvals) {
+      double2 st = s1, e1 = vw1, y0 = yb0;
+      if (lane > 0) {
+        st = zero;
+        for (int b = 0; b < nbA; b += 4) {
+          double2 pv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pv[u] = partA[(int64_t)min(b + u, nbA - 1) * NVAL + t];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (b + u < nbA) st = cadd(st, pv[u]);
+        }
+        if (t >= 2) e1 = VW[b0 + (int64_t)(((t - 2) / i) * TRD_NB + (t - 2) % i) * N];
+        else if (yp) y0 = yp[b0];
+      }
+      // v^H y_probe = y[c+1] + conj(scal) sum_{r >= c+2} conj(x_r) y_r
+      if (t == 1) {
+        if (yp) hs[HS_PDOT] = cadd(y0, cmulc(scal, st));
+      } else if (t < 2 + i) {
+        hs[HS_SVV + (t - 2)] = cadd(cconj(e1), cmul(scal, st));
+      } else {
+        hs[HS_SWV + (t - 2 - i)] = cadd(cconj(e1), cmul(scal, st));
+      }
     }
   }
   auto vval = [&](int e, double2 x) -> double2 {
     return (e < n) ? ((e == b0) ? make_double2(1.0, 0.0) : cmul(scal, x)) : zero;
   };
   int ub = 0;  // vrow buffer of the current unit
-  if (tid < HT) vrow[0][tid] = vval(b0 + C.I * HT + tid, xcol[min(b0 + C.I * HT + tid, nlast)]);
+  if (tid < HT) vrow[0][tid] = vval(b0 + C.I * HT + tid, xv0);
   __syncthreads();
 
   double2 ra[NL] = {zero, zero, zero, zero};
@@ -620,8 +695,8 @@ int hemv_grid(int64_t m, int K) {
 
 }  // namespace
 
-// [partA: column-kernel partials | partB: hemv tile partials of y^H v + one |
-//  Y: hemv slots]
+// [partA: column-kernel partials | partB: hemv unit partials of y^H v (+ one
+//  spare) | Y: hemv slots]
 int64_t trd_part_elems(int64_t n) {
   const int64_t a = ((n + ROWS_A - 1) / ROWS_A + 1) * NVAL;
   return a + hemv_tiles_max(n) + 1 + 2 * ycs_of(n) * n;
