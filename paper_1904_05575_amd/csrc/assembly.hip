@@ -24,50 +24,70 @@ namespace {
 
 // ---------------------------------------------------------------- class sort
 // perm[pos] lists the pairs grouped by class q = qm[ik][ik']; cls[q] is the
-// first position of class q; inv[p] the position of pair p.
-__global__ __launch_bounds__(1024) void k_class_sort(const int32_t* __restrict__ qm, int nk, int nq,
-                                                     int32_t* perm, int32_t* cls, int32_t* inv,
-                                                     int32_t* info) {
+// first position of class q; inv[p] the position of pair p.  Block 0 sorts by
+// qm0, block 1 (if qm1 is given) by qm1.  Wavefronts take rows ik, lanes ik'.
+__global__ __launch_bounds__(1024) void k_class_sort(const int32_t* __restrict__ qm0,
+                                                     const int32_t* __restrict__ qm1, int nk,
+                                                     int nq, int32_t* perm0, int32_t* cls0,
+                                                     int32_t* inv0, int32_t* perm1, int32_t* cls1,
+                                                     int32_t* inv1, int32_t* info) {
   extern __shared__ int32_t sh[];
+  __shared__ int32_t wtot[16];
+  const int32_t* __restrict__ qm = blockIdx.x == 0 ? qm0 : qm1;
+  int32_t* perm = blockIdx.x == 0 ? perm0 : perm1;
+  int32_t* cls = blockIdx.x == 0 ? cls0 : cls1;
+  int32_t* inv = blockIdx.x == 0 ? inv0 : inv1;
   int32_t* hist = sh;
   int32_t* cur = sh + nq;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
   for (int q = tid; q < nq; q += nt) hist[q] = 0;
   __syncthreads();
-  const int64_t nn = (int64_t)nk * nk;
-  for (int64_t e = tid; e < nn; e += nt) {
-    const int ik = (int)(e / nk), jk = (int)(e % nk);
-    if (ik > jk) continue;
-    const int q = qm[e];
-    if (q < 0 || q >= nq) {
-      set_info(info, BSE_INFO_BAD_QMAP);
-      continue;
+  for (int ik = wid; ik < nk; ik += nw)
+    for (int jk = ik + lane; jk < nk; jk += 64) {
+      const int q = qm[(int64_t)ik * nk + jk];
+      if (q < 0 || q >= nq) {
+        set_info(info, BSE_INFO_BAD_QMAP);
+        continue;
+      }
+      atomicAdd(&hist[q], 1);
     }
-    atomicAdd(&hist[q], 1);
-  }
   __syncthreads();
-  if (tid == 0) {
-    int run = 0;
-    for (int q = 0; q < nq; ++q) {
-      cls[q] = run;
-      cur[q] = run;
-      run += hist[q];
-    }
-    cls[nq] = run;
+  // exclusive scan of hist: chunk totals per thread, scanned within each
+  // wavefront by shuffles, then over the wavefront totals
+  const int per = cdiv(nq, nt), q0 = min(nq, tid * per), q1 = min(nq, q0 + per);
+  int tot = 0;
+  for (int q = q0; q < q1; ++q) tot += hist[q];
+  int incl = tot;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
   }
-  // a class holds at most nk pairs on a mesh (the stage-1 grid relies on it)
-  for (int q = tid; q < nq; q += nt)
+  if (lane == 63) wtot[wid] = incl;
+  __syncthreads();
+  int run = incl - tot, all = 0;
+  for (int w = 0; w < nw; ++w) {
+    if (w < wid) run += wtot[w];
+    all += wtot[w];
+  }
+  for (int q = q0; q < q1; ++q) {
+    // a class holds at most nk pairs on a mesh (the stage-1 grid relies on it)
     if (hist[q] > nk) set_info(info, BSE_INFO_BAD_QMAP);
+    cls[q] = run;
+    cur[q] = run;
+    run += hist[q];
+  }
+  if (tid == 0) cls[nq] = all;
   __syncthreads();
-  for (int64_t e = tid; e < nn; e += nt) {
-    const int ik = (int)(e / nk), jk = (int)(e % nk);
-    if (ik > jk) continue;
-    const int q = qm[e];
-    if (q < 0 || q >= nq) continue;
-    const int p = (int)((int64_t)ik * nk - (int64_t)ik * (ik - 1) / 2 + (jk - ik));
-    const int pos = atomicAdd(&cur[q], 1);
-    perm[pos] = p;
-    inv[p] = pos;
+  for (int ik = wid; ik < nk; ik += nw) {
+    const int prow = (int)((int64_t)ik * nk - (int64_t)ik * (ik - 1) / 2);
+    for (int jk = ik + lane; jk < nk; jk += 64) {
+      const int q = qm[(int64_t)ik * nk + jk];
+      if (q < 0 || q >= nq) continue;
+      const int p = prow + (jk - ik);
+      const int pos = atomicAdd(&cur[q], 1);
+      perm[pos] = p;
+      inv[p] = pos;
+    }
   }
 }
 
@@ -255,11 +275,9 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   (void)cls_ra;
 
   // class sorts
-  BSE_LAUNCH(k_class_sort, dim3(1), dim3(1024), 2 * nq * sizeof(int32_t), s, in->qmap, nk,
-                     nq, perm_rr, cls_rr, inv_rr, info);
-  if (full)
-    BSE_LAUNCH(k_class_sort, dim3(1), dim3(1024), 2 * nq * sizeof(int32_t), s, in->qramap,
-                       nk, nq, perm_ra, cls_ra, inv_ra, info);
+  BSE_LAUNCH(k_class_sort, dim3(full ? 2 : 1), dim3(1024), 2 * nq * sizeof(int32_t), s,
+             in->qmap, full ? in->qramap : nullptr, nk, nq, perm_rr, cls_rr, inv_rr, perm_ra,
+             cls_ra, inv_ra, info);
 
   const int prec = d->prec;
   const int nterms = d->split_terms == 0 ? 6 : d->split_terms;

@@ -614,7 +614,8 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
         rpart[4 * wid + lg][16 * s + lr] = ra[s];
         ra[s] = zero;
       }
-      if (tid < HT) vrow[ub ^ 1][tid] = vval(b0 + C.In * HT + tid, xnext);
+      if (tid < HT && C.u + G < nunits)  // the block has a next unit
+        vrow[ub ^ 1][tid] = vval(b0 + C.In * HT + tid, xnext);
       __syncthreads();
       const int row = tid >> 4, part = tid & 15;
       double2 rs = zero;

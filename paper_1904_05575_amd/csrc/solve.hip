@@ -37,6 +37,50 @@ __global__ void k_copy_c(const double2* __restrict__ src, double2* __restrict__ 
 __global__ void k_zero_ints(int32_t* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
+
+// y = U p for the upper triangle U (column-major, ld) in two passes: block
+// (row tile I, column chunk J) writes part[J][rows of I] = sum over the chunk's
+// columns j >= i of U[i][j] p[j] (coalesced down the columns); then k_trmv_sum
+// adds the chunks (in order) of every row.
+constexpr int TRMV_ROWS = 256, TRMV_COLS = 256;
+__global__ __launch_bounds__(TRMV_ROWS) void k_trmv_part(const double2* __restrict__ U,
+                                                         int64_t ld, int n,
+                                                         const double2* __restrict__ p,
+                                                         double2* __restrict__ part,
+                                                         const int32_t* info) {
+  if (failed(info)) return;
+  const int i0 = blockIdx.x * TRMV_ROWS, j0 = blockIdx.y * TRMV_COLS;
+  if (j0 + TRMV_COLS <= i0) return;  // the chunk lies below the diagonal
+  const int i = i0 + threadIdx.x;
+  const int ic = min(i, n - 1), jend = min(j0 + TRMV_COLS, n);
+  double2 acc = make_double2(0.0, 0.0);
+  constexpr int UB = 8;  // columns whose loads go out together
+  for (int j = max(j0, i0); j < jend; j += UB) {
+    double2 uu[UB], pp[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int jj = min(j + u, jend - 1);
+      uu[u] = U[ic + (int64_t)jj * ld];
+      pp[u] = p[jj];
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u)
+      if (j + u < jend && j + u >= i) acc = cadd(acc, cmul(uu[u], pp[u]));
+  }
+  if (i < n) part[(int64_t)blockIdx.y * n + i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_trmv_sum(const double2* __restrict__ part, int n,
+                                                  double2* __restrict__ y, const int32_t* info) {
+  if (failed(info)) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int nch = cdiv(n, TRMV_COLS);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int c = (i / TRMV_ROWS) * TRMV_ROWS / TRMV_COLS; c < nch; ++c)
+    acc = cadd(acc, part[(int64_t)c * n + i]);
+  y[i] = acc;
+}
 }  // namespace
 namespace {
 
@@ -412,7 +456,8 @@ BSE_DEV void stream_rows(const double* const (&A)[NA], const int64_t (&ld)[NA], 
       const int t = blk * TB + u;
       if (guarded && t >= count) break;
       if constexpr (NA == 2) body(t, buf[0][u], buf[1][u]);
-      else body(t, buf[0][u], buf[1][u], buf[2][u]);
+      else if constexpr (NA == 3) body(t, buf[0][u], buf[1][u], buf[2][u]);
+      else body(t, buf[0][u], buf[1][u], buf[2][u], buf[3][u]);
     }
   };
   const int nfull = count / TB, nblk = cdiv(count, TB);
@@ -448,6 +493,10 @@ BSE_DEV void stream_rows(const double* const (&A)[NA], const int64_t (&ld)[NA], 
 // (pivots kept at least eps tnorm in magnitude) from a pseudo-random start,
 // the second from the normalised first; k_cluster_orth then orthonormalises
 // the cluster.
+//
+// With yproj (the probe carried through the reduction), isolated lanes also
+// form t_j = z^T yproj on the fly, and store_z = 0 skips their Z stores (only
+// t is needed for the spectrum); cluster members always store Z.
 __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
                                                const double* __restrict__ es,
                                                const double* __restrict__ e2s, int n,
@@ -455,7 +504,8 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
                                                const double* __restrict__ stat, double ortol_rel,
                                                double* __restrict__ Z, double* __restrict__ Dp,
                                                double* __restrict__ Dm, double* __restrict__ zs,
-                                               int32_t* info) {
+                                               const double2* __restrict__ yproj, int store_z,
+                                               double2* __restrict__ tproj, int32_t* info) {
   if (failed(info)) return;
   const int nb = cdiv(n, 64);
   const bool cl_role = (int)blockIdx.x >= nb;
@@ -536,35 +586,48 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
     double nrm = 1.0, big = 1.0;
     bool neg = false;
     double z = 1.0;
-    auto track = [&](bool on) __attribute__((always_inline)) {
-      const double az = on ? fabs(z) : 0.0;
-      nrm = fma(az, az, nrm);
+    double2 tacc = make_double2(0.0, 0.0);
+    const bool st = act && store_z;
+    const double* yv = (const double*)(yproj ? yproj : (const double2*)ds) + zl;  // re at 2k
+    const int64_t yld = yproj ? 2 : 0;
+    auto track = [&](bool on, double yr, double yi) __attribute__((always_inline)) {
+      const double zon = on ? z : 0.0;
+      nrm = fma(zon, zon, nrm);
+      tacc.x = fma(zon, yr, tacc.x);
+      tacc.y = fma(zon, yi, tacc.y);
+      const double az = fabs(zon);
       const bool nbig = az > big;
       big = nbig ? az : big;
       neg = nbig ? (z < 0.0) : neg;
     };
-    stream_rows<2>({Dpc, esv}, {N, 1}, n - 2, -1, n - 1,
-                   [&](int t, double dp, double ek) __attribute__((always_inline)) {
-                     const int k = n - 2 - t;
-                     const double l = ek * recip(dp);
-                     const bool on = k < r;
-                     z = on ? -l * z : z;
-                     if (act && on) Z[(int64_t)k * N + j] = z;
-                     track(on);
-                   });
-    if (act) Z[(int64_t)r * N + j] = 1.0;
+    stream_rows<4>({Dpc, esv, yv, yv + 1}, {N, 1, yld, yld}, n - 2, -1, n - 1,
+                   [&](int t, double dp, double ek, double yr, double yi)
+                       __attribute__((always_inline)) {
+                         const int k = n - 2 - t;
+                         const double l = ek * recip(dp);
+                         const bool on = k < r;
+                         z = on ? -l * z : z;
+                         if (st && on) Z[(int64_t)k * N + j] = z;
+                         track(on, yr, yi);
+                       });
+    if (st) Z[(int64_t)r * N + j] = 1.0;
+    if (yproj) tacc = cadd(tacc, yproj[r]);
     z = 1.0;
     // row k + 1 from row k: D-_{k+1} and e_k
-    stream_rows<2>({Dmc, esv - 1}, {N, 1}, 1, 1, n - 1,
-                   [&](int t, double dm, double ek) __attribute__((always_inline)) {
-                     const int k = t;
-                     const double l = ek * recip(dm);
-                     const bool on = k >= r;
-                     z = on ? -l * z : z;
-                     if (act && on) Z[(int64_t)(k + 1) * N + j] = z;
-                     track(on);
-                   });
-    if (act) zs[j] = (neg ? -1.0 : 1.0) / sqrt(nrm);
+    stream_rows<4>({Dmc, esv - 1, yv, yv + 1}, {N, 1, yld, yld}, 1, 1, n - 1,
+                   [&](int t, double dm, double ek, double yr, double yi)
+                       __attribute__((always_inline)) {
+                         const int k = t;
+                         const double l = ek * recip(dm);
+                         const bool on = k >= r;
+                         z = on ? -l * z : z;
+                         if (st && on) Z[(int64_t)(k + 1) * N + j] = z;
+                         track(on, yr, yi);
+                       });
+    if (act) {
+      zs[j] = (neg ? -1.0 : 1.0) / sqrt(nrm);
+      if (yproj) tproj[j] = tacc;
+    }
     return;
   }
 
@@ -614,6 +677,8 @@ BSE_DEV ArgMax argmax_merge(ArgMax x, ArgMax y) {
 // then unit length with the largest component positive.
 __global__ __launch_bounds__(256) void k_cluster_orth(const double* __restrict__ w, int n,
                                                       double ortol_rel, double* __restrict__ Z,
+                                                      const double2* __restrict__ yproj,
+                                                      double2* __restrict__ tproj,
                                                       int32_t* info) {
   __shared__ double sh[4];
   __shared__ double sa[4], sv[4];
@@ -662,14 +727,29 @@ __global__ __launch_bounds__(256) void k_cluster_orth(const double* __restrict__
       return;
     }
     const double s = (m.v < 0.0 ? -1.0 : 1.0) / sqrt(nrm);
-    for (int i = tid; i < n; i += 256) Z[(int64_t)i * N + j] *= s;
+    double tx = 0.0, ty = 0.0;
+    for (int i = tid; i < n; i += 256) {
+      const double v = Z[(int64_t)i * N + j] * s;
+      Z[(int64_t)i * N + j] = v;
+      if (yproj) {
+        tx = fma(v, yproj[i].x, tx);
+        ty = fma(v, yproj[i].y, ty);
+      }
+    }
+    if (yproj) {
+      tx = block_sum(tx, sh);
+      ty = block_sum(ty, sh);
+      if (tid == 0) tproj[j] = make_double2(tx, ty);
+    }
   }
 }
 
 // E = sqrt(mu) (full) and the column scale of Z (E^-1/2), or E = mu (TDA); the
 // column scale also carries the normalisation zs of the tridiagonal eigenvectors.
+// With tproj (z^T of the projected probe, unnormalised), osc = |tproj|^2 scale^2.
 __global__ void k_eigvals(const double* __restrict__ mu, const double* __restrict__ zs, int n,
                           int full, double* __restrict__ E, double* __restrict__ colscale,
+                          const double2* __restrict__ tproj, double* __restrict__ osc,
                           int32_t* info) {
   if (failed(info)) return;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -687,6 +767,7 @@ __global__ void k_eigvals(const double* __restrict__ mu, const double* __restric
     E[k] = m;
     colscale[k] = zs[k];
   }
+  if (tproj) osc[k] = cabs2(tproj[k]) * colscale[k] * colscale[k];
 }
 
 // Z (complex, column-major, ldz)[i, j] = Ztri[i][j] * scale[j]
@@ -766,25 +847,6 @@ __global__ __launch_bounds__(256) void k_larft(const double2* __restrict__ M, in
   for (int e = tid; e < TRD_NB * TRD_NB; e += 256) To[e] = T[e % TRD_NB][e / TRD_NB];
 }
 
-// osc[l] = |sum_i Ztri[i][l] y[i]|^2 * scale2[l]
-__global__ __launch_bounds__(256) void k_osc_tri(const double* __restrict__ Zt, int n,
-                                                 const double2* __restrict__ y,
-                                                 const double* __restrict__ colscale,
-                                                 double* __restrict__ osc, const int32_t* info) {
-  if (failed(info)) return;
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= n) return;
-  double2 s = make_double2(0.0, 0.0);
-  for (int64_t i = 0; i < n; ++i) {
-    const double z = Zt[i * n + l];
-    const double2 yi = y[i];
-    s.x += z * yi.x;
-    s.y += z * yi.y;
-  }
-  const double cs = colscale[l];
-  osc[l] = cabs2(s) * cs * cs;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------ host side
@@ -800,6 +862,7 @@ struct SolveWs {
   double2* W2;    // TRD_NB x n
   double2* ybuf;  // n
   double2* yvec;  // n (probe projection)
+  double2* tproj; // n (eigenvectors of T against the projected probe)
   double2* hs;    // small state
   double2* part;  // partial sums
   double2* Tall;  // T factors
@@ -833,6 +896,7 @@ SolveWs carve(const bse_desc* d, void* base) {
   w.W2 = (double2*)L.add(n * TRD_NB * 16);
   w.ybuf = (double2*)L.add(n * 16);
   w.yvec = (double2*)L.add(n * 16);
+  w.tproj = (double2*)L.add(n * 16);
   w.hs = (double2*)L.add(HS_SIZE * 16);
   w.part = (double2*)L.add(trd_part_elems(n) * 16);
   w.Tall = (double2*)L.add(npnl * TRD_NB * TRD_NB * 16);
@@ -1021,23 +1085,10 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
   const bool project = (XpY == nullptr) && probe && osc;
   if (project) {
     if (full) {
-      ZgemmParams g;  // y = U p
-      g.M = (int)n;
-      g.N = 1;
-      g.K = (int)n;
-      g.A = H1;
-      g.a_rs = 1;
-      g.a_cs = ld;
-      g.a_tri = 1;
-      g.B = probe;
-      g.b_rs = 1;
-      g.b_cs = n;
-      g.C = w.yvec;
-      g.c_rs = 1;
-      g.c_cs = n;
-      g.info = info;
-      g.tag = "zgemm_probe_up";
-      if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
+      // y = U p (the hemv partial-sum space is free until the sweep starts)
+      const dim3 grid((unsigned)cdiv(n, TRMV_ROWS), (unsigned)cdiv(n, TRMV_COLS));
+      BSE_LAUNCH(k_trmv_part, grid, dim3(TRMV_ROWS), 0, s, H1, ld, (int)n, probe, w.part, info);
+      BSE_LAUNCH(k_trmv_sum, dim3(cdiv(n, 256)), dim3(256), 0, s, w.part, (int)n, w.yvec, info);
     } else {
       BSE_LAUNCH(k_copy_c, dim3(cdiv(n, 256)), dim3(256), 0, s, probe, w.yvec, n);
     }
@@ -1053,11 +1104,12 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
   BSE_LAUNCH(k_monotone, dim3(1), dim3(1024), 0, s, w.mu, (int)n, info);
   constexpr double ortol_rel = 1e-5;  // relative gap below which eigenvalues form a cluster
   BSE_LAUNCH(k_eigvec, dim3(2 * cdiv(n, 64)), dim3(64), 0, s, w.ds, w.es, w.e2s, (int)n, w.mu,
-             w.stat, ortol_rel, w.Ztri, w.Dp, w.Dm, w.zs, info);
+             w.stat, ortol_rel, w.Ztri, w.Dp, w.Dm, w.zs, project ? w.yvec : nullptr,
+             XpY ? 1 : 0, w.tproj, info);
   BSE_LAUNCH(k_cluster_orth, dim3((unsigned)n), dim3(256), 0, s, w.mu, (int)n, ortol_rel, w.Ztri,
-             info);
+             project ? w.yvec : nullptr, w.tproj, info);
   BSE_LAUNCH(k_eigvals, dim3(cdiv(n, 256)), dim3(256), 0, s, w.mu, w.zs, (int)n, full ? 1 : 0, E,
-             w.colscale, info);
+             w.colscale, project ? w.tproj : nullptr, osc, info);
 
   if (XpY) {
     const int64_t npnl = (n - 1 + TRD_NB - 1) / TRD_NB;
@@ -1092,9 +1144,6 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
     }
     if (probe && osc && launch_oscillator(n, XpY, ldx, probe, osc, s) != hipSuccess)
       return BSE_ERR_HIP;
-  } else if (project) {
-    BSE_LAUNCH(k_osc_tri, dim3(cdiv(n, 256)), dim3(256), 0, s, w.Ztri, (int)n, w.yvec,
-               w.colscale, osc, info);
   }
   return hipGetLastError() == hipSuccess ? BSE_OK : BSE_ERR_HIP;
 }
