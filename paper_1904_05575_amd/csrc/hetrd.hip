@@ -116,8 +116,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   constexpr int PER = TRD_NB / QP;                // panel columns per thread
   constexpr int YCH = 8;                          // y slots loaded per round
   constexpr int HW = ROWS_A / 64;                 // wavefronts per thread group qq
-  __shared__ double2 vps[ROWS_A], wps[ROWS_A], x0s[ROWS_A], xs[ROWS_A];
-  __shared__ double2 xpart[QP][ROWS_A];
+  __shared__ double2 vps[ROWS_A], wps[ROWS_A], xs[ROWS_A];
+  __shared__ double2 xpart[QP][ROWS_A], xpart2[QP][ROWS_A];
   __shared__ double2 vcs[TRD_NB], wcs[TRD_NB];
   __shared__ double2 red[QP][HW][2 * PER];
   __shared__ double2 red0[HW][2];
@@ -200,6 +200,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     const bool ok = lane < i - 1;
     vcl = keep(ok, vcl);
     wcl = keep(ok, wcl);
+    if (ok) {  // row c of the panel's earlier reflectors
+      vcs[lane] = vcl;
+      wcs[lane] = wcl;
+    }
     if (i > 0) {
 #pragma unroll
       for (int u = 0; u < YC; ++u)
@@ -212,10 +216,24 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   for (int u = 0; u < PB; ++u)
     if (tid + COL_THREADS * u < nun) pa = cadd(pa, pbl[u]);
   for (int b = tid + COL_THREADS * PB; b < nun; b += COL_THREADS) pa = cadd(pa, partB[b]);
-  __syncthreads();  // svw staged
+  __syncthreads();  // svw, vcs, wcs staged
 
-  // ---- 1. y_{c-1} = S v - V (W^H v) - W (V^H v) and alpha
+  // ---- 1. y_{c-1} = S v - V (W^H v) - W (V^H v) and alpha; with it, step 2's
+  // partial products: the panel's reflectors 0..i-2 applied to column c (they do
+  // not depend on reflector c-1), QP threads per row
   double2 al = make_double2(0.0, 0.0);
+  if (has_new && i > 1) {
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int ip = qq + u * QP;
+      if (ip < i - 1) {
+        acc = cadd(acc, cmulc(wcs[ip], vr[u]));   // v_ip[r] conj(w_ip[c])
+        acc = cadd(acc, cmulc(vcs[ip], wr[u]));   // w_ip[r] conj(v_ip[c])
+      }
+    }
+    xpart2[qq][rr] = acc;
+  }
   if (i > 0) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -240,7 +258,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     al = make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
   }
 
-  // ---- finish reflector c-1 (row threads) and stage row c of the panel
+  // ---- finish reflector c-1 and update column c (row threads)
   if (qq == 0) {
     double2 vprev_r = make_double2(0.0, 0.0), wprev_r = make_double2(0.0, 0.0);
     if (i > 0 && act) {
@@ -261,55 +279,37 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
         yp[r] = ypr;
       }
     }
-    vps[rr] = vprev_r;
-    wps[rr] = wprev_r;
-    x0s[rr] = x0;
-  } else if (qq == 1 && has_new && rr < i - 1) {
-    vcs[rr] = vcl;
-    wcs[rr] = wcl;
+    if (has_new) {
+      vps[rr] = vprev_r;
+      wps[rr] = wprev_r;
+      double2 x = make_double2(0.0, 0.0);
+      bool tail = false;
+      if (act) {
+        x = x0;
+        if (i > 1) {
+#pragma unroll
+          for (int q = 0; q < QP; ++q) x = csub(x, xpart2[q][rr]);
+        }
+        if (i > 0) {
+          // reflector c-1: v[c] = 1, w[c] = tau y[c] + alpha
+          const double2 wprev_c = cadd(cmul(tc, yc_s), al);
+          x = sub_mulc(x, vprev_r, wprev_c);
+          x = csub(x, wprev_r);
+        }
+        if (r == c) x.y = 0.0;
+        M[r + (int64_t)c * ld] = x;
+        tail = r >= c + 2;
+      }
+      xs[rr] = tail ? x : make_double2(0.0, 0.0);
+      const double2 s0 = wave_sum2_dpp(make_double2(tail ? cabs2(x) : 0.0, 0.0));
+      const double2 s1 = wave_sum2_dpp((tail && yp) ? cmulc(x, ypr) : make_double2(0.0, 0.0));
+      if (lane == 0) {
+        red0[wid][0] = s0;
+        red0[wid][1] = s1;
+      }
+    }
   }
   if (!has_new) return;
-  __syncthreads();
-
-  // ---- 2. apply the panel's earlier reflectors to column c: QP threads per row
-  {
-    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int ip = qq + u * QP;
-      if (ip < i - 1) {
-        acc = cadd(acc, cmulc(wcs[ip], vr[u]));   // v_ip[r] conj(w_ip[c])
-        acc = cadd(acc, cmulc(vcs[ip], wr[u]));   // w_ip[r] conj(v_ip[c])
-      }
-    }
-    xpart[qq][rr] = acc;
-  }
-  __syncthreads();
-  if (qq == 0) {
-    double2 x = make_double2(0.0, 0.0);
-    bool tail = false;
-    if (act) {
-      x = x0s[rr];
-#pragma unroll
-      for (int q = 0; q < QP; ++q) x = csub(x, xpart[q][rr]);
-      if (i > 0) {
-        // reflector c-1: v[c] = 1, w[c] = tau y[c] + alpha
-        const double2 wprev_c = cadd(cmul(tc, yc_s), al);
-        x = sub_mulc(x, vps[rr], wprev_c);
-        x = csub(x, wps[rr]);
-      }
-      if (r == c) x.y = 0.0;
-      M[r + (int64_t)c * ld] = x;
-      tail = r >= c + 2;
-    }
-    xs[rr] = tail ? x : make_double2(0.0, 0.0);
-    const double2 s0 = wave_sum2_dpp(make_double2(tail ? cabs2(x) : 0.0, 0.0));
-    const double2 s1 = wave_sum2_dpp((tail && yp) ? cmulc(x, ypr) : make_double2(0.0, 0.0));
-    if (lane == 0) {
-      red0[wid][0] = s0;
-      red0[wid][1] = s1;
-    }
-  }
   __syncthreads();
 
   // ---- 3. V^H x and W^H x over this block's rows from the panel values each

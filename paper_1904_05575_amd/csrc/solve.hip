@@ -916,35 +916,57 @@ SolveWs carve(const bse_desc* d, void* base) {
   return w;
 }
 
+// A12 := A12 - U01^H U01' on the upper triangle of the target (rows r0.., columns c0..), with
+// U01 the k rows of U starting at row u0: one MFMA GEMM.
+bool herk_update(double2* H1, int64_t ld, int64_t u0, int k, int64_t r0, int rows, int64_t c0,
+                 int cols, int tile, const char* tag, int32_t* info, hipStream_t s) {
+  ZgemmParams h;
+  h.M = rows;
+  h.N = cols;
+  h.K = k;
+  h.A = H1 + u0 + r0 * ld;  // (m, kk) = conj(U[u0 + kk][r0 + m])
+  h.a_rs = ld;
+  h.a_cs = 1;
+  h.conjA = 1;
+  h.B = H1 + u0 + c0 * ld;  // (kk, j) = U[u0 + kk][c0 + j]
+  h.b_rs = 1;
+  h.b_cs = ld;
+  h.C = H1 + r0 + c0 * ld;
+  h.c_rs = 1;
+  h.c_cs = ld;
+  h.alpha = make_double2(-1.0, 0.0);
+  h.beta = 1.0;
+  h.c_uplo = 1;
+  h.info = info;
+  h.tag = tag;
+  h.tile = tile;
+  return zgemm(h, 1, s) == hipSuccess;
+}
+
+// A - B = U^H U (upper).  Panels of CH_NB columns are factored in pairs: after
+// the first panel of a pair only the second panel's rows are updated (K =
+// CH_NB), and after the second the trailing matrix takes one update of
+// K = 2 CH_NB, which halves the passes over it.
 bool cholesky(double2* H1, int64_t n, int64_t ld, int32_t* info, hipStream_t s) {
-  for (int64_t j0 = 0; j0 < n; j0 += CH_NB) {
+  const int tile = tune_choice(BSE_TUNE_GEMM_POTRF, n, 0);
+  for (int64_t j0 = 0; j0 < n; j0 += 2 * CH_NB) {
     const int jb = (int)std::min<int64_t>(CH_NB, n - j0);
-    const int64_t rest = n - j0 - jb;
-    BSE_LAUNCH(k_potrf_panel, dim3((unsigned)std::max<int64_t>(1, cdiv(rest, PCOLS))),
+    const int64_t j1 = j0 + jb, rest1 = n - j1;
+    BSE_LAUNCH(k_potrf_panel, dim3((unsigned)std::max<int64_t>(1, cdiv(rest1, PCOLS))),
                dim3(PCOLS), 0, s, H1, ld, n, (int)j0, jb, info);
-    if (rest <= 0) break;
-    double2* A12 = H1 + j0 + (j0 + jb) * ld;
-    ZgemmParams h;  // A22 -= U12^H U12 (upper)
-    h.M = (int)rest;
-    h.N = (int)rest;
-    h.K = jb;
-    h.A = A12;
-    h.a_rs = ld;
-    h.a_cs = 1;
-    h.conjA = 1;
-    h.B = A12;
-    h.b_rs = 1;
-    h.b_cs = ld;
-    h.C = H1 + (j0 + jb) + (j0 + jb) * ld;
-    h.c_rs = 1;
-    h.c_cs = ld;
-    h.alpha = make_double2(-1.0, 0.0);
-    h.beta = 1.0;
-    h.c_uplo = 1;
-    h.info = info;
-    h.tag = "zgemm_potrf_herk";
-    h.tile = tune_choice(BSE_TUNE_GEMM_POTRF, n, 0);
-    if (zgemm(h, 1, s) != hipSuccess) return false;
+    if (rest1 <= 0) break;
+    const int jb2 = (int)std::min<int64_t>(CH_NB, rest1);
+    const int64_t j2 = j1 + jb2, rest2 = n - j2;
+    // rows j1 .. j2-1 (the next panel) over columns j1 .. n-1
+    if (!herk_update(H1, ld, j0, jb, j1, jb2, j1, (int)rest1, tile, "zgemm_potrf_rows", info, s))
+      return false;
+    BSE_LAUNCH(k_potrf_panel, dim3((unsigned)std::max<int64_t>(1, cdiv(rest2, PCOLS))),
+               dim3(PCOLS), 0, s, H1, ld, n, (int)j1, jb2, info);
+    if (rest2 <= 0) break;
+    // trailing matrix: rows and columns j2 .. n-1, K = jb + jb2
+    if (!herk_update(H1, ld, j0, jb + jb2, j2, (int)rest2, j2, (int)rest2, tile,
+                     "zgemm_potrf_herk", info, s))
+      return false;
   }
   return true;
 }
