@@ -208,7 +208,8 @@ constexpr int MR = 8;                  // rows between renormalisations of the m
 constexpr double E2_FLOOR = 0x1p-600;  // floor of e^2 in the minor recurrences
 constexpr int BS_G = 16384;            // points of the shared Sturm-count grid
 constexpr int BS_L = 8;                // probe points per eigenvalue and round
-constexpr int TB = 8;                  // rows prefetched per block in the vector sweeps
+constexpr int EV_NLDS = 6400;          // largest order whose shared rows (3 doubles) fit in LDS
+constexpr int EV_JUNK = 64;            // spare columns of the pivot arrays
 
 __global__ __launch_bounds__(1024) void k_tri_prep(const double* __restrict__ d,
                                                    const double* __restrict__ e, int n,
@@ -433,48 +434,76 @@ BSE_DEV int lane_zero() {
   return z;
 }
 
-// Runs body(t, v_0, ..., v_{NA-1}) for t = 0 .. count-1, where
-// v_q = A[q][row(t) * ld[q]] and row(t) = r0 + dir * t.  Rows are fetched TB
-// ahead into registers (two buffers); whole blocks run without bounds tests,
-// the last one or two with them (a fetch past the end repeats the last row).
-template <int NA, typename F>
-BSE_DEV void stream_rows(const double* const (&A)[NA], const int64_t (&ld)[NA], int r0, int dir,
-                         int count, F&& body) {
+// Runs body(t, u, v) for t = 0 .. count-1 with v (a small struct of doubles)
+// filled by fetch(t, v) one block of TB steps ahead (two buffers; u = t mod TB,
+// a compile-time index after unrolling; a fetch past the end repeats the last
+// step).  Whole blocks run without bounds tests, the last one or two with them.
+template <int TB, typename V, typename Fetch, typename Body>
+BSE_DEV void stream(int count, Fetch&& fetch, Body&& body) {
   if (count <= 0) return;
-  double b0[NA][TB], b1[NA][TB];
-  auto fetch = [&](double(&buf)[NA][TB], int blk) __attribute__((always_inline)) {
+  V b0[TB], b1[TB];
+  auto fill = [&](V(&buf)[TB], int blk) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < TB; ++u) {
-      const int64_t row = r0 + dir * min(blk * TB + u, count - 1);
-#pragma unroll
-      for (int q = 0; q < NA; ++q) buf[q][u] = A[q][row * ld[q]];
-    }
+    for (int u = 0; u < TB; ++u) fetch(min(blk * TB + u, count - 1), buf[u]);
   };
-  auto run = [&](double(&buf)[NA][TB], int blk, bool guarded) __attribute__((always_inline)) {
+  auto run = [&](V(&buf)[TB], int blk, bool guarded) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < TB; ++u) {
       const int t = blk * TB + u;
       if (guarded && t >= count) break;
-      if constexpr (NA == 2) body(t, buf[0][u], buf[1][u]);
-      else if constexpr (NA == 3) body(t, buf[0][u], buf[1][u], buf[2][u]);
-      else body(t, buf[0][u], buf[1][u], buf[2][u], buf[3][u]);
+      body(t, u, buf[u]);
     }
   };
   const int nfull = count / TB, nblk = cdiv(count, TB);
-  fetch(b0, 0);
+  fill(b0, 0);
   int blk = 0;
   for (; blk + 2 <= nfull; blk += 2) {
-    fetch(b1, blk + 1);
+    fill(b1, blk + 1);
     run(b0, blk, false);
-    fetch(b0, blk + 2);
+    fill(b0, blk + 2);
     run(b1, blk + 1, false);
   }
   if (blk < nblk) {
-    fetch(b1, blk + 1);
+    fill(b1, blk + 1);
     run(b0, blk, true);
     if (blk + 1 < nblk) run(b1, blk + 1, true);
   }
 }
+
+// Runs blockf(t0, buf, nvalid) over blocks of TB steps: the steps t0 .. t0+TB-1,
+// of which the first nvalid exist (the rest repeat the last one).  buf holds
+// the lanes' own values of those steps, filled by fetch(t, v) NB-1 blocks
+// ahead in a ring of NB buffers (indices fixed at compile time), so that
+// several blocks of loads are in flight while one is used.  The block
+// function can run its recurrence first and the independent per-step work
+// afterwards, without branches.
+template <int TB, int NB, typename V, typename Fetch, typename Block>
+BSE_DEV void stream_blocks(int count, Fetch&& fetch, Block&& blockf) {
+  if (count <= 0) return;
+  V buf[NB][TB];
+  auto fill = [&](V(&b)[TB], int blk) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < TB; ++u) fetch(min(blk * TB + u, count - 1), b[u]);
+  };
+  const int nblk = cdiv(count, TB);
+#pragma unroll
+  for (int i = 0; i < NB - 1; ++i) fill(buf[i], i);
+  for (int blk = 0; blk < nblk; blk += NB) {
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      if (blk + s >= nblk) break;
+      fill(buf[(s + NB - 1) % NB], blk + s + NB - 1);
+      blockf((blk + s) * TB, buf[s], min(TB, count - (blk + s) * TB));
+    }
+  }
+}
+
+struct EvV2 {
+  double a, b;
+};
+constexpr int EV_TB = 8;   // steps per block of the vector sweeps
+constexpr int EV_NB = 6;   // blocks of the lanes' own rows in flight (one value per step)
+constexpr int EV_NB2 = 4;  // the same with two values per step
 
 // Eigenvectors of T, one lane per eigenvalue; Z, Dp and Dm are [row i][eigenvalue j].
 //
@@ -506,6 +535,7 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
                                                double* __restrict__ Dm, double* __restrict__ zs,
                                                const double2* __restrict__ yproj, int store_z,
                                                double2* __restrict__ tproj, int32_t* info) {
+  __shared__ double ush[3][EV_NLDS];
   if (failed(info)) return;
   const int nb = cdiv(n, 64);
   const bool cl_role = (int)blockIdx.x >= nb;
@@ -522,111 +552,203 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
   const double lam = w[valid ? j : n - 1] * sigma;
   auto guard = [&](double v) { return fabs(v) >= pivmin ? v : -pivmin; };
 
+  // Dp and Dm have EV_JUNK spare columns after the n eigenvalues: lanes without
+  // work store there, so that the sweeps carry no branches around their stores.
+  const int64_t LDD = N + EV_JUNK;
+  const int col = act ? j : n + (int)threadIdx.x;
+  // Rows shared by the lanes are staged in LDS when they fit (d, e^2 for the
+  // pivot sweeps; then e and the probe), so that only the lanes' own pivot rows
+  // are prefetched, 16 ahead; otherwise they are read as vector loads.
+  const bool use_lds = n <= EV_NLDS;
+  auto stage = [&](const double* a0, const double* a1, const double2* y2)
+      __attribute__((always_inline)) {
+    __syncthreads();  // earlier readers are done (one wavefront per block)
+    constexpr int SU = 8;
+    for (int i0 = 0; i0 < n; i0 += 64 * SU) {
+      double t0[SU], t1[SU], t2[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int i = min(i0 + 64 * u + (int)threadIdx.x, n - 1);
+        t0[u] = a0[i];
+        t1[u] = a1 ? a1[i] : (y2 ? y2[i].x : 0.0);
+        t2[u] = y2 ? y2[i].y : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int i = i0 + 64 * u + (int)threadIdx.x;
+        if (i < n) {
+          ush[0][i] = t0[u];
+          ush[1][i] = t1[u];
+          ush[2][i] = t2[u];
+        }
+      }
+    }
+    __syncthreads();
+  };
+  if (use_lds) stage(ds, e2s, nullptr);
+
   // top-down pivots D+ (both roles)
-  {
-    double p2 = 1.0, p1 = ds[0] - lam;
-    if (act) Dp[j] = guard(p1);
+  auto sweep_down = [&](auto dk, auto e2k) __attribute__((always_inline)) {
+    double p2 = 1.0, p1 = dk(0) - lam;
+    Dp[col] = guard(p1);
     int i = 1;
     for (; i + MR <= n; i += MR) {
 #pragma unroll
       for (int u = 0; u < MR; ++u) {
-        const double pn = fma(ds[i + u] - lam, p1, -(e2s[i + u - 1] * p2));
-        const double dq = guard(pn * recip(p1));
-        if (act) Dp[(int64_t)(i + u) * N + j] = dq;
+        const double pn = fma(dk(i + u) - lam, p1, -(e2k(i + u - 1) * p2));
+        Dp[(int64_t)(i + u) * LDD + col] = guard(pn * recip(p1));
         p2 = p1;
         p1 = pn;
       }
       renorm(p1, p2);
     }
     for (; i < n; ++i) {
-      const double pn = fma(ds[i] - lam, p1, -(e2s[i - 1] * p2));
-      const double dq = guard(pn * recip(p1));
-      if (act) Dp[(int64_t)i * N + j] = dq;
+      const double pn = fma(dk(i) - lam, p1, -(e2k(i - 1) * p2));
+      Dp[(int64_t)i * LDD + col] = guard(pn * recip(p1));
       p2 = p1;
       p1 = pn;
     }
-  }
+  };
+  if (use_lds)
+    sweep_down([&](int i) { return ush[0][i]; }, [&](int i) { return ush[1][i]; });
+  else
+    sweep_down([&](int i) { return ds[i]; }, [&](int i) { return e2s[i]; });
 
   const int zl = lane_zero();
   const double* dsv = ds + zl;  // rows shared by the lanes, read as vector loads
   const double* esv = es + zl;
   const double* e2v = e2s + zl;
-  const double* Dpc = Dp + (valid ? j : 0);
-  const double* Dmc = Dm + (valid ? j : 0);
+  const double* Dpc = Dp + col;
+  const double* Dmc = Dm + col;
   const double* Zc = Z + (valid ? j : 0);
 
+  const int ldd = n + EV_JUNK;  // element offsets fit in int for the orders handled here
+  const int junk = n + (int)threadIdx.x;  // row 0 of this lane's spare column
   if (!cl_role) {
-    // bottom-up pivots D- and the twist index
-    double q2 = 1.0, q1 = ds[n - 1] - lam;
-    double best = INFINITY;
-    int r = n - 1;
-    stream_rows<3>({Dpc, dsv, e2v}, {N, 1, 1}, n - 1, -1, n,
-                   [&](int t, double dp, double dk, double e2k) __attribute__((always_inline)) {
-                     const int k = n - 1 - t;
-                     double dm, g;
-                     if (t == 0) {
-                       dm = guard(q1);
-                       g = dp;
-                     } else {
-                       const double a = dk - lam;
-                       const double qn = fma(a, q1, -(e2k * q2));
-                       dm = guard(qn * recip(q1));
-                       g = dp + dm - a;
-                       q2 = q1;
-                       q1 = qn;
-                       if (t % MR == 0) renorm(q1, q2);
-                     }
-                     if (act) Dm[(int64_t)k * N + j] = dm;
-                     const bool nb = fabs(g) < best;
-                     best = nb ? fabs(g) : best;
-                     r = nb ? k : r;
-                   });
-    // z below r (descending), then above r (ascending); branch-free bodies so
-    // that the ratios are formed ahead of the product chain
-    double nrm = 1.0, big = 1.0;
-    bool neg = false;
-    double z = 1.0;
-    double2 tacc = make_double2(0.0, 0.0);
-    const bool st = act && store_z;
-    const double* yv = (const double*)(yproj ? yproj : (const double2*)ds) + zl;  // re at 2k
-    const int64_t yld = yproj ? 2 : 0;
-    auto track = [&](bool on, double yr, double yi) __attribute__((always_inline)) {
-      const double zon = on ? z : 0.0;
-      nrm = fma(zon, zon, nrm);
-      tacc.x = fma(zon, yr, tacc.x);
-      tacc.y = fma(zon, yi, tacc.y);
-      const double az = fabs(zon);
-      const bool nbig = az > big;
-      big = nbig ? az : big;
-      neg = nbig ? (z < 0.0) : neg;
+    // Ud, Ue2: d and e^2 of row k; Ue, Uyr, Uyi: e and the probe of row k.
+    auto iso = [&](auto Ud, auto Ue2) __attribute__((always_inline)) {
+      // bottom-up pivots D- and the twist index (row n-1 first, then n-2 .. 0):
+      // per block the minors' recurrence, then the ratios, stores and argmin
+      double q2 = 1.0, q1 = Ud(n - 1) - lam;
+      Dm[(n - 1) * ldd + col] = guard(q1);
+      double best = fabs(Dpc[(n - 1) * ldd]);
+      int r = n - 1;
+      stream_blocks<EV_TB, EV_NB, double>(
+          n - 1, [&](int t, double& v) __attribute__((always_inline)) { v = Dpc[(n - 2 - t) * ldd]; },
+          [&](int t0, const double(&dp)[EV_TB], int nv) __attribute__((always_inline)) {
+            // qs: the minors as computed (numerators of their own ratios);
+            // qd: the same after a renormalisation (denominators of the next)
+            double qs[EV_TB], qd[EV_TB], as[EV_TB], e2k[EV_TB];
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u) {
+              const int k = max(n - 2 - (t0 + u), 0);
+              as[u] = Ud(k) - lam;
+              e2k[u] = Ue2(k);
+            }
+            const double qlast = q1;
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u) {
+              const double qn = fma(as[u], q1, -(e2k[u] * q2));
+              q2 = q1;
+              q1 = qn;
+              qs[u] = qn;
+              if (u % MR == MR - 1) renorm(q1, q2);
+              qd[u] = q1;
+            }
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u) {
+              const double qp = (u == 0) ? qlast : qd[u - 1];
+              const double dm = guard(qs[u] * recip(qp));
+              const double g = dp[u] + dm - as[u];
+              const bool ok = u < nv;
+              const int k = n - 2 - (t0 + u);
+              Dm[ok ? k * ldd + col : junk] = dm;
+              const bool nb = ok && fabs(g) < best;
+              best = nb ? fabs(g) : best;
+              r = nb ? k : r;
+            }
+          });
+      return r;
     };
-    stream_rows<4>({Dpc, esv, yv, yv + 1}, {N, 1, yld, yld}, n - 2, -1, n - 1,
-                   [&](int t, double dp, double ek, double yr, double yi)
-                       __attribute__((always_inline)) {
-                         const int k = n - 2 - t;
-                         const double l = ek * recip(dp);
-                         const bool on = k < r;
-                         z = on ? -l * z : z;
-                         if (st && on) Z[(int64_t)k * N + j] = z;
-                         track(on, yr, yi);
-                       });
-    if (st) Z[(int64_t)r * N + j] = 1.0;
-    if (yproj) tacc = cadd(tacc, yproj[r]);
-    z = 1.0;
-    // row k + 1 from row k: D-_{k+1} and e_k
-    stream_rows<4>({Dmc, esv - 1, yv, yv + 1}, {N, 1, yld, yld}, 1, 1, n - 1,
-                   [&](int t, double dm, double ek, double yr, double yi)
-                       __attribute__((always_inline)) {
-                         const int k = t;
-                         const double l = ek * recip(dm);
-                         const bool on = k >= r;
-                         z = on ? -l * z : z;
-                         if (st && on) Z[(int64_t)(k + 1) * N + j] = z;
-                         track(on, yr, yi);
-                       });
-    if (act) {
-      zs[j] = (neg ? -1.0 : 1.0) / sqrt(nrm);
-      if (yproj) tproj[j] = tacc;
+    auto vec = [&](int r, auto Ue, auto Uyr, auto Uyi) __attribute__((always_inline)) {
+      // z below r (descending), then above r (ascending): per block the ratios
+      // first, then the product chain, then the sums
+      double nrm = 1.0, big = 1.0;
+      bool neg = false;
+      double z = 1.0;
+      double2 tacc = make_double2(0.0, 0.0);
+      const bool st = act && store_z;
+      // below: step t is row k = n-2-t (D+_k, e_k); above: row k + 1 from
+      // row k = t (D-_{k+1}, e_k); the probe is taken at the row written
+      auto half = [&](int t0, const double(&dv)[EV_TB], int nv, bool below)
+          __attribute__((always_inline)) {
+        double zz[EV_TB], ls[EV_TB], yr[EV_TB], yi[EV_TB];
+        bool on[EV_TB];
+#pragma unroll
+        for (int u = 0; u < EV_TB; ++u) {
+          const int k = below ? max(n - 2 - (t0 + u), 0) : min(t0 + u, n - 2);
+          const int kw = below ? k : k + 1;
+          ls[u] = Ue(k) * recip(dv[u]);
+          yr[u] = Uyr(kw);
+          yi[u] = Uyi(kw);
+        }
+#pragma unroll
+        for (int u = 0; u < EV_TB; ++u) {
+          const int k = below ? n - 2 - (t0 + u) : t0 + u;
+          on[u] = (u < nv) && (below ? k < r : k >= r);
+          z = on[u] ? -ls[u] * z : z;
+          zz[u] = z;
+        }
+#pragma unroll
+        for (int u = 0; u < EV_TB; ++u) {
+          const double zon = on[u] ? zz[u] : 0.0;
+          nrm = fma(zon, zon, nrm);
+          tacc.x = fma(zon, yr[u], tacc.x);
+          tacc.y = fma(zon, yi[u], tacc.y);
+          const double az = fabs(zon);
+          const bool nbig = az > big;
+          big = nbig ? az : big;
+          neg = nbig ? (zz[u] < 0.0) : neg;
+        }
+        if (st) {
+#pragma unroll
+          for (int u = 0; u < EV_TB; ++u) {
+            const int kw = below ? n - 2 - (t0 + u) : t0 + u + 1;
+            if (on[u]) Z[(int64_t)kw * N + j] = zz[u];
+          }
+        }
+      };
+      stream_blocks<EV_TB, EV_NB, double>(
+          n - 1, [&](int t, double& v) __attribute__((always_inline)) { v = Dpc[(n - 2 - t) * ldd]; },
+          [&](int t0, const double(&dv)[EV_TB], int nv) __attribute__((always_inline)) {
+            half(t0, dv, nv, true);
+          });
+      if (st) Z[(int64_t)r * N + j] = 1.0;
+      if (yproj) tacc = cadd(tacc, yproj[r]);
+      z = 1.0;
+      stream_blocks<EV_TB, EV_NB, double>(
+          n - 1, [&](int t, double& v) __attribute__((always_inline)) { v = Dmc[(t + 1) * ldd]; },
+          [&](int t0, const double(&dv)[EV_TB], int nv) __attribute__((always_inline)) {
+            half(t0, dv, nv, false);
+          });
+      if (act) {
+        zs[j] = (neg ? -1.0 : 1.0) / sqrt(nrm);
+        if (yproj) tproj[j] = tacc;
+      }
+    };
+    const double* yv = (const double*)(yproj ? yproj : (const double2*)ds) + zl;  // re at 2k
+    const int yld = yproj ? 2 : 0;
+    if (use_lds) {
+      auto L0 = [&](int k) { return ush[0][k]; };
+      auto L1 = [&](int k) { return ush[1][k]; };
+      auto L2 = [&](int k) { return ush[2][k]; };
+      const int r = iso(L0, L1);
+      stage(es, nullptr, yproj);
+      vec(r, L0, L1, L2);
+    } else {
+      const int r = iso([&](int k) { return dsv[k]; }, [&](int k) { return e2v[k]; });
+      vec(r, [&](int k) { return esv[k]; }, [&](int k) { return yv[k * yld]; },
+          [&](int k) { return yv[k * yld + 1]; });
     }
     return;
   }
@@ -634,30 +756,67 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
   // cluster members: inverse iteration through L D+ L^T (e_{n-1} is stored as 0)
   const double tiny = 2.220446049250313e-16 * stat[3] * sigma;
   auto piv = [&](double v) { return fabs(v) >= tiny ? v : (v >= 0.0 ? tiny : -tiny); };
-  double scale = 1.0;
-  for (int it = 0; it < 2; ++it) {
-    double lprev = 0.0, yprev = 0.0;
-    stream_rows<3>({Dpc, Zc, esv}, {N, N, 1}, 0, 1, n,
-                   [&](int i, double dp, double zv, double ei) __attribute__((always_inline)) {
-                     const double b =
-                         (it == 0) ? hash_uniform((uint32_t)i, (uint32_t)j) : zv * scale;
-                     const double y = fma(-lprev, yprev, b);
-                     if (act) Z[(int64_t)i * N + j] = y;
-                     lprev = ei * recip(piv(dp));
-                     yprev = y;
-                   });
-    double xprev = 0.0, big = 0.0;
-    stream_rows<3>({Dpc, Zc, esv}, {N, N, 1}, n - 1, -1, n,
-                   [&](int t, double dp, double y, double ei) __attribute__((always_inline)) {
-                     const int i = n - 1 - t;
-                     const double rp = recip(piv(dp));
-                     const double x = fma(-(ei * rp), xprev, y * rp);
-                     if (act) Z[(int64_t)i * N + j] = x;
-                     xprev = x;
-                     big = fmax(big, fabs(x));
-                   });
-    if (act && (!(big > 0.0) || !(big < INFINITY))) set_info(info, BSE_INFO_NO_CONVERGE);
-    scale = 1.0 / big;
+  auto inv = [&](auto Ue) __attribute__((always_inline)) {
+    double scale = 1.0;
+    for (int it = 0; it < 2; ++it) {
+      double lprev = 0.0, yprev = 0.0;
+      stream_blocks<EV_TB, EV_NB2, EvV2>(
+          n,
+          [&](int i, EvV2& v) __attribute__((always_inline)) {
+            v.a = Dpc[i * ldd];
+            v.b = Zc[(int64_t)i * N];
+          },
+          [&](int t0, const EvV2(&v)[EV_TB], int nv) __attribute__((always_inline)) {
+            double ys[EV_TB], ls[EV_TB];
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u) ls[u] = Ue(min(t0 + u, n - 1)) * recip(piv(v[u].a));
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u) {
+              const double b =
+                  (it == 0) ? hash_uniform((uint32_t)(t0 + u), (uint32_t)j) : v[u].b * scale;
+              ys[u] = fma(-lprev, yprev, b);
+              lprev = ls[u];
+              yprev = ys[u];
+            }
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u)
+              if (act && u < nv) Z[(int64_t)(t0 + u) * N + j] = ys[u];
+          });
+      double xprev = 0.0, big = 0.0;
+      stream_blocks<EV_TB, EV_NB2, EvV2>(
+          n,
+          [&](int t, EvV2& v) __attribute__((always_inline)) {
+            const int i = n - 1 - t;
+            v.a = Dpc[i * ldd];
+            v.b = Zc[(int64_t)i * N];
+          },
+          [&](int t0, const EvV2(&v)[EV_TB], int nv) __attribute__((always_inline)) {
+            double xs[EV_TB], rp[EV_TB], el[EV_TB];
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u) {
+              rp[u] = recip(piv(v[u].a));
+              el[u] = Ue(max(n - 1 - (t0 + u), 0));
+            }
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u) {
+              xs[u] = fma(-(el[u] * rp[u]), xprev, v[u].b * rp[u]);
+              xprev = xs[u];
+            }
+#pragma unroll
+            for (int u = 0; u < EV_TB; ++u) {
+              if (u < nv) big = fmax(big, fabs(xs[u]));
+              if (act && u < nv) Z[(int64_t)(n - 1 - (t0 + u)) * N + j] = xs[u];
+            }
+          });
+      if (act && (!(big > 0.0) || !(big < INFINITY))) set_info(info, BSE_INFO_NO_CONVERGE);
+      scale = 1.0 / big;
+    }
+  };
+  if (use_lds) {
+    stage(es, nullptr, nullptr);
+    inv([&](int k) { return ush[0][k]; });
+  } else {
+    inv([&](int k) { return esv[k]; });
   }
   if (act) zs[j] = 1.0;
 }
@@ -854,8 +1013,8 @@ namespace {
 struct SolveWs {
   double2* Wk;    // n x n complex (T1 of the squared form, then Z)
   double* Ztri;   // n x n real, [row][eigenvalue]
-  double* Dp;     // n x n top-down pivots, [row][eigenvalue]
-  double* Dm;     // n x n bottom-up pivots, [row][eigenvalue]
+  double* Dp;     // n x (n + EV_JUNK) top-down pivots, [row][eigenvalue]
+  double* Dm;     // n x (n + EV_JUNK) bottom-up pivots, [row][eigenvalue]
   double2* VW;    // n x 2 TRD_NB panel [V | W]
   double2* WV;    // n x 2 TRD_NB panel [W | V]
   double2* W1;    // TRD_NB x n (back-transform)
@@ -888,8 +1047,8 @@ SolveWs carve(const bse_desc* d, void* base) {
   SolveWs w;
   w.Wk = (double2*)L.add(n * n * 16);
   w.Ztri = (double*)L.add(n * n * 8);
-  w.Dp = (double*)L.add(n * n * 8);
-  w.Dm = (double*)L.add(n * n * 8);
+  w.Dp = (double*)L.add(n * (n + EV_JUNK) * 8);
+  w.Dm = (double*)L.add(n * (n + EV_JUNK) * 8);
   w.VW = (double2*)L.add(n * 2 * TRD_NB * 16);
   w.WV = (double2*)L.add(n * 2 * TRD_NB * 16);
   w.W1 = (double2*)L.add(n * TRD_NB * 16);
