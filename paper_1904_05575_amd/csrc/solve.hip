@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_hermitize(double2* __restrict__ M, int6
 //
 // stat: [0] gl, [1] gu  Gershgorin bounds of the scaled T, widened by the
 //                       rounding of the counts
-//       [2] pivmin      smallest pivot magnitude kept in the ratio forms
+//       [2] pivmin      the underflow threshold (bisection tolerance)
 //       [3] tnorm       Gershgorin norm of T (unscaled)
 //       [4] sigma       the scale
 constexpr int MR = 8;                  // rows between renormalisations of the minors
@@ -527,8 +527,7 @@ constexpr int EV_NB2 = 4;  // the same with two values per step
 // form t_j = z^T yproj on the fly, and store_z = 0 skips their Z stores (only
 // t is needed for the spectrum); cluster members always store Z.
 __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
-                                               const double* __restrict__ es,
-                                               const double* __restrict__ e2s, int n,
+                                               const double* __restrict__ es, int n,
                                                const double* __restrict__ w,
                                                const double* __restrict__ stat, double ortol_rel,
                                                double* __restrict__ Z, double* __restrict__ Dp,
@@ -548,9 +547,20 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
   const bool act = valid && (member == cl_role);
   if (__ballot(act) == 0ull) return;
   const int64_t N = n;
-  const double pivmin = stat[2], sigma = stat[4];
+  const double sigma = stat[4];
   const double lam = w[valid ? j : n - 1] * sigma;
-  auto guard = [&](double v) { return fabs(v) >= pivmin ? v : -pivmin; };
+  // Pivots of the factorisations of T - lambda I: a pivot below eps ||T|| in
+  // magnitude is replaced by -eps ||T|| inside the recurrence (the minor
+  // becomes -eps ||T|| times the previous one), a perturbation of T of that
+  // size.  The recurrences use the exact e^2: the floor that keeps the Sturm
+  // counts of a split matrix going would here put a spurious coupling next to
+  // an exactly zero pivot.
+  const double tiny = 2.220446049250313e-16 * stat[3] * sigma;
+  auto guard = [&](double v) { return fabs(v) >= tiny ? v : -tiny; };
+  auto minor_next = [&](double a, double e2, double m1, double m2) __attribute__((always_inline)) {
+    const double mn = fma(a, m1, -(e2 * m2));
+    return fabs(mn) >= tiny * fabs(m1) ? mn : -tiny * m1;
+  };
 
   // Dp and Dm have EV_JUNK spare columns after the n eigenvalues: lanes without
   // work store there, so that the sweeps carry no branches around their stores.
@@ -585,17 +595,18 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
     }
     __syncthreads();
   };
-  if (use_lds) stage(ds, e2s, nullptr);
+  if (use_lds) stage(ds, es, nullptr);
 
   // top-down pivots D+ (both roles)
-  auto sweep_down = [&](auto dk, auto e2k) __attribute__((always_inline)) {
-    double p2 = 1.0, p1 = dk(0) - lam;
+  auto sweep_down = [&](auto dk, auto ek) __attribute__((always_inline)) {
+    double p2 = 1.0, p1 = minor_next(dk(0) - lam, 0.0, 1.0, 0.0);
     Dp[col] = guard(p1);
     int i = 1;
     for (; i + MR <= n; i += MR) {
 #pragma unroll
       for (int u = 0; u < MR; ++u) {
-        const double pn = fma(dk(i + u) - lam, p1, -(e2k(i + u - 1) * p2));
+        const double e = ek(i + u - 1);
+        const double pn = minor_next(dk(i + u) - lam, e * e, p1, p2);
         Dp[(int64_t)(i + u) * LDD + col] = guard(pn * recip(p1));
         p2 = p1;
         p1 = pn;
@@ -603,7 +614,8 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
       renorm(p1, p2);
     }
     for (; i < n; ++i) {
-      const double pn = fma(dk(i) - lam, p1, -(e2k(i - 1) * p2));
+      const double e = ek(i - 1);
+      const double pn = minor_next(dk(i) - lam, e * e, p1, p2);
       Dp[(int64_t)i * LDD + col] = guard(pn * recip(p1));
       p2 = p1;
       p1 = pn;
@@ -612,12 +624,11 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
   if (use_lds)
     sweep_down([&](int i) { return ush[0][i]; }, [&](int i) { return ush[1][i]; });
   else
-    sweep_down([&](int i) { return ds[i]; }, [&](int i) { return e2s[i]; });
+    sweep_down([&](int i) { return ds[i]; }, [&](int i) { return es[i]; });
 
   const int zl = lane_zero();
   const double* dsv = ds + zl;  // rows shared by the lanes, read as vector loads
   const double* esv = es + zl;
-  const double* e2v = e2s + zl;
   const double* Dpc = Dp + col;
   const double* Dmc = Dm + col;
   const double* Zc = Z + (valid ? j : 0);
@@ -625,11 +636,11 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
   const int ldd = n + EV_JUNK;  // element offsets fit in int for the orders handled here
   const int junk = n + (int)threadIdx.x;  // row 0 of this lane's spare column
   if (!cl_role) {
-    // Ud, Ue2: d and e^2 of row k; Ue, Uyr, Uyi: e and the probe of row k.
+    // Ud, Ue: d and e of row k; Uyr, Uyi: the probe of row k.
     auto iso = [&](auto Ud, auto Ue2) __attribute__((always_inline)) {
       // bottom-up pivots D- and the twist index (row n-1 first, then n-2 .. 0):
       // per block the minors' recurrence, then the ratios, stores and argmin
-      double q2 = 1.0, q1 = Ud(n - 1) - lam;
+      double q2 = 1.0, q1 = minor_next(Ud(n - 1) - lam, 0.0, 1.0, 0.0);
       Dm[(n - 1) * ldd + col] = guard(q1);
       double best = fabs(Dpc[(n - 1) * ldd]);
       int r = n - 1;
@@ -643,12 +654,13 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
             for (int u = 0; u < EV_TB; ++u) {
               const int k = max(n - 2 - (t0 + u), 0);
               as[u] = Ud(k) - lam;
-              e2k[u] = Ue2(k);
+              const double e = Ue2(k);
+              e2k[u] = e * e;
             }
             const double qlast = q1;
 #pragma unroll
             for (int u = 0; u < EV_TB; ++u) {
-              const double qn = fma(as[u], q1, -(e2k[u] * q2));
+              const double qn = minor_next(as[u], e2k[u], q1, q2);
               q2 = q1;
               q1 = qn;
               qs[u] = qn;
@@ -746,7 +758,7 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
       stage(es, nullptr, yproj);
       vec(r, L0, L1, L2);
     } else {
-      const int r = iso([&](int k) { return dsv[k]; }, [&](int k) { return e2v[k]; });
+      const int r = iso([&](int k) { return dsv[k]; }, [&](int k) { return esv[k]; });
       vec(r, [&](int k) { return esv[k]; }, [&](int k) { return yv[k * yld]; },
           [&](int k) { return yv[k * yld + 1]; });
     }
@@ -754,7 +766,6 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
   }
 
   // cluster members: inverse iteration through L D+ L^T (e_{n-1} is stored as 0)
-  const double tiny = 2.220446049250313e-16 * stat[3] * sigma;
   auto piv = [&](double v) { return fabs(v) >= tiny ? v : (v >= 0.0 ? tiny : -tiny); };
   auto inv = [&](auto Ue) __attribute__((always_inline)) {
     double scale = 1.0;
@@ -1284,7 +1295,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
              w.stat, w.grid, w.mu, info);
   BSE_LAUNCH(k_monotone, dim3(1), dim3(1024), 0, s, w.mu, (int)n, info);
   constexpr double ortol_rel = 1e-5;  // relative gap below which eigenvalues form a cluster
-  BSE_LAUNCH(k_eigvec, dim3(2 * cdiv(n, 64)), dim3(64), 0, s, w.ds, w.es, w.e2s, (int)n, w.mu,
+  BSE_LAUNCH(k_eigvec, dim3(2 * cdiv(n, 64)), dim3(64), 0, s, w.ds, w.es, (int)n, w.mu,
              w.stat, ortol_rel, w.Ztri, w.Dp, w.Dm, w.zs, project ? w.yvec : nullptr,
              XpY ? 1 : 0, w.tproj, info);
   BSE_LAUNCH(k_cluster_orth, dim3((unsigned)n), dim3(256), 0, s, w.mu, (int)n, ortol_rel, w.Ztri,
