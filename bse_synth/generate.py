@@ -11,6 +11,11 @@ Recipe (all complex draws are standard complex normal, E|z|^2 = 1):
   Mcv[a, G]        ~ CN / (1 + |G+Q|^2)  (or exp(-|G+Q|^2 / (2 w^2)) for core)
   Mvv[p, v, v', G] ~ CN / (1 + |G|^2)    (pairs p = (ik <= ik'))
   Mcc[p, c, c', G] ~ CN / (1 + |G|^2)
+                   (or, for mcc_generated workloads, only its description: the
+                   envelope 1 / (1 + |G|^2) and a 64-bit key; the values are
+                   drawn where they are used by a counter-based generator,
+                   Philox4x32-10 at counter (p, c, c', G) + Box-Muller, which
+                   each consumer implements from its published definition)
   Ncv[p, c, v', G], Nvc[p, v, c', G]  as Mvv (full BSE only)
   W[q] = v^1/2(q+G) (I + L_q L_q^H)^-1 v^1/2(q+G'),  L_q ~ 0.3 CN (NG x 8),
          v(p) = 4 pi / |p|^2 with |p|^2 replaced by 0.01 at p = 0.
@@ -85,6 +90,12 @@ def screened_interaction(w: Workload) -> np.ndarray:
     return W
 
 
+def mcc_key(w: Workload) -> int:
+    """64-bit key of the drawn Mcc: low word the workload seed, high word the
+    array kind."""
+    return (w.seed & 0xFFFFFFFF) | (_KIND["Mcc"] << 32)
+
+
 def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
     """All inputs of one BSE problem as NumPy arrays (host memory)."""
     nk, nv, nc, ng = w.nk, w.nv, w.nc, w.ng
@@ -108,7 +119,12 @@ def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
     if want_pairs:
         P = w.npairs
         out["Mvv"] = _complex_rows(w.seed, "Mvv", (P, nv, nv, ng), env)
-        out["Mcc"] = _complex_rows(w.seed, "Mcc", (P, nc, nc, ng), env)
+        if w.mcc_generated:
+            out["Mcc"] = None
+            out["mcc_env"] = env.astype(np.float64)
+            out["mcc_key"] = mcc_key(w)
+        else:
+            out["Mcc"] = _complex_rows(w.seed, "Mcc", (P, nc, nc, ng), env)
         if w.coupling == "full":
             out["Ncv"] = _complex_rows(w.seed, "Ncv", (P, nc, nv, ng), env)
             out["Nvc"] = _complex_rows(w.seed, "Nvc", (P, nv, nc, ng), env)

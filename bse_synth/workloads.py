@@ -38,6 +38,7 @@ class Workload:
     eps_c_range: tuple = (1.0, 5.0)
     core_level: float | None = None   # flat core levels (eV) instead of eps_v draws
     mcv_gauss_width: float | None = None  # Gaussian |G+Q| envelope of Mcv (bohr^-1)
+    mcc_generated: bool = False  # Mcc given by a key and an envelope, drawn where used
     scissor: float = 0.0
     note: str = ""
 
@@ -74,6 +75,19 @@ FULL_N6144 = _add(Workload(
     nw=4000, wmin=0.0, wmax=10.0, eta=0.05, seed=1, kernel_scale=0.25,
     note="Full BSE at Q=0, N=6144 transitions, 113 plane waves"))
 
+# Core-level (x-ray) TDA problem: two flat core levels at -400 eV, 32 conduction
+# bands, N = 32768, 137 plane waves, Mcv with a narrow Gaussian G-profile (a
+# localised core state), 8000 frequencies within 30 eV of the edge.  Its Mcc
+# would take 295 GB (131 328 pairs x 32 x 32 x 137), so it is given by a key and
+# an envelope and drawn where it is used.  With core transition energies near
+# 400 eV every kernel scale keeps A positive definite; s = 1 is the unscaled
+# prefactor 1/V_c.
+CORE_N32768 = _add(Workload(
+    name="core_tda_k8_c2c32_g137", mesh=8, nv=2, nc=32, ng=137, coupling="tda",
+    nw=8000, wmin=371.0, wmax=431.0, eta=0.05, seed=4, kernel_scale=1.0,
+    core_level=-400.0, mcv_gauss_width=0.5, mcc_generated=True,
+    note="Core-level TDA BSE, N=32768 transitions, 137 plane waves, Mcc drawn in place"))
+
 # Tiny problems used by the CPU pins and the GPU parity tests (several tiles
 # and ragged tails).
 TINY = {
@@ -89,6 +103,16 @@ TINY = {
     "mid_full": _add(Workload(name="mid_full_k4_v3c4_g59", mesh=4, nv=3, nc=4, ng=59,
                               coupling="full", nw=1000, wmin=0.0, wmax=10.0, eta=0.05,
                               seed=14, kernel_scale=0.0625)),
+    # the core-level structure (flat core levels, Gaussian Mcv, Mcc drawn in
+    # place) at sizes the oracle solves whole
+    "tiny_core": _add(Workload(name="tiny_core_k2_c2c6_g27", mesh=2, nv=2, nc=6, ng=27,
+                               coupling="tda", nw=300, wmin=371.0, wmax=431.0, eta=0.05,
+                               seed=15, kernel_scale=1.0, core_level=-400.0,
+                               mcv_gauss_width=0.5, mcc_generated=True)),
+    "mid_core": _add(Workload(name="mid_core_k4_c2c8_g59", mesh=4, nv=2, nc=8, ng=59,
+                              coupling="tda", nw=1000, wmin=371.0, wmax=431.0, eta=0.05,
+                              seed=16, kernel_scale=1.0, core_level=-400.0,
+                              mcv_gauss_width=0.5, mcc_generated=True)),
 }
 
 

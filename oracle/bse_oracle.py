@@ -33,6 +33,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import philox
+
 HARTREE_EV = 27.211386245988
 BSE_TYPES = {"singlet": (1.0, 1.0), "triplet": (0.0, 1.0), "rpa": (1.0, 0.0), "ip": (0.0, 0.0)}
 
@@ -145,6 +147,15 @@ def _place_blocks(nk: int, nvnc: int, ik, jk, blocks) -> np.ndarray:
     return K.reshape(nk * nvnc, nk * nvnc)
 
 
+def mcc(inputs: dict, ps) -> np.ndarray:
+    """M_{u u'}(G') of the pairs ps: the stored array, or the values drawn from
+    the workload's key and envelope (counter-based generator, oracle.philox)."""
+    if inputs.get("Mcc") is not None:
+        return inputs["Mcc"][ps]
+    w = inputs["workload"]
+    return philox.mcc_pairs(inputs["mcc_key"], inputs["mcc_env"], np.atleast_1d(ps), w.nc)
+
+
 def direct_blocks(inputs: dict, which: str, sel: np.ndarray | None = None) -> np.ndarray:
     """(nv*nc x nv*nc) blocks of W^rr ("rr") or W^ra ("ra") for the pairs `sel`
     (all pairs by default), contracted per momentum-transfer class:
@@ -159,15 +170,15 @@ def direct_blocks(inputs: dict, which: str, sel: np.ndarray | None = None) -> np
     out = np.empty((len(sel), nv, nc, nv, nc), dtype=np.complex128)
     Wq = inputs["W"]
     if which == "rr":
-        left, right = inputs["Mvv"], inputs["Mcc"]
+        left, right = inputs["Mvv"], (lambda ps: mcc(inputs, ps))
     else:
-        left, right = inputs["Ncv"], inputs["Nvc"]
+        left, right = inputs["Ncv"], (lambda ps: inputs["Nvc"][ps])
     for q in np.unique(qi):
         m = np.nonzero(qi == q)[0]
         ps = sel[m]
         L = np.conj(left[ps])
         T = (L.reshape(-1, ng) @ Wq[q]).reshape(L.shape)
-        R = right[ps]
+        R = right(ps)
         if which == "rr":
             # T[p, v, v', G'], R[p, c, c', G'] -> [p, v, c, v', c']
             out[m] = np.einsum("pabg,pcdg->pacbd", T, R)
@@ -205,7 +216,7 @@ def direct_literal(inputs: dict, which: str) -> np.ndarray:
             Wq = inputs["W"][qmat[k1, k2]]
             if which == "rr":
                 x = np.conj(inputs["Mvv"][p, o, o2])
-                y = inputs["Mcc"][p, u, u2]
+                y = mcc(inputs, [p])[0, u, u2]
             else:
                 x = np.conj(inputs["Ncv"][p, u, o2])
                 y = inputs["Nvc"][p, o, u2]
