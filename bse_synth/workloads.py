@@ -109,6 +109,10 @@ TINY = {
                                coupling="tda", nw=300, wmin=371.0, wmax=431.0, eta=0.05,
                                seed=15, kernel_scale=1.0, core_level=-400.0,
                                mcv_gauss_width=0.5, mcc_generated=True)),
+    "tiny_core_g137": _add(Workload(name="tiny_core_k2_c2c4_g137", mesh=2, nv=2, nc=4, ng=137,
+                                    coupling="tda", nw=300, wmin=371.0, wmax=431.0, eta=0.05,
+                                    seed=17, kernel_scale=1.0, core_level=-400.0,
+                                    mcv_gauss_width=0.5, mcc_generated=True)),
     "mid_core": _add(Workload(name="mid_core_k4_c2c8_g59", mesh=4, nv=2, nc=8, ng=59,
                               coupling="tda", nw=1000, wmin=371.0, wmax=431.0, eta=0.05,
                               seed=16, kernel_scale=1.0, core_level=-400.0,

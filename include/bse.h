@@ -97,7 +97,8 @@ typedef struct {
   const double* eps_c;   /* [nk][nc] unoccupied energies */
   const void* Mcv;       /* complex [n][ng]: M_a(G) of eq. vrrofM (pair a = (k, v, c)) */
   const void* Mvv;       /* complex [P][nv][nv'][ng]: M_{o o'}(G) of eq. wrrm for pair p */
-  const void* Mcc;       /* complex [P][nc][nc'][ng]: M_{u u'}(G') of eq. wrrm */
+  const void* Mcc;       /* complex [P][nc][nc'][ng]: M_{u u'}(G') of eq. wrrm, or NULL:
+                            drawn in place from mcc_env and mcc_key (below) */
   const void* Ncv;       /* complex [P][nc][nv'][ng]: N_{u o'}(G) of eq. wrabar (full only) */
   const void* Nvc;       /* complex [P][nv][nc'][ng]: N_{o u'}(G') of eq. wrabar (full only) */
   const void* W;         /* complex [nq][ng][ng]: screened interaction w_GG'(q), eq. wggq */
@@ -106,6 +107,17 @@ typedef struct {
   const int32_t* qramap; /* [nk][nk]: class of -k - k' (index into W), full only */
   int32_t nq;            /* number of W slices */
   int32_t reserved;
+  /* M_{u u'}(G') given implicitly, for problems where the array would not fit
+   * in memory (core-level spectra: P x nc^2 x ng values).  Used when Mcc is
+   * NULL:  M[p][u][u'][G] = mcc_env[G] * (x + i y) / sqrt(2), where x, y are
+   * the Box-Muller normals sqrt(-2 ln u1) (cos, sin)(2 pi u2) of the uniforms
+   * u1 = (k1 + 1) 2^-53 and u2 = k2 2^-53, k1 and k2 the top 53 bits of the
+   * 64-bit words (w1:w0) and (w3:w2) of the Philox4x32-10 block (Salmon et al.,
+   * SC'11) at counter (p, u, u', G) under key (mcc_key & 0xffffffff,
+   * mcc_key >> 32).  The values are drawn inside the direct-term contraction
+   * and never stored; results agree with the stored form to rounding. */
+  const double* mcc_env; /* [ng] real envelope (device), NULL when Mcc is given */
+  uint64_t mcc_key;
 } bse_inputs;
 
 /* Bytes of scratch space `ws` needed by bse_build (stage BUILD) or

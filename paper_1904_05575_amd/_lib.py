@@ -38,7 +38,8 @@ class BseInputs(ctypes.Structure):
                 ("Mcv", ctypes.c_void_p), ("Mvv", ctypes.c_void_p), ("Mcc", ctypes.c_void_p),
                 ("Ncv", ctypes.c_void_p), ("Nvc", ctypes.c_void_p), ("W", ctypes.c_void_p),
                 ("vbar", ctypes.c_void_p), ("qmap", ctypes.c_void_p), ("qramap", ctypes.c_void_p),
-                ("nq", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("nq", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mcc_env", ctypes.c_void_p), ("mcc_key", ctypes.c_uint64)]
 
 
 class BseTuneEntry(ctypes.Structure):

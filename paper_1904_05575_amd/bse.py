@@ -74,10 +74,13 @@ class Problem:
             "eps_c": _dev(inputs["eps_c"], f64, dv),
             "Mcv": _dev(inputs["Mcv"], c128, dv),
             "Mvv": _dev(inputs["Mvv"], c128, dv),
-            "Mcc": _dev(inputs["Mcc"], c128, dv),
             "W": _dev(inputs["W"], c128, dv),
             "qmap": _dev(inputs["qmap"], torch.int32, dv),
         }
+        if inputs.get("Mcc") is not None:
+            self.t["Mcc"] = _dev(inputs["Mcc"], c128, dv)
+        else:  # drawn in place from an envelope and a key
+            self.t["mcc_env"] = _dev(inputs["mcc_env"], f64, dv)
         if self.full:
             self.t["Ncv"] = _dev(inputs["Ncv"], c128, dv)
             self.t["Nvc"] = _dev(inputs["Nvc"], c128, dv)
@@ -99,7 +102,8 @@ class Problem:
         self.inp = L.BseInputs(eps_v=p("eps_v"), eps_c=p("eps_c"), Mcv=p("Mcv"), Mvv=p("Mvv"),
                                Mcc=p("Mcc"), Ncv=p("Ncv"), Nvc=p("Nvc"), W=p("W"),
                                vbar=p("vbar"), qmap=p("qmap"), qramap=p("qramap"),
-                               nq=int(inputs["W"].shape[0]), reserved=0)
+                               nq=int(inputs["W"].shape[0]), reserved=0,
+                               mcc_env=p("mcc_env"), mcc_key=int(inputs.get("mcc_key", 0)))
         self.info = torch.zeros(1, dtype=torch.int32, device=dv)
         self.ws_build = torch.empty(max(1, L.bse_workspace_size(self.desc, L.BSE_STAGE_BUILD)),
                                     dtype=torch.uint8, device=dv)

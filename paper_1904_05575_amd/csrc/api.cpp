@@ -2,6 +2,7 @@
 #include <math.h>
 
 #include "bse_internal.h"
+#include "timing.h"
 
 namespace {
 
@@ -33,10 +34,11 @@ size_t bse_workspace_size(const bse_desc* desc, int32_t stage) {
 
 bse_status bse_build(const bse_desc* d, const bse_inputs* in, void* H0, void* H1, void* ws,
                      size_t ws_bytes, int32_t* info, hipStream_t stream) {
+  launch_failure_reset();
   if (!desc_ok(d) || !in || !H0 || !info || !ws) return BSE_ERR_ARG;
   const bool full = d->coupling == BSE_FULL;
-  if (!in->eps_v || !in->eps_c || !in->Mcv || !in->Mvv || !in->Mcc || !in->W || !in->vbar ||
-      !in->qmap)
+  if (!in->eps_v || !in->eps_c || !in->Mcv || !in->Mvv || (!in->Mcc && !in->mcc_env) ||
+      !in->W || !in->vbar || !in->qmap)
     return BSE_ERR_ARG;
   if (full && (!in->Ncv || !in->Nvc || !in->qramap || !H1)) return BSE_ERR_ARG;
   if (in->nq <= 0 || in->nq > kMaxQ) return BSE_ERR_ARG;
@@ -48,6 +50,7 @@ bse_status bse_build(const bse_desc* d, const bse_inputs* in, void* H0, void* H1
 bse_status bse_solve(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, int64_t ldx,
                      const void* probe, double* osc, void* ws, size_t ws_bytes, int32_t* info,
                      hipStream_t stream) {
+  launch_failure_reset();
   if (!desc_ok(d) || !H0 || !E || !info || !ws) return BSE_ERR_ARG;
   const int64_t n = (int64_t)d->nk * d->nv * d->nc;
   if (d->coupling == BSE_FULL && !H1) return BSE_ERR_ARG;
@@ -60,6 +63,7 @@ bse_status bse_solve(const bse_desc* d, void* H0, void* H1, double* E, void* XpY
 
 bse_status bse_oscillator(int64_t n, const void* XpY, int64_t ldx, const void* probe, double* osc,
                           hipStream_t stream) {
+  launch_failure_reset();
   if (n <= 0 || !XpY || !probe || !osc || ldx < n) return BSE_ERR_ARG;
   return launch_oscillator(n, (const double2*)XpY, ldx, (const double2*)probe, osc, stream) ==
                  hipSuccess
@@ -69,6 +73,7 @@ bse_status bse_oscillator(int64_t n, const void* XpY, int64_t ldx, const void* p
 
 bse_status bse_spectrum(int64_t n, const double* E, const double* osc, double pref, double eta,
                         int64_t nw, const double* omega, void* eps, hipStream_t stream) {
+  launch_failure_reset();
   if (n <= 0 || nw <= 0 || !E || !osc || !omega || !eps) return BSE_ERR_ARG;
   if (!isfinite(pref) || !(eta > 0.0) || !isfinite(eta)) return BSE_ERR_ARG;
   return launch_spectrum(n, E, osc, pref, eta, nw, omega, (double2*)eps, stream) == hipSuccess
@@ -81,7 +86,10 @@ const char* bse_status_string(bse_status s) {
     case BSE_OK: return "ok";
     case BSE_ERR_ARG: return "invalid argument";
     case BSE_ERR_WORKSPACE: return "workspace too small";
-    case BSE_ERR_HIP: return "HIP launch failed";
+    case BSE_ERR_HIP: {
+      const char* m = launch_failure();
+      return m ? m : "HIP launch failed";
+    }
   }
   return "unknown status";
 }

@@ -131,6 +131,78 @@ __global__ __launch_bounds__(256) void k_stage1(const double2* __restrict__ Left
   });
 }
 
+// ---------------------------------------------------------------- stage 2, drawn M_cc
+// blk[pos][r][u u'] = sum_G' T[pos][r][G'] M[p][u][u'][G'] (p = perm[pos]) for
+// pair elements given by an envelope and a key instead of an array: each
+// M[p][u][u'][G'] is drawn where it is used, from the Philox4x32-10 block at
+// counter (p, u, u', G') (Salmon, Moraes, Dror, Shaw, SC'11: ten rounds of two
+// 32x32 -> 64-bit products, key bumped by the Weyl increments), turned into a
+// complex normal by Box-Muller and scaled by env[G'].  One thread per
+// (pair, u u'); the pair's rows of T, scaled by the envelope, sit in LDS and
+// are read as broadcasts.  The draws dominate (a log, a square root and a
+// sine/cosine pair per element), so the kernel is bound by the vector ALU.
+constexpr uint32_t PH_M0 = 0xD2511F53u, PH_M1 = 0xCD9E8D57u;  // round multipliers
+constexpr uint32_t PH_W0 = 0x9E3779B9u, PH_W1 = 0xBB67AE85u;  // key increments
+constexpr int S2D_THREADS = 256;
+constexpr int S2D_LDS = 4096;  // R x ng values of one pair held in LDS
+
+BSE_DEV double2 drawn_normal(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                             uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(PH_M0, c0), lo0 = PH_M0 * c0;
+    const uint32_t hi1 = __umulhi(PH_M1, c2), lo1 = PH_M1 * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += PH_W0;
+    k1 += PH_W1;
+  }
+  // uniforms from the top 53 bits of (w1:w0) and (w3:w2): u1 in (0, 1], u2 in [0, 1)
+  const uint64_t b1 = ((uint64_t)c1 << 32 | c0) >> 11;
+  const uint64_t b2 = ((uint64_t)c3 << 32 | c2) >> 11;
+  const double u1 = ((double)b1 + 1.0) * 0x1p-53;
+  const double u2 = (double)b2 * 0x1p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos((2.0 * M_PI) * u2, &sn, &cs);
+  constexpr double SQRT2 = 1.4142135623730951;
+  return make_double2((rad * cs) / SQRT2, (rad * sn) / SQRT2);
+}
+
+template <int RM>
+__global__ __launch_bounds__(S2D_THREADS) void k_stage2_drawn(
+    const double2* __restrict__ T, int R, int ng, int nc, const double* __restrict__ env,
+    uint64_t key, const int32_t* __restrict__ perm, double2* __restrict__ blk,
+    const int32_t* info) {
+  __shared__ double2 ts[S2D_LDS];
+  if (failed(info)) return;
+  const int pos = blockIdx.x;
+  const uint32_t p = (uint32_t)perm[pos];
+  const int n2 = nc * nc;
+  const double2* __restrict__ Tp = T + (int64_t)pos * R * ng;
+  for (int e = threadIdx.x; e < R * ng; e += S2D_THREADS) ts[e] = cscale(Tp[e], env[e % ng]);
+  __syncthreads();
+  const int cc = blockIdx.y * S2D_THREADS + threadIdx.x;
+  if (cc >= n2) return;
+  const uint32_t u = (uint32_t)(cc / nc), u2 = (uint32_t)(cc % nc);
+  const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+  double2 acc[RM];
+#pragma unroll
+  for (int r = 0; r < RM; ++r) acc[r] = make_double2(0.0, 0.0);
+  for (int g = 0; g < ng; ++g) {
+    const double2 z = drawn_normal(p, u, u2, (uint32_t)g, k0, k1);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+      if (r < R) acc[r] = cadd(acc[r], cmul(ts[r * ng + g], z));
+  }
+  double2* __restrict__ out = blk + (int64_t)pos * R * n2;
+#pragma unroll
+  for (int r = 0; r < RM; ++r)
+    if (r < R) out[(int64_t)r * n2 + cc] = acc[r];
+}
+
 // ---------------------------------------------------------------- combine
 // Scatter the per-pair blocks into the output matrices (column-major, ld).
 //   rr block: blk_rr[pos][(v*nv + v')][(c*nc + c')]
@@ -258,6 +330,8 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   double gx, gc;
   bse_gamma(d->type, &gx, &gc);
   const double kap = d->kappa;
+  // drawn M_cc: the pair's rows of T must fit in LDS (checked before any launch)
+  if (!in->Mcc && ((int64_t)nv * nv > 16 || (int64_t)nv * nv * ng > S2D_LDS)) return BSE_ERR_ARG;
 
   WsLayout L(ws);
   int32_t* perm_rr = (int32_t*)L.add(P * 4);
@@ -332,6 +406,16 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
       dim3 grid((unsigned)(nq * tiles), (unsigned)cdiv(ng, S1_BN));
       BSE_LAUNCH(k_stage1, grid, dim3(256), 0, s, (const double2*)left, R, ng,
                  (const double2*)in->W, perm, cls, tiles, T, info);
+    }
+    if (!right) {  // M_cc drawn in place (resonant term only)
+      const dim3 grid((unsigned)P, (unsigned)cdiv(N2, S2D_THREADS));
+      if (R <= 4)
+        BSE_LAUNCH(k_stage2_drawn<4>, grid, dim3(S2D_THREADS), 0, s, T, R, ng, nc, in->mcc_env,
+                   in->mcc_key, perm, blk, info);
+      else
+        BSE_LAUNCH(k_stage2_drawn<16>, grid, dim3(S2D_THREADS), 0, s, T, R, ng, nc, in->mcc_env,
+                   in->mcc_key, perm, blk, info);
+      return hipGetLastError() == hipSuccess;
     }
     ZgemmParams g;
     g.M = R;

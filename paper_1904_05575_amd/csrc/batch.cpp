@@ -97,6 +97,7 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
                              double* const* osc, const double* pref, const double* eta,
                              const int64_t* nw, const double* const* omega, void* const* eps,
                              void* ws, size_t ws_bytes, int32_t* info, hipStream_t stream) {
+  launch_failure_reset();
   if (!b || !inputs || !H0 || !E || !probe || !osc || !pref || !eta || !nw || !omega || !eps ||
       !ws || !info)
     return BSE_ERR_ARG;
@@ -108,8 +109,8 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
     if (!H0[i] || !E[i] || !probe[i] || !osc[i] || !omega[i] || !eps[i] || nw[i] <= 0) return BSE_ERR_ARG;
     if (d->coupling == BSE_FULL && (!H1 || !H1[i] || !in->Ncv || !in->Nvc || !in->qramap))
       return BSE_ERR_ARG;
-    if (!in->eps_v || !in->eps_c || !in->Mcv || !in->Mvv || !in->Mcc || !in->W || !in->vbar ||
-        !in->qmap || in->nq <= 0 || in->nq > kMaxQ)
+    if (!in->eps_v || !in->eps_c || !in->Mcv || !in->Mvv || (!in->Mcc && !in->mcc_env) ||
+        !in->W || !in->vbar || !in->qmap || in->nq <= 0 || in->nq > kMaxQ)
       return BSE_ERR_ARG;
     if (!(eta[i] > 0.0)) return BSE_ERR_ARG;
     if (d->prec != BSE_PREC_FP64 && in->nq > d->nk) return BSE_ERR_ARG;
@@ -158,6 +159,7 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
 }
 
 bse_status bse_batch_run(bse_batch_t b, hipStream_t stream) {
+  launch_failure_reset();
   if (!b || !b->exec) return BSE_ERR_ARG;
   return hipGraphLaunch(b->exec, stream) == hipSuccess ? BSE_OK : BSE_ERR_HIP;
 }

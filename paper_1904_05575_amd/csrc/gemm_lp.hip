@@ -217,8 +217,9 @@ __global__ __launch_bounds__(256) void k_split_w(const double2* __restrict__ W, 
 }
 
 // T[pos*R + sub, G'] = sum_G conj(L[p][sub][G]) W[q][G][G'] in the precision
-// form: 64 rows x all n2p real columns per block of 8 wavefronts (4 row groups
-// x 2 column halves of 8 tiles).  Each wavefront loads and splits its own A
+// form: 64 rows x up to S1L_NMAX real columns per block of 8 wavefronts (4 row
+// groups x 2 column halves of 8 tiles); wider W(q) (n2p > S1L_NMAX) take
+// several column blocks (blockIdx.y), each splitting its rows of A again.  Each wavefront loads and splits its own A
 // fragments (eight consecutive real k per lane); the block stages the split
 // W(q) through two LDS buffers, one 32-deep slice ahead in registers.  FP32
 // accumulation inside a slice (16 complex k), FP64 across slices.
@@ -252,7 +253,8 @@ __global__ __launch_bounds__(512) void k_stage1_lp(const double2* __restrict__ L
   if (m0 >= rows) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int rg = wid & 3, hf = wid >> 2, g = lane >> 4, l16 = lane & 15;
-  const int ntiles = n2p / 16;
+  const int col0 = blockIdx.y * S1L_NMAX;  // first real column of this block
+  const int ntiles = min(S1L_NMAX, n2p - col0) / 16;
   const int64_t per = (int64_t)n2p * k2p;
   const int nslices = k2p / S1L_KS;
 
@@ -281,12 +283,12 @@ __global__ __launch_bounds__(512) void k_stage1_lp(const double2* __restrict__ L
     for (int u = 0; u < UPT; ++u) {
       const int e = tid + 512 * u;
       if constexpr (PREC == BSE_PREC_FP32) {
-        const int kk = e / (S1L_NMAX / 4), c4 = min(e % (S1L_NMAX / 4), n2p / 4 - 1);
+        const int kk = e / (S1L_NMAX / 4), c4 = min(col0 / 4 + e % (S1L_NMAX / 4), n2p / 4 - 1);
         const int64_t off = (int64_t)q * per + (int64_t)(k0 + kk) * n2p + 4 * c4;  // floats
         bn[u] = *(const u32x4*)((const float*)Wsp + off);
       } else {
         const int seg = e & 3, row = e >> 2;  // row = plane * S1L_NMAX + n
-        const int plane = row / S1L_NMAX, nn = min(row % S1L_NMAX, n2p - 1);
+        const int plane = row / S1L_NMAX, nn = min(col0 + row % S1L_NMAX, n2p - 1);
         const int64_t off =
             (int64_t)q * 3 * per + (int64_t)plane * per + (int64_t)nn * k2p + k0 + 8 * seg;
         bn[u] = *(const u32x4*)((const unsigned short*)Wsp + off);
@@ -400,8 +402,8 @@ __global__ __launch_bounds__(512) void k_stage1_lp(const double2* __restrict__ L
   for (int j = 0; j < NTW; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = m0 + rg * 16 + 4 * g + r, n2 = 16 * (hf * NTW + j) + l16;
-      if (m < rows && n2 < 2 * ng) Td[((int64_t)s0 * R + m) * (2 * ng) + n2] = acc64[j][r];
+      const int m = m0 + rg * 16 + 4 * g + r, n2 = col0 + 16 * (hf * NTW + j) + l16;
+      if (hf * NTW + j < ntiles && m < rows && n2 < 2 * ng) Td[((int64_t)s0 * R + m) * (2 * ng) + n2] = acc64[j][r];
     }
 }
 
@@ -468,9 +470,8 @@ bool launch_stage1_lp(int prec, int nterms, const double2* left, int R, int ng, 
                       const int32_t* perm, const int32_t* cls, int nq, int nk, double2* T,
                       const int32_t* info, hipStream_t s) {
   const int n2p = lp_n2p(ng), k2p = lp_k2p(ng);
-  if (n2p > S1L_NMAX) return false;
   const int tiles = cdiv((int64_t)nk * R, S1L_BM);
-  dim3 grid((unsigned)(nq * tiles));
+  dim3 grid((unsigned)(nq * tiles), (unsigned)cdiv(n2p, S1L_NMAX));
   if (prec == BSE_PREC_FP32)
     BSE_LAUNCH((k_stage1_lp<BSE_PREC_FP32>), grid, dim3(512), 0, s, left, R, ng, Wsp, n2p, k2p,
                perm, cls, tiles, nterms, T, info);

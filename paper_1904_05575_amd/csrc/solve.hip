@@ -193,23 +193,31 @@ __global__ __launch_bounds__(256) void k_hermitize(double2* __restrict__ M, int6
 }
 
 // ------------------------------------------------------------------ tridiagonal eigensolver
-// T (diagonal d, off-diagonal e) is solved through a copy scaled by a power of
-// two sigma that brings its Gershgorin norm into [1/2, 1).  The leading and
-// trailing principal minors of T - x I then grow by at most a factor 3 per row
-// and are carried as plain numbers, renormalised by a power of two every MR
-// rows (exact, ratios unchanged): no division sits on their recurrence.
+// T (diagonal d, off-diagonal e) is solved through the copy (T - c I) sigma:
+// shifted by the centre c of its Gershgorin interval, so that the rounding of
+// every later step is relative to the spread of the spectrum, not to its
+// distance from zero (core-level spectra sit far from zero), and scaled by a
+// power of two sigma that brings its Gershgorin norm into [1/2, 1).  The
+// leading and trailing principal minors of the copy minus x I then grow by at
+// most a factor 3 per row and are carried as plain numbers, renormalised by a
+// power of two every MR rows (exact, ratios unchanged): no division sits on
+// their recurrence.  Eigenvalues are kept as lambda - c (unscaled) until the
+// output, so that the eigenvector kernels see them without the rounding of c.
 //
-// stat: [0] gl, [1] gu  Gershgorin bounds of the scaled T, widened by the
-//                       rounding of the counts
+// stat: [0] gl, [1] gu  Gershgorin bounds of the shifted, scaled T, widened by
+//                       the rounding of the counts
 //       [2] pivmin      the underflow threshold (bisection tolerance)
-//       [3] tnorm       Gershgorin norm of T (unscaled)
+//       [3] tnorm       Gershgorin norm of T - c I (unscaled; at least eps
+//                       times that of T)
 //       [4] sigma       the scale
+//       [5] c           the shift
 constexpr int MR = 8;                  // rows between renormalisations of the minors
 constexpr double E2_FLOOR = 0x1p-600;  // floor of e^2 in the minor recurrences
 constexpr int BS_G = 16384;            // points of the shared Sturm-count grid
 constexpr int BS_L = 8;                // probe points per eigenvalue and round
 constexpr int EV_NLDS = 6400;          // largest order whose shared rows (3 doubles) fit in LDS
 constexpr int EV_JUNK = 64;            // spare columns of the pivot arrays
+constexpr int STAT_N = 8;              // doubles of stat
 
 __global__ __launch_bounds__(1024) void k_tri_prep(const double* __restrict__ d,
                                                    const double* __restrict__ e, int n,
@@ -217,33 +225,44 @@ __global__ __launch_bounds__(1024) void k_tri_prep(const double* __restrict__ d,
                                                    double* __restrict__ e2s, double* stat,
                                                    const int32_t* info) {
   __shared__ double slo[16], shi[16];
-  __shared__ double ssig;
   if (failed(info)) return;
-  double lo = INFINITY, hi = -INFINITY;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double em = (k > 0) ? fabs(e[k - 1]) : 0.0, ep = (k < n - 1) ? fabs(e[k]) : 0.0;
-    lo = fmin(lo, d[k] - em - ep);
-    hi = fmax(hi, d[k] + em + ep);
-  }
-  for (int off = 32; off >= 1; off >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, off, 64));
-    hi = fmax(hi, __shfl_xor(hi, off, 64));
-  }
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
-    slo[w] = lo;
-    shi[w] = hi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
-      lo = fmin(lo, slo[i]);
-      hi = fmax(hi, shi[i]);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  // Gershgorin interval of T - shift I, every thread gets it
+  auto gersh = [&](double shift, double& glo, double& ghi) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      const double em = (k > 0) ? fabs(e[k - 1]) : 0.0, ep = (k < n - 1) ? fabs(e[k]) : 0.0;
+      const double dk = d[k] - shift;
+      lo = fmin(lo, dk - em - ep);
+      hi = fmax(hi, dk + em + ep);
     }
-    const double tnorm = fmax(fabs(lo), fabs(hi));
-    const double sigma =
-        (tnorm > 0.0 && tnorm < INFINITY) ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(tnorm)) : 1.0;
-    const double eps = 2.220446049250313e-16;
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, off, 64));
+      hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    __syncthreads();  // earlier readers of slo, shi are done
+    if (lane == 0) {
+      slo[w] = lo;
+      shi[w] = hi;
+    }
+    __syncthreads();
+    glo = slo[0];
+    ghi = shi[0];
+    for (int i = 1; i < nw; ++i) {
+      glo = fmin(glo, slo[i]);
+      ghi = fmax(ghi, shi[i]);
+    }
+  };
+  double lo0, hi0;
+  gersh(0.0, lo0, hi0);
+  const double c = (lo0 > -INFINITY && hi0 < INFINITY) ? 0.5 * (lo0 + hi0) : 0.0;
+  double lo, hi;
+  gersh(c, lo, hi);
+  const double eps = 2.220446049250313e-16;
+  const double tnorm = fmax(fmax(fabs(lo), fabs(hi)), eps * fmax(fabs(lo0), fabs(hi0)));
+  const double sigma =
+      (tnorm > 0.0 && tnorm < INFINITY) ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(tnorm)) : 1.0;
+  if (threadIdx.x == 0) {
     const double pivmin = 2.2250738585072014e-308;  // e^2 <= 1 after scaling
     const double tn = tnorm * sigma;
     stat[0] = lo * sigma - 2.0 * eps * tn * n - 2.0 * pivmin;
@@ -251,12 +270,10 @@ __global__ __launch_bounds__(1024) void k_tri_prep(const double* __restrict__ d,
     stat[2] = pivmin;
     stat[3] = tnorm;
     stat[4] = sigma;
-    ssig = sigma;
+    stat[5] = c;
   }
-  __syncthreads();
-  const double sigma = ssig;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    ds[k] = d[k] * sigma;
+    ds[k] = (d[k] - c) * sigma;
     const double v = (k < n - 1) ? e[k] * sigma : 0.0;  // es, e2s carry a zero at n-1
     es[k] = v;
     e2s[k] = (k < n - 1) ? fmax(v * v, E2_FLOOR) : 0.0;
@@ -517,7 +534,9 @@ constexpr int EV_NB2 = 4;  // the same with two values per step
 // keeps z unnormalised; zs[j] = +-1 / |z| makes it unit length with its
 // largest component positive.
 //
-// Eigenvalues of a cluster (gap <= ortol_rel |lambda|, blocks nb .. 2nb-1): two
+// Eigenvalues of a cluster (neighbours closer than ortol_rel ||T - c I||, an
+// absolute gap: the angle between a computed vector and the true one is about
+// eps ||T - c I|| / gap; blocks nb .. 2nb-1): two
 // solves of (T - lambda I) x = b through the top-down LDL^T factorisation
 // (pivots kept at least eps tnorm in magnitude) from a pseudo-random start,
 // the second from the normalised first; k_cluster_orth then orthonormalises
@@ -541,7 +560,7 @@ __global__ __launch_bounds__(64) void k_eigvec(const double* __restrict__ ds,
   const int j = ((int)blockIdx.x - (cl_role ? nb : 0)) * 64 + (int)threadIdx.x;
   const bool valid = j < n;
   auto close = [&](int a) {  // eigenvalues a and a+1
-    return w[a + 1] - w[a] <= ortol_rel * fmax(fabs(w[a]), fabs(w[a + 1]));
+    return w[a + 1] - w[a] <= ortol_rel * stat[3];
   };
   const bool member = valid && ((j > 0 && close(j - 1)) || (j + 1 < n && close(j)));
   const bool act = valid && (member == cl_role);
@@ -846,6 +865,7 @@ BSE_DEV ArgMax argmax_merge(ArgMax x, ArgMax y) {
 // eigenvalue): modified Gram-Schmidt, two passes, over the members in order,
 // then unit length with the largest component positive.
 __global__ __launch_bounds__(256) void k_cluster_orth(const double* __restrict__ w, int n,
+                                                      const double* __restrict__ stat,
                                                       double ortol_rel, double* __restrict__ Z,
                                                       const double2* __restrict__ yproj,
                                                       double2* __restrict__ tproj,
@@ -856,7 +876,7 @@ __global__ __launch_bounds__(256) void k_cluster_orth(const double* __restrict__
   if (failed(info)) return;
   const int k = blockIdx.x;
   auto close = [&](int a) {
-    return w[a + 1] - w[a] <= ortol_rel * fmax(fabs(w[a]), fabs(w[a + 1]));
+    return w[a + 1] - w[a] <= ortol_rel * stat[3];
   };
   if (k + 1 >= n || !close(k) || (k > 0 && close(k - 1))) return;
   int kend = k + 1;
@@ -917,14 +937,15 @@ __global__ __launch_bounds__(256) void k_cluster_orth(const double* __restrict__
 // E = sqrt(mu) (full) and the column scale of Z (E^-1/2), or E = mu (TDA); the
 // column scale also carries the normalisation zs of the tridiagonal eigenvectors.
 // With tproj (z^T of the projected probe, unnormalised), osc = |tproj|^2 scale^2.
-__global__ void k_eigvals(const double* __restrict__ mu, const double* __restrict__ zs, int n,
-                          int full, double* __restrict__ E, double* __restrict__ colscale,
+__global__ void k_eigvals(const double* __restrict__ mu, const double* __restrict__ stat,
+                          const double* __restrict__ zs, int n, int full,
+                          double* __restrict__ E, double* __restrict__ colscale,
                           const double2* __restrict__ tproj, double* __restrict__ osc,
                           int32_t* info) {
   if (failed(info)) return;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const double m = mu[k];
+  const double m = mu[k] + stat[5];  // mu holds lambda - c
   if (full) {
     if (!(m > 0.0)) {
       set_info(info, BSE_INFO_NOT_PD_PLUS);
@@ -1079,7 +1100,7 @@ SolveWs carve(const bse_desc* d, void* base) {
   w.mu = (double*)L.add(n * 8);
   w.zs = (double*)L.add(n * 8);
   w.colscale = (double*)L.add(n * 8);
-  w.stat = (double*)L.add(8 * 8);
+  w.stat = (double*)L.add(STAT_N * 8);
   w.grid = (int32_t*)L.add(BS_G * 4);
   w.counters = (int32_t*)L.add(64 * 4);
   w.total = L.total;
@@ -1294,13 +1315,15 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
   BSE_LAUNCH(k_bisect, dim3(cdiv(n, 4 * (64 / BS_L))), dim3(256), 0, s, w.ds, w.e2s, (int)n,
              w.stat, w.grid, w.mu, info);
   BSE_LAUNCH(k_monotone, dim3(1), dim3(1024), 0, s, w.mu, (int)n, info);
-  constexpr double ortol_rel = 1e-5;  // relative gap below which eigenvalues form a cluster
+  constexpr double ortol_rel = 1e-5;  // gap, relative to ||T - c I||, of a cluster
   BSE_LAUNCH(k_eigvec, dim3(2 * cdiv(n, 64)), dim3(64), 0, s, w.ds, w.es, (int)n, w.mu,
              w.stat, ortol_rel, w.Ztri, w.Dp, w.Dm, w.zs, project ? w.yvec : nullptr,
              XpY ? 1 : 0, w.tproj, info);
-  BSE_LAUNCH(k_cluster_orth, dim3((unsigned)n), dim3(256), 0, s, w.mu, (int)n, ortol_rel, w.Ztri,
+  BSE_LAUNCH(k_cluster_orth, dim3((unsigned)n), dim3(256), 0, s, w.mu, (int)n, w.stat, ortol_rel,
+             w.Ztri,
              project ? w.yvec : nullptr, w.tproj, info);
-  BSE_LAUNCH(k_eigvals, dim3(cdiv(n, 256)), dim3(256), 0, s, w.mu, w.zs, (int)n, full ? 1 : 0, E,
+  BSE_LAUNCH(k_eigvals, dim3(cdiv(n, 256)), dim3(256), 0, s, w.mu, w.stat, w.zs, (int)n,
+             full ? 1 : 0, E,
              w.colscale, project ? w.tproj : nullptr, osc, info);
 
   if (XpY) {

@@ -36,6 +36,22 @@ hipEvent_t get_event() {
 
 bool timing_on() { return enabled; }
 
+namespace {
+thread_local char fail_msg[256];
+}
+
+void launch_check(const char* name) {
+  const hipError_t e = hipPeekAtLastError();
+  if (e != hipSuccess && fail_msg[0] == 0)
+    snprintf(fail_msg, sizeof fail_msg, "HIP launch failed after %s: %s", name,
+             hipGetErrorString(e));
+}
+void launch_failure_reset() {
+  fail_msg[0] = 0;
+  (void)hipGetLastError();  // an error left by other code is not this call's
+}
+const char* launch_failure() { return fail_msg[0] ? fail_msg : nullptr; }
+
 void timing_begin(const char* name, hipEvent_t* a, hipEvent_t* b) {
   std::lock_guard<std::mutex> g(mu);
   while (*name == '(') ++name;  // launch macros may parenthesise template names

@@ -19,6 +19,13 @@ struct TimedLaunch {
   }
 };
 
+// Launch failures: the first kernel after which the runtime reports an error
+// is remembered (per thread) until the next public call starts, so that the
+// status string can name it.
+void launch_check(const char* name);
+void launch_failure_reset();
+const char* launch_failure();
+
 #define BSE_LAUNCH(kern, grid, block, shmem, stream, ...)                                 \
   do {                                                                                    \
     TimedLaunch _tl(#kern, stream);                                                       \
@@ -26,4 +33,5 @@ struct TimedLaunch {
       hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, _tl.a, _tl.b, 0, __VA_ARGS__); \
     else                                                                                  \
       hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                  \
+    launch_check(#kern);                                                                  \
   } while (0)

@@ -88,6 +88,7 @@ hipError_t launch(const ZgemmParams& p, int batch, hipStream_t s) {
                             first ? tl.a : nullptr, last ? tl.b : nullptr, 0, p, b0);
     else
       hipLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, b0);
+    launch_check(p.tag);
   }
   return hipGetLastError();
 }

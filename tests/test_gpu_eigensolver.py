@@ -112,3 +112,55 @@ def test_prescribed_spectra(name, vectors):
         x = r["X"]
         assert np.abs(a @ x - x * e).max() <= 1e-11 * scale * len(e)
         assert np.abs(x.conj().T @ x - np.eye(len(e))).max() <= 1e-8
+
+
+def _reflect(a, v):
+    """H a H with H = I - 2 v v^H (|v| = 1), in O(n^2)."""
+    av = a @ v
+    vha = v.conj() @ a
+    c = v.conj() @ av
+    return (a - 2.0 * np.outer(v, vha) - 2.0 * np.outer(av, v.conj())
+            + 4.0 * c * np.outer(v, v.conj()))
+
+
+def test_order_beyond_lds_staging_known_spectrum():
+    """n = 6656, above the order whose shared rows the eigenvector kernel keeps
+    in LDS: A = Q diag(lam) Q^H with Q a product of three Householder
+    reflectors, so the eigenvalues are lam and the oscillator strengths
+    |(Q^H p)_l|^2 by construction.  lam holds two triples of equal values (the
+    cluster path) among values spaced 3e-4 apart."""
+    torch = pytest.importorskip("torch")
+    nv, nc = 2, 3328
+    P = _problem(nv, nc)
+    n = P.n
+    rng = np.random.default_rng(9)
+    lam = np.linspace(1.0, 3.0, n)
+    lam[100:103] = lam[100]
+    lam[5000:5003] = lam[5000]
+    perm = rng.permutation(n)
+    a = np.diag(lam[perm]).astype(complex)
+    p = P.t["probe"].cpu().numpy()
+    vs = []
+    for _ in range(3):
+        v = rng.normal(size=n) + 1j * rng.normal(size=n)
+        v /= np.linalg.norm(v)
+        a = _reflect(a, v)
+        vs.append(v)
+    y = p.copy()  # A = Q D Q^H with Q = H3 H2 H1, so Q^H p = H1 H2 H3 p
+    for v in vs[::-1]:
+        y = y - 2.0 * v * np.vdot(v, y)
+    a = 0.5 * (a + a.conj().T)
+    ref_osc = np.abs(y) ** 2  # in the order of diag(lam[perm])
+    H0 = torch.tensor(a.T.copy(), dtype=torch.complex128, device="cuda")
+    del a
+    print(f"[gpu] prescribed known-spectrum n={n}", flush=True)
+    E, _, osc = P.solve(H0, None, vectors=False)
+    P.check_info()
+    e, o = E.cpu().numpy(), osc.cpu().numpy()
+    assert np.all(np.diff(e) >= 0)
+    assert np.abs(e - np.sort(lam)).max() <= 1e-12 * 3.0 * n
+    order = np.argsort(lam[perm], kind="stable")
+    ref = ref_osc[order]
+    pn2 = float(np.vdot(p, p).real)
+    for g in _clusters(np.sort(lam), 1e-6):
+        assert abs(o[g].sum() - ref[g].sum()) <= 1e-9 * pn2, g

@@ -60,6 +60,13 @@ def test_argument_errors_are_reported_without_launching(lib):
         L.bse_build(_desc(prec=L.BSE_PREC_BF16X3), full, 1, 1, 1, 1 << 40, 1, 0)  # split: nq <= nk
     with pytest.raises(L.BseError, match="BSE_ERR_WORKSPACE"):     # FP64 accepts nq > nk
         L.bse_build(d, full, 1, 1, 1, 16, 1, 0)
+    drawn = L.BseInputs(eps_v=1, eps_c=1, Mcv=1, Mvv=1, Mcc=None, Ncv=1, Nvc=1, W=1, vbar=1,
+                        qmap=1, qramap=1, nq=9, reserved=0, mcc_env=None, mcc_key=5)
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):          # no Mcc and no envelope
+        L.bse_build(d, drawn, 1, 1, 1, 1 << 40, 1, 0)
+    drawn.mcc_env = 1
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):          # drawn Mcc: nv^2 <= 16
+        L.bse_build(_desc(nv=5, ld=120), drawn, 1, 1, 1, 1 << 40, 1, 0)
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
         L.bse_solve(d, 1, 0, 1, 0, 48, 0, 0, 1, 1 << 30, 1, 0)   # full needs H1
     with pytest.raises(L.BseError, match="BSE_ERR_WORKSPACE"):
