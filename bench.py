@@ -64,6 +64,30 @@ def kernel_roofline_table(w) -> dict:
     }
 
 
+def measured_traffic(kernel: str, n: int):
+    """Bytes per launch fetched by `kernel` at order n, from a committed
+    rocprofv3 FETCH_SIZE summary (scaled by its copy-kernel calibration), or
+    None when there is none or the kernel's source changed since it was taken."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("machine-readable:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+            if kv.get("kernel") != kernel or int(kv.get("order", -1)) != n:
+                continue
+            src = os.path.join(here, kv["source"])
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["sha256"]:
+                return None
+            return {"bytes": float(kv["fetch_bytes_per_launch"]),
+                    "source": os.path.relpath(path, here),
+                    "note": "FETCH_SIZE only (bytes read, calibrated against a 1 GiB copy); "
+                            "no WRITE_SIZE count exists"}
+    return None
+
+
 def cpu_baseline(inputs, w, budget_s: float = 20.0) -> dict:
     """The oracle's assembly timed on a bounded sample of k-pairs."""
     from oracle import bse_oracle as O
@@ -248,8 +272,12 @@ def main() -> int:
             ach, peak, u = per_launch / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
         else:
             ach, peak, u = per_launch / avg_s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+        tr = measured_traffic(dom, w.n) if bound == "hbm" else None
         roof = {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": u,
-                "frac": ach / peak, "traffic": None, "launches_per_step": launches / args.steps,
+                "frac": ach / peak, "traffic": tr["bytes"] if tr else None,
+                "traffic_unit": "B per launch", "traffic_source": tr["source"] if tr else None,
+                "traffic_note": tr["note"] if tr else None,
+                "launches_per_step": launches / args.steps,
                 "avg_launch_us": total_ms / launches * 1e3,
                 "ms_per_step_with_events": roof_step_ms,
                 "per_launch_" + ("bytes" if bound == "hbm" else "flop"): per_launch}
