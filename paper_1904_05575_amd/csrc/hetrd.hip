@@ -33,7 +33,13 @@ constexpr int HT = 64;          // square tile of the hemv kernel
 constexpr int HV_THREADS = 1024; // hemv block: 16 wavefronts, 4 tile columns each
 constexpr int NVAL = 2 + 2 * TRD_NB;  // |x|^2, conj(x) y_probe, V^H x (i), W^H x (i)
 
-// Partial sums of y = S v for a trailing matrix of order m starting at row b0,
+// The hemv tiling of the trailing matrix (rows and columns b0..n-1) starts at
+// org = b0 rounded down to 8 elements (128 bytes), so that every column segment
+// of a tile covers whole cache lines (unaligned segments fetch one line more in
+// eight); rows and columns org..b0-1 are masked (v = 0 there).
+__host__ __device__ inline int trd_org(int b0) { return b0 & ~7; }
+
+// Partial sums of y = S v for a trailing matrix of order m starting at row org,
 // cut into nI x nI tiles of order HT (lower triangle: tile-row I >= tile-column
 // J).  The hemv kernel's work unit is tile-row I over the panels
 // J = kK .. min(I, kK + K - 1) (chunk k).  Row r, in tile-row Ir, collects
@@ -155,9 +161,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     wr[u] = VW[rc + (int64_t)(TRD_NB + ip) * N];
   }
   // y_{c-1}[r]: the previous hemv kernel's slots, QP threads per row
-  const int nIp = i > 0 ? cdiv(n - c, HT) : 0;
+  const int orgp = trd_org(c);  // origin of the tiling of the hemv launch for reflector c-1
+  const int nIp = i > 0 ? cdiv(n - orgp, HT) : 0;
   const int Kp = kprev;  // unit width of the hemv launch that produced the slots
-  const int Ir = (rc - c) / HT, nrs = cdiv(Ir + 1, Kp), tot = max(nrs + nIp - Ir, 1);
+  const int Ir = (rc - orgp) / HT, nrs = cdiv(Ir + 1, Kp), tot = max(nrs + nIp - Ir, 1);
   double2 ysl[YCH];
 #pragma unroll
   for (int u = 0; u < YCH; ++u) ysl[u] = Y[yslot(min(qq + u * QP, tot - 1), Ir, nrs, ycs, N, rc)];
@@ -418,9 +425,9 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   __shared__ double2 vrow[2][HT];
   __shared__ double2 rpart[NW * 4][HT];  // [wavefront x lane group][row]
   __shared__ double2 pred[NW];
-  const int c = j0 + i, b0 = c + 1;
+  const int c = j0 + i, b0 = c + 1, org = trd_org(b0);
   const int64_t N = n;
-  const int m = n - b0;
+  const int m = n - org;
   const int nI = cdiv(m, HT), nunits = hemv_units(nI, K);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;  // row in slab, column group
@@ -451,8 +458,8 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   };
   // loads without conditions (indices clamped; past the end, values unused)
   auto load = [&](Rec& rc, const Cur& q) {
-    const int rb0 = b0 + q.I * HT;
-    const int64_t j = min(b0 + (q.k * K + q.t) * HT + jl, nlast);
+    const int rb0 = org + q.I * HT;
+    const int64_t j = min(org + (q.k * K + q.t) * HT + jl, nlast);
 #pragma unroll
     for (int s = 0; s < NL; ++s) rc.s[s] = M[min(rb0 + 16 * s + lr, nlast) + j * ld];
     rc.xj = xcol[j];
@@ -467,7 +474,7 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   Cur C{(int)blockIdx.x, 0, 0, 0, 1, 0};
   decode(C);
   const double2 ax = xcol[b0];
-  const double2 xv0 = xcol[min(b0 + C.I * HT + (tid & (HT - 1)), nlast)];
+  const double2 xv0 = xcol[min(org + C.I * HT + (tid & (HT - 1)), nlast)];
   constexpr int PQ = 4;  // partial sums per lane issued together
   double2 pq[PQ];
   const int t0 = 1 + (int)blockIdx.x;  // first value of wavefront 1
@@ -563,10 +570,10 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     }
   }
   auto vval = [&](int e, double2 x) -> double2 {
-    return (e < n) ? ((e == b0) ? make_double2(1.0, 0.0) : cmul(scal, x)) : zero;
+    return (e < n && e >= b0) ? ((e == b0) ? make_double2(1.0, 0.0) : cmul(scal, x)) : zero;
   };
   int ub = 0;  // vrow buffer of the current unit
-  if (tid < HT) vrow[0][tid] = vval(b0 + C.I * HT + tid, xv0);
+  if (tid < HT) vrow[0][tid] = vval(org + C.I * HT + tid, xv0);
   __syncthreads();
 
   double2 ra[NL] = {zero, zero, zero, zero};
@@ -575,13 +582,14 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   auto tile = [&](const Rec& cb, Rec& nb) {
     // x on the rows of the next unit (issued before the tile loads, so that
     // waiting for it at the end of the unit leaves those in flight)
-    const double2 xnext = xcol[min(b0 + C.In * HT + lane, nlast)];
+    const double2 xnext = xcol[min(org + C.In * HT + lane, nlast)];
     load(nb, Lq);
     advance(Lq);
     const int I = C.I, J = C.k * K + C.t;
-    const int rb0 = b0 + I * HT, cj0 = b0 + J * HT;
+    const int rb0 = org + I * HT, cj0 = org + J * HT;
     const double2 vj = vval(cj0 + jl, cb.xj);
-    const bool plain = J != I && rb0 + HT <= n && cj0 + HT <= n;  // uniform
+    // uniform; tiles touching the masked rows and columns take the masked path
+    const bool plain = J != I && cj0 >= b0 && rb0 + HT <= n && cj0 + HT <= n;
     double2 ca = zero;
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
@@ -592,7 +600,8 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
         ra[s] = cadd(ra[s], cmul(sv, vj));
         ca = cadd(ca, cmulc(sv, vr));
       } else {
-        const bool ok = (rb0 + rl < n) && (cj0 + jl < n) && (J != I || rl >= jl);
+        const bool ok = (rb0 + rl < n) && (cj0 + jl < n) && (rb0 + rl >= b0) && (cj0 + jl >= b0) &&
+                        (J != I || rl >= jl);
         const bool strict = J != I || rl > jl;
         double2 sr = ok ? sv : zero;
         if (J == I && rl == jl) sr.y = 0.0;  // the diagonal of a Hermitian matrix is real
@@ -615,7 +624,7 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
         ra[s] = zero;
       }
       if (tid < HT && C.u + G < nunits)  // the block has a next unit
-        vrow[ub ^ 1][tid] = vval(b0 + C.In * HT + tid, xnext);
+        vrow[ub ^ 1][tid] = vval(org + C.In * HT + tid, xnext);
       __syncthreads();
       const int row = tid >> 4, part = tid & 15;
       double2 rs = zero;
@@ -671,7 +680,7 @@ __global__ void k_trd_zero_cols(double2* VW, double2* WV, int64_t n, int jb) {
 
 int64_t ycs_of(int64_t n) { return (n + 63) / 64; }
 int64_t hemv_tiles_max(int64_t n) {
-  const int64_t nI = (n - 1 + HT - 1) / HT;
+  const int64_t nI = (n + HT - 1) / HT;  // the tiling starts at row 0 for the first column
   return nI * (nI + 1) / 2;
 }
 
@@ -715,7 +724,7 @@ bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t
     if (jb < TRD_NB)
       BSE_LAUNCH(k_trd_zero_cols, dim3(256), dim3(256), 0, s, w.VW, w.WV, n, jb);
     for (int i = 0; i < jb; ++i) {
-      const int64_t c = j0 + i, m = n - c - 1;
+      const int64_t c = j0 + i, m = n - trd_org((int)c + 1);  // order of the tiled block
       BSE_LAUNCH(k_trd_col, dim3(cdiv(n - c, ROWS_A)), dim3(COL_THREADS), 0, s, M, ld, (int)n, w.VW,
                  w.WV, (int)j0, i, 1, w.hs, Y, ycs, kprev, partA, partB, w.yproj);
       const int K = hemv_unit(m);
