@@ -207,8 +207,10 @@ int64_t bse_timing_report(char* buf, int64_t len);
  * (paper_1904_05575_amd/tune.py, run on the GPU).  Each entry selects, for one
  * call site and for sizes up to size_max, a tile choice:
  *   BSE_TUNE_HEMV_UNIT     size = trailing order m of a Householder step;
- *                          choice = panels of 64 columns per work unit of the
- *                          Hermitian matrix-vector kernel: 1, 2, 4 or 8
+ *                          choice = least number of 64 x 64 tiles per block of
+ *                          the Hermitian matrix-vector kernel (blocks take equal
+ *                          runs of tiles, at most one per compute unit): 1, 2,
+ *                          4 or 8
  *   BSE_TUNE_GEMM_*        size = problem order n; choice = GEMM tile edge
  *                          16, 32 or 64 (squared form S = U (A+B) U^H; Cholesky
  *                          trailing updates; Householder panel updates; the

@@ -11,9 +11,10 @@
 //               of |x|^2, V^H x, W^H x;
 //   k_trd_hemv  every block reduces |x|^2 (same order everywhere) and forms
 //               reflector c; the blocks then cover the lower triangle of the
-//               trailing matrix in square tiles, each tile (I, J) giving the
-//               partial products S_IJ v_J (rows of I) and S_IJ^H v_I (rows
-//               of J, off-diagonal tiles) plus its share of y^H v.
+//               trailing matrix in square tiles, each block an equal run of
+//               consecutive tiles, each tile (I, J) giving the partial
+//               products S_IJ v_J (rows of I) and S_IJ^H v_I (rows of J,
+//               off-diagonal tiles) plus its share of y^H v.
 // Kernel boundaries order every exchange between blocks: no atomics, no
 // fences.  After each panel one MFMA GEMM applies S -= [V W][W V]^H to the
 // lower triangle of the trailing matrix.  The panel's V and W live in two
@@ -41,18 +42,20 @@ __host__ __device__ inline int trd_org(int b0) { return b0 & ~7; }
 
 // Partial sums of y = S v for a trailing matrix of order m starting at row org,
 // cut into nI x nI tiles of order HT (lower triangle: tile-row I >= tile-column
-// J).  The hemv kernel's work unit is tile-row I over the panels
-// J = kK .. min(I, kK + K - 1) (chunk k).  Row r, in tile-row Ir, collects
-//   Y[k][r]        k = 0 .. cdiv(Ir + 1, K) - 1  (unit (k, Ir): S v over its panels)
-//   Y[ycs + I][r]  I = Ir .. nI - 1              (tile (I, Ir): S_{I,Ir}^H v_I)
-// i.e. nrs + nI - Ir slots with nrs = cdiv(Ir + 1, K).
-// Built-in unit width (panels per unit) for nI tile-rows; a tuning table entry may replace it.
-inline int hemv_k_default(int nI) { return nI >= 48 ? 4 : (nI >= 24 ? 2 : 1); }
-__host__ __device__ inline int hemv_punits(int j, int nI, int K) {
-  return j * nI - K * (j * (j - 1) / 2);
+// J).  Tile (I, J) has index I (I + 1) / 2 + J (tile-rows in order); block b
+// of a launch with G blocks over T tiles takes the run [T b / G, T (b+1) / G),
+// so that no block has more than one tile above the mean.  The part of a
+// tile-row inside one block's run is a piece; piece p of tile-row I (p counted
+// from the block that holds the row's first tile) leaves its row sums in slot
+// p.  Row r, in tile-row Ir, collects
+//   Y[p][r]        p = 0 .. nrs - 1   (the pieces of tile-row Ir: S v over them)
+//   Y[ycs + I][r]  I = Ir .. nI - 1   (tile (I, Ir): S_{I,Ir}^H v_I)
+// i.e. nrs + nI - Ir slots, nrs = block_of(last tile of Ir) - block_of(first) + 1.
+__host__ __device__ inline int64_t hemv_tile_start(int64_t T, int G, int b) {
+  return T * b / G;
 }
-__host__ __device__ inline int hemv_units(int nI, int K) {
-  return hemv_punits((nI + K - 1) / K, nI, K);
+__host__ __device__ inline int hemv_block_of(int64_t T, int G, int64_t t) {
+  return (int)(((t + 1) * G - 1) / T);
 }
 BSE_DEV int64_t yslot(int q, int Ir, int nrs, int ycs, int64_t n, int r) {
   return (int64_t)(q < nrs ? q : ycs + Ir + (q - nrs)) * n + r;
@@ -116,7 +119,7 @@ BSE_DEV double2 sub_mulc(double2 x, double2 a, double2 b) {
 __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     double2* __restrict__ M, int64_t ld, int n, double2* __restrict__ VW, double2* __restrict__ WV,
     int j0, int i, int has_new, const double2* __restrict__ hs, const double2* __restrict__ Y,
-    int ycs, int kprev, double2* __restrict__ partA, const double2* __restrict__ partB,
+    int ycs, int gprev, double2* __restrict__ partA, const double2* __restrict__ partB,
     double2* __restrict__ yp) {
   constexpr int QP = COL_THREADS / ROWS_A;        // threads sharing one row
   constexpr int PER = TRD_NB / QP;                // panel columns per thread
@@ -163,14 +166,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   // y_{c-1}[r]: the previous hemv kernel's slots, QP threads per row
   const int orgp = trd_org(c);  // origin of the tiling of the hemv launch for reflector c-1
   const int nIp = i > 0 ? cdiv(n - orgp, HT) : 0;
-  const int Kp = kprev;  // unit width of the hemv launch that produced the slots
-  const int Ir = (rc - orgp) / HT, nrs = cdiv(Ir + 1, Kp), tot = max(nrs + nIp - Ir, 1);
+  // pieces of tile-row Ir in the hemv launch (gprev blocks) that produced the slots
+  const int Ir = (rc - orgp) / HT;
+  const int64_t Tp = (int64_t)nIp * (nIp + 1) / 2, s_ir = (int64_t)Ir * (Ir + 1) / 2;
+  const int nrs = Tp > 0 ? hemv_block_of(Tp, gprev, s_ir + Ir) - hemv_block_of(Tp, gprev, s_ir) + 1 : 1;
+  const int tot = max(nrs + nIp - Ir, 1);
   double2 ysl[YCH];
 #pragma unroll
   for (int u = 0; u < YCH; ++u) ysl[u] = Y[yslot(min(qq + u * QP, tot - 1), Ir, nrs, ycs, N, rc)];
-  // the hemv units' partials of y^H v
+  // the hemv blocks' partials of y^H v
   constexpr int PB = 2;  // unit partials per thread issued together
-  const int nun = i > 0 ? hemv_units(nIp, Kp) : 0;
+  const int nun = i > 0 ? gprev : 0;  // one y^H v partial per hemv block
   double2 pbl[PB];
 #pragma unroll
   for (int u = 0; u < PB; ++u) pbl[u] = partB[min(tid + COL_THREADS * u, max(nun - 1, 0))];
@@ -361,20 +367,6 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   }
 }
 
-// Unit u (numbered chunk-major: chunk k holds tile-rows kK .. nI-1) of the
-// hemv tiling: the largest k with hemv_punits(k) <= u, from the root of that
-// quadratic corrected by one step either way, and its tile-row I.
-BSE_DEV void unit_of(int u, int nI, int K, int& k, int& I) {
-  const int nK = (nI + K - 1) / K;
-  const double a = nI + 0.5 * K;
-  int j = (int)floor((a - sqrt(a * a - 2.0 * K * u)) / K);
-  j = max(0, min(j, nK - 1));
-  j = (j + 1 <= nK - 1 && hemv_punits(j + 1, nI, K) <= u) ? j + 1 : j;
-  j = (hemv_punits(j, nI, K) > u) ? j - 1 : j;
-  k = j;
-  I = j * K + (u - hemv_punits(j, nI, K));
-}
-
 // Sum over the 16 lanes of each row of the wavefront (DPP within rows); every
 // lane of a row gets its row's total.
 BSE_DEV double row16_sum(double v) {
@@ -387,19 +379,21 @@ BSE_DEV double row16_sum(double v) {
 
 // Reflector c from the column kernel's partials, then the Hermitian product
 // S v over the lower triangle of the trailing matrix (rows and columns c+1..n-1)
-// in HT x HT tiles, grouped into units (tile-row I, up to K consecutive
-// panels).  Persistent blocks (one per compute unit) take units b, b + G, ...;
-// every result is stored per unit or per tile, never per block.  Tiles stream
-// through three register buffers (two in flight while one is used) and their
-// loads carry no conditions, so the wait for one tile never covers the next.
-// Within a unit no barrier is taken: each lane keeps its rows' partial sums
-// in registers, and each tile's column sums go from the lanes straight to
-// the slots.  A unit ends with one LDS reduction of its row sums.  Block 0
-// also stores the reflector; V^H v, W^H v and conj(v) y_probe for the next
-// column kernel are spread over the blocks, one value each (the panel's share
-// of y^H v follows from them in that kernel).  The column kernel's partial
-// sums are loaded before the tile prefetch so that the reflector is not held
-// up behind it.
+// in HT x HT tiles.  Persistent blocks (at most one per compute unit) take
+// equal runs of consecutive tiles in tile-row order, so that the most loaded
+// block has at most one tile more than the mean (the launch lasts as long as
+// its most loaded block).  Results are stored per tile or per piece (a
+// tile-row's part of a run); each block also leaves one partial of y^H v.
+// Tiles stream through three register buffers (two in flight while one is
+// used) and their loads carry no conditions, so the wait for one tile never
+// covers the next.  Within a piece no barrier is taken: each lane keeps its
+// rows' partial sums in registers, and each tile's column sums go from the
+// lanes straight to the slots.  A piece ends with one LDS reduction of its row
+// sums.  Block 0 also stores the reflector; V^H v, W^H v and conj(v) y_probe
+// for the next column kernel are spread over the blocks, one value each (the
+// panel's share of y^H v follows from them in that kernel).  The column
+// kernel's partial sums are loaded before the tile prefetch so that the
+// reflector is not held up behind it.
 //
 // Wavefront w owns tile column 4w + l / 16 (lane l); load s of lane l reads
 // row 16 s + l % 16: four contiguous 256-byte column segments per
@@ -408,7 +402,7 @@ BSE_DEV double row16_sum(double v) {
 __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     const double2* __restrict__ M, int64_t ld, int n, const double2* __restrict__ VW, int j0,
     int i, double2* __restrict__ hs, const double2* __restrict__ partA,
-    double2* __restrict__ partB, double2* __restrict__ Y, int ycs, int K,
+    double2* __restrict__ partB, double2* __restrict__ Y, int ycs,
     double* __restrict__ dd, double* __restrict__ ee, double2* __restrict__ tau,
     const double2* __restrict__ yp) {
   constexpr int NW = HV_THREADS / 64;     // 16 wavefronts
@@ -418,8 +412,9 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     double2 s[NL];    // elements (rows 16 s + lr, column jl)
     double2 xj;       // x at column jl
   };
-  struct Cur {        // position in this block's tile sequence
-    int u, t, k, I, nt, In;  // In: tile-row of the block's next unit
+  struct Pos {        // a tile: index in tile-row order and its (I, J)
+    int64_t t;
+    int I, J;
   };
   __shared__ double2 sums[1];
   __shared__ double2 vrow[2][HT];
@@ -428,38 +423,36 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   const int c = j0 + i, b0 = c + 1, org = trd_org(b0);
   const int64_t N = n;
   const int m = n - org;
-  const int nI = cdiv(m, HT), nunits = hemv_units(nI, K);
+  const int nI = cdiv(m, HT);
+  const int64_t T = (int64_t)nI * (nI + 1) / 2;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;  // row in slab, column group
   const int jl = 4 * wid + lg;               // this lane's tile column
   const int nlast = n - 1, G = gridDim.x;
+  const int64_t t_end = hemv_tile_start(T, G, (int)blockIdx.x + 1);
   const double2* xcol = M + (int64_t)c * ld;
   const double2 zero = make_double2(0.0, 0.0);
 
-  auto decode = [&](Cur& q) {
-    if (q.u < nunits) {
-      unit_of(q.u, nI, K, q.k, q.I);
-      q.nt = min(q.I, q.k * K + K - 1) - q.k * K + 1;
-    } else {
-      q.k = 0;
-      q.I = 0;
-      q.nt = 1;
-    }
-    int kn = 0;
-    q.In = 0;
-    if (q.u + G < nunits) unit_of(q.u + G, nI, K, kn, q.In);
+  auto pos_of = [&](int64_t t) -> Pos {
+    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    I = ((int64_t)(I + 1) * (I + 2) / 2 <= t) ? I + 1 : I;
+    I = ((int64_t)I * (I + 1) / 2 > t) ? I - 1 : I;
+    return Pos{t, I, (int)(t - (int64_t)I * (I + 1) / 2)};
   };
-  auto advance = [&](Cur& q) {
-    if (++q.t == q.nt) {
-      q.u += G;
-      q.t = 0;
-      decode(q);
+  auto step = [&](Pos& q) {
+    ++q.t;
+    if (++q.J > q.I) {
+      ++q.I;
+      q.J = 0;
     }
   };
-  // loads without conditions (indices clamped; past the end, values unused)
-  auto load = [&](Rec& rc, const Cur& q) {
-    const int rb0 = org + q.I * HT;
-    const int64_t j = min(org + (q.k * K + q.t) * HT + jl, nlast);
+  // loads without conditions (indices clamped; past the run the cursor reads
+  // tile (0, 0) again, which every block shares, so that the look-ahead costs
+  // no memory traffic; those values are unused)
+  auto load = [&](Rec& rc, const Pos& q) {
+    const bool in = q.t < t_end;  // uniform
+    const int rb0 = org + (in ? q.I : 0) * HT;
+    const int64_t j = min(org + (in ? q.J : 0) * HT + jl, nlast);
 #pragma unroll
     for (int s = 0; s < NL; ++s) rc.s[s] = M[min(rb0 + 16 * s + lr, nlast) + j * ld];
     rc.xj = xcol[j];
@@ -468,13 +461,14 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   // ---- the small loads first, so that they are not queued behind the tile
   // prefetch of every block: the column kernel's |x|^2 partials (wavefront 0),
   // this block's share of the other partial sums (wavefront 1: value
-  // t = 1 + blockIdx.x, + G, ...), and x on the first unit's rows
+  // t = 1 + blockIdx.x, + G, ...), and x on the first tile-row's rows
   const int nbA = cdiv(n - c, ROWS_A);
   const int nvals = 2 + 2 * i;
-  Cur C{(int)blockIdx.x, 0, 0, 0, 1, 0};
-  decode(C);
+  Pos C = pos_of(hemv_tile_start(T, G, (int)blockIdx.x));
   const double2 ax = xcol[b0];
   const double2 xv0 = xcol[min(org + C.I * HT + (tid & (HT - 1)), nlast)];
+  // x on the rows of the next tile-row, loaded one piece ahead of its use
+  double2 xnx = xcol[min(org + (C.I + 1) * HT + lane, nlast)];
   constexpr int PQ = 4;  // partial sums per lane issued together
   double2 pq[PQ];
   const int t0 = 1 + (int)blockIdx.x;  // first value of wavefront 1
@@ -492,12 +486,12 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
       }
     }
   }
-  Cur Lq = C;
+  Pos Lq = C;
   Rec r0, r1, r2;
   load(r0, Lq);
-  advance(Lq);
+  step(Lq);
   load(r1, Lq);
-  advance(Lq);
+  step(Lq);
   // sum over the column kernel's blocks of value col (lanes over blocks)
   auto colsum = [&](int col) -> double2 {
     double2 a = zero;
@@ -572,20 +566,22 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   auto vval = [&](int e, double2 x) -> double2 {
     return (e < n && e >= b0) ? ((e == b0) ? make_double2(1.0, 0.0) : cmul(scal, x)) : zero;
   };
-  int ub = 0;  // vrow buffer of the current unit
+  int ub = 0;  // vrow buffer of the current piece
   if (tid < HT) vrow[0][tid] = vval(org + C.I * HT + tid, xv0);
   __syncthreads();
 
   double2 ra[NL] = {zero, zero, zero, zero};
   double2 pbl = zero;
+  // slot of this block's piece of tile-row I: pieces are counted from the
+  // block that holds the row's first tile
+  auto row_slot = [&](int I) {
+    return (int)blockIdx.x - hemv_block_of(T, G, (int64_t)I * (I + 1) / 2);
+  };
   // cb: tile C; nb receives tile C + 2 (tile C + 1 is in flight in the third buffer)
   auto tile = [&](const Rec& cb, Rec& nb) {
-    // x on the rows of the next unit (issued before the tile loads, so that
-    // waiting for it at the end of the unit leaves those in flight)
-    const double2 xnext = xcol[min(org + C.In * HT + lane, nlast)];
     load(nb, Lq);
-    advance(Lq);
-    const int I = C.I, J = C.k * K + C.t;
+    step(Lq);
+    const int I = C.I, J = C.J;
     const int rb0 = org + I * HT, cj0 = org + J * HT;
     const double2 vj = vval(cj0 + jl, cb.xj);
     // uniform; tiles touching the masked rows and columns take the masked path
@@ -615,16 +611,17 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
       Y[(int64_t)(ycs + I) * N + cj0 + jl] = ca;
       pbl = cadd(pbl, cmulc(ca, vj));
     }
-    if (C.t == C.nt - 1) {
-      // ---- end of unit: row sums over 64 partials (16 threads per row, then a
-      // 16-lane reduction), the next unit's v rows, and the unit's y^H v share
+    const bool last = C.t + 1 == t_end;  // uniform
+    if (J == I || last) {
+      // ---- end of a piece: row sums over 64 partials (16 threads per row, then
+      // a 16-lane reduction), the next tile-row's v rows, and its y^H v share
 #pragma unroll
       for (int s = 0; s < NL; ++s) {
         rpart[4 * wid + lg][16 * s + lr] = ra[s];
         ra[s] = zero;
       }
-      if (tid < HT && C.u + G < nunits)  // the block has a next unit
-        vrow[ub ^ 1][tid] = vval(org + C.In * HT + tid, xnext);
+      if (tid < HT && !last)  // the block goes on with tile-row I + 1
+        vrow[ub ^ 1][tid] = vval(org + (I + 1) * HT + tid, xnx);
       __syncthreads();
       const int row = tid >> 4, part = tid & 15;
       double2 rs = zero;
@@ -633,30 +630,32 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
       rs.x = row16_sum(rs.x);
       rs.y = row16_sum(rs.y);
       if (part == 0 && rb0 + row < n) {
-        Y[(int64_t)C.k * N + rb0 + row] = rs;
+        Y[(int64_t)row_slot(I) * N + rb0 + row] = rs;
         pbl = cadd(pbl, cmulc(rs, vrow[ub][row]));
       }
-      pbl.x = wave_total63(pbl.x);
-      pbl.y = wave_total63(pbl.y);
-      if (lane == 63) pred[wid] = pbl;
-      pbl = zero;
-      __syncthreads();
-      if (tid == 0) {
-        double2 t = zero;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) t = cadd(t, pred[w]);
-        partB[C.u] = t;
-      }
+      __syncthreads();  // rpart and vrow[ub] are free again
       ub ^= 1;
+      xnx = xcol[min(org + (I + 2) * HT + lane, nlast)];  // for the next piece's end
     }
-    advance(C);
+    step(C);
   };
-  while (C.u < nunits) {  // uniform
+  while (C.t < t_end) {  // uniform
     tile(r0, r2);
-    if (C.u >= nunits) break;
+    if (C.t >= t_end) break;
     tile(r1, r0);
-    if (C.u >= nunits) break;
+    if (C.t >= t_end) break;
     tile(r2, r1);
+  }
+  // this block's share of y^H v
+  pbl.x = wave_total63(pbl.x);
+  pbl.y = wave_total63(pbl.y);
+  if (lane == 63) pred[wid] = pbl;
+  __syncthreads();
+  if (tid == 0) {
+    double2 t = zero;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t = cadd(t, pred[w]);
+    partB[blockIdx.x] = t;
   }
 }
 
@@ -684,13 +683,10 @@ int64_t hemv_tiles_max(int64_t n) {
   return nI * (nI + 1) / 2;
 }
 
-// Units per hemv work item for a trailing matrix of order m.
-int hemv_unit(int64_t m) {
-  const int nI = (int)((m + HT - 1) / HT);
-  return tune_choice(BSE_TUNE_HEMV_UNIT, m, hemv_k_default(nI));
-}
-
-int hemv_grid(int64_t m, int K) {
+// Blocks of a hemv launch over a trailing block of order m: one per compute
+// unit, or fewer so that each takes at least the tuned number of tiles (1, 2,
+// 4 or 8; fewer, longer runs can pay for small trailing matrices).
+int hemv_grid(int64_t m) {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
@@ -699,13 +695,14 @@ int hemv_grid(int64_t m, int K) {
         cus <= 0)
       cus = 256;
   }
-  const int nI = (int)((m + HT - 1) / HT);
-  return std::min(hemv_units(nI, K), cus);
+  const int64_t nI = (m + HT - 1) / HT, T = nI * (nI + 1) / 2;
+  const int least = tune_choice(BSE_TUNE_HEMV_UNIT, m, 1);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cus, (T + least - 1) / least));
 }
 
 }  // namespace
 
-// [partA: column-kernel partials | partB: hemv unit partials of y^H v (+ one
+// [partA: column-kernel partials | partB: hemv block partials of y^H v (+ one
 //  spare) | Y: hemv slots]
 int64_t trd_part_elems(int64_t n) {
   const int64_t a = ((n + ROWS_A - 1) / ROWS_A + 1) * NVAL;
@@ -718,7 +715,7 @@ bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t
   double2* partB = w.part + ((n + ROWS_A - 1) / ROWS_A + 1) * NVAL;
   double2* Y = partB + hemv_tiles_max(n) + 1;
   const int ycs = (int)ycs_of(n);
-  int kprev = 1;  // unit width of the last hemv launch (read by the next column kernel)
+  int gprev = 1;  // blocks of the last hemv launch (read by the next column kernel)
   for (int64_t j0 = 0; j0 < n - 1; j0 += TRD_NB) {
     const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
     if (jb < TRD_NB)
@@ -726,16 +723,16 @@ bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t
     for (int i = 0; i < jb; ++i) {
       const int64_t c = j0 + i, m = n - trd_org((int)c + 1);  // order of the tiled block
       BSE_LAUNCH(k_trd_col, dim3(cdiv(n - c, ROWS_A)), dim3(COL_THREADS), 0, s, M, ld, (int)n, w.VW,
-                 w.WV, (int)j0, i, 1, w.hs, Y, ycs, kprev, partA, partB, w.yproj);
-      const int K = hemv_unit(m);
-      BSE_LAUNCH(k_trd_hemv, dim3(hemv_grid(m, K)), dim3(HV_THREADS), 0, s, M, ld, (int)n, w.VW,
-                 (int)j0, i, w.hs, partA, partB, Y, ycs, K, w.dd, w.ee, w.tau, w.yproj);
-      kprev = K;
+                 w.WV, (int)j0, i, 1, w.hs, Y, ycs, gprev, partA, partB, w.yproj);
+      const int g = hemv_grid(m);
+      BSE_LAUNCH(k_trd_hemv, dim3(g), dim3(HV_THREADS), 0, s, M, ld, (int)n, w.VW, (int)j0, i,
+                 w.hs, partA, partB, Y, ycs, w.dd, w.ee, w.tau, w.yproj);
+      gprev = g;
     }
     // finish the panel's last reflector
     const int64_t cl = j0 + jb;
     BSE_LAUNCH(k_trd_col, dim3(cdiv(n - cl, ROWS_A)), dim3(COL_THREADS), 0, s, M, ld, (int)n,
-               w.VW, w.WV, (int)j0, jb, 0, w.hs, Y, ycs, kprev, partA, partB, w.yproj);
+               w.VW, w.WV, (int)j0, jb, 0, w.hs, Y, ycs, gprev, partA, partB, w.yproj);
     const int64_t t = j0 + jb;
     if (t < n) {
       ZgemmParams g;  // S[t:, t:] -= [V W] [W V]^H

@@ -1,6 +1,6 @@
 """Autotuner of the library's tile choices (run on the GPU; writes a JSON table).
 
-    python -m paper_1904_05575_amd.tune [--out PATH] [--reps 2]
+    python -m paper_1904_05575_amd.tune [--out PATH] [--reps 2] [--hemv-only]
 
 For every tunable call site of the FP64 path (see bse_tune_entry in
 include/bse.h) the tuner builds and solves seeded synthetic problems of the
@@ -10,8 +10,8 @@ fastest:
   * GEMM tile edge (32 or 64; 16 or 32 for the per-pair second contraction)
     for the squared form, the Cholesky and Householder trailing updates, the
     per-pair contraction and the exchange term, per problem order n;
-  * panels per work unit of the Householder hemv kernel (1, 2, 4, 8), per
-    bucket of the trailing order m, on the largest problem.
+  * the least number of tiles per block of the Householder hemv kernel
+    (1, 2, 4, 8), per bucket of the trailing order m, on the largest problem.
 `load()` installs the table in the library (Problem and Batch call it once).
 """
 from __future__ import annotations
@@ -77,6 +77,46 @@ def _time_sites(P, tags, reps):
     return best
 
 
+def run_hemv_only(out: str, reps: int = 2) -> dict:
+    """Re-tune only the hemv buckets, keeping the table's other entries (which
+    stay installed while the hemv choices are timed)."""
+    import torch
+    from bse_synth import get, make_inputs
+    from .bse import Problem
+
+    with open(TABLE) as f:
+        tab = json.load(f)
+    keep = [e for e in tab["entries"] if e["site"] != "hemv_unit"]
+    base = [(L.TUNE_SITES[e["site"]], int(e["size_max"]), int(e["choice"])) for e in keep]
+    measured = {k: v for k, v in tab.get("measured_ms", {}).items()
+                if not k.startswith("hemv_unit")}
+    t0 = time.time()
+    big = make_inputs(get("full_q0_k8_v3c4_g113"))
+    P = Problem(big)
+    entries = list(keep)
+    lo = 0
+    for hi in HEMV_BUCKETS:
+        if lo >= big["workload"].n:
+            break
+        times = {}
+        for K in HEMV_UNITS:
+            L.bse_tune_set(base + [(L.TUNE_SITES["hemv_unit"], hi, K)])
+            times[K] = _time_sites(P, HEMV_TAGS, reps)
+        best = min(times, key=times.get)
+        entries.append({"site": "hemv_unit", "size_max": hi, "choice": best})
+        measured[f"hemv_unit@m<={hi}"] = {str(k): round(v, 4) for k, v in times.items()}
+        print(f"[tune] m<={hi} hemv_unit: {times} -> {best}", file=sys.stderr, flush=True)
+        lo = hi
+    L.bse_tune_set([])
+    del P
+    torch.cuda.empty_cache()
+    tab["entries"], tab["measured_ms"] = entries, measured
+    tab["seconds_hemv"] = round(time.time() - t0, 1)
+    with open(out, "w") as f:
+        json.dump(tab, f, indent=1)
+    return tab
+
+
 def run(out: str, reps: int = 2) -> dict:
     import torch
     from bse_synth import BATCHES, get, make_batch_inputs, make_inputs
@@ -132,9 +172,12 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--hemv-only", action="store_true",
+                    help="re-tune the hemv buckets only, keeping the other entries")
     args = ap.parse_args()
-    tab = run(args.out, args.reps)
-    print(json.dumps({"entries": len(tab["entries"]), "seconds": tab["seconds"], "out": args.out}))
+    tab = run_hemv_only(args.out, args.reps) if args.hemv_only else run(args.out, args.reps)
+    print(json.dumps({"entries": len(tab["entries"]), "seconds": tab.get("seconds"),
+                      "out": args.out}))
     return 0
 
 
