@@ -94,19 +94,6 @@ BSE_DEV double2 wave_sum2_dpp(double2 v) {
   return make_double2(bcast63(wave_total63(v.x)), bcast63(wave_total63(v.y)));
 }
 
-// Deterministic block-wide complex sum (wavefront butterflies, then waves in
-// order); every thread gets the result.  sh needs blockDim.x / 64 entries.
-BSE_DEV double2 block_sum2(double2 v, double2* sh) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = wave_sum2_dpp(v);
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double2 s = make_double2(0.0, 0.0);
-  for (int k = 0; k < nw; ++k) s = cadd(s, sh[k]);
-  return s;
-}
-
 // v where ok, else 0 (component selects: a select of the whole vector type
 // would send register arrays to scratch)
 BSE_DEV double2 keep(bool ok, double2 v) { return make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0); }
@@ -128,9 +115,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   __shared__ double2 vps[ROWS_A], wps[ROWS_A], xs[ROWS_A];
   __shared__ double2 xpart[QP][ROWS_A], xpart2[QP][ROWS_A];
   __shared__ double2 vcs[TRD_NB], wcs[TRD_NB];
-  __shared__ double2 red[QP][HW][2 * PER];
-  __shared__ double2 red0[HW][2];
-  __shared__ double2 shb[COL_THREADS / 64];
+  static_assert(HW == 1, "one wavefront per row group: its sums are the block's partials");
   __shared__ double2 yc_s;
   __shared__ double2 svw[2 * TRD_NB];  // V^H v | W^H v of reflector c-1
   const int c = j0 + i;
@@ -174,12 +159,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   double2 ysl[YCH];
 #pragma unroll
   for (int u = 0; u < YCH; ++u) ysl[u] = Y[yslot(min(qq + u * QP, tot - 1), Ir, nrs, ycs, N, rc)];
-  // the hemv blocks' partials of y^H v
-  constexpr int PB = 2;  // unit partials per thread issued together
+  // the hemv blocks' partials of y^H v (wavefront 0 reduces them: only it
+  // needs y^H v)
+  constexpr int PB = 4;  // partials per lane issued together
   const int nun = i > 0 ? gprev : 0;  // one y^H v partial per hemv block
   double2 pbl[PB];
+  if (wid == 0) {
 #pragma unroll
-  for (int u = 0; u < PB; ++u) pbl[u] = partB[min(tid + COL_THREADS * u, max(nun - 1, 0))];
+    for (int u = 0; u < PB; ++u) pbl[u] = partB[min(lane + 64 * u, max(nun - 1, 0))];
+  }
   const double2 tc = hs[HS_TAU], scal_p = hs[HS_SCAL], pdot = hs[HS_PDOT];
   // row c of the panel's earlier reflectors and the slots of y_{c-1}[c] (wavefront 1)
   constexpr int YC = 2;  // slots of row c per lane issued together
@@ -225,10 +213,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     }
   }
   double2 pa = zero;
+  if (wid == 0) {
 #pragma unroll
-  for (int u = 0; u < PB; ++u)
-    if (tid + COL_THREADS * u < nun) pa = cadd(pa, pbl[u]);
-  for (int b = tid + COL_THREADS * PB; b < nun; b += COL_THREADS) pa = cadd(pa, partB[b]);
+    for (int u = 0; u < PB; ++u)
+      if (lane + 64 * u < nun) pa = cadd(pa, pbl[u]);
+    for (int b = lane + 64 * PB; b < nun; b += 64) pa = cadd(pa, partB[b]);
+  }
   __syncthreads();  // svw, vcs, wcs staged
 
   // ---- 1. y_{c-1} = S v - V (W^H v) - W (V^H v) and alpha; with it, step 2's
@@ -261,14 +251,17 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
       if (lane == 0) yc_s = ycq;
     }
     xpart[qq][rr] = yq;
-    // the panel's share of y^H v: -sum_ip conj(W^H v) V^H v + conj(V^H v) W^H v
-    if (tid < i - 1) {
-      const double2 sv = svw[tid], sw = svw[TRD_NB + tid];
-      pa = csub(pa, cadd(cmulc(sw, sv), cmulc(sv, sw)));
+    if (wid == 0) {
+      // the panel's share of y^H v: -sum_ip conj(W^H v) V^H v + conj(V^H v) W^H v
+      if (lane < i - 1) {
+        const double2 sv = svw[lane], sw = svw[TRD_NB + lane];
+        pa = csub(pa, cadd(cmulc(sw, sv), cmulc(sv, sw)));
+      }
+      const double2 s = wave_sum2_dpp(pa);  // y^H v
+      const double t2 = cabs2(tc);
+      al = make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
     }
-    const double2 s = block_sum2(pa, shb);  // y^H v; synchronises the block
-    const double t2 = cabs2(tc);
-    al = make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
+    __syncthreads();  // xpart, xpart2 and yc_s are read by wavefront 0
   }
 
   // ---- finish reflector c-1 and update column c (row threads)
@@ -316,9 +309,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
       xs[rr] = tail ? x : make_double2(0.0, 0.0);
       const double2 s0 = wave_sum2_dpp(make_double2(tail ? cabs2(x) : 0.0, 0.0));
       const double2 s1 = wave_sum2_dpp((tail && yp) ? cmulc(x, ypr) : make_double2(0.0, 0.0));
-      if (lane == 0) {
-        red0[wid][0] = s0;
-        red0[wid][1] = s1;
+      if (has_new && lane == 0) {  // the block's |x|^2 and conj(x) y_probe
+        partA[(int64_t)blockIdx.x * NVAL + 0] = s0;
+        partA[(int64_t)blockIdx.x * NVAL + 1] = s1;
       }
     }
   }
@@ -343,27 +336,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
         pv.y = wave_total63(pv.y);
         pw.x = wave_total63(pw.x);
         pw.y = wave_total63(pw.y);
+        // block partials, compact layout [|x|^2, conj(x) y, V^H x (i), W^H x (i)]
         if (lane == 63) {
-          red[qq][wid % HW][2 * u] = pv;
-          red[qq][wid % HW][2 * u + 1] = pw;
+          partA[(int64_t)blockIdx.x * NVAL + 2 + ip] = pv;
+          partA[(int64_t)blockIdx.x * NVAL + 2 + i + ip] = pw;
         }
       }
     }
-  }
-  __syncthreads();
-  // block partials, compact layout [|x|^2, conj(x) y, V^H x (i), W^H x (i)]
-  const int nvals = 2 + 2 * i;
-  if (tid < nvals) {
-    const int t = tid;
-    double2 sb = make_double2(0.0, 0.0);
-    if (t < 2) {
-      for (int w = 0; w < HW; ++w) sb = cadd(sb, red0[w][t]);
-    } else {
-      const bool isw = t >= 2 + i;
-      const int ip = isw ? t - 2 - i : t - 2;
-      for (int h = 0; h < HW; ++h) sb = cadd(sb, red[ip % QP][h][2 * (ip / QP) + (isw ? 1 : 0)]);
-    }
-    partA[(int64_t)blockIdx.x * NVAL + t] = sb;
   }
 }
 
