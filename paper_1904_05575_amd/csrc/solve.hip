@@ -91,11 +91,14 @@ namespace {
 // through LDS, one barrier per column), then solves U11^H X = A12 for its own
 // PCOLS columns of the panel row by forward substitution (one column per
 // thread, in registers; the updates of one step are independent).  Block 0
-// stores U11.
+// stores U11 into u11 (panel j0 / CH_NB holds CH_NB x CH_NB entries), not into
+// A: the other blocks may still be reading A11 when block 0 is done.
+// k_potrf_store moves every U11 into A once the factorisation is complete.
 constexpr int PCOLS = 256;
 constexpr int PEL = CH_NB * CH_NB / PCOLS;  // diagonal-block elements per thread
 __global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, int64_t ld,
                                                        int64_t n, int j0, int jb,
+                                                       double2* __restrict__ u11,
                                                        int32_t* info) {
   __shared__ double2 u[CH_NB][CH_NB + 1];  // rows of U11 as they are finished
   __shared__ double dsh[CH_NB];
@@ -145,11 +148,13 @@ __global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, 
       u[r][c] = (r == c) ? make_double2(dsh[r], 0.0) : cscale(u[r][c], 1.0 / dsh[r]);
   }
   __syncthreads();
-  if (blockIdx.x == 0)
+  if (blockIdx.x == 0) {
+    double2* dst = u11 + (int64_t)(j0 / CH_NB) * CH_NB * CH_NB;
     for (int e = tid; e < jb * jb; e += PCOLS) {
       const int r = e % jb, c = e / jb;
-      if (r <= c) A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * ld] = u[r][c];
+      if (r <= c) dst[r + c * CH_NB] = u[r][c];
     }
+  }
   if (jb != CH_NB) return;  // the last panel has no panel row
   // U11^H X = A12, right-looking: x[k] /= U[k][k]; x[r] -= conj(U[k][r]) x[k], r > k
 #pragma unroll
@@ -161,6 +166,21 @@ __global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, 
   if (solve)
 #pragma unroll
     for (int r = 0; r < CH_NB; ++r) A[(int64_t)(j0 + r) + (c0 + tid) * ld] = x[r];
+}
+
+// U11 of every panel (staged by k_potrf_panel) into the upper triangle of A.
+__global__ __launch_bounds__(256) void k_potrf_store(double2* __restrict__ A, int64_t ld,
+                                                     int64_t n,
+                                                     const double2* __restrict__ u11,
+                                                     const int32_t* info) {
+  if (failed(info)) return;
+  const int64_t j0 = (int64_t)blockIdx.x * CH_NB;
+  const int jb = (int)std::min<int64_t>(CH_NB, n - j0);
+  const double2* src = u11 + (int64_t)blockIdx.x * CH_NB * CH_NB;
+  for (int e = threadIdx.x; e < jb * jb; e += 256) {
+    const int r = e % jb, c = e / jb;
+    if (r <= c) A[(j0 + r) + (j0 + c) * ld] = src[r + c * CH_NB];
+  }
 }
 
 // Mirror one triangle onto the other: from_lower ? upper = conj(lower) :
@@ -1049,7 +1069,7 @@ struct SolveWs {
   double* Dm;     // n x (n + EV_JUNK) bottom-up pivots, [row][eigenvalue]
   double2* VW;    // n x 2 TRD_NB panel [V | W]
   double2* WV;    // n x 2 TRD_NB panel [W | V]
-  double2* W1;    // TRD_NB x n (back-transform)
+  double2* W1;    // TRD_NB x n (back-transform); the Cholesky's U11 blocks before that
   double2* W2;    // TRD_NB x n
   double2* ybuf;  // n
   double2* yvec;  // n (probe projection)
@@ -1083,7 +1103,8 @@ SolveWs carve(const bse_desc* d, void* base) {
   w.Dm = (double*)L.add(n * (n + EV_JUNK) * 8);
   w.VW = (double2*)L.add(n * 2 * TRD_NB * 16);
   w.WV = (double2*)L.add(n * 2 * TRD_NB * 16);
-  w.W1 = (double2*)L.add(n * TRD_NB * 16);
+  static_assert(CH_NB <= TRD_NB, "the U11 blocks fit in W1");
+  w.W1 = (double2*)L.add((n + CH_NB) * TRD_NB * 16);
   w.W2 = (double2*)L.add(n * TRD_NB * 16);
   w.ybuf = (double2*)L.add(n * 16);
   w.yvec = (double2*)L.add(n * 16);
@@ -1138,13 +1159,13 @@ bool herk_update(double2* H1, int64_t ld, int64_t u0, int k, int64_t r0, int row
 // the first panel of a pair only the second panel's rows are updated (K =
 // CH_NB), and after the second the trailing matrix takes one update of
 // K = 2 CH_NB, which halves the passes over it.
-bool cholesky(double2* H1, int64_t n, int64_t ld, int32_t* info, hipStream_t s) {
+bool cholesky(double2* H1, int64_t n, int64_t ld, double2* u11, int32_t* info, hipStream_t s) {
   const int tile = tune_choice(BSE_TUNE_GEMM_POTRF, n, 0);
   for (int64_t j0 = 0; j0 < n; j0 += 2 * CH_NB) {
     const int jb = (int)std::min<int64_t>(CH_NB, n - j0);
     const int64_t j1 = j0 + jb, rest1 = n - j1;
     BSE_LAUNCH(k_potrf_panel, dim3((unsigned)std::max<int64_t>(1, cdiv(rest1, PCOLS))),
-               dim3(PCOLS), 0, s, H1, ld, n, (int)j0, jb, info);
+               dim3(PCOLS), 0, s, H1, ld, n, (int)j0, jb, u11, info);
     if (rest1 <= 0) break;
     const int jb2 = (int)std::min<int64_t>(CH_NB, rest1);
     const int64_t j2 = j1 + jb2, rest2 = n - j2;
@@ -1152,13 +1173,14 @@ bool cholesky(double2* H1, int64_t n, int64_t ld, int32_t* info, hipStream_t s) 
     if (!herk_update(H1, ld, j0, jb, j1, jb2, j1, (int)rest1, tile, "zgemm_potrf_rows", info, s))
       return false;
     BSE_LAUNCH(k_potrf_panel, dim3((unsigned)std::max<int64_t>(1, cdiv(rest2, PCOLS))),
-               dim3(PCOLS), 0, s, H1, ld, n, (int)j1, jb2, info);
+               dim3(PCOLS), 0, s, H1, ld, n, (int)j1, jb2, u11, info);
     if (rest2 <= 0) break;
     // trailing matrix: rows and columns j2 .. n-1, K = jb + jb2
     if (!herk_update(H1, ld, j0, jb + jb2, j2, (int)rest2, j2, (int)rest2, tile,
                      "zgemm_potrf_herk", info, s))
       return false;
   }
+  BSE_LAUNCH(k_potrf_store, dim3((unsigned)cdiv(n, CH_NB)), dim3(256), 0, s, H1, ld, n, u11, info);
   return true;
 }
 
@@ -1251,7 +1273,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
 
   double2* Hm = H0;  // Hermitian matrix handed to the tridiagonalisation
   if (full) {
-    if (!cholesky(H1, n, ld, info, s)) return BSE_ERR_HIP;
+    if (!cholesky(H1, n, ld, w.W1, info, s)) return BSE_ERR_HIP;
     ZgemmParams a;  // T1 = (A+B) U^H
     a.M = (int)n;
     a.N = (int)n;

@@ -68,7 +68,8 @@ def test_graph_batch_mixed_precision():
 def test_full_size_batch_sum_rules():
     """16 momentum transfers, N = 1296..5184, one graph: every member's E is
     positive and ascending, Im eps >= 0, and for three members the f-sum rule
-    sum E |t|^2 = p^H (A-B) p holds with A-B from the oracle's blocks."""
+    sum E |t|^2 = p^H (A-B) p holds with A-B from the oracle's blocks; a
+    replay and the sequential path give identical results."""
     ms = _members("batch16_k6_g89")
     print(f"[gpu] batch16: sizes {[m['workload'].n for m in ms]}", flush=True)
     B = _batch(ms, nbranch=4)
@@ -96,3 +97,10 @@ def test_full_size_batch_sum_rules():
             else:
                 fs += 2.0 * np.vdot(p[i], blk @ p[j]).real
         assert abs(np.sum(out["E"] * out["osc"]) - fs) < 1e-9 * fs, (idx, fs)
+    # four concurrent branches change the timing only: a replay and the plain
+    # entry points one problem after another reproduce every bit (a kernel
+    # whose blocks read what another block of it writes would not)
+    for again in (lambda: B.run(), lambda: B.run_sequential()):
+        again()
+        for i, (a, b) in enumerate(zip(res, B.results())):
+            assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["osc"], b["osc"]), i
