@@ -116,7 +116,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   __shared__ double2 xpart[QP][ROWS_A], xpart2[QP][ROWS_A];
   __shared__ double2 vcs[TRD_NB], wcs[TRD_NB];
   static_assert(HW == 1, "one wavefront per row group: its sums are the block's partials");
-  __shared__ double2 yc_s;
+  __shared__ double2 yc_s;     // y_{c-1}[c]
+  __shared__ double2 yt_s;     // (S xt)[c]: row c of the unscaled product
+  __shared__ double scc_s;     // S[c][c]
   __shared__ double2 svw[2 * TRD_NB];  // V^H v | W^H v of reflector c-1
   const int c = j0 + i;
   const int64_t N = n;
@@ -171,8 +173,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   const double2 tc = hs[HS_TAU], scal_p = hs[HS_SCAL], pdot = hs[HS_PDOT];
   // row c of the panel's earlier reflectors and the slots of y_{c-1}[c] (wavefront 1)
   constexpr int YC = 2;  // slots of row c per lane issued together
-  double2 vcl = zero, wcl = zero, ycl[YC];
+  double2 vcl = zero, wcl = zero, ycl[YC], scc = zero;
   if (wid == 1) {
+    scc = hs[HS_S00];  // S[c][c] as the hemv kernel saw it (block 0 rewrites it here)
     const int ip = min(lane, ipmax);
     vcl = VW[c + (int64_t)ip * N];
     wcl = VW[c + (int64_t)(TRD_NB + ip) * N];
@@ -188,6 +191,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
     vr[u] = keep(ok, vr[u]);
     wr[u] = keep(ok, wr[u]);
   }
+  // y_{c-1}[r] = scal (S xt)[r] + S[r][c]: the hemv kernel multiplied the
+  // unscaled reflector xt (v = scal xt + e_c); column c of S is x0
   double2 yq = zero;
   if (i > 0 && act) {
 #pragma unroll
@@ -195,6 +200,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
       if (qq + u * QP < tot) yq = cadd(yq, ysl[u]);
     for (int q0 = qq + YCH * QP; q0 < tot; q0 += QP)  // beyond the first round (very large n)
       yq = cadd(yq, Y[yslot(q0, Ir, nrs, ycs, N, r)]);
+    yq = cmul(scal_p, yq);
+    if (qq == 0) yq = cadd(yq, r == c ? make_double2(x0.x, 0.0) : x0);
   }
   double2 ycq = zero;
   if (wid == 1) {
@@ -245,23 +252,36 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
         yq = csub(yq, cadd(cmul(vr[u], svw[TRD_NB + ip]), cmul(wr[u], svw[ip])));
     }
     if (wid == ROWS_A / 64) {
-      if (lane < i - 1)
-        ycq = csub(ycq, cadd(cmul(vcl, svw[TRD_NB + lane]), cmul(wcl, svw[lane])));
-      ycq = wave_sum2_dpp(ycq);
-      if (lane == 0) yc_s = ycq;
+      // row c: yt = (S xt)[c] (slots, unscaled); y = scal yt + S[c][c] - panel terms
+      const double2 yt = wave_sum2_dpp(ycq);
+      double2 corr = zero;
+      if (lane < i - 1) corr = cadd(cmul(vcl, svw[TRD_NB + lane]), cmul(wcl, svw[lane]));
+      corr = wave_sum2_dpp(corr);
+      if (lane == 0) {
+        yt_s = yt;
+        scc_s = scc.x;
+        yc_s = csub(cadd(cmul(scal_p, yt), make_double2(scc.x, 0.0)), corr);
+      }
     }
     xpart[qq][rr] = yq;
+    double2 s = zero;
     if (wid == 0) {
-      // the panel's share of y^H v: -sum_ip conj(W^H v) V^H v + conj(V^H v) W^H v
+      // y^H v = v^H S v - panel terms, v^H S v = S[c][c] + 2 Re(scal yt[c])
+      // + |scal|^2 xt^H S xt (the hemv blocks' partials sum to xt^H S xt); the
+      // panel's share: -sum_ip conj(W^H v) V^H v + conj(V^H v) W^H v
+      pa = cscale(pa, cabs2(scal_p));
       if (lane < i - 1) {
         const double2 sv = svw[lane], sw = svw[TRD_NB + lane];
         pa = csub(pa, cadd(cmulc(sw, sv), cmulc(sv, sw)));
       }
-      const double2 s = wave_sum2_dpp(pa);  // y^H v
-      const double t2 = cabs2(tc);
-      al = make_double2(-0.5 * t2 * s.x, -0.5 * t2 * s.y);
+      s = wave_sum2_dpp(pa);
     }
-    __syncthreads();  // xpart, xpart2 and yc_s are read by wavefront 0
+    __syncthreads();  // xpart, xpart2, yc_s, yt_s and scc_s are read by wavefront 0
+    if (wid == 0) {
+      const double2 sy = cmul(scal_p, yt_s);
+      const double t2 = cabs2(tc);
+      al = make_double2(-0.5 * t2 * (s.x + scc_s + 2.0 * sy.x), -0.5 * t2 * s.y);
+    }
   }
 
   // ---- finish reflector c-1 and update column c (row threads)
@@ -395,7 +415,6 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     int64_t t;
     int I, J;
   };
-  __shared__ double2 sums[1];
   __shared__ double2 vrow[2][HT];
   __shared__ double2 rpart[NW * 4][HT];  // [wavefront x lane group][row]
   __shared__ double2 pred[NW];
@@ -438,25 +457,28 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   };
 
   // ---- the small loads first, so that they are not queued behind the tile
-  // prefetch of every block: the column kernel's |x|^2 partials (wavefront 0),
-  // this block's share of the other partial sums (wavefront 1: value
-  // t = 1 + blockIdx.x, + G, ...), and x on the first tile-row's rows
+  // prefetch of every block: x on the first tile-row's rows and, for
+  // wavefront 1, the column kernel's |x|^2 partials and this block's share of
+  // the other partial sums (value t = 1 + blockIdx.x, + G, ...)
   const int nbA = cdiv(n - c, ROWS_A);
   const int nvals = 2 + 2 * i;
   Pos C = pos_of(hemv_tile_start(T, G, (int)blockIdx.x));
-  const double2 ax = xcol[b0];
   const double2 xv0 = xcol[min(org + C.I * HT + (tid & (HT - 1)), nlast)];
   // x on the rows of the next tile-row, loaded one piece ahead of its use
   double2 xnx = xcol[min(org + (C.I + 1) * HT + lane, nlast)];
   constexpr int PQ = 4;  // partial sums per lane issued together
-  double2 pq[PQ];
+  double2 pq0[PQ], pq1[PQ];
   const int t0 = 1 + (int)blockIdx.x;  // first value of wavefront 1
-  double2 vw1 = zero, yb0 = zero;
-  if (wid <= 1) {
-    const int col = (wid == 0) ? 0 : min(t0, NVAL - 1);
+  double2 ax = zero, vw1 = zero, yb0 = zero;
+  if (wid == 1) {
+    ax = xcol[b0];
+    const int col1 = min(t0, NVAL - 1);
 #pragma unroll
-    for (int q = 0; q < PQ; ++q) pq[q] = partA[(int64_t)min(lane + 64 * q, nbA - 1) * NVAL + col];
-    if (wid == 1 && t0 < nvals) {
+    for (int q = 0; q < PQ; ++q) {
+      pq0[q] = partA[(int64_t)min(lane + 64 * q, nbA - 1) * NVAL];
+      pq1[q] = partA[(int64_t)min(lane + 64 * q, nbA - 1) * NVAL + col1];
+    }
+    if (t0 < nvals) {
       if (t0 >= 2) {
         const int ip = (t0 - 2) % max(i, 1), w = (t0 - 2) / max(i, 1);
         vw1 = VW[b0 + (int64_t)(w * TRD_NB + ip) * N];
@@ -471,51 +493,55 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   step(Lq);
   load(r1, Lq);
   step(Lq);
-  // sum over the column kernel's blocks of value col (lanes over blocks)
-  auto colsum = [&](int col) -> double2 {
-    double2 a = zero;
-#pragma unroll
-    for (int q = 0; q < PQ; ++q)
-      if (lane + 64 * q < nbA) a = cadd(a, pq[q]);
-    for (int b = lane + 64 * PQ; b < nbA; b += 64) a = cadd(a, partA[(int64_t)b * NVAL + col]);
-    return wave_sum2(a);
-  };
-  double2 s1 = zero;  // wavefront 1: the sum of value t0
-  if (wid == 0) {
-    const double2 a = colsum(0);
-    if (lane == 0) sums[0] = a;
-  } else if (wid == 1 && t0 < nvals) {
-    s1 = colsum(t0);
-  }
+  // The tiles multiply the unscaled reflector: v = scal xt + e_b0 with xt = x
+  // below b0 and xt_b0 = 0, so S v = scal (S xt) + S e_b0.  The column kernel
+  // applies scal and adds S e_b0, the column b0 of S that it reads anyway; the
+  // product therefore does not wait for the reflector.
+  auto vval = [&](int e, double2 x) -> double2 { return (e < n && e > b0) ? x : zero; };
+  int ub = 0;  // vrow buffer of the current piece
+  if (tid < HT) vrow[0][tid] = vval(org + C.I * HT + tid, xv0);
   __syncthreads();
 
-  // ---- reflector c (the same arithmetic in every thread)
-  const double xn2 = sums[0].x;
-  double2 tv, scal;
-  double beta;
-  if (xn2 == 0.0 && ax.y == 0.0) {
-    tv = zero;
-    beta = ax.x;
-    scal = zero;
-  } else {
-    beta = -copysign(sqrt(ax.x * ax.x + ax.y * ax.y + xn2), ax.x);
-    tv = make_double2((beta - ax.x) / beta, -ax.y / beta);
-    const double2 dnm = make_double2(ax.x - beta, ax.y);
-    const double q = 1.0 / cabs2(dnm);
-    scal = make_double2(dnm.x * q, -dnm.y * q);
-  }
-  // next column kernel's inputs: the reflector (block 0); V^H v, W^H v of the
-  // panel and conj(v) y_probe (one value per block and round of G)
-  if (blockIdx.x == 0 && tid == 0) {
-    ee[c] = beta;
-    tau[c] = tv;
-    dd[c] = M[c + (int64_t)c * ld].x;
-    hs[HS_SCAL] = scal;
-    hs[HS_TAU] = tv;
-  }
+  // ---- reflector c and the next column kernel's inputs: wavefront 1 of every
+  // block, before its share of the tiles (the other wavefronts go ahead)
   if (wid == 1) {
-    // lane k takes value t0 + k G (more than one only when there are fewer
-    // blocks than values, i.e. for small trailing matrices)
+    // sum over the column kernel's blocks of value col (lanes over blocks)
+    auto colsum = [&](const double2(&pq)[PQ], int col) -> double2 {
+      double2 a = zero;
+#pragma unroll
+      for (int q = 0; q < PQ; ++q)
+        if (lane + 64 * q < nbA) a = cadd(a, pq[q]);
+      for (int b = lane + 64 * PQ; b < nbA; b += 64) a = cadd(a, partA[(int64_t)b * NVAL + col]);
+      return wave_sum2(a);
+    };
+    const double xn2 = colsum(pq0, 0).x;
+    double2 tv, scal;
+    double beta;
+    if (xn2 == 0.0 && ax.y == 0.0) {
+      tv = zero;
+      beta = ax.x;
+      scal = zero;
+    } else {
+      beta = -copysign(sqrt(ax.x * ax.x + ax.y * ax.y + xn2), ax.x);
+      tv = make_double2((beta - ax.x) / beta, -ax.y / beta);
+      const double2 dnm = make_double2(ax.x - beta, ax.y);
+      const double q = 1.0 / cabs2(dnm);
+      scal = make_double2(dnm.x * q, -dnm.y * q);
+    }
+    if (blockIdx.x == 0 && lane == 0) {
+      ee[c] = beta;
+      tau[c] = tv;
+      dd[c] = M[c + (int64_t)c * ld].x;
+      hs[HS_SCAL] = scal;
+      hs[HS_TAU] = tv;
+      // S[b0][b0] for the next column kernel, which overwrites that element
+      // while its other blocks would still read it
+      hs[HS_S00] = make_double2(M[b0 + (int64_t)b0 * ld].x, 0.0);
+    }
+    const double2 s1 = (t0 < nvals) ? colsum(pq1, min(t0, NVAL - 1)) : zero;  // uniform
+    // V^H v, W^H v of the panel and conj(v) y_probe: lane k takes value
+    // t0 + k G (more than one only when there are fewer blocks than values,
+    // i.e. for small trailing matrices)
     const int t = t0 + lane * G;
     if (t < nvals) {
       double2 st = s1, e1 = vw1, y0 = yb0;
@@ -542,12 +568,6 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
       }
     }
   }
-  auto vval = [&](int e, double2 x) -> double2 {
-    return (e < n && e >= b0) ? ((e == b0) ? make_double2(1.0, 0.0) : cmul(scal, x)) : zero;
-  };
-  int ub = 0;  // vrow buffer of the current piece
-  if (tid < HT) vrow[0][tid] = vval(org + C.I * HT + tid, xv0);
-  __syncthreads();
 
   double2 ra[NL] = {zero, zero, zero, zero};
   double2 pbl = zero;

@@ -7,9 +7,11 @@ constexpr int TRD_NB = 32;  // Householder panel width
 
 // Small shared state of the tridiagonalisation kernels (complex slots):
 //   [0] scal = 1/(alpha_x - beta) of the current reflector, [1] tau,
+//   [2] S[b0][b0], the first diagonal element of the trailing matrix the
+//       current reflector multiplies (b0 = c + 1),
 //   [3] v^H y_probe of the current reflector,
 //   [4, 4 + TRD_NB) V^H v and [4 + TRD_NB, 4 + 2 TRD_NB) W^H v over the panel
-constexpr int HS_SCAL = 0, HS_TAU = 1, HS_PDOT = 3, HS_SVV = 4, HS_SWV = 4 + TRD_NB,
+constexpr int HS_SCAL = 0, HS_TAU = 1, HS_S00 = 2, HS_PDOT = 3, HS_SVV = 4, HS_SWV = 4 + TRD_NB,
               HS_SIZE = 4 + 2 * TRD_NB;
 
 struct TrdBufs {
