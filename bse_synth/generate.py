@@ -17,6 +17,9 @@ Recipe (all complex draws are standard complex normal, E|z|^2 = 1):
                    Philox4x32-10 at counter (p, c, c', G) + Box-Muller, which
                    each consumer implements from its published definition)
   Ncv[p, c, v', G], Nvc[p, v, c', G]  as Mvv (full BSE only)
+  Dcv[a, j] ~ CN / (eps_c - eps_v)      (dipole elements along x, y, z: a
+                                         momentum element over the transition's
+                                         energy difference, the optical limit)
   W[q] = v^1/2(q+G) (I + L_q L_q^H)^-1 v^1/2(q+G'),  L_q ~ 0.3 CN (NG x 8),
          v(p) = 4 pi / |p|^2 with |p|^2 replaced by 0.01 at p = 0.
 Transition index a = (ik * nv + iv) * nc + ic.
@@ -35,7 +38,8 @@ import numpy as np
 from . import lattice
 from .workloads import Workload
 
-_KIND = {"eps_v": 1, "eps_c": 2, "Mcv": 3, "Mvv": 4, "Mcc": 5, "Ncv": 6, "Nvc": 7, "L": 8}
+_KIND = {"eps_v": 1, "eps_c": 2, "Mcv": 3, "Mvv": 4, "Mcc": 5, "Ncv": 6, "Nvc": 7, "L": 8,
+         "Dcv": 9}
 _CHUNK_ROWS = 1024
 _INV_SQRT2 = 1.0 / np.sqrt(2.0)
 
@@ -115,6 +119,8 @@ def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
     else:
         env_cv = 1.0 / (1.0 + gq2)
     out["Mcv"] = _complex_rows(w.seed, "Mcv", (w.n, ng), env_cv)
+    de = (out["eps_c"][:, None, :] - out["eps_v"][:, :, None]).reshape(w.n)
+    out["Dcv"] = _complex_rows(w.seed, "Dcv", (w.n, 3), np.ones(3)) / de[:, None]
     env = 1.0 / (1.0 + np.sum(G ** 2, axis=1))
     if want_pairs:
         P = w.npairs
