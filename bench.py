@@ -170,6 +170,57 @@ def batched_section(name: str, steps: int) -> dict:
             "bf16x6_error_vs_fp64": {"eig_rel": eig, "spec_err": spec}, "branches": 4}
 
 
+def observables_section(P, H0, H1, reps: int) -> dict:
+    """Optical-limit observables on the same problem: one solve with
+    eigenvectors, then the transition coefficients along x, y, z (eq.
+    tlambdai), the 3 x 3 dielectric tensor (eq. epsmij) on the frequency grid
+    and the loss function with S(Q, w) of each diagonal element (eq. Lofeps),
+    each timed with HIP events over `reps` repetitions."""
+    import torch
+    from paper_1904_05575_amd import _lib as L
+
+    n = P.n
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    P.build(H0, H1)
+    ev[1].record()
+    E, XpY, _ = P.solve(H0, H1, vectors=True, probe=False)
+    ev[2].record()
+    torch.cuda.synchronize()
+    P.check_info()
+    solve_vec_ms = ev[1].elapsed_time(ev[2])
+    t = P.transitions(XpY)
+    eps = P.dielectric_tensor(E, t)
+    torch.cuda.synchronize()
+    L.bse_timing_enable(True)
+    for _ in range(reps):
+        t = P.transitions(XpY)
+        eps = P.dielectric_tensor(E, t)
+        for a in range(3):
+            P.loss(eps, diag=a)
+    torch.cuda.synchronize()
+    L.bse_timing_enable(False)
+    k = L.bse_timing_report()
+    P.check_info()
+    tr_ms = k["k_transitions"][1] / k["k_transitions"][0]
+    te_ms = k["k_dielectric_tensor"][1] / k["k_dielectric_tensor"][0]
+    lo_ms = k["k_loss"][1] / k["k_loss"][0]
+    nw = P.t["omega"].numel()
+    tr_bytes = n * n * 16 + 2 * 3 * n * 16      # X+Y once, the probes and t
+    te_flop = nw * n * (9 * 14 + 12)            # 9 conj(t_a) t_b g products + g per term
+    del XpY
+    torch.cuda.empty_cache()
+    return {"solve_with_vectors_ms": solve_vec_ms,
+            "transitions": {"ms": tr_ms, "bytes": tr_bytes,
+                            "achieved_GBps": tr_bytes / (tr_ms * 1e-3) / 1e9,
+                            "frac_hbm_peak": tr_bytes / (tr_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "dielectric_tensor": {"ms": te_ms, "nw": nw, "flop": te_flop,
+                                  "achieved_TFLOPs": te_flop / (te_ms * 1e-3) / 1e12,
+                                  "frac_fp64_vector_peak":
+                                      te_flop / (te_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
+            "loss_ms": lo_ms}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +232,8 @@ def main() -> int:
                     help="batched finite-Q workload timed after the main steps ('' to skip)")
     ap.add_argument("--precisions", default="fp32,bf16x6",
                     help="assembly precisions timed after the FP64 steps")
+    ap.add_argument("--no-observables", action="store_true",
+                    help="skip the optical-limit observables (eigenvector path) section")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -337,6 +390,9 @@ def main() -> int:
         "kernels_ms_per_step": kernels_ms,
         "tile_choices": f"{len(L.bse_tune_get())} autotuner entries (paper_1904_05575_amd/tuning_gfx950.json)",
     }
+    if not args.no_observables:
+        out["observables"] = observables_section(P, H0, H1, args.steps)
+        print("[bench] observables done", file=sys.stderr, flush=True)
     if args.batch:
         out["batched"] = batched_section(args.batch, min(args.steps, 3))
     if not args.no_cpu_baseline:

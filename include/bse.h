@@ -164,6 +164,43 @@ bse_status bse_oscillator(int64_t n, const void* XpY, int64_t ldx, const void* p
 bse_status bse_spectrum(int64_t n, const double* E, const double* osc, double pref, double eta,
                         int64_t nw, const double* omega, void* eps, hipStream_t stream);
 
+/* Transition coefficients along several directions (Sec. 4.4, eq. tlambdai):
+ *   t[l + i ldt] = -i sum_a conj(XpY[a, l]) probe[a + i ldp],  l < n, i < nprobe
+ * With probe column i = conj(D_{., i}), D the dipole elements of eq.
+ * dipolfromp (the D~ of eq. tlambdai), t_{l,i} is the paper's coefficient for
+ * Cartesian direction i.  nprobe: 1..4.  XpY: complex n x n, column-major,
+ * ldx >= n (from bse_solve); probe: complex n x nprobe, ldp >= n; t: complex
+ * n x nprobe (output), ldt >= n.  Device pointers owned by the caller.
+ * BSE_ERR_ARG for a non-positive size, a short leading dimension or a NULL
+ * pointer. */
+bse_status bse_transitions(int64_t n, const void* XpY, int64_t ldx, int32_t nprobe,
+                           const void* probe, int64_t ldp, void* t, int64_t ldt,
+                           hipStream_t stream);
+
+/* Macroscopic dielectric tensor in the optical limit (Sec. 4.4, eq. epsmij):
+ *   eps[(j nd + a) nd + b] = delta_ab - pref sum_l conj(t_la) t_lb
+ *                            [1/(w_j - E_l + i eta) - 1/(w_j + E_l + i eta)]
+ * nd: 1..3 directions; E: [n] (bse_solve); t: complex n x nd (bse_transitions),
+ * ldt >= n; omega: [nw]; eps: complex [nw][nd][nd] (output).  pref = 8 pi kappa
+ * (spin factor 2, 1/V_c, and the 4 pi left of v(q) once M = i q.D cancels its
+ * 1/q^2, eq. mofd); eta > 0 is the half width.  Contracting eps with a unit
+ * direction q gives the scalar eps_M of that direction (eq. epsmtensor).
+ * BSE_ERR_ARG for bad sizes, NULL pointers, eta <= 0 or a non-finite pref. */
+bse_status bse_dielectric_tensor(int64_t n, const double* E, int32_t nd, const void* t,
+                                 int64_t ldt, double pref, double eta, int64_t nw,
+                                 const double* omega, void* eps, hipStream_t stream);
+
+/* Electron energy-loss function and dynamic structure factor (Sec. 4.4, eq.
+ * Lofeps and the definition of S(Q, w) beside it):
+ *   loss[j] = -Im 1/eps[j inc],   sqw[j] = loss[j] vinv / pi
+ * eps: complex, element j at index j * inc (inc = 1 for bse_spectrum's output;
+ * inc = nd * nd, with the pointer moved to element (a, a) of the first
+ * frequency, for a diagonal element of bse_dielectric_tensor's output); vinv = 1 / v_G(q) > 0; loss: [nw] (output); sqw: [nw] (output)
+ * or NULL (then vinv is not used).  BSE_ERR_ARG for nw <= 0, inc < 1, NULL
+ * eps or loss, or a bad vinv with sqw given. */
+bse_status bse_loss(int64_t nw, const void* eps, int64_t inc, double vinv, double* loss,
+                    double* sqw, hipStream_t stream);
+
 /* ---- Batches of independent problems (one per momentum transfer Q; the BSE
  * decouples per q, Sec. 2.3 eq. chimatrixq).  The whole pipeline of every
  * problem (bse_build, the spectrum path of bse_solve, bse_spectrum) is

@@ -18,7 +18,7 @@ BSE_PREC_FP64, BSE_PREC_FP32, BSE_PREC_BF16X3 = 0, 1, 2
 BSE_STAGE_BUILD, BSE_STAGE_SOLVE = 0, 1
 STATUS = {0: "BSE_OK", 1: "BSE_ERR_ARG", 2: "BSE_ERR_WORKSPACE", 3: "BSE_ERR_HIP"}
 EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bse_spectrum",
-           "bse_status_string", "bse_timing_enable", "bse_timing_report",
+           "bse_transitions", "bse_dielectric_tensor", "bse_loss", "bse_status_string", "bse_timing_enable", "bse_timing_report",
            "bse_batch_workspace_size", "bse_batch_create", "bse_batch_capture", "bse_batch_run",
            "bse_batch_destroy", "bse_tune_set", "bse_tune_get")
 TUNE_SITES = {"hemv_unit": 0, "gemm_squared": 1, "gemm_potrf": 2, "gemm_her2k": 3,
@@ -75,6 +75,12 @@ def lib() -> ctypes.CDLL:
         L.bse_oscillator.restype = ctypes.c_int
         L.bse_spectrum.argtypes = [i64, vp, vp, dbl, dbl, i64, vp, vp, vp]
         L.bse_spectrum.restype = ctypes.c_int
+        L.bse_transitions.argtypes = [i64, vp, i64, i32, vp, i64, vp, i64, vp]
+        L.bse_transitions.restype = ctypes.c_int
+        L.bse_dielectric_tensor.argtypes = [i64, vp, i32, vp, i64, dbl, dbl, i64, vp, vp, vp]
+        L.bse_dielectric_tensor.restype = ctypes.c_int
+        L.bse_loss.argtypes = [i64, vp, i64, dbl, vp, vp, vp]
+        L.bse_loss.restype = ctypes.c_int
         L.bse_timing_enable.argtypes = [i32, ctypes.c_char_p]
         L.bse_timing_enable.restype = None
         L.bse_timing_report.argtypes = [ctypes.c_char_p, i64]
@@ -132,6 +138,24 @@ def bse_spectrum(n: int, E: int, osc: int, pref: float, eta: float, nw: int, ome
                  stream: int) -> None:
     _check(lib().bse_spectrum(n, E, osc, pref, eta, nw, omega, eps, stream or None),
            "bse_spectrum")
+
+
+def bse_transitions(n: int, XpY: int, ldx: int, nprobe: int, probe: int, ldp: int, t: int,
+                    ldt: int, stream: int) -> None:
+    _check(lib().bse_transitions(n, XpY or None, ldx, nprobe, probe or None, ldp, t or None, ldt,
+                                 stream or None), "bse_transitions")
+
+
+def bse_dielectric_tensor(n: int, E: int, nd: int, t: int, ldt: int, pref: float, eta: float,
+                          nw: int, omega: int, eps: int, stream: int) -> None:
+    _check(lib().bse_dielectric_tensor(n, E or None, nd, t or None, ldt, pref, eta, nw,
+                                       omega or None, eps or None, stream or None),
+           "bse_dielectric_tensor")
+
+
+def bse_loss(nw: int, eps: int, inc: int, vinv: float, loss: int, sqw: int, stream: int) -> None:
+    _check(lib().bse_loss(nw, eps or None, inc, vinv, loss or None, sqw or None, stream or None),
+           "bse_loss")
 
 
 def bse_timing_enable(on: bool, name: str | None = None) -> None:

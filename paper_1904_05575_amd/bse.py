@@ -3,7 +3,8 @@
 PyTorch supplies device memory and the stream; every step of the method runs
 in libbse.so.  The small host computations here are the problem's geometry
 (Coulomb potential without its macroscopic term, eq. vbar_def; the kernel
-prefactor 1/V_c of eq. vft) and the probe vector of eq. osci.
+prefactor 1/V_c of eq. vft), the probe vector of eq. osci and the probe
+vectors conj(D) of eq. tlambdai.
 """
 from __future__ import annotations
 
@@ -90,8 +91,12 @@ class Problem:
         gq = g_index_of_q(inputs["gvec"], inputs["alat"], w.q)
         self.t["probe"] = _dev(np.conj(inputs["Mcv"][:, gq]), c128, dv)
         self.t["omega"] = _dev(inputs["omega"], f64, dv)
+        if inputs.get("Dcv") is not None:  # column i = conj(D_{., i}), column-major n x 3
+            self.t["dprobe"] = _dev(np.conj(inputs["Dcv"]).T, c128, dv)
         self.kappa = kernel_prefactor(w.kernel_scale, w.nk, inputs["cell_volume"])
         self.pref = 2.0 * self.kappa * coulomb_v0(w.q)
+        self.tensor_pref = 8.0 * np.pi * self.kappa  # spin 2, 1/V_c, 4 pi of v(q) (eq. mofd)
+        self.vinv = 1.0 / coulomb_v0(w.q)
         self.eta = w.eta
         self.desc = L.BseDesc(nk=w.nk, nv=w.nv, nc=w.nc, ng=w.ng,
                               coupling=L.BSE_FULL if self.full else L.BSE_TDA,
@@ -163,6 +168,39 @@ class Problem:
         L.bse_oscillator(self.n, XpY.data_ptr(), self.n, self.t["probe"].data_ptr(),
                          osc.data_ptr(), self.stream())
         return osc
+
+    def transitions(self, XpY, probes=None):
+        """t (column-major n x nprobe, as a [nprobe, n] tensor) of eq. tlambdai
+        for the probe columns conj(D) (default: the three Cartesian directions)."""
+        P = self.t["dprobe"] if probes is None else probes
+        nprobe = P.shape[0]
+        t = torch.empty((nprobe, self.n), dtype=torch.complex128, device=self.device)
+        L.bse_transitions(self.n, XpY.data_ptr(), self.n, nprobe, P.data_ptr(), self.n,
+                          t.data_ptr(), self.n, self.stream())
+        return t
+
+    def dielectric_tensor(self, E, t):
+        """eps[w, a, b] of eq. epsmij from bse_transitions' t ([nd, n])."""
+        nd, nw = t.shape[0], self.t["omega"].numel()
+        eps = torch.empty((nw, nd, nd), dtype=torch.complex128, device=self.device)
+        L.bse_dielectric_tensor(self.n, E.data_ptr(), nd, t.data_ptr(), self.n, self.tensor_pref,
+                                self.eta, nw, self.t["omega"].data_ptr(), eps.data_ptr(),
+                                self.stream())
+        return eps
+
+    def loss(self, eps, diag: int | None = None):
+        """(-Im 1/eps, S(Q, w)) for a scalar spectrum [nw], or for the diagonal
+        element (diag, diag) of a tensor [nw, nd, nd]."""
+        nw = eps.shape[0]
+        ptr, inc = eps.data_ptr(), 1
+        if diag is not None:
+            nd = eps.shape[1]
+            ptr += 16 * diag * (nd + 1)
+            inc = nd * nd
+        L_ = torch.empty(nw, dtype=torch.float64, device=self.device)
+        S = torch.empty(nw, dtype=torch.float64, device=self.device)
+        L.bse_loss(nw, ptr, inc, self.vinv, L_.data_ptr(), S.data_ptr(), self.stream())
+        return L_, S
 
     def run(self, vectors: bool = False):
         """build -> solve -> spectrum; returns host arrays."""

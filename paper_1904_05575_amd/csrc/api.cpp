@@ -81,6 +81,40 @@ bse_status bse_spectrum(int64_t n, const double* E, const double* osc, double pr
              : BSE_ERR_HIP;
 }
 
+bse_status bse_transitions(int64_t n, const void* XpY, int64_t ldx, int32_t nprobe,
+                           const void* probe, int64_t ldp, void* t, int64_t ldt,
+                           hipStream_t stream) {
+  launch_failure_reset();
+  if (n <= 0 || nprobe < 1 || nprobe > 4 || !XpY || !probe || !t) return BSE_ERR_ARG;
+  if (ldx < n || ldp < n || ldt < n) return BSE_ERR_ARG;
+  return launch_transitions(n, (const double2*)XpY, ldx, nprobe, (const double2*)probe, ldp,
+                            (double2*)t, ldt, stream) == hipSuccess
+             ? BSE_OK
+             : BSE_ERR_HIP;
+}
+
+bse_status bse_dielectric_tensor(int64_t n, const double* E, int32_t nd, const void* t,
+                                 int64_t ldt, double pref, double eta, int64_t nw,
+                                 const double* omega, void* eps, hipStream_t stream) {
+  launch_failure_reset();
+  if (n <= 0 || nw <= 0 || nd < 1 || nd > 3 || !E || !t || !omega || !eps) return BSE_ERR_ARG;
+  if (ldt < n || !isfinite(pref) || !(eta > 0.0) || !isfinite(eta)) return BSE_ERR_ARG;
+  return launch_dielectric_tensor(n, E, nd, (const double2*)t, ldt, pref, eta, nw, omega,
+                                  (double2*)eps, stream) == hipSuccess
+             ? BSE_OK
+             : BSE_ERR_HIP;
+}
+
+bse_status bse_loss(int64_t nw, const void* eps, int64_t inc, double vinv, double* loss,
+                    double* sqw, hipStream_t stream) {
+  launch_failure_reset();
+  if (nw <= 0 || inc < 1 || !eps || !loss) return BSE_ERR_ARG;
+  if (sqw && (!isfinite(vinv) || !(vinv > 0.0))) return BSE_ERR_ARG;
+  return launch_loss(nw, (const double2*)eps, inc, vinv, loss, sqw, stream) == hipSuccess
+             ? BSE_OK
+             : BSE_ERR_HIP;
+}
+
 const char* bse_status_string(bse_status s) {
   switch (s) {
     case BSE_OK: return "ok";

@@ -74,3 +74,11 @@ hipError_t launch_oscillator(int64_t n, const double2* XpY, int64_t ldx, const d
                              double* osc, hipStream_t s);
 hipError_t launch_spectrum(int64_t n, const double* E, const double* osc, double pref, double eta,
                            int64_t nw, const double* omega, double2* eps, hipStream_t s);
+hipError_t launch_transitions(int64_t n, const double2* XpY, int64_t ldx, int nprobe,
+                              const double2* probe, int64_t ldp, double2* t, int64_t ldt,
+                              hipStream_t s);
+hipError_t launch_dielectric_tensor(int64_t n, const double* E, int nd, const double2* t,
+                                    int64_t ldt, double pref, double eta, int64_t nw,
+                                    const double* omega, double2* eps, hipStream_t s);
+hipError_t launch_loss(int64_t nw, const double2* eps, int64_t inc, double vinv, double* loss,
+                       double* sqw, hipStream_t s);

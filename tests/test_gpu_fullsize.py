@@ -7,6 +7,11 @@ and on identities that hold at any size.
              Hermitian-definite solver on the GPU-built A+-B (1e-10);
              sum E^2 = tr((A-B)(A+B)); f-sum and static-limit rules (1e-10)
   spectrum : bse_spectrum vs the eigen-sum evaluated on the host (1e-12)
+  observables (vectors path): sampled columns of t (eq. tlambdai) and sampled
+             frequencies of eps^ij (eq. epsmij) vs the oracle on the GPU's E
+             and X+Y (1e-12); contractions of eps^ij with an axis and a complex
+             direction vs the spectrum-only path with the matching probe
+             (no eigenvectors, a different route; 1e-10)
 """
 import numpy as np
 import pytest
@@ -90,3 +95,50 @@ def test_spectrum_at_full_size(run):
     P = run["P"]
     ref = O.spectrum(E, osc, d["omega"], d["workload"].eta, P.pref)
     assert np.abs(run["eps"] - ref).max() / np.abs(ref - 1).max() < 1e-12
+
+
+def test_observables_at_full_size(run):
+    """N = 6144 full BSE: sampled t columns and sampled frequencies of eps^ij
+    against the oracle on the GPU's E and X+Y; contractions of eps^ij with
+    an axis and a complex direction against the GPU's spectrum-only path
+    with the matching probe (no eigenvectors, a different route)."""
+    import torch
+    from oracle import observables as X
+    d, P = run["d"], run["P"]
+    print("[gpu] observables at full size: build, solve with vectors", flush=True)
+    H0, H1 = P.build()
+    E, XpY, _ = P.solve(H0, H1, vectors=True, probe=False)
+    t = P.transitions(XpY)
+    eps = P.dielectric_tensor(E, t)
+    P.check_info()
+    print("[gpu] vectors path done", flush=True)
+    n = P.n
+    rng = np.random.default_rng(11)
+    cols = np.unique(np.concatenate([rng.choice(n, 48, replace=False), [0, n - 1]]))
+    Xs = XpY[cols].cpu().numpy().T                      # columns cols of X+Y, [a, l]
+    th = t.cpu().numpy().T
+    assert _relx(th[cols], X.transition_coefficients(Xs, d["Dcv"])) < 1e-12
+    del XpY
+    torch.cuda.empty_cache()
+    Eh = E.cpu().numpy()
+    om = d["omega"]
+    ws = np.unique(np.concatenate([rng.choice(len(om), 40, replace=False), [0, len(om) - 1]]))
+    epsh = eps.cpu().numpy()
+    ref = X.dielectric_tensor(Eh, th, om[ws], d["workload"].eta, X.tensor_prefactor(d))
+    assert _relx(epsh[ws], ref) < 1e-12
+    u = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    for u in (np.eye(3)[1], u / np.linalg.norm(u)):
+        p_u = d["Dcv"].conj() @ u
+        P.t["probe"] = torch.from_numpy(p_u).cuda()
+        H0, H1 = P.build(H0, H1)
+        E2, _, osc = P.solve(H0, H1, vectors=False)
+        pref, P.pref = P.pref, P.tensor_pref
+        scal = P.spectrum(E2, osc).cpu().numpy()
+        P.pref = pref
+        P.check_info()
+        con = X.contract(epsh, u)
+        assert np.abs(con - scal).max() < 1e-10 * np.abs(scal - 1).max(), u
+
+
+def _relx(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)

@@ -75,6 +75,23 @@ def test_argument_errors_are_reported_without_launching(lib):
         L.bse_spectrum(10, 1, 1, 1.0, 0.0, 5, 1, 1, 0)      # eta must be > 0
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
         L.bse_oscillator(10, 1, 5, 1, 1, 0)                 # ldx < n
+    for bad in (dict(nprobe=0), dict(nprobe=5), dict(ldp=9), dict(ldt=9), dict(ldx=9),
+                dict(n=0), dict(probe=0)):
+        a = dict(n=10, XpY=1, ldx=10, nprobe=3, probe=1, ldp=10, t=1, ldt=10, stream=0)
+        a.update(bad)
+        with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+            L.bse_transitions(**a)
+    for bad in (dict(nd=0), dict(nd=4), dict(ldt=9), dict(eta=0.0), dict(nw=0),
+                dict(pref=float("nan"))):
+        a = dict(n=10, E=1, nd=3, t=1, ldt=10, pref=1.0, eta=0.1, nw=5, omega=1, eps=1, stream=0)
+        a.update(bad)
+        with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+            L.bse_dielectric_tensor(**a)
+    for bad in (dict(nw=0), dict(inc=0), dict(loss=0), dict(vinv=0.0), dict(vinv=float("inf"))):
+        a = dict(nw=5, eps=1, inc=1, vinv=1.0, loss=1, sqw=1, stream=0)
+        a.update(bad)
+        with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+            L.bse_loss(**a)
     assert lib.bse_status_string(2) == b"workspace too small"
 
 
