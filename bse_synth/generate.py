@@ -22,6 +22,12 @@ Recipe (all complex draws are standard complex normal, E|z|^2 = 1):
                                          energy difference, the optical limit)
   W[q] = v^1/2(q+G) (I + L_q L_q^H)^-1 v^1/2(q+G'),  L_q ~ 0.3 CN (NG x 8),
          v(p) = 4 pi / |p|^2 with |p|^2 replaced by 0.01 at p = 0.
+Inputs of the RPA screening (make_screening_inputs): the workload's energies
+and, for every q of the mesh and k, pair elements between the bands at k and
+at k + q,
+  Svc[q, k, v, c, G], Scv[q, k, c, v, G] ~ CN |p| / (1 + |p|^2),  p = q + G
+         (|p| replaced by 0.1 at p = 0; the factor |p| mimics M ~ q.D near
+         p = 0, which keeps v |M|^2 finite).
 Transition index a = (ik * nv + iv) * nc + ic.
 
 Large arrays are drawn in fixed-size chunks, each from its own Philox stream
@@ -39,7 +45,7 @@ from . import lattice
 from .workloads import Workload
 
 _KIND = {"eps_v": 1, "eps_c": 2, "Mcv": 3, "Mvv": 4, "Mcc": 5, "Ncv": 6, "Nvc": 7, "L": 8,
-         "Dcv": 9}
+         "Dcv": 9, "Svc": 10, "Scv": 11}
 _CHUNK_ROWS = 1024
 _INV_SQRT2 = 1.0 / np.sqrt(2.0)
 
@@ -163,4 +169,33 @@ def make_batch_inputs(bw) -> list:
             d["Nvc"] = master["Nvc"][:, :nv, :nc, :]
         d["master"] = master
         out.append(d)
+    return out
+
+
+def make_screening_inputs(w: Workload) -> dict:
+    """Inputs of the RPA screening on the workload's mesh and bands: energies,
+    the index of k + q on the mesh, and the pair elements of both orders."""
+    base = make_inputs(w, want_pairs=False)
+    n, nk, nv, nc, ng = w.mesh, w.nk, w.nv, w.nc, w.ng
+    km = lattice.kmesh(n)
+    kq = lattice.mesh_index(km[None, :, :] + km[:, None, :], n).astype(np.int32)  # [q, k]
+    qc = lattice.centred_cart(km, n)
+    G = lattice.gcart(ng)
+    p = np.sqrt(np.sum((qc[:, None, :] + G[None, :, :]) ** 2, axis=2))       # [q, G]
+    p = np.where(p < 1e-6, 0.1, p)
+    env = p / (1.0 + p ** 2)
+    out = {"workload": w, "eps_v": base["eps_v"], "eps_c": base["eps_c"], "kqmap": kq,
+           "qcart": qc, "gvec": base["gvec"], "alat": base["alat"],
+           "cell_volume": base["cell_volume"]}
+    for kind, b1, b2 in (("Svc", nv, nc), ("Scv", nc, nv)):
+        a = np.empty((nk, nk, b1, b2, ng), dtype=np.complex128)
+
+        def fill(iq: int) -> None:  # one Philox stream per q
+            blk = a[iq].reshape(-1).view(np.float64)
+            _rng(w.seed * 4096 + iq, kind, 0).standard_normal(out=blk)
+            a[iq] *= env[iq] * _INV_SQRT2
+
+        with ThreadPoolExecutor(_threads()) as ex:
+            list(ex.map(fill, range(nk)))
+        out[kind] = a
     return out
