@@ -221,6 +221,50 @@ def observables_section(P, H0, H1, reps: int) -> dict:
             "loss_ms": lo_ms}
 
 
+def screening_section(w, reps: int) -> dict:
+    """Static RPA screening on the workload's mesh and bands: W(q) for every q
+    (bse_screening), timed with HIP events over `reps` calls; the two pair
+    contractions on MFMA against the FP64 peak."""
+    import torch
+    from bse_synth import make_screening_inputs
+    from paper_1904_05575_amd import _lib as L
+    from paper_1904_05575_amd.bse import Screening
+
+    t0 = time.perf_counter()
+    sd = make_screening_inputs(w)
+    gen_s = time.perf_counter() - t0
+    Sc = Screening(sd)
+    del sd
+    W = Sc.run()
+    Sc.check_info()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        Sc.run(W)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    L.bse_timing_enable(True)
+    Sc.run(W)
+    torch.cuda.synchronize()
+    L.bse_timing_enable(False)
+    k = L.bse_timing_report()
+    Sc.check_info()
+    k1 = w.nk * w.nv * w.nc
+    flop = 2 * 8 * w.nk * w.ng * w.ng * k1          # two pair sets, 8 flop per cMAC
+    chi_ms = k.get("zgemm_screen_chi", (1, float("nan")))[1]
+    out = {"workload": f"{w.name} mesh", "nq": w.nk, "ng": w.ng, "pair_rows_per_q": 2 * k1,
+           "ms": ms, "chi_gflop": flop / 1e9, "chi_ms": chi_ms,
+           "chi_TFLOPs": flop / (chi_ms * 1e-3) / 1e12,
+           "chi_frac_fp64_peak": flop / (chi_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+           "invert_ms": k.get("k_screen_invert", (1, float("nan")))[1],
+           "weights_ms": k.get("k_screen_weights", (1, float("nan")))[1],
+           "input_generation_s": gen_s}
+    del Sc, W
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +278,8 @@ def main() -> int:
                     help="assembly precisions timed after the FP64 steps")
     ap.add_argument("--no-observables", action="store_true",
                     help="skip the optical-limit observables (eigenvector path) section")
+    ap.add_argument("--no-screening", action="store_true",
+                    help="skip the RPA screening section")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -393,6 +439,11 @@ def main() -> int:
     if not args.no_observables:
         out["observables"] = observables_section(P, H0, H1, args.steps)
         print("[bench] observables done", file=sys.stderr, flush=True)
+    if not args.no_screening:
+        del P, H0, H1
+        torch.cuda.empty_cache()
+        out["screening"] = screening_section(w, args.steps)
+        print("[bench] screening done", file=sys.stderr, flush=True)
     if args.batch:
         out["batched"] = batched_section(args.batch, min(args.steps, 3))
     if not args.no_cpu_baseline:

@@ -201,6 +201,45 @@ bse_status bse_dielectric_tensor(int64_t n, const double* E, int32_t nd, const v
 bse_status bse_loss(int64_t nw, const void* eps, int64_t inc, double vinv, double* loss,
                     double* sqw, hipStream_t stream);
 
+/* ---- Static RPA screening (Sec. 4.2: the RPA dielectric matrix at w = 0 and
+ * the screened interaction w_GG'(q) = v_G(q) eps^-1_GG'(q), eq. wggq), the
+ * W(q) input of bse_build.  An insulator at zero temperature: f = 1 in the nv
+ * occupied and 0 in the nc unoccupied bands, so the sum over band pairs runs
+ * over (occupied at k, unoccupied at k+q) and (unoccupied at k, occupied at
+ * k+q), each with weight 1/|e_j,k+q - e_i,k| (in 1/Hartree). */
+typedef struct {
+  int32_t nk;                /* k-points of the mesh; W is formed for every q of it */
+  int32_t nv, nc;            /* occupied and unoccupied bands */
+  int32_t ng;                /* plane waves G (1..512) */
+  double inv_vc;             /* 1/V_c = 1/(N_k Omega), bohr^-3 */
+  double units_per_hartree;  /* energy units per Hartree: 27.211386245988 for eV */
+} bse_screen_desc;
+
+/* Bytes of scratch space `ws` needed by bse_screening (the pair weights);
+ * 0 for an invalid descriptor. */
+size_t bse_screening_workspace_size(const bse_screen_desc* desc);
+
+/* W[q][G][G'] (complex, row-major, the layout bse_inputs.W takes) for every q:
+ *   W = v^1/2 (I + v^1/2 Xt v^1/2)^-1 v^1/2,
+ *   Xt[G,G'] = inv_vc sum_{k, pairs} |F| conj(M(G)) M(G')
+ * which equals v_G eps^-1_GG' for eps_GG' = delta_GG' - v_G' X_GG', X = -Xt.
+ *  eps_v: [nk][nv], eps_c: [nk][nc] band energies (in the units of the desc);
+ *  kqmap: int32 [q][k], the mesh index of k + q;
+ *  Svc: complex [q][k][nv][nc][ng], elements between occupied band v at k
+ *       and unoccupied band c at k+q;
+ *  Scv: complex [q][k][nc][nv][ng], unoccupied c at k and occupied v at k+q;
+ *  vsqrt: [q][ng], v(q+G)^1/2 (the caller's Coulomb potential, regularised
+ *       where q+G = 0);
+ *  W: complex [q][ng][ng] (output).
+ * Errors on the device: info = -5 when an occupied band is not below an
+ * unoccupied one (no gap), -6 when a pivot of the inversion is not positive.
+ * BSE_ERR_ARG for a bad descriptor or a NULL pointer, BSE_ERR_WORKSPACE when
+ * ws_bytes is short. */
+bse_status bse_screening(const bse_screen_desc* desc, const double* eps_v, const double* eps_c,
+                         const int32_t* kqmap, const void* Svc, const void* Scv,
+                         const double* vsqrt, void* W, void* ws, size_t ws_bytes, int32_t* info,
+                         hipStream_t stream);
+
 /* ---- Batches of independent problems (one per momentum transfer Q; the BSE
  * decouples per q, Sec. 2.3 eq. chimatrixq).  The whole pipeline of every
  * problem (bse_build, the spectrum path of bse_solve, bse_spectrum) is

@@ -18,7 +18,8 @@ BSE_PREC_FP64, BSE_PREC_FP32, BSE_PREC_BF16X3 = 0, 1, 2
 BSE_STAGE_BUILD, BSE_STAGE_SOLVE = 0, 1
 STATUS = {0: "BSE_OK", 1: "BSE_ERR_ARG", 2: "BSE_ERR_WORKSPACE", 3: "BSE_ERR_HIP"}
 EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bse_spectrum",
-           "bse_transitions", "bse_dielectric_tensor", "bse_loss", "bse_status_string", "bse_timing_enable", "bse_timing_report",
+           "bse_transitions", "bse_dielectric_tensor", "bse_loss", "bse_screening_workspace_size",
+           "bse_screening", "bse_status_string", "bse_timing_enable", "bse_timing_report",
            "bse_batch_workspace_size", "bse_batch_create", "bse_batch_capture", "bse_batch_run",
            "bse_batch_destroy", "bse_tune_set", "bse_tune_get")
 TUNE_SITES = {"hemv_unit": 0, "gemm_squared": 1, "gemm_potrf": 2, "gemm_her2k": 3,
@@ -40,6 +41,12 @@ class BseInputs(ctypes.Structure):
                 ("vbar", ctypes.c_void_p), ("qmap", ctypes.c_void_p), ("qramap", ctypes.c_void_p),
                 ("nq", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("mcc_env", ctypes.c_void_p), ("mcc_key", ctypes.c_uint64)]
+
+
+class BseScreenDesc(ctypes.Structure):
+    _fields_ = [("nk", ctypes.c_int32), ("nv", ctypes.c_int32), ("nc", ctypes.c_int32),
+                ("ng", ctypes.c_int32), ("inv_vc", ctypes.c_double),
+                ("units_per_hartree", ctypes.c_double)]
 
 
 class BseTuneEntry(ctypes.Structure):
@@ -81,6 +88,11 @@ def lib() -> ctypes.CDLL:
         L.bse_dielectric_tensor.restype = ctypes.c_int
         L.bse_loss.argtypes = [i64, vp, i64, dbl, vp, vp, vp]
         L.bse_loss.restype = ctypes.c_int
+        L.bse_screening_workspace_size.argtypes = [ctypes.POINTER(BseScreenDesc)]
+        L.bse_screening_workspace_size.restype = sz
+        L.bse_screening.argtypes = [ctypes.POINTER(BseScreenDesc), vp, vp, vp, vp, vp, vp, vp, vp,
+                                    sz, vp, vp]
+        L.bse_screening.restype = ctypes.c_int
         L.bse_timing_enable.argtypes = [i32, ctypes.c_char_p]
         L.bse_timing_enable.restype = None
         L.bse_timing_report.argtypes = [ctypes.c_char_p, i64]
@@ -156,6 +168,17 @@ def bse_dielectric_tensor(n: int, E: int, nd: int, t: int, ldt: int, pref: float
 def bse_loss(nw: int, eps: int, inc: int, vinv: float, loss: int, sqw: int, stream: int) -> None:
     _check(lib().bse_loss(nw, eps or None, inc, vinv, loss or None, sqw or None, stream or None),
            "bse_loss")
+
+
+def bse_screening_workspace_size(desc: BseScreenDesc) -> int:
+    return int(lib().bse_screening_workspace_size(ctypes.byref(desc)))
+
+
+def bse_screening(desc: BseScreenDesc, eps_v: int, eps_c: int, kqmap: int, Svc: int, Scv: int,
+                  vsqrt: int, W: int, ws: int, ws_bytes: int, info: int, stream: int) -> None:
+    _check(lib().bse_screening(ctypes.byref(desc), eps_v or None, eps_c or None, kqmap or None,
+                               Svc or None, Scv or None, vsqrt or None, W or None, ws or None,
+                               ws_bytes, info or None, stream or None), "bse_screening")
 
 
 def bse_timing_enable(on: bool, name: str | None = None) -> None:

@@ -212,3 +212,46 @@ class Problem:
         if vectors:
             out["XpY"] = XpY.T.cpu().numpy()  # column-major storage -> [a, l]
         return out
+
+
+class Screening:
+    """The static RPA screening of one k-mesh resident on the GPU: W(q) for
+    every q of the mesh (bse_screening), in the layout bse_build takes."""
+
+    def __init__(self, sinputs: dict, device: str = "cuda"):
+        w = sinputs["workload"]
+        self.workload = w
+        self.device = torch.device(device)
+        dv, c128, f64 = self.device, torch.complex128, torch.float64
+        self.nk, self.ng = w.nk, w.ng
+        G = sinputs["gvec"].astype(np.float64) * (2.0 * np.pi / sinputs["alat"])
+        p2 = np.sum((sinputs["qcart"][:, None, :] + G[None, :, :]) ** 2, axis=2)
+        vsqrt = np.sqrt(4.0 * np.pi / np.where(p2 < 1e-12, 0.01, p2))  # v(q+G)^1/2
+        self.t = {"eps_v": _dev(sinputs["eps_v"], f64, dv), "eps_c": _dev(sinputs["eps_c"], f64, dv),
+                  "kqmap": _dev(sinputs["kqmap"], torch.int32, dv),
+                  "Svc": _dev(sinputs["Svc"], c128, dv), "Scv": _dev(sinputs["Scv"], c128, dv),
+                  "vsqrt": _dev(vsqrt, f64, dv)}
+        self.desc = L.BseScreenDesc(nk=w.nk, nv=w.nv, nc=w.nc, ng=w.ng,
+                                    inv_vc=1.0 / (w.nk * sinputs["cell_volume"]),
+                                    units_per_hartree=HARTREE_EV)
+        self.ws = torch.empty(max(1, L.bse_screening_workspace_size(self.desc)),
+                              dtype=torch.uint8, device=dv)
+        self.info = torch.zeros(1, dtype=torch.int32, device=dv)
+
+    def run(self, W=None):
+        """W[q, G, G'] (complex128 tensor on the device)."""
+        if W is None:
+            W = torch.empty((self.nk, self.ng, self.ng), dtype=torch.complex128, device=self.device)
+        t = self.t
+        L.bse_screening(self.desc, t["eps_v"].data_ptr(), t["eps_c"].data_ptr(),
+                        t["kqmap"].data_ptr(), t["Svc"].data_ptr(), t["Scv"].data_ptr(),
+                        t["vsqrt"].data_ptr(), W.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+                        self.info.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        return W
+
+    def check_info(self) -> None:
+        torch.cuda.synchronize()
+        code = int(self.info.item())
+        if code != 0:
+            raise L.BseError(f"device status info = {code}")
+

@@ -115,6 +115,23 @@ bse_status bse_loss(int64_t nw, const void* eps, int64_t inc, double vinv, doubl
              : BSE_ERR_HIP;
 }
 
+size_t bse_screening_workspace_size(const bse_screen_desc* d) {
+  return screening_desc_ok(d) ? screening_workspace(d) : 0;
+}
+
+bse_status bse_screening(const bse_screen_desc* d, const double* eps_v, const double* eps_c,
+                         const int32_t* kqmap, const void* Svc, const void* Scv,
+                         const double* vsqrt, void* W, void* ws, size_t ws_bytes, int32_t* info,
+                         hipStream_t stream) {
+  launch_failure_reset();
+  if (!screening_desc_ok(d)) return BSE_ERR_ARG;
+  if (!eps_v || !eps_c || !kqmap || !Svc || !Scv || !vsqrt || !W || !ws || !info)
+    return BSE_ERR_ARG;
+  if (ws_bytes < screening_workspace(d)) return BSE_ERR_WORKSPACE;
+  return screening_run(d, eps_v, eps_c, kqmap, (const double2*)Svc, (const double2*)Scv, vsqrt,
+                       (double2*)W, ws, info, stream);
+}
+
 const char* bse_status_string(bse_status s) {
   switch (s) {
     case BSE_OK: return "ok";

@@ -69,6 +69,14 @@ size_t solve_workspace(const bse_desc* d);
 bse_status solve_run(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, int64_t ldx,
                      const void* probe, double* osc, void* ws, int32_t* info, hipStream_t s);
 
+// screening.hip
+size_t screening_workspace(const bse_screen_desc* d);
+bool screening_desc_ok(const bse_screen_desc* d);
+bse_status screening_run(const bse_screen_desc* d, const double* eps_v, const double* eps_c,
+                         const int32_t* kqmap, const double2* Svc, const double2* Scv,
+                         const double* vsqrt, double2* W, void* ws, int32_t* info,
+                         hipStream_t s);
+
 // spectrum.hip
 hipError_t launch_oscillator(int64_t n, const double2* XpY, int64_t ldx, const double2* probe,
                              double* osc, hipStream_t s);

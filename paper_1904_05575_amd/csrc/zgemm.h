@@ -25,7 +25,8 @@ struct ZgemmParams {
   int c_uplo = 0;  // 0 all; 1 store only m <= n; 2 store only m >= n
   int a_tri = 0;   // 1: A(m,k) = 0 for k < m; 2: A(m,k) = 0 for k > m
   int b_tri = 0;   // 1: B(k,n) = 0 for k > n; 2: B(k,n) = 0 for k < n
-  const double* kscale = nullptr;  // A(m,k) *= kscale[k]
+  const double* kscale = nullptr;  // A(m,k) *= kscale[b*ks_bs + k]
+  int64_t ks_bs = 0;
   const int32_t* info = nullptr;   // skip all work when *info != 0
   const char* tag = "zgemm";        // name under which the launch is timed
   int tile = 0;                     // 16, 32 or 64: tile edge; 0: chosen from the shape

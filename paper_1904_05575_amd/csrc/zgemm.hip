@@ -18,6 +18,7 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
   const int64_t bb = p.b_batch_idx ? (int64_t)p.b_batch_idx[b] : (int64_t)b;
   const double2* __restrict__ A = p.A + b * p.a_bs;
   const double2* __restrict__ B = p.B + bb * p.b_bs;
+  const double* __restrict__ ks = p.kscale ? p.kscale + b * p.ks_bs : nullptr;
 
   int k_lo = 0, k_hi = p.K;
   if (p.a_tri == 1) k_lo = max(k_lo, m0);
@@ -43,8 +44,8 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
   };
   auto fixA = [&](double2 v, int k) -> double2 {
     v.y *= asgn;
-    if (p.kscale) {
-      const double s = p.kscale[k];
+    if (ks) {
+      const double s = ks[k];
       v.x *= s;
       v.y *= s;
     }

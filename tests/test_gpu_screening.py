@@ -1,0 +1,103 @@
+"""GPU parity of the static RPA screening (bse_screening) against the FP64
+oracle: W(q) element by element on small meshes (1e-12 of max|W|), sampled
+q at the benchmark's mesh, and the BSE built on the GPU's W against the
+oracle's path built on the oracle's W (1e-10)."""
+import numpy as np
+import pytest
+
+from oracle import bse_oracle as O
+from oracle import screening as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _screening(name):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from bse_synth import get, make_screening_inputs
+    from paper_1904_05575_amd.bse import Screening
+    w = get(name) if isinstance(name, str) else name
+    print(f"[gpu] screening {w.name}", flush=True)
+    d = make_screening_inputs(w)
+    return d, Screening(d)
+
+
+def _oracle_q(d, iq):
+    from bse_synth import lattice
+    w = d["workload"]
+    v = S.coulomb(d["qcart"], lattice.gcart(w.ng))[iq]
+    X = S.chi_sum(d["Svc"], d["Scv"], d["eps_v"], d["eps_c"], d["kqmap"], iq,
+                  1.0 / (w.nk * d["cell_volume"]))
+    return S.screened_w(S.dielectric_matrix(X, v), v)
+
+
+@pytest.mark.parametrize("name", ["tiny_tda_k2_v2c2_g9", "tiny_full_k2_v2c3_g15",
+                                  "small_full_k3_v3c4_g27", "tda_q0_k4_v2c3_g59"])
+def test_screening_matches_oracle(name):
+    d, Sc = _screening(name)
+    W = Sc.run()
+    Sc.check_info()
+    got = W.cpu().numpy()
+    ref = S.screening(d)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_screening_sampled_q_at_ng89_and_repeated_calls():
+    """N_G = 89 takes the 32-wide GEMM tiles (3 x 3 per q, ragged); a second
+    call into the same output gives the same bits (nothing carried over)."""
+    from bse_synth import BATCHES
+    d, Sc = _screening(BATCHES["batch16_k6_g89"].members[0])
+    W = Sc.run()
+    Sc.check_info()
+    first = W.cpu().numpy()
+    W.fill_(float("nan"))
+    Sc.run(W)
+    Sc.check_info()
+    assert np.array_equal(first, W.cpu().numpy())
+    for iq in (0, 1, 107, d["workload"].nk - 1):
+        ref = _oracle_q(d, iq)
+        assert np.abs(first[iq] - ref).max() < 1e-12 * np.abs(ref).max(), iq
+
+
+def test_screening_at_the_benchmark_mesh():
+    """8^3 mesh, 3 + 4 bands, N_G = 113 (K = 6144 pair rows per q): sampled q
+    against the oracle; every W(q) Hermitian to rounding with
+    0 < v^-1/2 W v^-1/2 <= 1."""
+    d, Sc = _screening("full_q0_k8_v3c4_g113")
+    W = Sc.run()
+    Sc.check_info()
+    got = W.cpu().numpy()
+    rng = np.random.default_rng(3)
+    for iq in np.unique(np.concatenate([[0, 1, d["workload"].nk - 1],
+                                         rng.choice(d["workload"].nk, 5, replace=False)])):
+        ref = _oracle_q(d, int(iq))
+        assert np.abs(got[iq] - ref).max() < 1e-12 * np.abs(ref).max(), iq
+    sv = 1.0 / Sc.t["vsqrt"].cpu().numpy()
+    for iq in range(0, d["workload"].nk, 37):
+        R = sv[iq][:, None] * got[iq] * sv[iq][None, :]
+        assert np.abs(R - R.conj().T).max() < 1e-12
+        lam = np.linalg.eigvalsh(0.5 * (R + R.conj().T))
+        assert lam.min() > 0.0 and lam.max() <= 1.0 + 1e-12
+
+
+@pytest.mark.parametrize("name", ["tiny_full_k2_v2c3_g15", "small_full_k3_v3c4_g27"])
+def test_bse_on_the_screened_interaction(name):
+    """The whole chain on the GPU (screening -> build -> solve -> spectrum,
+    W handed over in device memory) against the oracle's chain on its own W."""
+    torch = pytest.importorskip("torch")
+    from bse_synth import get, make_inputs
+    from paper_1904_05575_amd.bse import Problem
+    ds, Sc = _screening(name)
+    Wd = Sc.run()
+    Sc.check_info()
+    d = make_inputs(get(name))
+    d["W"] = S.screening(ds)
+    P = Problem(d)
+    P.t["W"] = Wd
+    P.inp.W = Wd.data_ptr()
+    out = P.run()
+    r = O.run(d)
+    assert np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min() < 1e-10
+    assert np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max() < 1e-10
+    torch.cuda.synchronize()

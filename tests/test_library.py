@@ -92,6 +92,18 @@ def test_argument_errors_are_reported_without_launching(lib):
         a.update(bad)
         with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
             L.bse_loss(**a)
+    sd = dict(nk=8, nv=2, nc=3, ng=15, inv_vc=0.01, units_per_hartree=27.2)
+    assert L.bse_screening_workspace_size(L.BseScreenDesc(**sd)) == 2 * 8 * 8 * 2 * 3 * 8
+    for bad in (dict(ng=0), dict(ng=513), dict(nk=0), dict(nv=0), dict(inv_vc=-1.0),
+                dict(units_per_hartree=float("nan"))):
+        d2 = L.BseScreenDesc(**{**sd, **bad})
+        assert L.bse_screening_workspace_size(d2) == 0, bad
+        with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+            L.bse_screening(d2, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 30, 1, 0)
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+        L.bse_screening(L.BseScreenDesc(**sd), 1, 1, 0, 1, 1, 1, 1, 1, 1 << 30, 1, 0)
+    with pytest.raises(L.BseError, match="BSE_ERR_WORKSPACE"):
+        L.bse_screening(L.BseScreenDesc(**sd), 1, 1, 1, 1, 1, 1, 1, 1, 16, 1, 0)
     assert lib.bse_status_string(2) == b"workspace too small"
 
 
