@@ -251,7 +251,8 @@ def screening_section(w, reps: int) -> dict:
     k = L.bse_timing_report()
     Sc.check_info()
     k1 = w.nk * w.nv * w.nc
-    flop = 2 * 8 * w.nk * w.ng * w.ng * k1          # two pair sets, 8 flop per cMAC
+    # two pair sets, upper triangle of the Hermitian Xt, 8 flop per cMAC
+    flop = 2 * 8 * w.nk * (w.ng * (w.ng + 1) // 2) * k1
     chi_ms = k.get("zgemm_screen_chi", (1, float("nan")))[1]
     out = {"workload": f"{w.name} mesh", "nq": w.nk, "ng": w.ng, "pair_rows_per_q": 2 * k1,
            "ms": ms, "chi_gflop": flop / 1e9, "chi_ms": chi_ms,

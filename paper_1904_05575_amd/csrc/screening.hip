@@ -50,7 +50,8 @@ __global__ __launch_bounds__(256) void k_screen_weights(int nk, int nv, int nc,
   (set == 0 ? w1 : w2)[rem] = wt;
 }
 
-// In place on W[q] (row-major ng x ng, holding Xt): A = I + s Xt s, then the
+// In place on W[q] (row-major ng x ng, holding the upper triangle of the
+// Hermitian Xt): A = I + s Xt s, mirrored onto the lower triangle, then the
 // sweep operator over every pivot (Goodnight, The American Statistician 33,
 // 1979), which leaves -A^-1, then W = -s (-A^-1) s = s A^-1 s.  One block per
 // q; A is Hermitian positive definite, so no pivoting is needed; a pivot
@@ -69,8 +70,14 @@ __global__ __launch_bounds__(256) void k_screen_invert(double2* __restrict__ W,
   __syncthreads();
   for (int e = tid; e < nn; e += 256) {
     const int i = e / ng, j = e % ng;
+    if (i > j) continue;
     const double2 x = A[e];
-    A[e] = make_double2((i == j ? 1.0 : 0.0) + s[i] * x.x * s[j], s[i] * x.y * s[j]);
+    A[e] = make_double2((i == j ? 1.0 : 0.0) + s[i] * x.x * s[j], i == j ? 0.0 : s[i] * x.y * s[j]);
+  }
+  __syncthreads();
+  for (int e = tid; e < nn; e += 256) {  // reads the upper triangle only
+    const int i = e / ng, j = e % ng;
+    if (i > j) A[e] = cconj(A[(int64_t)j * ng + i]);
   }
   __syncthreads();
   for (int k = 0; k < ng; ++k) {
@@ -128,7 +135,7 @@ bse_status screening_run(const bse_screen_desc* d, const double* eps_v, const do
   const int64_t p64 = (int64_t)cdiv(ng, 64) * 64, p32 = (int64_t)cdiv(ng, 32) * 32;
   const int tile = (p64 * p64 * 100 <= p32 * p32 * 115) ? 64 : 32;
   for (int set = 0; set < 2; ++set) {
-    ZgemmParams g;  // Xt[q] (+)= M_q^H diag(w_q) M_q
+    ZgemmParams g;  // upper triangle of Xt[q] (+)= M_q^H diag(w_q) M_q
     g.M = ng;
     g.N = ng;
     g.K = (int)k1;
@@ -147,6 +154,7 @@ bse_status screening_run(const bse_screen_desc* d, const double* eps_v, const do
     g.c_rs = ng;
     g.c_cs = 1;
     g.c_bs = (int64_t)ng * ng;
+    g.c_uplo = 1;
     g.alpha = make_double2(1.0, 0.0);
     g.beta = set == 0 ? 0.0 : 1.0;
     g.info = info;
