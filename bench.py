@@ -253,12 +253,12 @@ def screening_section(w, reps: int) -> dict:
     k1 = w.nk * w.nv * w.nc
     # two pair sets, upper triangle of the Hermitian Xt, 8 flop per cMAC
     flop = 2 * 8 * w.nk * (w.ng * (w.ng + 1) // 2) * k1
-    chi_ms = k.get("zgemm_screen_chi", (1, float("nan")))[1]
+    chi_ms = k.get("k_screen_chi", k.get("zgemm_screen_chi", (1, float("nan"))))[1]
     out = {"workload": f"{w.name} mesh", "nq": w.nk, "ng": w.ng, "pair_rows_per_q": 2 * k1,
            "ms": ms, "chi_gflop": flop / 1e9, "chi_ms": chi_ms,
            "chi_TFLOPs": flop / (chi_ms * 1e-3) / 1e12,
            "chi_frac_fp64_peak": flop / (chi_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-           "invert_ms": k.get("k_screen_invert", (1, float("nan")))[1],
+           "invert_ms": k.get("k_screen_invert_reg", k.get("k_screen_invert", (1, float("nan"))))[1],
            "weights_ms": k.get("k_screen_weights", (1, float("nan")))[1],
            "input_generation_s": gen_s}
     del Sc, W

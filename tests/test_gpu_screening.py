@@ -33,8 +33,11 @@ def _oracle_q(d, iq):
 
 
 @pytest.mark.parametrize("name", ["tiny_tda_k2_v2c2_g9", "tiny_full_k2_v2c3_g15",
-                                  "small_full_k3_v3c4_g27", "tda_q0_k4_v2c3_g59"])
+                                  "small_full_k3_v3c4_g27", "tda_q0_k4_v2c3_g59",
+                                  "tiny_core_k2_c2c4_g137"])
 def test_screening_matches_oracle(name):
+    """N_G = 9 ... 59 take the one-block-per-q contraction and the register
+    inversion; N_G = 137 (above 128) the batched GEMM and the L2 inversion."""
     d, Sc = _screening(name)
     W = Sc.run()
     Sc.check_info()
