@@ -82,14 +82,16 @@ def _complex_rows(seed: int, kind: str, shape: tuple, envelope: np.ndarray) -> n
 
 
 def screened_interaction(w: Workload) -> np.ndarray:
-    """W[iq, G, G'] for every q of the mesh (the BSE's input from screening)."""
+    """W[iq, G, G'] for every q class of lattice.q_maps (the BSE's input from
+    screening): the q-mesh and, for a generic k-shift, the second set."""
     ng, n = w.ng, w.mesh
     G = lattice.gcart(ng)
-    qc = lattice.centred_cart(lattice.kmesh(n), n)
-    L = _complex_rows(w.seed, "L", (w.nk, ng, 8), np.full((ng, 8), 0.3))
-    W = np.empty((w.nk, ng, ng), dtype=np.complex128)
+    qc = lattice.qset_cart(n, w.kshift)
+    nq = len(qc)
+    L = _complex_rows(w.seed, "L", (nq, ng, 8), np.full((ng, 8), 0.3))
+    W = np.empty((nq, ng, ng), dtype=np.complex128)
     eye = np.eye(ng)
-    for iq in range(w.nk):
+    for iq in range(nq):
         p2 = np.sum((qc[iq][None, :] + G) ** 2, axis=1)
         p2 = np.where(p2 < 1e-12, 0.01, p2)
         sv = np.sqrt(4.0 * np.pi / p2)
@@ -141,7 +143,7 @@ def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
             out["Ncv"] = _complex_rows(w.seed, "Ncv", (P, nc, nv, ng), env)
             out["Nvc"] = _complex_rows(w.seed, "Nvc", (P, nv, nc, ng), env)
     out["W"] = screened_interaction(w) if want_pairs else None
-    qmap, qramap = lattice.q_maps(w.mesh)
+    qmap, qramap = lattice.q_maps(w.mesh, w.kshift)
     out["qmap"], out["qramap"] = qmap, qramap
     out["gvec"] = lattice.gvectors(ng)
     out["kcoords"] = lattice.kmesh(w.mesh)

@@ -92,10 +92,37 @@ def pair_list(nk: int) -> np.ndarray:
     return np.stack([ik, jk], axis=1).astype(np.int64)
 
 
-def q_maps(n: int) -> tuple[np.ndarray, np.ndarray]:
+def _second_set(shift) -> tuple[bool, np.ndarray]:
+    """For k = (i + s)/n: -k-k' = (-(i + i') - 2s)/n.  Returns whether 2s is
+    integral (then -k-k' is on the q-mesh itself) and 2s rounded."""
+    m = 2.0 * np.asarray(shift, dtype=np.float64)
+    return not np.allclose(m, np.round(m), atol=1e-12), np.round(m).astype(np.int64)
+
+
+def q_maps(n: int, shift=(0.0, 0.0, 0.0)) -> tuple[np.ndarray, np.ndarray]:
     """Momentum-transfer classes of k-pairs on the mesh:
-    qmap[ik, ik'] = index of k - k'  and  qramap[ik, ik'] = index of -k - k'."""
+    qmap[ik, ik'] = index of k - k' (always on the q-mesh {j/n}) and
+    qramap[ik, ik'] = index of -k - k': on the q-mesh when 2 shift is integral,
+    else on the second set {(j - 2 shift)/n}, whose entries follow the Nk
+    entries of the first in W (index Nk + j)."""
     km = kmesh(n)
     qmap = mesh_index(km[:, None, :] - km[None, :, :], n)
-    qramap = mesh_index(-km[:, None, :] - km[None, :, :], n)
+    second, m = _second_set(shift)
+    if second:
+        qramap = n ** 3 + mesh_index(-km[:, None, :] - km[None, :, :], n)
+    else:
+        qramap = mesh_index(-km[:, None, :] - km[None, :, :] - m, n)
     return qmap.astype(np.int32), qramap.astype(np.int32)
+
+
+def qset_cart(n: int, shift=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Cartesian q-vectors (centred) of every class of q_maps: the q-mesh, then
+    (for a generic shift) the second set (j - 2 shift)/n."""
+    km = kmesh(n)
+    qa = centred_cart(km, n)
+    second, _ = _second_set(shift)
+    if not second:
+        return qa
+    c = km.astype(np.float64) - 2.0 * np.asarray(shift, dtype=np.float64)
+    c = np.mod(c + n / 2.0, n) - n / 2.0
+    return np.concatenate([qa, (c / n) @ recip_basis()])

@@ -22,7 +22,7 @@ from dataclasses import dataclass, field, replace
 @dataclass(frozen=True)
 class Workload:
     name: str
-    mesh: int                 # k-mesh is mesh x mesh x mesh, Gamma-centred
+    mesh: int                 # k-mesh is mesh x mesh x mesh (Gamma-centred unless kshift)
     nv: int                   # occupied (valence or core) bands
     nc: int                   # unoccupied bands
     ng: int                   # plane waves (closed shell)
@@ -40,6 +40,7 @@ class Workload:
     mcv_gauss_width: float | None = None  # Gaussian |G+Q| envelope of Mcv (bohr^-1)
     mcc_generated: bool = False  # Mcc given by a key and an envelope, drawn where used
     scissor: float = 0.0
+    kshift: tuple = (0.0, 0.0, 0.0)  # k = (i + kshift) / mesh along b1, b2, b3
     note: str = ""
 
     @property
@@ -100,6 +101,20 @@ TINY = {
     "small_full": _add(Workload(name="small_full_k3_v3c4_g27", mesh=3, nv=3, nc=4, ng=27,
                                 coupling="full", nw=500, wmin=0.0, wmax=10.0, eta=0.05,
                                 seed=13, kernel_scale=0.0625)),
+    # shifted meshes (a generic offset as in the paper's runs): -k-k' falls on a
+    # second q-set, so W is given on both sets (nq = 2 Nk)
+    "tiny_full_shift": _add(Workload(name="tiny_full_k2s_v2c3_g15", mesh=2, nv=2, nc=3, ng=15,
+                                     coupling="full", nw=200, wmin=0.0, wmax=10.0, eta=0.05,
+                                     seed=17, kernel_scale=0.03125,
+                                     kshift=(0.097, 0.273, 0.493))),
+    "small_full_shift": _add(Workload(name="small_full_k3s_v3c4_g27", mesh=3, nv=3, nc=4,
+                                      ng=27, coupling="full", nw=500, wmin=0.0, wmax=10.0,
+                                      eta=0.05, seed=18, kernel_scale=0.03125,
+                                      kshift=(0.097, 0.273, 0.493))),
+    # half-step offset: -k-k' lands back on the unshifted q-mesh (nq = Nk)
+    "tiny_full_half": _add(Workload(name="tiny_full_k2h_v2c3_g15", mesh=2, nv=2, nc=3, ng=15,
+                                    coupling="full", nw=200, wmin=0.0, wmax=10.0, eta=0.05,
+                                    seed=19, kernel_scale=0.03125, kshift=(0.5, 0.5, 0.5))),
     "mid_full": _add(Workload(name="mid_full_k4_v3c4_g59", mesh=4, nv=3, nc=4, ng=59,
                               coupling="full", nw=1000, wmin=0.0, wmax=10.0, eta=0.05,
                               seed=14, kernel_scale=0.0625)),

@@ -74,8 +74,10 @@ typedef enum { BSE_SINGLET = 0, BSE_TRIPLET = 1, BSE_RPA = 2, BSE_IP = 3 } bse_t
  *           first three.
  * The per-pair second contraction of the direct terms (R x N_G x R' per
  * k-pair, memory-bound) runs in FP64 in every mode.  The reduced modes split
- * W once per call into a part of the BUILD workspace sized for nk slices, so
- * they require nq <= nk (else BSE_ERR_ARG). */
+ * W once per call into a part of the BUILD workspace sized for nk slices
+ * (2 nk for the full BSE: the q-mesh and the second q-set of -k-k' on a
+ * shifted k-mesh), so they require nq <= nk, or nq <= 2 nk for the full BSE
+ * (else BSE_ERR_ARG). */
 typedef enum { BSE_PREC_FP64 = 0, BSE_PREC_FP32 = 1, BSE_PREC_BF16X3 = 2 } bse_precision;
 
 typedef enum { BSE_STAGE_BUILD = 0, BSE_STAGE_SOLVE = 1 } bse_stage;
@@ -104,7 +106,11 @@ typedef struct {
   const void* W;         /* complex [nq][ng][ng]: screened interaction w_GG'(q), eq. wggq */
   const double* vbar;    /* [ng]: Coulomb potential without the G_Q term, eq. vbar_def */
   const int32_t* qmap;   /* [nk][nk]: class of k - k'  (index into W) */
-  const int32_t* qramap; /* [nk][nk]: class of -k - k' (index into W), full only */
+  const int32_t* qramap; /* [nk][nk]: class of -k - k' (index into W), full only.  On a
+                            k-mesh shifted by s (k = (i + s)/n, Sec. 5), -k - k' lies
+                            on the q-mesh only when 2s is integral; otherwise its W
+                            slices (the second set (j - 2s)/n) follow the nk of the
+                            q-mesh in W and qramap indexes them (nq = 2 nk). */
   int32_t nq;            /* number of W slices */
   int32_t reserved;
   /* M_{u u'}(G') given implicitly, for problems where the array would not fit

@@ -89,12 +89,21 @@ def probe(inputs: dict) -> np.ndarray:
 
 
 def q_index_of(inputs: dict, sign: int) -> np.ndarray:
-    """Mesh index of k - k' (sign=+1) or -k - k' (sign=-1) for every (ik, ik')."""
-    n = inputs["workload"].mesh
-    kc = inputs["kcoords"]
+    """Index into W of k - k' (sign=+1) or -k - k' (sign=-1) for every (ik, ik').
+    With k = (i + s)/n (Sec. 5: shifted meshes) the difference in mesh units is
+    sign (i + s) - (i' + s).  When it is integral it is a point j of the
+    q-mesh (index j); otherwise it is j - 2s with j integral, a point of the
+    second set, whose W entries follow the Nk of the first (index Nk + j)."""
+    w = inputs["workload"]
+    n = w.mesh
+    kc = inputs["kcoords"].astype(np.float64) + np.asarray(w.kshift, dtype=np.float64)
     d = sign * kc[:, None, :] - kc[None, :, :]
-    d = np.mod(d, n)
-    return (d[..., 0] * n + d[..., 1]) * n + d[..., 2]
+    on_mesh = np.allclose(d, np.round(d), atol=1e-9)
+    if not on_mesh:
+        d = d + 2.0 * np.asarray(w.kshift, dtype=np.float64)
+    j = np.mod(np.round(d).astype(np.int64), n)
+    idx = (j[..., 0] * n + j[..., 1]) * n + j[..., 2]
+    return idx if on_mesh else w.nk + idx
 
 
 def pairs(nk: int) -> tuple[np.ndarray, np.ndarray]:

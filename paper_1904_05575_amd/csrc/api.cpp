@@ -42,7 +42,8 @@ bse_status bse_build(const bse_desc* d, const bse_inputs* in, void* H0, void* H1
     return BSE_ERR_ARG;
   if (full && (!in->Ncv || !in->Nvc || !in->qramap || !H1)) return BSE_ERR_ARG;
   if (in->nq <= 0 || in->nq > kMaxQ) return BSE_ERR_ARG;
-  if (d->prec != BSE_PREC_FP64 && in->nq > d->nk) return BSE_ERR_ARG;  // W split holds nk slices
+  // the W split holds nk slices (2 nk for the full BSE)
+  if (d->prec != BSE_PREC_FP64 && in->nq > (full ? 2 : 1) * d->nk) return BSE_ERR_ARG;
   if (ws_bytes < build_workspace_fp64(d)) return BSE_ERR_WORKSPACE;
   return build_fp64(d, in, H0, H1, ws, info, stream);
 }

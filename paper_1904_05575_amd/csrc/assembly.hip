@@ -317,7 +317,9 @@ size_t build_workspace_fp64(const bse_desc* d) {
   L.add(full ? P * R2 * d->ng * 16 : 0);         // T_ra
   L.add(P * R1 * N1 * 16);                       // blk_rr
   L.add(full ? P * R2 * R2 * 16 : 0);            // blk_ra
-  L.add((int64_t)split_w_bytes(d->nk, d->ng));   // W split for the precision form
+  // W split for the precision form: the q-mesh and, for the coupling block on
+  // a generically shifted k-mesh, the second q-set of -k-k'
+  L.add((int64_t)split_w_bytes(full ? 2 * d->nk : d->nk, d->ng));
   return L.total;
 }
 
@@ -345,7 +347,7 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   double2* T_ra = (double2*)L.add(full ? P * R2 * ng * 16 : 0);
   double2* blk_rr = (double2*)L.add(P * R1 * N1 * 16);
   double2* blk_ra = (double2*)L.add(full ? P * R2 * R2 * 16 : 0);
-  void* Wsp = L.add((int64_t)split_w_bytes(nk, ng));
+  void* Wsp = L.add((int64_t)split_w_bytes(full ? 2 * nk : nk, ng));
   (void)cls_ra;
 
   // class sorts
@@ -357,7 +359,7 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   const int nterms = d->split_terms == 0 ? 6 : d->split_terms;
   // the precision form splits W once per build; its buffer holds nk slices
   if (prec != BSE_PREC_FP64) {
-    if (nq > nk) return BSE_ERR_ARG;
+    if (nq > (full ? 2 * nk : nk)) return BSE_ERR_ARG;
     if (!launch_split_w(prec, (const double2*)in->W, nq, ng, Wsp, s)) return BSE_ERR_HIP;
   }
   // exchange: out0 (upper) = alpha * conj(Mcv) diag(vbar) Mcv^T

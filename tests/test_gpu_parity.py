@@ -17,7 +17,9 @@ pytestmark = pytest.mark.gpu
 
 SMALL = ["tiny_tda_k2_v2c2_g9", "tiny_full_k2_v2c3_g15", "small_full_k3_v3c4_g27",
          "mid_full_k4_v3c4_g59", "tda_q0_k4_v2c3_g59", "tiny_core_k2_c2c6_g27",
-         "mid_core_k4_c2c8_g59", "tiny_core_k2_c2c4_g137"]
+         "mid_core_k4_c2c8_g59", "tiny_core_k2_c2c4_g137",
+         # shifted k-meshes: -k-k' on a second q-set (nq = 2 Nk), or back on the mesh
+         "tiny_full_k2s_v2c3_g15", "small_full_k3s_v3c4_g27", "tiny_full_k2h_v2c3_g15"]
 
 
 def _problem(name, bse_type="singlet"):

@@ -55,9 +55,9 @@ def test_argument_errors_are_reported_without_launching(lib):
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
         L.bse_build(d, inp, 1, 1, 1, 1 << 30, 1, 0)       # null input pointers
     full = L.BseInputs(eps_v=1, eps_c=1, Mcv=1, Mvv=1, Mcc=1, Ncv=1, Nvc=1, W=1, vbar=1,
-                       qmap=1, qramap=1, nq=9, reserved=0)
+                       qmap=1, qramap=1, nq=17, reserved=0)
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):          # the precision form's W
-        L.bse_build(_desc(prec=L.BSE_PREC_BF16X3), full, 1, 1, 1, 1 << 40, 1, 0)  # split: nq <= nk
+        L.bse_build(_desc(prec=L.BSE_PREC_BF16X3), full, 1, 1, 1, 1 << 40, 1, 0)  # split: nq <= 2 nk
     with pytest.raises(L.BseError, match="BSE_ERR_WORKSPACE"):     # FP64 accepts nq > nk
         L.bse_build(d, full, 1, 1, 1, 16, 1, 0)
     drawn = L.BseInputs(eps_v=1, eps_c=1, Mcv=1, Mvv=1, Mcc=None, Ncv=1, Nvc=1, W=1, vbar=1,

@@ -24,7 +24,10 @@ def _rel(a, b):
 
 
 # ----------------------------------------------------------------- assembly
-@pytest.mark.parametrize("name", TINY)
+SHIFTED = ["tiny_full_k2s_v2c3_g15", "small_full_k3s_v3c4_g27", "tiny_full_k2h_v2c3_g15"]
+
+
+@pytest.mark.parametrize("name", TINY + SHIFTED[:1] + SHIFTED[2:])
 def test_assembly_literal_double_sums(name):
     """Factorised per-q-class contraction == literal sums of eqs. vrrofM,
     wrrm, wrabar entry by entry."""
@@ -36,20 +39,33 @@ def test_assembly_literal_double_sums(name):
         assert _rel(B, B2) < 1e-13
 
 
-def test_q_index_against_cartesian_vectors():
-    """The oracle's k-k' and -k-k' classes land on the mesh point that differs
-    from the Cartesian difference by a reciprocal lattice vector."""
-    d = inputs("small_full_k3_v3c4_g27")
-    n = 3
+@pytest.mark.parametrize("name", ["small_full_k3_v3c4_g27", "small_full_k3s_v3c4_g27",
+                                  "tiny_full_k2h_v2c3_g15"])
+def test_q_index_against_cartesian_vectors(name):
+    """The oracle's k-k' and -k-k' classes name a q-vector (of the q-mesh or,
+    on a generically shifted k-mesh, of the second set) that differs from the
+    Cartesian difference by a reciprocal lattice vector; the maps handed to
+    the GPU agree with the oracle's."""
+    d = inputs(name)
+    w = d["workload"]
+    n = w.mesh
     b = lattice.recip_basis()
-    kc = (d["kcoords"] / n) @ b
+    kc = ((d["kcoords"] + np.asarray(w.kshift)) / n) @ b
+    qv = lattice.qset_cart(n, w.kshift)
+    second = not np.allclose(2 * np.asarray(w.kshift), np.round(2 * np.asarray(w.kshift)))
+    assert len(qv) == d["W"].shape[0] == (2 if second else 1) * w.nk
     binv = np.linalg.inv(b)
-    for sign in (1, -1):
+    for sign, gpu_map in ((1, d["qmap"]), (-1, d["qramap"])):
         qi = O.q_index_of(d, sign)
+        assert np.array_equal(qi, gpu_map)
         for i in range(len(kc)):
             for j in range(len(kc)):
-                diff = (sign * kc[i] - kc[j] - kc[qi[i, j]]) @ binv
+                diff = (sign * kc[i] - kc[j] - qv[qi[i, j]]) @ binv
                 assert np.allclose(diff, np.round(diff), atol=1e-12)
+        if sign == 1 or not second:
+            assert qi.max() < w.nk
+        else:
+            assert qi.min() >= w.nk
 
 
 def test_direct_uses_w_of_k_minus_kprime():
@@ -119,7 +135,7 @@ def test_vbar_and_coulomb():
     assert np.isclose(O.coulomb_v0(d), 4 * np.pi / 0.01)
 
 
-@pytest.mark.parametrize("name", SMALL + ["tda_q0_k4_v2c3_g59"])
+@pytest.mark.parametrize("name", SMALL + SHIFTED + ["tda_q0_k4_v2c3_g59"])
 def test_hermitian_and_positive(name):
     """A (and B) Hermitian with real diagonal; the calibrated kernel scale keeps
     A - B and A + B (or A) positive definite with the 0.1 min(E) margin."""
