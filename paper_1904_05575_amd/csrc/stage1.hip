@@ -60,12 +60,16 @@ __global__ __launch_bounds__(NTHR, (BN2 == 240 || BN2 == 192) ? 4 : 2) void k_st
     const int64_t p = perm[s0 + m / R];
     arow_ptr = Left + (p * R + m % R) * ng;
   }
-  double2 ra;
-  double rb[BPER];
+  // one chunk's loads in registers; two sets, so that the loads of chunk
+  // ch + 2 are in flight while chunk ch is multiplied
+  struct Regs {
+    double2 ra;
+    double rb[BPER];
+  };
 
-  auto load_chunk = [&](int k0) {
+  auto load_chunk = [&](Regs& g_, int k0) {
     const int kc = (k0 >> 1) + akc;  // complex k
-    ra = arow_ptr[kc < ng ? kc : ng - 1];
+    g_.ra = arow_ptr[kc < ng ? kc : ng - 1];
 #pragma unroll
     for (int u = 0; u < BPER; ++u) {
       const int e = tid + u * NTHR;
@@ -73,10 +77,12 @@ __global__ __launch_bounds__(NTHR, (BN2 == 240 || BN2 == 192) ? 4 : 2) void k_st
       int g = (k0 >> 1) + wr;
       g = g < ng ? g : ng - 1;
       const int nc = nn < N2 ? nn : N2 - 1;
-      rb[u] = Wq[(int64_t)g * N2 + nc];
+      g_.rb[u] = Wq[(int64_t)g * N2 + nc];
     }
   };
-  auto store_chunk = [&](int buf, int k0) {
+  auto store_chunk = [&](int buf, const Regs& g_, int k0) {
+    const double2 ra = g_.ra;
+    const double* rb = g_.rb;
     const int kc = (k0 >> 1) + akc;
     const bool okA = arow_ok && kc < ng;
     sm.a[buf][2 * akc][arow] = okA ? ra.x : 0.0;
@@ -100,12 +106,16 @@ __global__ __launch_bounds__(NTHR, (BN2 == 240 || BN2 == 192) ? 4 : 2) void k_st
   for (int j = 0; j < NTH; ++j) acc[j] = d4{0, 0, 0, 0};
 
   const int nchunks = (K2 + BK - 1) / BK;
-  load_chunk(0);
-  store_chunk(0, 0);
+  Regs R0, R1;
+  load_chunk(R0, 0);
+  store_chunk(0, R0, 0);
+  if (nchunks > 1) load_chunk(R1, BK);
+  if (nchunks > 2) load_chunk(R0, 2 * BK);
   __syncthreads();
-  for (int ch = 0; ch < nchunks; ++ch) {
+  // step ch: multiply chunk ch (LDS buffer ch & 1), store chunk ch + 1 from
+  // `next` into the other buffer, then reuse `next` for chunk ch + 3
+  auto step = [&](int ch, Regs& next) {
     const int buf = ch & 1;
-    if (ch + 1 < nchunks) load_chunk((ch + 1) * BK);
     const int k0 = ch * BK;
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
@@ -121,8 +131,13 @@ __global__ __launch_bounds__(NTHR, (BN2 == 240 || BN2 == 192) ? 4 : 2) void k_st
         }
       }
     }
-    if (ch + 1 < nchunks) store_chunk(buf ^ 1, (ch + 1) * BK);
+    if (ch + 1 < nchunks) store_chunk(buf ^ 1, next, (ch + 1) * BK);
     __syncthreads();
+    if (ch + 3 < nchunks) load_chunk(next, (ch + 3) * BK);
+  };
+  for (int ch = 0; ch < nchunks; ch += 2) {
+    step(ch, R1);                           // R1 holds chunk ch + 1
+    if (ch + 1 < nchunks) step(ch + 1, R0);  // R0 holds chunk ch + 2
   }
 
   double* Td = (double*)T;
