@@ -104,3 +104,22 @@ def test_bse_on_the_screened_interaction(name):
     assert np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min() < 1e-10
     assert np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max() < 1e-10
     torch.cuda.synchronize()
+
+
+def test_screening_reports_a_missing_gap_and_a_bad_pivot():
+    """Failure handling forced from the host: an unoccupied band below an
+    occupied one gives info = -5 (weights), a NaN in v^1/2 gives info = -6 (the
+    inversion's first pivot); every kernel still exits normally."""
+    torch = pytest.importorskip("torch")
+    from paper_1904_05575_amd import _lib as L
+    d, Sc = _screening("tiny_full_k2_v2c3_g15")
+    Sc.t["eps_c"][0, 0] = -10.0
+    W = Sc.run()
+    with pytest.raises(L.BseError, match="-5"):
+        Sc.check_info()
+    d2, Sc2 = _screening("tiny_full_k2_v2c3_g15")
+    Sc2.t["vsqrt"][3, 0] = float("nan")
+    Sc2.run()
+    with pytest.raises(L.BseError, match="-6"):
+        Sc2.check_info()
+    torch.cuda.synchronize()
