@@ -128,7 +128,7 @@ def batched_section(name: str, steps: int) -> dict:
     from paper_1904_05575_amd.batch import Batch
     bw = BATCHES[name]
     members = make_batch_inputs(bw)
-    B = Batch(members, precision="fp64", nbranch=4)
+    B = Batch(members, precision="fp64", nbranch=16)  # one branch per problem (up to 16)
     tuned = L.bse_tune_get()
 
     def timed(fn):
@@ -167,7 +167,8 @@ def batched_section(name: str, steps: int) -> dict:
             "graph_fp64_builtin_tiles_ms": graph_builtin_ms, "graph_fp64_tuned_ms": graph64_ms,
             "graph_bf16x6_tuned_ms": graph_mixed_ms,
             "speedup_vs_sequential_fp64": seq_ms / graph_mixed_ms,
-            "bf16x6_error_vs_fp64": {"eig_rel": eig, "spec_err": spec}, "branches": 4}
+            "bf16x6_error_vs_fp64": {"eig_rel": eig, "spec_err": spec},
+            "branches": min(16, len(members))}
 
 
 def observables_section(P, H0, H1, reps: int) -> dict:

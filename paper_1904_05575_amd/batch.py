@@ -12,7 +12,7 @@ from .bse import (PRECISIONS, TYPES, _dev, coulomb_v0, coulomb_vbar, g_index_of_
 
 
 class Batch:
-    def __init__(self, members: list, precision: str = "fp64", nbranch: int = 4,
+    def __init__(self, members: list, precision: str = "fp64", nbranch: int = 16,
                  bse_type: str = "singlet", device: str = "cuda"):
         from . import tune
         tune.load()  # the autotuner's tile choices, when a table is present

@@ -72,7 +72,7 @@ def test_full_size_batch_sum_rules():
     replay and the sequential path give identical results."""
     ms = _members("batch16_k6_g89")
     print(f"[gpu] batch16: sizes {[m['workload'].n for m in ms]}", flush=True)
-    B = _batch(ms, nbranch=4)
+    B = _batch(ms, nbranch=16)  # the benchmark's launch configuration
     B.run()
     res = B.results()
     for d, out in zip(ms, res):
@@ -97,7 +97,7 @@ def test_full_size_batch_sum_rules():
             else:
                 fs += 2.0 * np.vdot(p[i], blk @ p[j]).real
         assert abs(np.sum(out["E"] * out["osc"]) - fs) < 1e-9 * fs, (idx, fs)
-    # four concurrent branches change the timing only: a replay and the plain
+    # sixteen concurrent branches change the timing only: a replay and the plain
     # entry points one problem after another reproduce every bit (a kernel
     # whose blocks read what another block of it writes would not)
     for again in (lambda: B.run(), lambda: B.run_sequential()):
