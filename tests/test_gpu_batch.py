@@ -104,3 +104,36 @@ def test_full_size_batch_sum_rules():
         again()
         for i, (a, b) in enumerate(zip(res, B.results())):
             assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["osc"], b["osc"]), i
+
+
+def test_concurrent_streams_reproduce_the_sequential_path():
+    """The plain entry points on four streams at once (each with its own
+    workspace slice), largest problems of batch16 first: every bit equals the
+    sequential path (no kernel reads what another of its blocks writes)."""
+    torch = pytest.importorskip("torch")
+    from paper_1904_05575_amd import _lib as L
+    ms = _members("batch16_k6_g89")
+    B = _batch(ms, nbranch=4)
+    B.run_sequential()
+    seq = B.results()
+    slice_b = L.bse_batch_workspace_size(B.descs, 1)
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    wss = [torch.empty(slice_b, dtype=torch.uint8, device="cuda") for _ in range(4)]
+    order = sorted(range(len(ms)), key=lambda i: -ms[i]["workload"].n)[:8]
+    print(f"[gpu] concurrent streams: members {order}", flush=True)
+    torch.cuda.synchronize()
+    for k, i in enumerate(order):
+        s = streams[k % 4]
+        t, d = B.t[i], B.descs[i]
+        n = int(d.nk * d.nv * d.nc)
+        info = B.info.data_ptr() + 4 * i
+        L.bse_build(d, B.inputs[i], t["H0"].data_ptr(), t["H1"].data_ptr(), wss[k % 4].data_ptr(),
+                    slice_b, info, s.cuda_stream)
+        L.bse_solve(d, t["H0"].data_ptr(), t["H1"].data_ptr(), t["E"].data_ptr(), 0, n,
+                    t["probe"].data_ptr(), t["osc"].data_ptr(), wss[k % 4].data_ptr(), slice_b,
+                    info, s.cuda_stream)
+    torch.cuda.synchronize()
+    conc = B.results()
+    for i in order:
+        assert np.array_equal(conc[i]["E"], seq[i]["E"]), i
+        assert np.array_equal(conc[i]["osc"], seq[i]["osc"]), i
