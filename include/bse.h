@@ -32,6 +32,9 @@
  *      -2   a non-finite value on the diagonal of an assembled matrix
  *      -3   a squared-form eigenvalue E^2 <= 0: A+B is not positive definite
  *      -4   the tridiagonal eigensolver did not converge
+ *      -5   bse_screening: an occupied band is not below an unoccupied one
+ *      -6   bse_screening: a pivot of the dielectric-matrix inversion is not
+ *           positive (non-finite input)
  *    Once `info` is non-zero, the later kernels of the same calls return at
  *    entry, except the per-column kernels of the Householder sweep, which
  *    index no memory by data and run on; outputs are then undefined.
