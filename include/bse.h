@@ -31,7 +31,8 @@
  *      -1   a qmap / qramap entry outside [0, nq)
  *      -2   a non-finite value on the diagonal of an assembled matrix
  *      -3   a squared-form eigenvalue E^2 <= 0: A+B is not positive definite
- *      -4   the tridiagonal eigensolver did not converge
+ *      -4   a tridiagonal eigenvector came out zero or non-finite (the
+ *           twisted factorisation, or inverse iteration inside a cluster)
  *      -5   bse_screening: an occupied band is not below an unoccupied one
  *      -6   bse_screening: a pivot of the dielectric-matrix inversion is not
  *           positive (non-finite input)
@@ -146,19 +147,26 @@ bse_status bse_build(const bse_desc* desc, const bse_inputs* in, void* H0, void*
 /* Eigenproblem (Sec. 4.3).
  *  full: A-B = U^H U (Cholesky), S = U (A+B) U^H, S Z = E^2 Z,
  *        X+Y = U^H Z E^-1/2  (same E and, up to phase, the same X+Y as the
- *        (A-B)^1/2 form of eq. auxham).
+ *        (A-B)^1/2 form of eq. auxham),
+ *        X-Y = U^-1 Z E^1/2  (the (A-B)^-1/2 E^1/2 Z of the same section in
+ *        Cholesky form), formed from the first coupled equation
+ *        (A+B)(X+Y) = (X-Y) E; then (X+Y)^H (X-Y) = I.
  *  TDA : A X = E X.
  *  H0, H1: the matrices from bse_build (overwritten).
  *  E     : [n] excitation energies, ascending (output).
  *  XpY   : complex n x n column-major with leading dimension ldx, column l =
  *          (X+Y)_l (X_l in the TDA); may be NULL when only the spectrum is
  *          wanted, which skips the eigenvector back-transform.
+ *  XmY   : complex n x n column-major, leading dimension ldx, column l =
+ *          (X-Y)_l with the phase of (X+Y)_l (X_l again in the TDA), or NULL.
+ *          Needs XpY (else BSE_ERR_ARG) and a buffer of its own; it holds a
+ *          copy of A+B while the solve runs.
  *  probe : complex [n] vector p (for eps_M: p_a = conj M_a(G_Q)) or NULL.
  *  osc   : [n] |t_l|^2 = |sum_a conj((X+Y)_al) p_a|^2 (eq. osci), written
  *          when probe != NULL. */
-bse_status bse_solve(const bse_desc* desc, void* H0, void* H1, double* E, void* XpY, int64_t ldx,
-                     const void* probe, double* osc, void* ws, size_t ws_bytes, int32_t* info,
-                     hipStream_t stream);
+bse_status bse_solve(const bse_desc* desc, void* H0, void* H1, double* E, void* XpY, void* XmY,
+                     int64_t ldx, const void* probe, double* osc, void* ws, size_t ws_bytes,
+                     int32_t* info, hipStream_t stream);
 
 /* Oscillator strengths from eigenvectors: osc[l] = |sum_a conj(XpY[a,l]) probe[a]|^2
  * (eq. osci without the 1/V_c factor, which the prefactor of bse_spectrum carries). */

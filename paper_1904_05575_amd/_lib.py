@@ -75,8 +75,8 @@ def lib() -> ctypes.CDLL:
         L.bse_build.argtypes = [ctypes.POINTER(BseDesc), ctypes.POINTER(BseInputs), vp, vp, vp, sz,
                                 vp, vp]
         L.bse_build.restype = ctypes.c_int
-        L.bse_solve.argtypes = [ctypes.POINTER(BseDesc), vp, vp, vp, vp, i64, vp, vp, vp, sz, vp,
-                                vp]
+        L.bse_solve.argtypes = [ctypes.POINTER(BseDesc), vp, vp, vp, vp, vp, i64, vp, vp, vp, sz,
+                                vp, vp]
         L.bse_solve.restype = ctypes.c_int
         L.bse_oscillator.argtypes = [i64, vp, i64, vp, vp, vp]
         L.bse_oscillator.restype = ctypes.c_int
@@ -136,10 +136,11 @@ def bse_build(desc: BseDesc, inputs: BseInputs, H0: int, H1: int, ws: int, ws_by
                            info, stream or None), "bse_build")
 
 
-def bse_solve(desc: BseDesc, H0: int, H1: int, E: int, XpY: int, ldx: int, probe: int, osc: int,
-              ws: int, ws_bytes: int, info: int, stream: int) -> None:
-    _check(lib().bse_solve(ctypes.byref(desc), H0, H1 or None, E, XpY or None, ldx, probe or None,
-                           osc or None, ws, ws_bytes, info, stream or None), "bse_solve")
+def bse_solve(desc: BseDesc, H0: int, H1: int, E: int, XpY: int, XmY: int, ldx: int, probe: int,
+              osc: int, ws: int, ws_bytes: int, info: int, stream: int) -> None:
+    _check(lib().bse_solve(ctypes.byref(desc), H0, H1 or None, E, XpY or None, XmY or None, ldx,
+                           probe or None, osc or None, ws, ws_bytes, info, stream or None),
+           "bse_solve")
 
 
 def bse_oscillator(n: int, XpY: int, ldx: int, probe: int, osc: int, stream: int) -> None:

@@ -113,7 +113,7 @@ class Batch:
                         t["H1"].data_ptr() if t["H1"] is not None else 0,
                         self.ws.data_ptr(), ws_bytes, info, s)
             L.bse_solve(d, t["H0"].data_ptr(), t["H1"].data_ptr() if t["H1"] is not None else 0,
-                        t["E"].data_ptr(), 0, n, t["probe"].data_ptr(), t["osc"].data_ptr(),
+                        t["E"].data_ptr(), 0, 0, n, t["probe"].data_ptr(), t["osc"].data_ptr(),
                         self.ws.data_ptr(), ws_bytes, info, s)
             L.bse_spectrum(n, t["E"].data_ptr(), t["osc"].data_ptr(), self.pref[i], self.eta[i],
                            self.nw[i], t["omega"].data_ptr(), t["eps"].data_ptr(), s)

@@ -135,25 +135,41 @@ class Problem:
         H1 = torch.empty((n, n), dtype=torch.complex128, device=self.device) if self.full else None
         return H0, H1
 
+    def reset_info(self) -> None:
+        """Clear the device status word (a fill kernel on the current stream).
+        The library's kernels return at entry while it is non-zero, so every
+        build starts from a cleared word: a failure of an earlier call does
+        not silence the next one."""
+        self.info.zero_()
+
     def build(self, H0=None, H1=None):
-        """A+B and A-B (full) or A (TDA), column-major: element (i, j) is H.T[i, j]."""
+        """A+B and A-B (full) or A (TDA), column-major: element (i, j) is H.T[i, j].
+        Clears the status word first (see reset_info)."""
         if H0 is None:
             H0, H1 = self.alloc_matrices()
+        self.reset_info()
         L.bse_build(self.desc, self.inp, H0.data_ptr(), H1.data_ptr() if H1 is not None else 0,
                     self.ws_build.data_ptr(), self.ws_build.numel(), self.info.data_ptr(),
                     self.stream())
         return H0, H1
 
-    def solve(self, H0, H1, vectors: bool = False, probe: bool = True):
+    def solve(self, H0, H1, vectors: bool = False, probe: bool = True, xmy: bool = False):
+        """(E, X+Y, |t|^2); with xmy=True (implies vectors) (E, X+Y, X-Y, |t|^2).
+        X+Y and X-Y are column-major n x n: column l is X.T[l]."""
         n = self.n
+        vectors = vectors or xmy
         E = torch.empty(n, dtype=torch.float64, device=self.device)
         XpY = torch.empty((n, n), dtype=torch.complex128, device=self.device) if vectors else None
+        XmY = torch.empty((n, n), dtype=torch.complex128, device=self.device) if xmy else None
         osc = torch.empty(n, dtype=torch.float64, device=self.device) if probe else None
         L.bse_solve(self.desc, H0.data_ptr(), H1.data_ptr() if H1 is not None else 0,
-                    E.data_ptr(), XpY.data_ptr() if XpY is not None else 0, n,
+                    E.data_ptr(), XpY.data_ptr() if XpY is not None else 0,
+                    XmY.data_ptr() if XmY is not None else 0, n,
                     self.t["probe"].data_ptr() if probe else 0,
                     osc.data_ptr() if osc is not None else 0, self.ws_solve.data_ptr(),
                     self.ws_solve.numel(), self.info.data_ptr(), self.stream())
+        if xmy:
+            return E, XpY, XmY, osc
         return E, XpY, osc
 
     def spectrum(self, E, osc):

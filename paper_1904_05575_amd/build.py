@@ -58,29 +58,9 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
-COUNTERS_SRC = os.path.join(PKG, "counters", "trd_counters.hip")
-COUNTERS_BIN = os.path.join(PKG, "counters", "trd_counters")
-
-
-def build_counters(verbose: bool = True) -> str:
-    """The standalone driver for hardware-counter runs of the Householder sweep
-    (links libbse.so from the package directory)."""
-    tmp = COUNTERS_BIN + ".tmp"
-    cmd = ["hipcc", *FLAGS, COUNTERS_SRC, "-L", PKG, "-lbse", "-Wl,-rpath,$ORIGIN/..", "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
-        raise RuntimeError(f"counter driver build failed:\n{err}")
-    os.replace(tmp, COUNTERS_BIN)
-    if verbose:
-        print(f"built {COUNTERS_BIN}", flush=True)
-    return COUNTERS_BIN
-
-
 if __name__ == "__main__":
     try:
         build()
-        build_counters()
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)

@@ -48,18 +48,19 @@ bse_status bse_build(const bse_desc* d, const bse_inputs* in, void* H0, void* H1
   return build_fp64(d, in, H0, H1, ws, info, stream);
 }
 
-bse_status bse_solve(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, int64_t ldx,
-                     const void* probe, double* osc, void* ws, size_t ws_bytes, int32_t* info,
-                     hipStream_t stream) {
+bse_status bse_solve(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, void* XmY,
+                     int64_t ldx, const void* probe, double* osc, void* ws, size_t ws_bytes,
+                     int32_t* info, hipStream_t stream) {
   launch_failure_reset();
   if (!desc_ok(d) || !H0 || !E || !info || !ws) return BSE_ERR_ARG;
   const int64_t n = (int64_t)d->nk * d->nv * d->nc;
   if (d->coupling == BSE_FULL && !H1) return BSE_ERR_ARG;
   if (XpY && ldx < n) return BSE_ERR_ARG;
+  if (XmY && (!XpY || XmY == XpY)) return BSE_ERR_ARG;  // X-Y comes with X+Y, in its own buffer
   if ((probe == nullptr) != (osc == nullptr)) return BSE_ERR_ARG;
   if (!XpY && !probe) return BSE_ERR_ARG;  // nothing but eigenvalues: pass a probe or XpY
   if (ws_bytes < solve_workspace(d)) return BSE_ERR_WORKSPACE;
-  return solve_run(d, H0, H1, E, XpY, ldx, probe, osc, ws, info, stream);
+  return solve_run(d, H0, H1, E, XpY, XmY, ldx, probe, osc, ws, info, stream);
 }
 
 bse_status bse_oscillator(int64_t n, const void* XpY, int64_t ldx, const void* probe, double* osc,

@@ -116,11 +116,12 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
     if (d->prec != BSE_PREC_FP64 && in->nq > d->nk) return BSE_ERR_ARG;
   }
   release(b);
-  const bool was_timing = timing_on();
-  if (was_timing) bse_timing_enable(0, nullptr);
+  const TimingState timing = timing_suspend();  // no events inside the graph
   bse_status st = BSE_OK;
-  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    timing_resume(timing);
     return BSE_ERR_HIP;
+  }
   launch_zero_ints(info, b->nprob, stream);
   hipEventRecord(b->events[0], stream);
   for (int br = 0; br < b->nbranch; ++br) hipStreamWaitEvent(b->streams[br], b->events[0], 0);
@@ -133,7 +134,7 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
     const int64_t n = (int64_t)d->nk * d->nv * d->nc;
     st = build_fp64(d, &inputs[i], H0[i], h1, wsb, info + i, s);
     if (st == BSE_OK)
-      st = solve_run(d, H0[i], h1, E[i], nullptr, n, probe[i], osc[i], wsb, info + i, s);
+      st = solve_run(d, H0[i], h1, E[i], nullptr, nullptr, n, probe[i], osc[i], wsb, info + i, s);
     if (st == BSE_OK &&
         launch_spectrum(n, E[i], osc[i], pref[i], eta[i], nw[i], omega[i], (double2*)eps[i], s) !=
             hipSuccess)
@@ -145,7 +146,7 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
   }
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(stream, &g);
-  if (was_timing) bse_timing_enable(1, nullptr);
+  timing_resume(timing);  // the caller's switch and name filter
   if (st != BSE_OK || ec != hipSuccess || !g) {
     if (g) hipGraphDestroy(g);
     return st != BSE_OK ? st : BSE_ERR_HIP;

@@ -66,8 +66,9 @@ int tune_choice(int site, int64_t size, int deflt);
 // solve.hip
 void launch_zero_ints(int32_t* p, int n, hipStream_t s);
 size_t solve_workspace(const bse_desc* d);
-bse_status solve_run(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, int64_t ldx,
-                     const void* probe, double* osc, void* ws, int32_t* info, hipStream_t s);
+bse_status solve_run(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, void* XmY,
+                     int64_t ldx, const void* probe, double* osc, void* ws, int32_t* info,
+                     hipStream_t s);
 
 // screening.hip
 size_t screening_workspace(const bse_screen_desc* d);

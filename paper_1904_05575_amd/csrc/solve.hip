@@ -34,6 +34,16 @@ __global__ void k_copy_c(const double2* __restrict__ src, double2* __restrict__ 
   if (i < n) dst[i] = src[i];
 }
 
+// dst[:, j] = src[:, j] for the n x n complex matrices (column-major, lds / ldd)
+__global__ __launch_bounds__(256) void k_copy_mat(const double2* __restrict__ src, int64_t lds,
+                                                  double2* __restrict__ dst, int64_t ldd,
+                                                  int64_t n) {
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+      dst[i + j * ldd] = src[i + j * lds];
+}
+
 __global__ void k_zero_ints(int32_t* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -1260,16 +1270,23 @@ void launch_zero_ints(int32_t* p, int n, hipStream_t s) {
   BSE_LAUNCH(k_zero_ints, dim3(1), dim3(64), 0, s, p, n);
 }
 
-bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* XpYv, int64_t ldx,
-                     const void* probev, double* osc, void* ws, int32_t* info, hipStream_t s) {
+bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* XpYv, void* XmYv,
+                     int64_t ldx, const void* probev, double* osc, void* ws, int32_t* info,
+                     hipStream_t s) {
   const int64_t n = (int64_t)d->nk * d->nv * d->nc, ld = d->ld;
   const bool full = d->coupling == BSE_FULL;
   double2* H0 = (double2*)H0v;
   double2* H1 = (double2*)H1v;
   double2* XpY = (double2*)XpYv;
+  double2* XmY = XpY ? (double2*)XmYv : nullptr;
   const double2* probe = (const double2*)probev;
   SolveWs w = carve(d, ws);
   BSE_LAUNCH(k_zero_ints, dim3(1), dim3(64), 0, s, w.counters, 64);
+  const dim3 cgrid((unsigned)std::min<int64_t>(cdiv(n, 256), 8),
+                   (unsigned)std::min<int64_t>(n, 65535));
+  // X-Y (full BSE) comes from the first of the coupled equations,
+  // (A+B)(X+Y) = (X-Y) E: A+B is kept in the X-Y buffer until X+Y exists
+  if (full && XmY) BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, H0, ld, XmY, ldx, n);
 
   double2* Hm = H0;  // Hermitian matrix handed to the tridiagonalisation
   if (full) {
@@ -1378,6 +1395,28 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
       g.info = info;
       g.tag = "zgemm_recon";
       if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
+      if (XmY) {
+        ZgemmParams h;  // X-Y = (A+B)(X+Y) E^-1 = U^-1 Z E^1/2  (Z free after the above)
+        h.M = (int)n;
+        h.N = (int)n;
+        h.K = (int)n;
+        h.A = XmY;
+        h.a_rs = 1;
+        h.a_cs = ldx;
+        h.B = XpY;
+        h.b_rs = 1;
+        h.b_cs = ldx;
+        h.C = w.Wk;
+        h.c_rs = 1;
+        h.c_cs = n;
+        h.ndiv = E;
+        h.info = info;
+        h.tag = "zgemm_xmy";
+        if (zgemm(h, 1, s) != hipSuccess) return BSE_ERR_HIP;
+        BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, w.Wk, n, XmY, ldx, n);
+      }
+    } else if (XmY) {  // TDA: Y = 0, X-Y = X+Y = X
+      BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, XpY, ldx, XmY, ldx, n);
     }
     if (probe && osc && launch_oscillator(n, XpY, ldx, probe, osc, s) != hipSuccess)
       return BSE_ERR_HIP;

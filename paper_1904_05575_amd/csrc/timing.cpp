@@ -36,6 +36,19 @@ hipEvent_t get_event() {
 
 bool timing_on() { return enabled; }
 
+TimingState timing_suspend() {
+  std::lock_guard<std::mutex> g(mu);
+  TimingState st{enabled, only};
+  enabled = false;
+  return st;
+}
+
+void timing_resume(const TimingState& st) {
+  std::lock_guard<std::mutex> g(mu);
+  enabled = st.on;
+  only = st.only;
+}
+
 namespace {
 thread_local char fail_msg[256];
 }

@@ -7,7 +7,17 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 bool timing_on();
+// Timing switched off for a stretch of work (graph capture records no
+// events) and switched back on afterwards with the same kernel-name filter.
+struct TimingState {
+  bool on = false;
+  std::string only;
+};
+TimingState timing_suspend();
+void timing_resume(const TimingState& st);
 // Registers a launch of `name`; *a / *b receive the events to launch with, or
 // nullptr when this launch is not timed.
 void timing_begin(const char* name, hipEvent_t* a, hipEvent_t* b);

@@ -27,6 +27,7 @@ struct ZgemmParams {
   int b_tri = 0;   // 1: B(k,n) = 0 for k > n; 2: B(k,n) = 0 for k < n
   const double* kscale = nullptr;  // A(m,k) *= kscale[b*ks_bs + k]
   int64_t ks_bs = 0;
+  const double* ndiv = nullptr;     // C(m,n) = alpha * sum(...) / ndiv[n] (+ beta C)
   const int32_t* info = nullptr;   // skip all work when *info != 0
   const char* tag = "zgemm";        // name under which the launch is timed
   int tile = 0;                     // 16, 32 or 64: tile edge; 0: chosen from the shape

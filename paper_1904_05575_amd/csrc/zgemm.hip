@@ -66,6 +66,7 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
     if (p.c_uplo == 1 && m > n) return;
     if (p.c_uplo == 2 && m < n) return;
     double2 v = cmul(p.alpha, acc);
+    if (p.ndiv) v = cscale(v, 1.0 / p.ndiv[n]);
     double2* dst = C + (int64_t)m * p.c_rs + (int64_t)n * p.c_cs;
     if (p.beta != 0.0) {
       const double2 o = *dst;

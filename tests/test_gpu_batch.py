@@ -129,7 +129,7 @@ def test_concurrent_streams_reproduce_the_sequential_path():
         info = B.info.data_ptr() + 4 * i
         L.bse_build(d, B.inputs[i], t["H0"].data_ptr(), t["H1"].data_ptr(), wss[k % 4].data_ptr(),
                     slice_b, info, s.cuda_stream)
-        L.bse_solve(d, t["H0"].data_ptr(), t["H1"].data_ptr(), t["E"].data_ptr(), 0, n,
+        L.bse_solve(d, t["H0"].data_ptr(), t["H1"].data_ptr(), t["E"].data_ptr(), 0, 0, n,
                     t["probe"].data_ptr(), t["osc"].data_ptr(), wss[k % 4].data_ptr(), slice_b,
                     info, s.cuda_stream)
     torch.cuda.synchronize()

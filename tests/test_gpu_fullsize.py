@@ -140,5 +140,32 @@ def test_observables_at_full_size(run):
         assert np.abs(con - scal).max() < 1e-10 * np.abs(scal - 1).max(), u
 
 
+def test_x_minus_y_at_full_size(run):
+    """N = 6144: X+Y and X-Y from bse_solve on sampled columns: the coupled
+    equations (A+-B) against the host copy of the GPU-built A+B and A-B
+    (which the oracle's sampled blocks pin), and (X+Y)^H (X-Y) = I."""
+    import torch
+    P = run["P"]
+    print("[gpu] X-Y at full size: build, solve with X+Y and X-Y", flush=True)
+    H0, H1 = P.build()
+    E, XpY, XmY, _ = P.solve(H0, H1, xmy=True, probe=False)
+    P.check_info()
+    rng = np.random.default_rng(5)
+    n = P.n
+    cols = np.unique(np.concatenate([rng.choice(n, 40, replace=False), [0, n - 1]]))
+    Xp = XpY[cols].cpu().numpy().T          # [a, l] for the sampled l
+    Xm = XmY[cols].cpu().numpy().T
+    G = (XpY.conj() @ XmY[cols].T.contiguous()).cpu().numpy()  # (X+Y)^H (X-Y), sampled
+    del XpY, XmY, H0, H1
+    torch.cuda.empty_cache()
+    Es = E.cpu().numpy()[cols]
+    scale = E.max().item()
+    assert np.abs(run["ApB"] @ Xp - Xm * Es).max() < 1e-10 * scale
+    assert np.abs(run["AmB"] @ Xm - Xp * Es).max() < 1e-10 * scale
+    I = np.zeros_like(G)
+    I[cols, np.arange(len(cols))] = 1.0
+    assert np.abs(G - I).max() < 1e-10
+
+
 def _relx(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)

@@ -91,6 +91,41 @@ def test_eigenvectors_residual_and_normalisation(name):
         assert np.abs(G - np.eye(len(E))).max() < 1e-10
 
 
+@pytest.mark.parametrize("name", ["tiny_full_k2_v2c3_g15", "small_full_k3_v3c4_g27",
+                                  "mid_full_k4_v3c4_g59", "small_full_k3s_v3c4_g27",
+                                  "tda_q0_k4_v2c3_g59"])
+def test_x_minus_y(name):
+    """X-Y of Sec. 4.3 (the (A-B)^-1/2 E^1/2 Z reading) through bse_solve's
+    XmY output: the coupled equations (A+B)(X+Y) = (X-Y)E and
+    (A-B)(X-Y) = (X+Y)E, the normalisation (X+Y)^H (X-Y) = I, the 2N form
+    H [X; Y] = E Delta [X; Y], and the oracle's X-Y column by column once the
+    phase of each column is fixed by X+Y (non-degenerate columns)."""
+    P = _problem(name)
+    H0, H1 = P.build()
+    E, XpY, XmY, _ = P.solve(H0, H1, xmy=True)
+    P.check_info()
+    E, XpY, XmY = E.cpu().numpy(), XpY.T.cpu().numpy(), XmY.T.cpu().numpy()
+    r = oracle_run(name)
+    A, B = r["A"], r["B"]
+    if B is None:
+        assert np.array_equal(XmY, XpY)
+        return
+    n, scale = len(E), E.max()
+    assert np.abs((A + B) @ XpY - XmY * E).max() < 1e-10 * scale
+    assert np.abs((A - B) @ XmY - XpY * E).max() < 1e-10 * scale
+    assert np.abs(XpY.conj().T @ XmY - np.eye(n)).max() < 1e-10
+    X, Y = (XpY + XmY) / 2, (XpY - XmY) / 2
+    H = np.block([[A, B], [B, A]])
+    res = H @ np.vstack([X, Y]) - np.vstack([X, -Y]) * E
+    assert np.abs(res).max() < 1e-10 * scale
+    gap = np.minimum(np.diff(E, prepend=-np.inf), np.diff(E, append=np.inf))
+    iso = gap > 1e-6 * scale
+    ph = np.sum(np.conj(r["XpY"]) * XpY, axis=0)
+    ph = ph / np.abs(ph)
+    dif = np.abs(XmY - r["XmY"] * ph[None, :])[:, iso]
+    assert dif.max() < 1e-8 * np.abs(r["XmY"]).max(), dif.max()
+
+
 @pytest.mark.parametrize("name", ["tiny_full_k2_v2c3_g15", "tda_q0_k4_v2c3_g59"])
 def test_spectrum_kernel_alone(name):
     """bse_spectrum fed with the oracle's E and |t|^2."""

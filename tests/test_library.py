@@ -68,9 +68,13 @@ def test_argument_errors_are_reported_without_launching(lib):
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):          # drawn Mcc: nv^2 <= 16
         L.bse_build(_desc(nv=5, ld=120), drawn, 1, 1, 1, 1 << 40, 1, 0)
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
-        L.bse_solve(d, 1, 0, 1, 0, 48, 0, 0, 1, 1 << 30, 1, 0)   # full needs H1
+        L.bse_solve(d, 1, 0, 1, 0, 0, 48, 0, 0, 1, 1 << 30, 1, 0)   # full needs H1
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+        L.bse_solve(d, 1, 1, 1, 0, 2, 48, 0, 0, 1, 1 << 40, 1, 0)   # X-Y needs X+Y
+    with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
+        L.bse_solve(d, 1, 1, 1, 2, 2, 48, 0, 0, 1, 1 << 40, 1, 0)   # X-Y in its own buffer
     with pytest.raises(L.BseError, match="BSE_ERR_WORKSPACE"):
-        L.bse_solve(d, 1, 1, 1, 1, 48, 0, 0, 1, 16, 1, 0)
+        L.bse_solve(d, 1, 1, 1, 1, 0, 48, 0, 0, 1, 16, 1, 0)
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
         L.bse_spectrum(10, 1, 1, 1.0, 0.0, 5, 1, 1, 0)      # eta must be > 0
     with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
