@@ -168,6 +168,22 @@ bse_status bse_solve(const bse_desc* desc, void* H0, void* H1, double* E, void* 
                      int64_t ldx, const void* probe, double* osc, void* ws, size_t ws_bytes,
                      int32_t* info, hipStream_t stream);
 
+/* bse_solve without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The scratch space is a fixed array of
+ * BSE_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends; its address is looked up on the first call made on each
+ * device.  The call allocates nothing (no hipMalloc, no library allocation).
+ * Arguments, outputs and device errors are those of bse_solve.
+ * BSE_ERR_WORKSPACE when bse_workspace_size(desc, BSE_STAGE_SOLVE) exceeds
+ * the array (orders up to about 780 for the full BSE fit).  Calls on one GPU
+ * share the array: calls that overlap in time on one GPU race and give
+ * undefined results; order them on one stream. */
+#define BSE_NOALLOC_SCRATCH_BYTES (32u << 20)
+bse_status bse_solve_noalloc(const bse_desc* desc, void* H0, void* H1, double* E, void* XpY,
+                             void* XmY, int64_t ldx, const void* probe, double* osc,
+                             int32_t* info, hipStream_t stream);
+
 /* Oscillator strengths from eigenvectors: osc[l] = |sum_a conj(XpY[a,l]) probe[a]|^2
  * (eq. osci without the 1/V_c factor, which the prefactor of bse_spectrum carries). */
 bse_status bse_oscillator(int64_t n, const void* XpY, int64_t ldx, const void* probe, double* osc,

@@ -21,7 +21,8 @@ EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bs
            "bse_transitions", "bse_dielectric_tensor", "bse_loss", "bse_screening_workspace_size",
            "bse_screening", "bse_status_string", "bse_timing_enable", "bse_timing_report",
            "bse_batch_workspace_size", "bse_batch_create", "bse_batch_capture", "bse_batch_run",
-           "bse_batch_destroy", "bse_tune_set", "bse_tune_get")
+           "bse_batch_destroy", "bse_tune_set", "bse_tune_get", "bse_solve_noalloc")
+NOALLOC_SCRATCH_BYTES = 32 << 20  # BSE_NOALLOC_SCRATCH_BYTES of bse.h
 TUNE_SITES = {"hemv_unit": 0, "gemm_squared": 1, "gemm_potrf": 2, "gemm_her2k": 3,
               "gemm_stage2": 4, "gemm_exchange": 5}
 
@@ -78,6 +79,9 @@ def lib() -> ctypes.CDLL:
         L.bse_solve.argtypes = [ctypes.POINTER(BseDesc), vp, vp, vp, vp, vp, i64, vp, vp, vp, sz,
                                 vp, vp]
         L.bse_solve.restype = ctypes.c_int
+        L.bse_solve_noalloc.argtypes = [ctypes.POINTER(BseDesc), vp, vp, vp, vp, vp, i64, vp, vp,
+                                        vp, vp]
+        L.bse_solve_noalloc.restype = ctypes.c_int
         L.bse_oscillator.argtypes = [i64, vp, i64, vp, vp, vp]
         L.bse_oscillator.restype = ctypes.c_int
         L.bse_spectrum.argtypes = [i64, vp, vp, dbl, dbl, i64, vp, vp, vp]
@@ -141,6 +145,13 @@ def bse_solve(desc: BseDesc, H0: int, H1: int, E: int, XpY: int, XmY: int, ldx: 
     _check(lib().bse_solve(ctypes.byref(desc), H0, H1 or None, E, XpY or None, XmY or None, ldx,
                            probe or None, osc or None, ws, ws_bytes, info, stream or None),
            "bse_solve")
+
+
+def bse_solve_noalloc(desc: BseDesc, H0: int, H1: int, E: int, XpY: int, XmY: int, ldx: int,
+                      probe: int, osc: int, info: int, stream: int) -> None:
+    _check(lib().bse_solve_noalloc(ctypes.byref(desc), H0, H1 or None, E, XpY or None,
+                                   XmY or None, ldx, probe or None, osc or None, info,
+                                   stream or None), "bse_solve_noalloc")
 
 
 def bse_oscillator(n: int, XpY: int, ldx: int, probe: int, osc: int, stream: int) -> None:
