@@ -22,6 +22,13 @@ Recipe (all complex draws are standard complex normal, E|z|^2 = 1):
                                          energy difference, the optical limit)
   W[q] = v^1/2(q+G) (I + L_q L_q^H)^-1 v^1/2(q+G'),  L_q ~ 0.3 CN (NG x 8),
          v(p) = 4 pi / |p|^2 with |p|^2 replaced by 0.01 at p = 0.
+Workloads with orbitals > 0 carry, instead of the pair elements and M_cv,
+synthetic orbitals: plane-wave coefficients C[k, n, K] on the sphere of the
+first `orbitals` reciprocal vectors K (occupied bands first), complex normal
+times 1/(1 + |K|^2), each orbital normalised (sum_K |C|^2 = 1) but the bands
+of one k not orthogonalised (so that the G = 0 element between an occupied
+and an unoccupied band at the same k, the Q = 0 probe, does not vanish);
+`kvec` holds the sphere's integer coordinates, `gvec` those of the G-set.
 Inputs of the RPA screening (make_screening_inputs): the workload's energies
 and, for every q of the mesh and k, pair elements between the bands at k and
 at k + q,
@@ -45,7 +52,7 @@ from . import lattice
 from .workloads import Workload
 
 _KIND = {"eps_v": 1, "eps_c": 2, "Mcv": 3, "Mvv": 4, "Mcc": 5, "Ncv": 6, "Nvc": 7, "L": 8,
-         "Dcv": 9, "Svc": 10, "Scv": 11}
+         "Dcv": 9, "Svc": 10, "Scv": 11, "C": 12}
 _CHUNK_ROWS = 1024
 _INV_SQRT2 = 1.0 / np.sqrt(2.0)
 
@@ -130,6 +137,17 @@ def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
     de = (out["eps_c"][:, None, :] - out["eps_v"][:, :, None]).reshape(w.n)
     out["Dcv"] = _complex_rows(w.seed, "Dcv", (w.n, 3), np.ones(3)) / de[:, None]
     env = 1.0 / (1.0 + np.sum(G ** 2, axis=1))
+    if w.orbitals:
+        # orbitals instead of pair elements (the consumers form M, N, M_cv)
+        Kc = lattice.gcart(w.orbitals)
+        nb = nv + nc
+        C = _complex_rows(w.seed, "C", (nk * nb, w.orbitals),
+                          1.0 / (1.0 + np.sum(Kc ** 2, axis=1)))
+        C /= np.linalg.norm(C, axis=1, keepdims=True)
+        out["C"] = C.reshape(nk, nb, w.orbitals)
+        out["kvec"] = lattice.gvectors(w.orbitals)
+        del out["Mcv"]
+        want_pairs = False
     if want_pairs:
         P = w.npairs
         out["Mvv"] = _complex_rows(w.seed, "Mvv", (P, nv, nv, ng), env)
@@ -142,7 +160,7 @@ def make_inputs(w: Workload, want_pairs: bool = True) -> dict:
         if w.coupling == "full":
             out["Ncv"] = _complex_rows(w.seed, "Ncv", (P, nc, nv, ng), env)
             out["Nvc"] = _complex_rows(w.seed, "Nvc", (P, nv, nc, ng), env)
-    out["W"] = screened_interaction(w) if want_pairs else None
+    out["W"] = screened_interaction(w) if (want_pairs or w.orbitals) else None
     qmap, qramap = lattice.q_maps(w.mesh, w.kshift)
     out["qmap"], out["qramap"] = qmap, qramap
     out["gvec"] = lattice.gvectors(ng)

@@ -41,6 +41,8 @@ class Workload:
     mcc_generated: bool = False  # Mcc given by a key and an envelope, drawn where used
     scissor: float = 0.0
     kshift: tuple = (0.0, 0.0, 0.0)  # k = (i + kshift) / mesh along b1, b2, b3
+    orbitals: int = 0         # > 0: pair elements come from synthetic orbitals expanded in
+                              # this many plane waves (a closed shell), not drawn directly
     note: str = ""
 
     @property
@@ -132,7 +134,20 @@ TINY = {
                               coupling="tda", nw=1000, wmin=371.0, wmax=431.0, eta=0.05,
                               seed=16, kernel_scale=1.0, core_level=-400.0,
                               mcv_gauss_width=0.5, mcc_generated=True)),
+    # pair elements from synthetic orbitals (plane-wave coefficients on a
+    # sphere of K-vectors), formed where they are used
+    "tiny_orb": _add(Workload(name="tiny_orb_k2_v2c3_g15_o27", mesh=2, nv=2, nc=3, ng=15,
+                              coupling="full", nw=200, wmin=0.0, wmax=10.0, eta=0.05, seed=31,
+                              kernel_scale=0.0625, orbitals=27)),
+    "small_orb": _add(Workload(name="small_orb_k3_v3c4_g27_o51", mesh=3, nv=3, nc=4, ng=27,
+                               coupling="full", nw=500, wmin=0.0, wmax=10.0, eta=0.05, seed=32,
+                               kernel_scale=0.125, orbitals=51)),
+    "mid_orb_tda": _add(Workload(name="mid_orb_tda_k4_v2c3_g59_o89", mesh=4, nv=2, nc=3, ng=59,
+                                 coupling="tda", nw=1000, wmin=0.0, wmax=10.0, eta=0.05,
+                                 seed=33, kernel_scale=0.5, orbitals=89)),
 }
+
+
 
 
 @dataclass(frozen=True)

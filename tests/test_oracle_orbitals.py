@@ -1,0 +1,132 @@
+"""Pins of the pair elements formed from orbitals (oracle/orbitals.py).
+
+The oracle writes M_mn(G) = sum_K conj(C_m(K)) C_n(K + G) and
+N_mn(G) = sum_K conj(C_m(K)) conj(C_n(-K - G)) as sums over the plane-wave
+sphere (Sec. 4.1, with plane-wave orbitals).  Pinned here by another route,
+the one of the convolution theorem: the periodic parts u_n(r) = sum_K C_n(K)
+exp(i K r) are laid on a real-space grid by an inverse FFT, the products
+conj(u_m) u_n and conj(u_m) conj(u_n) are formed point by point, and a
+forward FFT gives their Fourier coefficients at every G (exact once the grid
+is wide enough that the products' spectra do not alias).  Also pinned: the
+conjugate symmetry M_nm(k', k, -G) = conj(M_mn(k, k', G)); the wiring of the
+BSE arrays (which bands, which k, which element kind) against the FFT route;
+and the positive definiteness the calibrated kernel scales promise.  Planted
+mistakes (conjugate on the wrong factor, K - G for K + G, N without its
+conjugate) each fail the FFT comparison.
+"""
+import numpy as np
+import pytest
+
+from bse_synth import get, lattice, make_inputs
+from oracle import bse_oracle as O
+from oracle import orbitals as OR
+
+
+def _prim(v):
+    """Integer (h, k, l) of the bcc reciprocal lattice -> coordinates in the
+    primitive reciprocal basis b1 = (-1,1,1), b2 = (1,-1,1), b3 = (1,1,-1)."""
+    h, k, l = v[..., 0], v[..., 1], v[..., 2]
+    return np.stack([(k + l) // 2, (h + l) // 2, (h + k) // 2], axis=-1)
+
+
+def _fft_products(Ca, Cb, kvec, gvec, modified):
+    """[nbm][nbn][NG] Fourier coefficients of conj(u_m) u_n (conj(u_m) conj(u_n)
+    when modified) at the G-set, from FFTs on an alias-free grid."""
+    nk_ = _prim(kvec)
+    span = int(np.abs(nk_).max())
+    N = 4 * span + 3
+    def field(C):
+        A = np.zeros((C.shape[0], N, N, N), dtype=np.complex128)
+        idx = np.mod(nk_, N)
+        A[:, idx[:, 0], idx[:, 1], idx[:, 2]] = C
+        return np.fft.ifftn(A, axes=(1, 2, 3)) * N ** 3   # u(r_j) = sum_K C(K) e^{i K r_j}
+    ua, ub = field(Ca), field(Cb)
+    if modified:
+        ub = np.conj(ub)
+    prod = np.conj(ua)[:, None] * ub[None, :]
+    spec = np.fft.fftn(prod, axes=(2, 3, 4)) / N ** 3
+    g = np.mod(_prim(gvec), N)
+    return spec[:, :, g[:, 0], g[:, 1], g[:, 2]]
+
+
+def _random_orbitals(rng, nb, nkv):
+    C = rng.standard_normal((nb, nkv)) + 1j * rng.standard_normal((nb, nkv))
+    return C / np.linalg.norm(C, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("nkv,ng", [(27, 15), (51, 27), (89, 59)])
+def test_sums_match_convolution_route(nkv, ng):
+    rng = np.random.default_rng(nkv)
+    kvec, gvec = lattice.gvectors(nkv), lattice.gvectors(ng)
+    Ca, Cb = _random_orbitals(rng, 4, nkv), _random_orbitals(rng, 3, nkv)
+    for modified in (False, True):
+        ref = _fft_products(Ca, Cb, kvec, gvec, modified)
+        got = OR.pair_element(Ca, Cb, kvec, gvec, modified)
+        assert np.abs(got - ref).max() < 1e-14 * max(1.0, np.abs(ref).max())
+
+
+def test_planted_mistakes_fail_the_convolution_route():
+    rng = np.random.default_rng(3)
+    kvec, gvec = lattice.gvectors(51), lattice.gvectors(27)
+    Ca, Cb = _random_orbitals(rng, 3, 51), _random_orbitals(rng, 3, 51)
+    refM = _fft_products(Ca, Cb, kvec, gvec, False)
+    refN = _fft_products(Ca, Cb, kvec, gvec, True)
+    tp = OR.partner(kvec, gvec, False)
+    wrong = []
+    # conjugate on the right factor instead of the left: sum_K C_m(K) conj(C_n(K + G))
+    wrong.append(OR.pair_element(np.conj(Ca), np.conj(Cb), kvec, gvec, False, tp) - refM)
+    # K - G instead of K + G: the partner table of -G
+    wrong.append(OR.pair_element(Ca, Cb, kvec, -gvec, False) - refM)
+    # N without the conjugate of its right factor
+    wrong.append(OR.pair_element(Ca, np.conj(Cb), kvec, gvec, True) - refN)
+    for dlt in wrong:
+        assert np.abs(dlt).max() > 1e-3
+
+
+def test_conjugate_symmetry():
+    rng = np.random.default_rng(5)
+    kvec, gvec = lattice.gvectors(51), lattice.gvectors(27)
+    Ca, Cb = _random_orbitals(rng, 3, 51), _random_orbitals(rng, 4, 51)
+    pos = {tuple(g): i for i, g in enumerate(gvec)}
+    neg = np.array([pos[tuple(-g)] for g in gvec])
+    M = OR.pair_element(Ca, Cb, kvec, gvec, False)
+    Mt = OR.pair_element(Cb, Ca, kvec, gvec, False)
+    assert np.abs(Mt[:, :, neg] - np.conj(np.transpose(M, (1, 0, 2)))).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", ["tiny_orb_k2_v2c3_g15_o27", "small_orb_k3_v3c4_g27_o51"])
+def test_bse_arrays_wiring(name):
+    """Each BSE array against the convolution route for a few pairs: Mvv and
+    Mcc from conj(u) u of the occupied / unoccupied bands at k and k', Ncv
+    and Nvc from conj(u) conj(u) with the bands crossed, M_cv at k = k'."""
+    d = make_inputs(get(name))
+    w = d["workload"]
+    nv = w.nv
+    arr = OR.bse_pair_arrays(d["C"], nv, d["kvec"], d["gvec"])
+    ik, jk = np.triu_indices(w.nk)
+    for p in sorted({0, len(ik) // 2, len(ik) - 1, 1}):
+        Ca, Cb = d["C"][ik[p]], d["C"][jk[p]]
+        M = _fft_products(Ca, Cb, d["kvec"], d["gvec"], False)
+        N = _fft_products(Ca, Cb, d["kvec"], d["gvec"], True)
+        assert np.abs(arr["Mvv"][p] - M[:nv, :nv]).max() < 1e-14
+        assert np.abs(arr["Mcc"][p] - M[nv:, nv:]).max() < 1e-14
+        assert np.abs(arr["Ncv"][p] - N[nv:, :nv]).max() < 1e-14
+        assert np.abs(arr["Nvc"][p] - N[:nv, nv:]).max() < 1e-14
+    k = w.nk - 1
+    M = _fft_products(d["C"][k], d["C"][k], d["kvec"], d["gvec"], False)
+    mcv = arr["Mcv"].reshape(w.nk, nv, w.nc, w.ng)[k]
+    assert np.abs(mcv - M[:nv, nv:]).max() < 1e-14
+    # the probe (G = 0 between bands at one k) does not vanish: orbitals of a
+    # k are normalised, not orthogonalised
+    assert np.abs(mcv[:, :, 0]).min() > 1e-4
+
+
+@pytest.mark.parametrize("name", ["tiny_orb_k2_v2c3_g15_o27", "small_orb_k3_v3c4_g27_o51",
+                                  "mid_orb_tda_k4_v2c3_g59_o89"])
+def test_orbital_workloads_are_positive_definite(name):
+    d = OR.complete_inputs(make_inputs(get(name)))
+    A, B = O.assemble(d)
+    E = O.transition_energies(d)
+    mats = [A] if B is None else [A - B, A + B]
+    for Mx in mats:
+        assert np.linalg.eigvalsh(0.5 * (Mx + Mx.conj().T)).min() > 0.1 * E.min()
