@@ -324,6 +324,21 @@ int64_t bse_timing_report(char* buf, int64_t len);
  *                          16, 32 or 64 (squared form S = U (A+B) U^H; Cholesky
  *                          trailing updates; Householder panel updates; the
  *                          second contraction of the direct terms; exchange)
+ *   BSE_TUNE_DIRECT        size = problem order n; choice = how the FP64 (and
+ *                          FP32) direct terms with stored pair elements and
+ *                          N_G <= 128 run: 0 two passes (T = conj(M) W(q) to
+ *                          memory on the real view, then a batched product
+ *                          per pair and a scatter); 1, 2, 3 one fused pass per
+ *                          term (T kept on chip) with 16, 8 or 8 wavefronts per
+ *                          block of 64 rows (wavefront tiles 16 x 32, 16 x 64,
+ *                          32 x 32), the first product in three real products
+ *                          per complex one; 4, 5, 6 that first product (same
+ *                          three shapes) writing T, then the two-pass rest
+ *   BSE_TUNE_GEMM_PRODUCTS size = the larger output dimension of a complex GEMM;
+ *                          choice = real matrix-core products per complex one
+ *                          on 16- and 32-edge tiles: 4 (re = ar br - ai bi,
+ *                          im = ar bi + ai br) or 3 (Gauss: ar br, ai bi,
+ *                          (ar + ai)(br + bi)); 64-edge tiles always take 4
  * Among the entries of a site, the one with the smallest size_max >= size
  * applies; sizes no entry covers use built-in rules.  Every choice gives the
  * same results up to rounding order.  The table is read on the host when work
@@ -338,7 +353,9 @@ enum {
   BSE_TUNE_GEMM_POTRF = 2,
   BSE_TUNE_GEMM_HER2K = 3,
   BSE_TUNE_GEMM_STAGE2 = 4,
-  BSE_TUNE_GEMM_EXCHANGE = 5
+  BSE_TUNE_GEMM_EXCHANGE = 5,
+  BSE_TUNE_DIRECT = 6,
+  BSE_TUNE_GEMM_PRODUCTS = 7
 };
 typedef struct {
   int32_t site;

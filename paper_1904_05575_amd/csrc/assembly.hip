@@ -14,6 +14,8 @@
 //   stage 1  T[pair rows, G'] = conj(M_left) x W(q)         grouped GEMM over classes
 //   stage 2  blk[pair]        = T[pair] x M_right[pair]^T    batched GEMM over pairs
 // followed by a scatter of the (nv nc)^2 block of every pair into A+B / A-B.
+// In FP64 with stored pair elements (N_G <= 128) both stages of a term run in
+// one fused pass instead (direct.hip), which adds its blocks into the outputs.
 #include "bse_internal.h"
 #include "common.h"
 #include "mfma_tile.h"
@@ -357,8 +359,17 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
 
   const int prec = d->prec;
   const int nterms = d->split_terms == 0 ? 6 : d->split_terms;
-  // the precision form splits W once per build; its buffer holds nk slices
-  if (prec != BSE_PREC_FP64) {
+  // default 4: the Gauss first product writing T, then the batched second
+  // product (measured at N = 6144: 5.8 + 2.5 ms against 7.0 + 2.5 ms on the
+  // real view and 10.8 ms fused, whose vector-ALU second product waits on memory)
+  const int dvar = tune_choice(BSE_TUNE_DIRECT, n, 4);
+  const bool shape_ok = (prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32) && in->Mcc &&
+                        ng <= 128 && R1 <= 64 && (!full || R2 <= 64);
+  const bool use_fused = shape_ok && dvar >= 1 && dvar <= 3;
+  const bool use_g3_t = shape_ok && dvar >= 4;  // Gauss first product, then two passes
+  // the precision form splits W once per build (the two-pass products read
+  // it); its buffer holds nk slices
+  if (prec != BSE_PREC_FP64 && !use_fused && !use_g3_t) {
     if (nq > (full ? 2 * nk : nk)) return BSE_ERR_ARG;
     if (!launch_split_w(prec, (const double2*)in->W, nq, ng, Wsp, s)) return BSE_ERR_HIP;
   }
@@ -396,7 +407,12 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   // direct terms, stage 1 (grouped by class) and stage 2 (batched by pair)
   auto direct = [&](const void* left, int R, const void* right, int N2, const int32_t* perm,
                     const int32_t* cls, double2* T, double2* blk) -> bool {
-    if (prec != BSE_PREC_FP64) {
+    if (use_g3_t) {
+      if (!launch_direct_fused(prec, dvar - 3, (const double2*)left, (const double2*)right, R, N2,
+                               ng, nk, nv, nc, (const double2*)in->W, perm, cls, nq, 0, 0.0,
+                               nullptr, nullptr, 0, T, info, s))
+        return false;
+    } else if (prec != BSE_PREC_FP64) {
       // stage 1 in the precision form; stage 2 (R x ng x N2 per pair, memory-bound)
       // runs in FP64 below
       if (!launch_stage1_lp(prec, nterms, (const double2*)left, R, ng, Wsp, perm, cls, nq, nk, T,
@@ -441,13 +457,36 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
     g.tile = tune_choice(BSE_TUNE_GEMM_STAGE2, n, 0);
     return zgemm(g, (int)P, s) == hipSuccess;
   };
+  const double c = -gc * kap;
+  // FP64 and FP32 with stored pair elements: one fused pass per term (T stays
+  // on chip), each adding its blocks into the outputs (A+B += c rr,
+  // A-B = c rr; then A+B += c ra, A-B -= c ra), unless the tuning table asks
+  // for two passes
+  if (use_fused) {
+    bool ok = launch_direct_fused(prec, dvar, (const double2*)in->Mvv, (const double2*)in->Mcc,
+                                  (int)R1, (int)N1, ng, nk, nv, nc, (const double2*)in->W,
+                                  perm_rr, cls_rr, nq, 0, c, (double2*)out0,
+                                  full ? (double2*)out1 : nullptr, ld, nullptr, info, s);
+    if (ok && full)
+      ok = launch_direct_fused(prec, dvar, (const double2*)in->Ncv, (const double2*)in->Nvc,
+                               (int)R2, (int)R2, ng, nk, nv, nc, (const double2*)in->W, perm_ra,
+                               cls_ra, nq, 1, c, (double2*)out0, (double2*)out1, ld, nullptr,
+                               info, s);
+    if (!ok) return BSE_ERR_HIP;
+    const int nt = cdiv(n, FT);
+    BSE_LAUNCH(k_finalize, dim3(nt, nt), dim3(256), 0, s, (double2*)out0, n, ld, in->eps_v,
+               in->eps_c, nv, nc, d->scissor, info);
+    if (full)
+      BSE_LAUNCH(k_finalize, dim3(nt, nt), dim3(256), 0, s, (double2*)out1, n, ld, in->eps_v,
+                 in->eps_c, nv, nc, d->scissor, info);
+    return hipGetLastError() == hipSuccess ? BSE_OK : BSE_ERR_HIP;
+  }
   if (!direct(in->Mvv, (int)R1, in->Mcc, (int)N1, perm_rr, cls_rr, T_rr, blk_rr)) return BSE_ERR_HIP;
   if (full && !direct(in->Ncv, (int)R2, in->Nvc, (int)R2, perm_ra, cls_ra, T_ra, blk_ra))
     return BSE_ERR_HIP;
 
   // scatter: A+B += -gc kappa (rr + ra), A-B = -gc kappa (rr - ra); TDA: A += -gc kappa rr
   {
-    const double c = -gc * kap;
     const int64_t total = P * (int64_t)(nv * nc) * (nv * nc);
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
     BSE_LAUNCH(k_combine, dim3(blocks), dim3(256), 0, s, (int)P, nk, nv, nc, ld, inv_rr,

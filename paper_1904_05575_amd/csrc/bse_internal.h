@@ -50,6 +50,14 @@ bool launch_stage1(const double2* left, int R, int ng, const double2* W, const i
                    const int32_t* cls, int nq, int nk, double2* T, const int32_t* info,
                    hipStream_t s);
 
+// direct.hip: both direct-term contractions in one pass, added into the
+// outputs (false: shape not handled, nothing launched)
+bool launch_direct_fused(int prec, int variant, const double2* left, const double2* right, int R,
+                         int N2, int ng, int nk, int nv, int nc, const double2* W,
+                         const int32_t* perm, const int32_t* cls, int nq, int ra, double coef,
+                         double2* out0, double2* out1, int64_t ld, double2* Tout,
+                         const int32_t* info, hipStream_t s);
+
 // gemm_lp.hip: reduced-precision products of the assembly
 size_t split_w_bytes(int nq, int ng);
 bool launch_split_w(int prec, const double2* W, int nq, int ng, void* Wsp, hipStream_t s);

@@ -1,0 +1,443 @@
+// Direct terms of the kernel (paper Sec. 4.2, eqs. wrrm and wrabar) in one
+// pass per term, for pair elements given as arrays:
+//   T_p[r][G'] = sum_G conj(L_p[r][G]) W[q][G][G']      (q = class of pair p)
+//   blk_p[r][j] = sum_G' T_p[r][G'] Rt_p[j][G']
+// and the blocks added straight into the outputs (A+B and A-B, or A).
+//
+// One block takes up to 64 rows of T (PPT whole pairs of one momentum-transfer
+// class) and all N_G columns:
+//  * the first product runs on the matrix cores (FP64, or FP32 in the
+//    precision form) with complex products in three real products each
+//    (Gauss: P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); Re = P1 - P2,
+//    Im = P3 - P1 - P2), the operands staged through LDS in chunks of 8 (16)
+//    complex k with the next chunks' loads in flight in registers; in FP32
+//    each chunk's products are added into FP64 sums;
+//  * T then goes to LDS, 64 columns at a time, and the second product runs
+//    on the vector ALU: each group of four lanes owns one (pair, j, row set)
+//    and splits the G' sum four ways (reduced by DPP at the end); the right
+//    operand Rt_p is read once from HBM;
+//  * the finished entries are added into the outputs (column-major, ld).
+// T never leaves the chip.  Requires N_G <= 128 and R <= 64 rows per pair.
+#include "bse_internal.h"
+#include "common.h"
+#include "timing.h"
+
+#include <type_traits>
+
+namespace {
+
+constexpr int DBM = 64;      // rows of T per block (whole pairs only)
+constexpr int DMAXR = 8;     // rows of a pair one thread takes in the second product
+constexpr int DPAD = 2;
+
+// complex k per LDS chunk: two MFMA k-steps in FP64; in FP32 four, which is
+// also the length of the FP32 partial sums added into FP64 accumulators
+template <int PREC>
+constexpr int dbk() { return PREC == BSE_PREC_FP32 ? 16 : 8; }
+
+template <int PREC, int BN>
+struct DSmem1 {
+  using Real = typename std::conditional<PREC == BSE_PREC_FP32, float, double>::type;
+  static constexpr int BK = dbk<PREC>();
+  Real a_re[2][BK][DBM + DPAD], a_im[2][BK][DBM + DPAD];
+  Real b_re[2][BK][BN + DPAD], b_im[2][BK][BN + DPAD];
+};
+struct DSmem2 {
+  double2 t[DBM][64 + 1];
+};
+template <int PREC, int BN>
+union DSmem {
+  DSmem1<PREC, BN> s1;
+  DSmem2 s2;
+};
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// quad sum by DPP (lanes 4i .. 4i+3), every lane of the quad gets the total
+template <int CTRL>
+BSE_DEV double dpp_q(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+BSE_DEV double quad_sum(double v) {
+  v += dpp_q<0xB1>(v);  // quad_perm [1,0,3,2]
+  v += dpp_q<0x4E>(v);  // quad_perm [2,3,0,1]
+  return v;
+}
+
+BSE_DEV int pair_row(int p, int nk) {  // ik of pair p = ik*nk - ik(ik-1)/2 + (jk - ik)
+  int lo = 0, hi = nk - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t start = (int64_t)mid * nk - (int64_t)mid * (mid - 1) / 2;
+    if (start <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// WM x WN wavefronts; each wave TI x TJ tiles of 16 x 16 (WM*TI*16 = 64,
+// WN*TJ*16 = BN).  ra = 0: resonant term (left Mvv, right Mcc); ra = 1:
+// coupling term (left Ncv, right Nvc).  PREC: FP64, or FP32 (operands
+// rounded to FP32, FP32 products summed over 16 complex k, FP64 across).
+template <int PREC, int WM, int WN, int TI, int TJ, int BN, bool TOUT>
+__global__ __launch_bounds__(WM* WN * 64) void k_direct_fused(
+    const double2* __restrict__ Left, const double2* __restrict__ Right, int R, int N2, int ng,
+    int nk, int nv, int nc, const double2* __restrict__ W, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ cls, int tiles_per_class, int ra, double coef,
+    double2* __restrict__ out0, double2* __restrict__ out1, int64_t ld, double2* __restrict__ Tout,
+    const int32_t* info) {
+  static_assert(WM * TI * 16 == DBM && WN * TJ * 16 == BN, "tile shape");
+  constexpr bool F32 = PREC == BSE_PREC_FP32;
+  using Real = typename DSmem1<PREC, BN>::Real;
+  constexpr int DBK = dbk<PREC>();
+  constexpr int NT = WM * WN * 64;
+  constexpr int NA = DBM * DBK / NT > 0 ? DBM * DBK / NT : 1;   // A complex per thread
+  constexpr int NB = DBK * BN / NT > 0 ? DBK * BN / NT : 1;     // B complex per thread
+  static_assert(NA * NT >= DBM * DBK && NB * NT >= DBK * BN, "staging");
+  __shared__ DSmem<PREC, BN> sm;
+  if (failed(info)) return;
+  const int q = blockIdx.x / tiles_per_class, mt = blockIdx.x % tiles_per_class;
+  const int ppt = DBM / R;                   // whole pairs per block
+  const int s0 = cls[q], np = cls[q + 1] - s0;
+  const int pos0 = mt * ppt;                 // first pair (position in class q)
+  if (pos0 >= np) return;
+  const int npb = min(ppt, np - pos0);       // pairs of this block
+  const int rows = npb * R;
+  const double2* __restrict__ Wq = W + (int64_t)q * ng * ng;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm0 = (wid % WM) * (TI * 16), wn0 = (wid / WM) * (TJ * 16);
+
+  // ---- first product (matrix cores, 3 real products per complex one)
+  // A staging: element e -> (row mm = e / DBK, k = e % DBK): DBK threads read
+  // DBK consecutive k of one row (contiguous bytes)
+  const double2* arow[NA];
+  bool aok[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int e = tid + NT * u;
+    const int mm = e / DBK;
+    aok[u] = e < DBM * DBK && mm < rows;
+    const int m = aok[u] ? mm : 0;
+    const int64_t p = perm[s0 + pos0 + m / R];
+    arow[u] = Left + (p * R + m % R) * ng;
+  }
+  double2 ra0[NA], rb0[NB], ra1[NA], rb1[NB];
+  auto fetch = [&](double2 (&ra_)[NA], double2 (&rb_)[NB], int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int k = k0 + (tid + NT * u) % DBK;
+      ra_[u] = arow[u][k < ng ? k : ng - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + NT * u;
+      const int kk = e / BN, nn = e % BN;
+      const int k = k0 + kk;
+      rb_[u] = Wq[(int64_t)(k < ng ? k : ng - 1) * ng + (nn < ng ? nn : ng - 1)];
+    }
+  };
+  auto put = [&](int buf, const double2 (&ra_)[NA], const double2 (&rb_)[NB], int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + NT * u;
+      if (e < DBM * DBK) {
+        const int mm = e / DBK, kk = e % DBK;
+        const bool ok = aok[u] && k0 + kk < ng;
+        sm.s1.a_re[buf][kk][mm] = ok ? (Real)ra_[u].x : (Real)0;
+        sm.s1.a_im[buf][kk][mm] = ok ? (Real)(-ra_[u].y) : (Real)0;  // conj(L)
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + NT * u;
+      if (e < DBK * BN) {
+        const int kk = e / BN, nn = e % BN;
+        const bool ok = k0 + kk < ng && nn < ng;
+        sm.s1.b_re[buf][kk][nn] = ok ? (Real)rb_[u].x : (Real)0;
+        sm.s1.b_im[buf][kk][nn] = ok ? (Real)rb_[u].y : (Real)0;
+      }
+    }
+  };
+  // FP64: the three products accumulate for the whole K; FP32: per chunk,
+  // then added into the FP64 real and imaginary parts of T
+  d4 p1[TI][TJ], p2[TI][TJ], p3[TI][TJ];
+  d4 tre[TI][TJ], tim[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+      p1[i][j] = p2[i][j] = p3[i][j] = tre[i][j] = tim[i][j] = d4{0, 0, 0, 0};
+  auto mma = [&](int buf, int k0) {
+    if constexpr (F32) {
+      f4 c1[TI][TJ], c2[TI][TJ], c3[TI][TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) c1[i][j] = c2[i][j] = c3[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < DBK / 4; ++ks) {
+        if (k0 + ks * 4 < ng) {
+          const int kr = ks * 4 + (lane >> 4);
+          float ar[TI], ai[TI], as[TI], br[TJ], bi[TJ], bs[TJ];
+#pragma unroll
+          for (int i = 0; i < TI; ++i) {
+            ar[i] = sm.s1.a_re[buf][kr][wm0 + i * 16 + (lane & 15)];
+            ai[i] = sm.s1.a_im[buf][kr][wm0 + i * 16 + (lane & 15)];
+            as[i] = ar[i] + ai[i];
+          }
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) {
+            br[j] = sm.s1.b_re[buf][kr][wn0 + j * 16 + (lane & 15)];
+            bi[j] = sm.s1.b_im[buf][kr][wn0 + j * 16 + (lane & 15)];
+            bs[j] = br[j] + bi[j];
+          }
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+              c1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], c1[i][j], 0, 0, 0);
+              c2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], bi[j], c2[i][j], 0, 0, 0);
+              c3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[i], bs[j], c3[i][j], 0, 0, 0);
+            }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            tre[i][j][r] += (double)(c1[i][j][r] - c2[i][j][r]);
+            tim[i][j][r] += (double)(c3[i][j][r] - c1[i][j][r] - c2[i][j][r]);
+          }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < DBK / 4; ++ks) {
+        if (k0 + ks * 4 < ng) {
+          const int kr = ks * 4 + (lane >> 4);
+          double ar[TI], ai[TI], as[TI], br[TJ], bi[TJ], bs[TJ];
+#pragma unroll
+          for (int i = 0; i < TI; ++i) {
+            ar[i] = sm.s1.a_re[buf][kr][wm0 + i * 16 + (lane & 15)];
+            ai[i] = sm.s1.a_im[buf][kr][wm0 + i * 16 + (lane & 15)];
+            as[i] = ar[i] + ai[i];
+          }
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) {
+            br[j] = sm.s1.b_re[buf][kr][wn0 + j * 16 + (lane & 15)];
+            bi[j] = sm.s1.b_im[buf][kr][wn0 + j * 16 + (lane & 15)];
+            bs[j] = br[j] + bi[j];
+          }
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+              p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
+              p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], p2[i][j], 0, 0, 0);
+              p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], bs[j], p3[i][j], 0, 0, 0);
+            }
+        }
+      }
+    }
+  };
+  const int nch = (ng + DBK - 1) / DBK;
+  fetch(ra0, rb0, 0);
+  put(0, ra0, rb0, 0);
+  if (nch > 1) fetch(ra1, rb1, DBK);
+  if (nch > 2) fetch(ra0, rb0, 2 * DBK);
+  __syncthreads();
+  // step ch: multiply chunk ch, stage chunk ch + 1 (held in `cur`) into the
+  // other buffer, then reuse `cur` for the loads of chunk ch + 3
+  auto step = [&](int ch, double2 (&ra_)[NA], double2 (&rb_)[NB]) {
+    mma(ch & 1, ch * DBK);
+    if (ch + 1 < nch) put((ch + 1) & 1, ra_, rb_, (ch + 1) * DBK);
+    __syncthreads();
+    if (ch + 3 < nch) fetch(ra_, rb_, (ch + 3) * DBK);
+  };
+  for (int ch = 0; ch < nch; ch += 2) {
+    step(ch, ra1, rb1);
+    if (ch + 1 < nch) step(ch + 1, ra0, rb0);
+  }
+
+  // FP64: T = P1 - P2 + i (P3 - P1 - P2); the three products are dead after this
+  if constexpr (!F32) {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          tre[i][j][r] = p1[i][j][r] - p2[i][j][r];
+          tim[i][j][r] = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+        }
+  }
+  // row of accumulator register r (f64: l/16 + 4r; f32: 4 (l/16) + r)
+  auto acc_row = [&](int r) { return F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r; };
+  if constexpr (TOUT) {
+    // first product only: T of the class's rows, [row][G'], for a separate
+    // second pass
+    double2* __restrict__ Tq = Tout + ((int64_t)s0 + pos0) * R * ng;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = wm0 + i * 16 + acc_row(r), n = wn0 + j * 16 + (lane & 15);
+          if (m < rows && n < ng) Tq[(int64_t)m * ng + n] = make_double2(tre[i][j][r], tim[i][j][r]);
+        }
+    return;
+  }
+
+  // ---- second product (vector ALU), 64 columns of T at a time
+  // item = ((pp * N2 + j) * RS + rs) * 4 + g4: pair pp of the block, right
+  // index j, row set rs (DMAXR rows at most), quarter g4 of each 64-column
+  // phase (G' = 64 ph + 4 gg + g4); the items go in rounds of NT
+  const int RS = (R + DMAXR - 1) / DMAXR;
+  const int rpt = (R + RS - 1) / RS;
+  const int nitems = ppt * N2 * RS * 4;
+  constexpr int NPH = BN / 64;
+  const int nvnc = nv * nc;
+  for (int base = 0; base < nitems; base += NT) {
+    const int item = base + tid;
+    const int g4 = item & 3;
+    const int rs = (item >> 2) % RS;
+    const int jj = (item >> 2) / RS % N2;
+    const int pp = (item >> 2) / RS / N2;
+    const int r0 = rs * rpt;
+    const bool own = item < nitems && pp < npb;  // the same for the four lanes of a quad
+    const double2* __restrict__ rt = Right;
+    if (own) rt = Right + ((int64_t)perm[s0 + pos0 + pp] * N2 + jj) * ng;
+    double2 acc[DMAXR];
+#pragma unroll
+    for (int r = 0; r < DMAXR; ++r) acc[r] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int ph = 0; ph < NPH; ++ph) {
+      // waves holding columns [64 ph, 64 ph + 64) store their part of T
+      if (wn0 >= 64 * ph && wn0 < 64 * (ph + 1)) {
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int m = wm0 + i * 16 + acc_row(r);
+              const int n = wn0 - 64 * ph + j * 16 + (lane & 15);
+              sm.s2.t[m][n] = make_double2(tre[i][j][r], tim[i][j][r]);
+            }
+      }
+      __syncthreads();
+      if (own) {
+#pragma unroll 4
+        for (int gg = 0; gg < 16; ++gg) {
+          const int gl = 4 * gg + g4, g = 64 * ph + gl;
+          if (g < ng) {
+            const double2 m = rt[g];
+#pragma unroll
+            for (int r = 0; r < DMAXR; ++r)
+              if (r < rpt && r0 + r < R) {
+                const double2 t = sm.s2.t[pp * R + r0 + r][gl];
+                acc[r].x = fma(t.x, m.x, fma(-t.y, m.y, acc[r].x));
+                acc[r].y = fma(t.x, m.y, fma(t.y, m.x, acc[r].y));
+              }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // quad reduction: every lane of the block takes part
+#pragma unroll
+    for (int r = 0; r < DMAXR; ++r) {
+      acc[r].x = quad_sum(acc[r].x);
+      acc[r].y = quad_sum(acc[r].y);
+    }
+    if (own && g4 == 0) {
+      const int p = perm[s0 + pos0 + pp];
+      const int ik = pair_row(p, nk);
+      const int jk = ik + (int)(p - ((int64_t)ik * nk - (int64_t)ik * (ik - 1) / 2));
+#pragma unroll
+      for (int r = 0; r < DMAXR; ++r) {
+        if (r >= rpt || r0 + r >= R) continue;
+        const int rr = r0 + r;
+        int v, c, v2, c2;
+        if (!ra) {  // rows (v, v'), columns j = (c, c')
+          v = rr / nv; v2 = rr % nv; c = jj / nc; c2 = jj % nc;
+        } else {    // rows (c, v'), columns j = (v, c')
+          c = rr / nv; v2 = rr % nv; v = jj / nc; c2 = jj % nc;
+        }
+        const int64_t row = (int64_t)ik * nvnc + v * nc + c;
+        const int64_t col = (int64_t)jk * nvnc + v2 * nc + c2;
+        const double2 val = cscale(acc[r], coef);
+        double2* d0 = out0 + row + col * ld;
+        const double2 o = *d0;
+        *d0 = make_double2(o.x + val.x, o.y + val.y);
+        if (out1) {
+          double2* d1 = out1 + row + col * ld;
+          if (!ra) {
+            *d1 = val;  // the resonant term writes A-B first
+          } else {
+            const double2 o1 = *d1;
+            *d1 = make_double2(o1.x - val.x, o1.y - val.y);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int PREC, int WM, int WN, int TI, int TJ, int BN>
+void launch(const double2* left, const double2* right, int R, int N2, int ng, int nk, int nv,
+            int nc, const double2* W, const int32_t* perm, const int32_t* cls, int nq, int ra,
+            double coef, double2* out0, double2* out1, int64_t ld, double2* Tout,
+            const int32_t* info, hipStream_t s) {
+  const int ppt = DBM / R;
+  const int tiles = cdiv(nk, ppt);  // a class holds at most nk pairs
+  if (Tout)
+    BSE_LAUNCH((k_direct_fused<PREC, WM, WN, TI, TJ, BN, true>), dim3((unsigned)(nq * tiles)),
+               dim3(WM * WN * 64), 0, s, left, right, R, N2, ng, nk, nv, nc, W, perm, cls, tiles,
+               ra, coef, out0, out1, ld, Tout, info);
+  else
+    BSE_LAUNCH((k_direct_fused<PREC, WM, WN, TI, TJ, BN, false>), dim3((unsigned)(nq * tiles)),
+               dim3(WM * WN * 64), 0, s, left, right, R, N2, ng, nk, nv, nc, W, perm, cls, tiles,
+               ra, coef, out0, out1, ld, Tout, info);
+}
+
+template <int PREC>
+void dispatch(int variant, const double2* left, const double2* right, int R, int N2, int ng,
+              int nk, int nv, int nc, const double2* W, const int32_t* perm, const int32_t* cls,
+              int nq, int ra, double coef, double2* out0, double2* out1, int64_t ld,
+              double2* Tout, const int32_t* info, hipStream_t s) {
+#define BSE_DIRECT_ARGS left, right, R, N2, ng, nk, nv, nc, W, perm, cls, nq, ra, coef, out0, out1, ld, Tout, info, s
+  if (ng <= 64) {
+    if (variant == 1) launch<PREC, 4, 2, 1, 2, 64>(BSE_DIRECT_ARGS);
+    else launch<PREC, 2, 2, 2, 2, 64>(BSE_DIRECT_ARGS);
+  } else {
+    if (variant == 1) launch<PREC, 4, 4, 1, 2, 128>(BSE_DIRECT_ARGS);
+    else if (variant == 2) launch<PREC, 4, 2, 1, 4, 128>(BSE_DIRECT_ARGS);
+    else launch<PREC, 2, 4, 2, 2, 128>(BSE_DIRECT_ARGS);
+  }
+#undef BSE_DIRECT_ARGS
+}
+
+}  // namespace
+
+// Returns false when the shape is outside what the fused kernel handles
+// (nothing is launched; the caller takes the two-pass path).
+bool launch_direct_fused(int prec, int variant, const double2* left, const double2* right, int R,
+                         int N2, int ng, int nk, int nv, int nc, const double2* W,
+                         const int32_t* perm, const int32_t* cls, int nq, int ra, double coef,
+                         double2* out0, double2* out1, int64_t ld, double2* Tout,
+                         const int32_t* info, hipStream_t s) {
+  if (ng > 128 || R < 1 || R > DBM || N2 < 1) return false;
+  if (prec == BSE_PREC_FP32)
+    dispatch<BSE_PREC_FP32>(variant, left, right, R, N2, ng, nk, nv, nc, W, perm, cls, nq, ra,
+                            coef, out0, out1, ld, Tout, info, s);
+  else if (prec == BSE_PREC_FP64)
+    dispatch<BSE_PREC_FP64>(variant, left, right, R, N2, ng, nk, nv, nc, W, perm, cls, nq, ra,
+                            coef, out0, out1, ld, Tout, info, s);
+  else
+    return false;
+  return hipGetLastError() == hipSuccess;
+}

@@ -10,10 +10,15 @@
 // v_mfma_f64_16x16x4_f64 lane layout: A operand lane l -> (m = l%16, k = l/16),
 // B operand lane l -> (k = l/16, n = l%16), accumulator register r of lane l
 // -> (m = l/16 + 4*r, n = l%16).
+//
+// G3 = false: four real products per complex one (re = ar br - ai bi,
+// im = ar bi + ai br).  G3 = true: three (Gauss's product: P1 = ar br,
+// P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2, im = P3 - P1 - P2),
+// a quarter fewer matrix-core operations for one more accumulator per tile.
 #pragma once
 #include "common.h"
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool G3 = false>
 struct ZTile {
   static constexpr int BK = 16;
   static constexpr int PAD = 2;
@@ -27,7 +32,8 @@ struct ZTile {
     double b_re[BK][BN + PAD], b_im[BK][BN + PAD];
   };
 
-  d4 cr[TI][TJ], ci[TI][TJ];
+  d4 cr[TI][TJ], ci[TI][TJ];  // G3: P1 and P2
+  d4 c3[G3 ? TI : 1][G3 ? TJ : 1];  // G3: P3
   int wm0, wn0, lane;
 
   BSE_DEV void init() {
@@ -41,7 +47,22 @@ struct ZTile {
       for (int j = 0; j < TJ; ++j) {
         cr[i][j] = d4{0, 0, 0, 0};
         ci[i][j] = d4{0, 0, 0, 0};
+        if constexpr (G3) c3[i][j] = d4{0, 0, 0, 0};
       }
+  }
+
+  // acc (+)= a b for one 16 x 16 x 4 slice of tile (i, j)
+  BSE_DEV void mac(int i, int j, double ar, double ai, double nai, double br, double bi) {
+    if constexpr (G3) {
+      cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr[i][j], 0, 0, 0);
+      ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, ci[i][j], 0, 0, 0);
+      c3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, br + bi, c3[i][j], 0, 0, 0);
+    } else {
+      cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr[i][j], 0, 0, 0);
+      cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bi, cr[i][j], 0, 0, 0);
+      ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci[i][j], 0, 0, 0);
+      ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci[i][j], 0, 0, 0);
+    }
   }
 
   // loadA(mm, k) / loadB(k, nn): element of the operand at tile-local row mm
@@ -85,12 +106,7 @@ struct ZTile {
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
-          for (int j = 0; j < TJ; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
-            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
-          }
+          for (int j = 0; j < TJ; ++j) mac(i, j, ar[i], ai[i], nai[i], br[j], bi[j]);
       }
       __syncthreads();
     }
@@ -189,12 +205,7 @@ struct ZTile {
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < TJ; ++j) mac(i, j, ar[i], ai[i], nai[i], br[j], bi[j]);
     }
   }
 
@@ -207,7 +218,13 @@ struct ZTile {
       for (int j = 0; j < TJ; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          st(wm0 + i * 16 + (lane >> 4) + 4 * r, wn0 + j * 16 + (lane & 15),
-             make_double2(cr[i][j][r], ci[i][j][r]));
+        {
+          double2 v;
+          if constexpr (G3)
+            v = make_double2(cr[i][j][r] - ci[i][j][r], c3[i][j][r] - cr[i][j][r] - ci[i][j][r]);
+          else
+            v = make_double2(cr[i][j][r], ci[i][j][r]);
+          st(wm0 + i * 16 + (lane >> 4) + 4 * r, wn0 + j * 16 + (lane & 15), v);
+        }
   }
 };

@@ -31,6 +31,9 @@ struct ZgemmParams {
   const int32_t* info = nullptr;   // skip all work when *info != 0
   const char* tag = "zgemm";        // name under which the launch is timed
   int tile = 0;                     // 16, 32 or 64: tile edge; 0: chosen from the shape
+  int products = 0;                 // real MFMA products per complex one on 16- and 32-edge
+                                    // tiles: 3 (Gauss) or 4; 0: the tuning table's choice
+                                    // (default 3); 64-edge tiles always take 4
 };
 
 // Enqueue `batch` products on `stream`.

@@ -1,4 +1,5 @@
 // Strided / batched complex FP64 GEMM on MFMA (see zgemm.h).
+#include "bse_internal.h"
 #include "common.h"
 #include "mfma_tile.h"
 #include "timing.h"
@@ -6,9 +7,9 @@
 
 namespace {
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool G3>
 __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b_off) {
-  using T = ZTile<BM, BN, WM, WN>;
+  using T = ZTile<BM, BN, WM, WN, G3>;
   __shared__ typename T::Smem2 sm;
   if (failed(p.info)) return;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
   });
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool G3>
 hipError_t launch(const ZgemmParams& p, int batch, hipStream_t s) {
   TimedLaunch tl(p.tag, s);
   // a timed product spans its first and last chunk of at most 65535 batch entries
@@ -86,24 +87,40 @@ hipError_t launch(const ZgemmParams& p, int batch, hipStream_t s) {
     dim3 grid(cdiv(p.M, BM), cdiv(p.N, BN), nb);
     const bool first = b0 == 0, last = b0 + nb >= batch;
     if (tl.a)
-      hipExtLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s,
+      hipExtLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN, G3>), grid, dim3(WM * WN * 64), 0, s,
                             first ? tl.a : nullptr, last ? tl.b : nullptr, 0, p, b0);
     else
-      hipLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, p, b0);
+      hipLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN, G3>), grid, dim3(WM * WN * 64), 0, s, p, b0);
     launch_check(p.tag);
   }
   return hipGetLastError();
 }
 
+// Tile edge: the caller's choice, else from the shape.
+int tile_edge(const ZgemmParams& p, int batch) {
+  if (p.tile == 16 || p.tile == 32 || p.tile == 64) return p.tile;
+  if (p.M <= 16 && p.N <= 16) return 16;
+  if (p.M <= 32 || p.N <= 32 || (int64_t)cdiv(p.M, 64) * cdiv(p.N, 64) * batch < 512) return 32;
+  return 64;
+}
+
 }  // namespace
 
+// Gauss's three products take a third more accumulators; measured at N = 6144
+// they pay on the 16- and 32-edge tiles (Householder and Cholesky updates,
+// exchange) and lose on the 64-edge tile, whose four-product form is kept.
 hipError_t zgemm(const ZgemmParams& p, int batch, hipStream_t s) {
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
-  if (p.tile == 16) return launch<16, 16, 1, 1>(p, batch, s);
-  if (p.tile == 32) return launch<32, 32, 2, 2>(p, batch, s);
-  if (p.tile == 64) return launch<64, 64, 2, 2>(p, batch, s);
-  if (p.M <= 16 && p.N <= 16) return launch<16, 16, 1, 1>(p, batch, s);
-  if (p.M <= 32 || p.N <= 32 || (int64_t)cdiv(p.M, 64) * cdiv(p.N, 64) * batch < 512)
-    return launch<32, 32, 2, 2>(p, batch, s);
-  return launch<64, 64, 2, 2>(p, batch, s);
+  const int prods = p.products ? p.products
+                               : tune_choice(BSE_TUNE_GEMM_PRODUCTS, std::max(p.M, p.N), 3);
+  switch (tile_edge(p, batch)) {
+    case 16:
+      return prods == 3 ? launch<16, 16, 1, 1, true>(p, batch, s)
+                        : launch<16, 16, 1, 1, false>(p, batch, s);
+    case 32:
+      return prods == 3 ? launch<32, 32, 2, 2, true>(p, batch, s)
+                        : launch<32, 32, 2, 2, false>(p, batch, s);
+    default:
+      return launch<64, 64, 2, 2, false>(p, batch, s);
+  }
 }

@@ -33,3 +33,68 @@ def test_parity_under_forced_tile_choices(name, unit, tile):
     eig = np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min()
     spec = np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max()
     assert eig < 1e-10 and spec < 1e-10, (eig, spec)
+
+
+@pytest.mark.parametrize("choice", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("name", ["mid_full_k4_v3c4_g59", "tda_q0_k4_v2c3_g59",
+                                  "tiny_full_k2_v2c3_g15", "small_full_k3s_v3c4_g27"])
+def test_direct_term_paths(name, choice):
+    """The FP64 direct terms through the two-pass path (choice 0), the three
+    fused variants (1-3) and the three Gauss first products writing T (4-6):
+    the assembled matrices against the oracle (1e-12 of max|H|, sums of
+    <= 2 N_G products) and the same spectrum."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_05575_amd import _lib as L
+    from paper_1904_05575_amd.bse import Problem
+    print(f"[gpu] {name} direct choice {choice}", flush=True)
+    P = Problem(inputs(name))
+    old = L.bse_tune_get()
+    try:
+        L.bse_tune_set([(L.TUNE_SITES["direct"], 1 << 20, choice)])
+        H0, H1 = P.build()
+        P.check_info()
+        r = oracle_run(name)
+        ref0 = r["A"] if r["B"] is None else r["A"] + r["B"]
+        assert np.abs(H0.T.cpu().numpy() - ref0).max() < 1e-12 * np.abs(ref0).max()
+        if r["B"] is not None:
+            ref1 = r["A"] - r["B"]
+            assert np.abs(H1.T.cpu().numpy() - ref1).max() < 1e-12 * np.abs(ref1).max()
+        out = P.run()
+    finally:
+        L.bse_tune_set(old)
+    eig = np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min()
+    spec = np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max()
+    assert eig < 1e-10 and spec < 1e-10, (eig, spec)
+
+
+@pytest.mark.parametrize("products", [3, 4])
+@pytest.mark.parametrize("name", ["mid_full_k4_v3c4_g59", "tda_q0_k4_v2c3_g59"])
+def test_gemm_products(name, products):
+    """Every complex GEMM (exchange, Cholesky, squared form, Householder
+    updates, back-transform) with three (Gauss) or four real products per
+    complex one: eigenvalues and spectrum against the oracle (1e-10), and the
+    eigenvectors through their residual."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_05575_amd import _lib as L
+    from paper_1904_05575_amd.bse import Problem
+    print(f"[gpu] {name} gemm products {products}", flush=True)
+    P = Problem(inputs(name))
+    old = L.bse_tune_get()
+    try:
+        L.bse_tune_set([(L.TUNE_SITES["gemm_products"], 1 << 20, products)])
+        out = P.run(vectors=True)
+    finally:
+        L.bse_tune_set(old)
+    r = oracle_run(name)
+    eig = np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min()
+    spec = np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max()
+    assert eig < 1e-10 and spec < 1e-10, (eig, spec)
+    A, B, E, X = r["A"], r["B"], out["E"], out["XpY"]
+    if B is None:
+        assert np.abs(A @ X - X * E).max() < 1e-11 * E.max()
+    else:
+        assert np.abs((A - B) @ ((A + B) @ X) - X * E ** 2).max() < 1e-10 * E.max() ** 2
