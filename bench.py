@@ -346,6 +346,49 @@ def core_section(name: str) -> dict:
     return out
 
 
+def orbitals_section(name: str, reps: int) -> dict:
+    """Pair elements formed on the device from synthetic orbitals
+    (bse_pair_elements) for a workload of the benchmark's shape, then the FP64
+    build on them; HIP events over `reps` repetitions.  Flops: 8 per complex
+    multiply-add, one per K whose partner K + G (or -K - G) is in the sphere."""
+    import torch
+    from bse_synth import get, make_inputs
+    from paper_1904_05575_amd.bse import Problem, sphere_partners
+    w = get(name)
+    d = make_inputs(w)
+    P = Problem(d)
+    H0, H1 = P.alloc_matrices()
+    P.build(H0, H1)
+    torch.cuda.synchronize()
+    plus, minus = sphere_partners(d["kvec"], d["gvec"])
+    cp, cm = float((plus >= 0).sum()), float((minus >= 0).sum())
+    npairs = w.npairs
+    flop = 8.0 * (npairs * ((w.nv ** 2 + w.nc ** 2) * cp + 2 * w.nv * w.nc * cm)
+                  + w.nk * w.nv * w.nc * cp)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        P.pair_elements()
+    ev[1].record()
+    for _ in range(reps):
+        P.build(H0, H1)
+    ev[2].record()
+    torch.cuda.synchronize()
+    P.check_info()
+    gen_ms = ev[0].elapsed_time(ev[1]) / reps
+    build_ms = ev[1].elapsed_time(ev[2]) / reps
+    out = {"workload": name, "n": w.n, "ng": w.ng, "orbital_plane_waves": w.orbitals,
+           "pair_elements_ms": gen_ms, "pair_elements_gflop": flop / 1e9,
+           "pair_elements_TFLOPs": flop / (gen_ms * 1e-3) / 1e12,
+           "pair_elements_frac_fp64_vector_peak": flop / (gen_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+           "pair_bytes_written": float(sum(P.t[k].numel() * 16 for k in
+                                           ("Mcv", "Mvv", "Mcc", "Ncv", "Nvc"))),
+           "build_on_formed_elements_ms": build_ms}
+    del P, H0, H1
+    torch.cuda.empty_cache()
+    return out
+
+
 def screening_section(w, reps: int) -> dict:
     """Static RPA screening on the workload's mesh and bands: W(q) for every q
     (bse_screening), timed with HIP events over `reps` calls; the two pair
@@ -410,6 +453,8 @@ def main() -> int:
                     help="skip the all-eigenpairs (X+Y, X-Y) steps")
     ap.add_argument("--core", default="core_tda_k8_c2c32_g137",
                     help="core-level workload timed for one step ('' to skip)")
+    ap.add_argument("--orbitals", default="full_orb_k8_v3c4_g113_o113",
+                    help="workload whose pair elements are formed from orbitals ('' to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -580,6 +625,14 @@ def main() -> int:
         torch.cuda.empty_cache()
         out["screening"] = screening_section(w, args.steps)
         print("[bench] screening done", file=sys.stderr, flush=True)
+    if args.orbitals:
+        if "P" in locals():
+            del P, H0, H1
+            torch.cuda.empty_cache()
+        out["pair_elements_from_orbitals"] = orbitals_section(args.orbitals, args.steps)
+        print(f"[bench] pair elements from orbitals: "
+              f"{out['pair_elements_from_orbitals']['pair_elements_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
     if args.core:
         if "P" in locals():
             del P, H0, H1

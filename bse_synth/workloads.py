@@ -150,6 +150,14 @@ TINY = {
 
 
 
+# The benchmark workload's shape with its pair elements formed from orbitals
+# (113 plane waves per orbital), for the on-device generation of the elements.
+FULL_ORB = _add(Workload(
+    name="full_orb_k8_v3c4_g113_o113", mesh=8, nv=3, nc=4, ng=113, coupling="full",
+    nw=4000, wmin=0.0, wmax=10.0, eta=0.05, seed=34, kernel_scale=1.0, orbitals=113,
+    note="Full BSE at Q=0, N=6144, pair elements from synthetic orbitals"))
+
+
 @dataclass(frozen=True)
 class BatchWorkload:
     """Many momentum transfers Q solved as one batch: W(q) and the pair

@@ -234,6 +234,33 @@ bse_status bse_dielectric_tensor(int64_t n, const double* E, int32_t nd, const v
 bse_status bse_loss(int64_t nw, const void* eps, int64_t inc, double vinv, double* loss,
                     double* sqw, hipStream_t stream);
 
+/* ---- Pair elements from orbitals (Sec. 4.1: plane-wave matrix elements
+ * between Bloch states, here with orbitals expanded in plane waves only,
+ * phi_n,k(r) = Omega^-1/2 sum_K C_n,k(K) exp(i (k + K) r); the cell integral
+ * keeps the plane waves whose wave vectors cancel):
+ *   M_mn(k, k', G) = sum_K conj(C_m,k(K)) C_n,k'(K + G)        (q = k' - k)
+ *   N_mn(k, k', G) = sum_K conj(C_m,k(K)) conj(C_n,k'(-K - G)) (q = -k - k')
+ * For every pair p = (ik <= ik') the call forms the bse_inputs arrays
+ *   Mvv[p][v][v'][G] = M_vv'(k, k', G),  Mcc[p][c][c'][G] = M_cc'(k, k', G)
+ *   Ncv[p][c][v'][G] = N_cv'(k, k', G),  Nvc[p][v][c'][G] = N_vc'(k, k', G)
+ *   Mcv[(k nv + v) nc + c][G] = M_vc(k, k, G)        (momentum transfer Q = 0)
+ * (band index v < nv occupied, c the c-th unoccupied band, nv + c in C). */
+typedef struct {
+  int32_t nk, nv, nc, ng; /* k-points, occupied and unoccupied bands, plane waves G */
+  int32_t nkb;            /* plane waves K of each orbital (the sphere) */
+  int32_t coupling;       /* bse_coupling: BSE_FULL forms Ncv and Nvc too */
+} bse_orb_desc;
+
+/* C: complex [nk][nv + nc][nkb] orbital coefficients (occupied bands first);
+ * kpg, mkg: int32 [nkb][ng], position in the sphere of K + G and of -K - G
+ * (-1 when outside; mkg may be NULL in the TDA); outputs: device arrays in the
+ * layouts of bse_inputs (Ncv, Nvc may be NULL in the TDA).  BSE_ERR_ARG for
+ * a bad descriptor, a NULL pointer, or 2 (nv + nc) nkb coefficients beyond
+ * 160 KB of LDS. */
+bse_status bse_pair_elements(const bse_orb_desc* desc, const void* C, const int32_t* kpg,
+                             const int32_t* mkg, void* Mcv, void* Mvv, void* Mcc, void* Ncv,
+                             void* Nvc, hipStream_t stream);
+
 /* ---- Static RPA screening (Sec. 4.2: the RPA dielectric matrix at w = 0 and
  * the screened interaction w_GG'(q) = v_G(q) eps^-1_GG'(q), eq. wggq), the
  * W(q) input of bse_build.  An insulator at zero temperature: f = 1 in the nv

@@ -21,7 +21,7 @@ EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bs
            "bse_transitions", "bse_dielectric_tensor", "bse_loss", "bse_screening_workspace_size",
            "bse_screening", "bse_status_string", "bse_timing_enable", "bse_timing_report",
            "bse_batch_workspace_size", "bse_batch_create", "bse_batch_capture", "bse_batch_run",
-           "bse_batch_destroy", "bse_tune_set", "bse_tune_get", "bse_solve_noalloc")
+           "bse_batch_destroy", "bse_tune_set", "bse_tune_get", "bse_solve_noalloc", "bse_pair_elements")
 NOALLOC_SCRATCH_BYTES = 32 << 20  # BSE_NOALLOC_SCRATCH_BYTES of bse.h
 TUNE_SITES = {"hemv_unit": 0, "gemm_squared": 1, "gemm_potrf": 2, "gemm_her2k": 3,
               "gemm_stage2": 4, "gemm_exchange": 5, "direct": 6, "gemm_products": 7}
@@ -42,6 +42,11 @@ class BseInputs(ctypes.Structure):
                 ("vbar", ctypes.c_void_p), ("qmap", ctypes.c_void_p), ("qramap", ctypes.c_void_p),
                 ("nq", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("mcc_env", ctypes.c_void_p), ("mcc_key", ctypes.c_uint64)]
+
+
+class BseOrbDesc(ctypes.Structure):
+    _fields_ = [("nk", ctypes.c_int32), ("nv", ctypes.c_int32), ("nc", ctypes.c_int32),
+                ("ng", ctypes.c_int32), ("nkb", ctypes.c_int32), ("coupling", ctypes.c_int32)]
 
 
 class BseScreenDesc(ctypes.Structure):
@@ -82,6 +87,9 @@ def lib() -> ctypes.CDLL:
         L.bse_solve_noalloc.argtypes = [ctypes.POINTER(BseDesc), vp, vp, vp, vp, vp, i64, vp, vp,
                                         vp, vp]
         L.bse_solve_noalloc.restype = ctypes.c_int
+        L.bse_pair_elements.argtypes = [ctypes.POINTER(BseOrbDesc), vp, vp, vp, vp, vp, vp, vp,
+                                        vp, vp]
+        L.bse_pair_elements.restype = ctypes.c_int
         L.bse_oscillator.argtypes = [i64, vp, i64, vp, vp, vp]
         L.bse_oscillator.restype = ctypes.c_int
         L.bse_spectrum.argtypes = [i64, vp, vp, dbl, dbl, i64, vp, vp, vp]
@@ -152,6 +160,13 @@ def bse_solve_noalloc(desc: BseDesc, H0: int, H1: int, E: int, XpY: int, XmY: in
     _check(lib().bse_solve_noalloc(ctypes.byref(desc), H0, H1 or None, E, XpY or None,
                                    XmY or None, ldx, probe or None, osc or None, info,
                                    stream or None), "bse_solve_noalloc")
+
+
+def bse_pair_elements(desc: BseOrbDesc, C: int, kpg: int, mkg: int, Mcv: int, Mvv: int,
+                      Mcc: int, Ncv: int, Nvc: int, stream: int) -> None:
+    _check(lib().bse_pair_elements(ctypes.byref(desc), C, kpg, mkg or None, Mcv, Mvv, Mcc,
+                                   Ncv or None, Nvc or None, stream or None),
+           "bse_pair_elements")
 
 
 def bse_oscillator(n: int, XpY: int, ldx: int, probe: int, osc: int, stream: int) -> None:

@@ -55,6 +55,27 @@ def _dev(a: np.ndarray, dtype, device) -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
 
 
+def sphere_partners(kvec: np.ndarray, gvec: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """int32 [NK][NG] tables of bse_pair_elements: position in the orbital
+    sphere of K + G and of -K - G, -1 outside.  Integer vectors are keyed by
+    one integer (each coordinate offset into [0, 2^20)) and searched in the
+    sorted keys of the sphere."""
+    def key(v):
+        v = np.asarray(v, dtype=np.int64) + (1 << 19)
+        return (v[..., 0] << 40) | (v[..., 1] << 20) | v[..., 2]
+    ks = key(kvec)
+    order = np.argsort(ks)
+    sk = ks[order]
+
+    def find(vecs):
+        q = key(vecs)
+        at = np.clip(np.searchsorted(sk, q), 0, len(sk) - 1)
+        return np.where(sk[at] == q, order[at], -1).astype(np.int32)
+    plus = find(kvec[:, None, :] + gvec[None, :, :])
+    minus = find(-kvec[:, None, :] - gvec[None, :, :])
+    return plus, minus
+
+
 class Problem:
     """One BSE problem resident on the GPU."""
 
@@ -73,23 +94,30 @@ class Problem:
         self.t = {
             "eps_v": _dev(inputs["eps_v"], f64, dv),
             "eps_c": _dev(inputs["eps_c"], f64, dv),
-            "Mcv": _dev(inputs["Mcv"], c128, dv),
-            "Mvv": _dev(inputs["Mvv"], c128, dv),
             "W": _dev(inputs["W"], c128, dv),
             "qmap": _dev(inputs["qmap"], torch.int32, dv),
         }
-        if inputs.get("Mcc") is not None:
-            self.t["Mcc"] = _dev(inputs["Mcc"], c128, dv)
-        else:  # drawn in place from an envelope and a key
-            self.t["mcc_env"] = _dev(inputs["mcc_env"], f64, dv)
         if self.full:
-            self.t["Ncv"] = _dev(inputs["Ncv"], c128, dv)
-            self.t["Nvc"] = _dev(inputs["Nvc"], c128, dv)
             self.t["qramap"] = _dev(inputs["qramap"], torch.int32, dv)
+        gq = g_index_of_q(inputs["gvec"], inputs["alat"], w.q)
+        if inputs.get("C") is not None:
+            # pair elements formed on the device from the orbitals
+            self.form_pair_elements(inputs)
+            mcv_gq = self.t["Mcv"][:, gq].cpu().numpy()
+        else:
+            self.t["Mcv"] = _dev(inputs["Mcv"], c128, dv)
+            self.t["Mvv"] = _dev(inputs["Mvv"], c128, dv)
+            if inputs.get("Mcc") is not None:
+                self.t["Mcc"] = _dev(inputs["Mcc"], c128, dv)
+            else:  # drawn in place from an envelope and a key
+                self.t["mcc_env"] = _dev(inputs["mcc_env"], f64, dv)
+            if self.full:
+                self.t["Ncv"] = _dev(inputs["Ncv"], c128, dv)
+                self.t["Nvc"] = _dev(inputs["Nvc"], c128, dv)
+            mcv_gq = inputs["Mcv"][:, gq]
         vbar = coulomb_vbar(inputs["gvec"], inputs["alat"], w.q)
         self.t["vbar"] = _dev(vbar, f64, dv)
-        gq = g_index_of_q(inputs["gvec"], inputs["alat"], w.q)
-        self.t["probe"] = _dev(np.conj(inputs["Mcv"][:, gq]), c128, dv)
+        self.t["probe"] = _dev(np.conj(mcv_gq), c128, dv)
         self.t["omega"] = _dev(inputs["omega"], f64, dv)
         if inputs.get("Dcv") is not None:  # column i = conj(D_{., i}), column-major n x 3
             self.t["dprobe"] = _dev(np.conj(inputs["Dcv"]).T, c128, dv)
@@ -114,6 +142,34 @@ class Problem:
                                     dtype=torch.uint8, device=dv)
         self.ws_solve = torch.empty(max(1, L.bse_workspace_size(self.desc, L.BSE_STAGE_SOLVE)),
                                     dtype=torch.uint8, device=dv)
+
+    def form_pair_elements(self, inputs: dict) -> None:
+        """Mcv, Mvv, Mcc (Ncv, Nvc) on the device from the orbital coefficients
+        (bse_pair_elements); sets self.t and keeps C and the partner tables."""
+        w = inputs["workload"]
+        dv, c128 = self.device, torch.complex128
+        P = w.nk * (w.nk + 1) // 2
+        plus, minus = sphere_partners(inputs["kvec"], inputs["gvec"])
+        t = self.t
+        t["C"] = _dev(inputs["C"], c128, dv)
+        t["kpg"] = _dev(plus, torch.int32, dv)
+        t["mkg"] = _dev(minus, torch.int32, dv)
+        t["Mcv"] = torch.empty((self.n, w.ng), dtype=c128, device=dv)
+        t["Mvv"] = torch.empty((P, w.nv, w.nv, w.ng), dtype=c128, device=dv)
+        t["Mcc"] = torch.empty((P, w.nc, w.nc, w.ng), dtype=c128, device=dv)
+        if self.full:
+            t["Ncv"] = torch.empty((P, w.nc, w.nv, w.ng), dtype=c128, device=dv)
+            t["Nvc"] = torch.empty((P, w.nv, w.nc, w.ng), dtype=c128, device=dv)
+        self.orb_desc = L.BseOrbDesc(nk=w.nk, nv=w.nv, nc=w.nc, ng=w.ng, nkb=w.orbitals,
+                                     coupling=L.BSE_FULL if self.full else L.BSE_TDA)
+        self.pair_elements()
+
+    def pair_elements(self) -> None:
+        """Form the pair elements again from the resident orbitals (enqueued)."""
+        t = self.t
+        p = lambda k: t[k].data_ptr() if k in t else 0  # noqa: E731
+        L.bse_pair_elements(self.orb_desc, p("C"), p("kpg"), p("mkg"), p("Mcv"), p("Mvv"),
+                            p("Mcc"), p("Ncv"), p("Nvc"), self.stream())
 
     def set_precision(self, precision: str) -> None:
         """Switch the arithmetic of the assembly (same inputs and workspaces)."""

@@ -130,3 +130,14 @@ def test_orbital_workloads_are_positive_definite(name):
     mats = [A] if B is None else [A - B, A + B]
     for Mx in mats:
         assert np.linalg.eigvalsh(0.5 * (Mx + Mx.conj().T)).min() > 0.1 * E.min()
+
+
+def test_device_partner_tables_match_oracle():
+    """The product's host-side partner tables (Problem's bse_pair_elements
+    input, built by key search) equal the oracle's lookups."""
+    from paper_1904_05575_amd.bse import sphere_partners
+    for nkv, ng in ((27, 15), (113, 113), (169, 59)):
+        kvec, gvec = lattice.gvectors(nkv), lattice.gvectors(ng)
+        plus, minus = sphere_partners(kvec, gvec)
+        assert np.array_equal(plus.T, OR.partner(kvec, gvec, False))
+        assert np.array_equal(minus.T, OR.partner(kvec, gvec, True))
