@@ -120,6 +120,14 @@ TINY = {
     "mid_full": _add(Workload(name="mid_full_k4_v3c4_g59", mesh=4, nv=3, nc=4, ng=59,
                               coupling="full", nw=1000, wmin=0.0, wmax=10.0, eta=0.05,
                               seed=14, kernel_scale=0.0625)),
+    # N_G = 113 (the benchmark's) and 51: one and three plane waves past a
+    # multiple of 16, one and three past a multiple of 4
+    "small_full_g113": _add(Workload(name="small_full_k3_v3c4_g113", mesh=3, nv=3, nc=4, ng=113,
+                                     coupling="full", nw=500, wmin=0.0, wmax=10.0, eta=0.05,
+                                     seed=41, kernel_scale=0.03125)),
+    "tiny_full_g51": _add(Workload(name="tiny_full_k2_v2c3_g51", mesh=2, nv=2, nc=3, ng=51,
+                                   coupling="full", nw=200, wmin=0.0, wmax=10.0, eta=0.05,
+                                   seed=42, kernel_scale=0.015625)),
     # the core-level structure (flat core levels, Gaussian Mcv, Mcc drawn in
     # place) at sizes the oracle solves whole
     "tiny_core": _add(Workload(name="tiny_core_k2_c2c6_g27", mesh=2, nv=2, nc=6, ng=27,

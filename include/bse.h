@@ -360,7 +360,13 @@ int64_t bse_timing_report(char* buf, int64_t len);
  *                          block of 64 rows (wavefront tiles 16 x 32, 16 x 64,
  *                          32 x 32), the first product in three real products
  *                          per complex one; 4, 5, 6 that first product (same
- *                          three shapes) writing T, then the two-pass rest
+ *                          three shapes) writing T, then the two-pass rest;
+ *                          7, 8 the first product with N_G unpadded (up to
+ *                          3 trailing columns and k on the vector ALU; 64
+ *                          rows per block on 4 wavefronts; operands through
+ *                          registers or copied straight into LDS) writing T,
+ *                          then the two-pass rest (FP64, N_G <= 113; else 4).
+ *                          Default 7
  *   BSE_TUNE_GEMM_PRODUCTS size = the larger output dimension of a complex GEMM;
  *                          choice = real matrix-core products per complex one
  *                          on 16- and 32-edge tiles: 4 (re = ar br - ai bi,

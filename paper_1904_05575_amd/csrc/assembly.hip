@@ -359,10 +359,11 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
 
   const int prec = d->prec;
   const int nterms = d->split_terms == 0 ? 6 : d->split_terms;
-  // default 4: the Gauss first product writing T, then the batched second
-  // product (measured at N = 6144: 5.8 + 2.5 ms against 7.0 + 2.5 ms on the
-  // real view and 10.8 ms fused, whose vector-ALU second product waits on memory)
-  const int dvar = tune_choice(BSE_TUNE_DIRECT, n, 4);
+  // default 7: the unpadded Gauss first product writing T, then the batched
+  // second product (measured at N = 6144: 5.4 + 2.4 ms, against 5.7 + 2.4 ms
+  // with N_G padded to 128, 7.0 + 2.4 ms on the real view and 10.8 ms fused,
+  // whose vector-ALU second product waits on memory); N_G > 113 and FP32 take 4
+  const int dvar = tune_choice(BSE_TUNE_DIRECT, n, 7);
   const bool shape_ok = (prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32) && in->Mcc &&
                         ng <= 128 && R1 <= 64 && (!full || R2 <= 64);
   const bool use_fused = shape_ok && dvar >= 1 && dvar <= 3;
@@ -407,10 +408,15 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   // direct terms, stage 1 (grouped by class) and stage 2 (batched by pair)
   auto direct = [&](const void* left, int R, const void* right, int N2, const int32_t* perm,
                     const int32_t* cls, double2* T, double2* blk) -> bool {
-    if (use_g3_t) {
-      if (!launch_direct_fused(prec, dvar - 3, (const double2*)left, (const double2*)right, R, N2,
-                               ng, nk, nv, nc, (const double2*)in->W, perm, cls, nq, 0, 0.0,
-                               nullptr, nullptr, 0, T, info, s))
+    if (use_g3_t && dvar >= 7 && prec == BSE_PREC_FP64 && first_product_fits(ng, R)) {
+      if (!launch_first_product(dvar - 7, (const double2*)left, R, ng, nk, (const double2*)in->W,
+                                perm, cls, nq, T, info, s))
+        return false;
+    } else if (use_g3_t) {
+      if (!launch_direct_fused(prec, dvar >= 7 ? 1 : dvar - 3, (const double2*)left,
+                               (const double2*)right, R, N2, ng, nk, nv, nc,
+                               (const double2*)in->W, perm, cls, nq, 0, 0.0, nullptr, nullptr, 0,
+                               T, info, s))
         return false;
     } else if (prec != BSE_PREC_FP64) {
       // stage 1 in the precision form; stage 2 (R x ng x N2 per pair, memory-bound)

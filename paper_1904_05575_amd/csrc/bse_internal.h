@@ -52,6 +52,10 @@ bool launch_stage1(const double2* left, int R, int ng, const double2* W, const i
 
 // direct.hip: both direct-term contractions in one pass, added into the
 // outputs (false: shape not handled, nothing launched)
+bool first_product_fits(int ng, int R);
+bool launch_first_product(int shape, const double2* left, int R, int ng, int nk,
+                          const double2* W, const int32_t* perm, const int32_t* cls, int nq,
+                          double2* Tout, const int32_t* info, hipStream_t s);
 bool launch_direct_fused(int prec, int variant, const double2* left, const double2* right, int R,
                          int N2, int ng, int nk, int nv, int nc, const double2* W,
                          const int32_t* perm, const int32_t* cls, int nq, int ra, double coef,

@@ -421,6 +421,446 @@ void dispatch(int variant, const double2* left, const double2* right, int R, int
 #undef BSE_DIRECT_ARGS
 }
 
+// ---- First product alone, T = conj(L) W(q), with no padding of N_G on the
+// matrix cores.  A block takes 64 consecutive rows of its class (pairs may
+// straddle blocks: T's rows are independent), so no row slot is left empty
+// except at the end of a class, and all N_G columns: NCT 16-column tiles on
+// the matrix cores (Gauss's three real products), the columns past 16 NCT (VC,
+// at most 3) and the k past the last multiple of 4 (at most 3) on the vector
+// ALU.  4 wavefronts, wavefront w taking row tile w across all NCT column
+// tiles (7 x 3 accumulator tiles at N_G = 113, so two wavefronts per SIMD, one
+// from each of two blocks); the next chunk of operands is in flight in
+// registers while one is multiplied.  (Dealing the tiles of one class to one
+// XCD, for W(q) to stay in its L2, was measured slower: the blocks are
+// handed out in order, and XCDs that finish their tiles early wait for the
+// others.)
+constexpr int FP_BM = 64;
+constexpr int FP_BK = 8;
+
+template <int NCT>
+struct FpSmem {
+  static constexpr int BW = NCT * 16 + 4;  // staged W columns
+  double a_re[2][FP_BK][FP_BM + 2], a_im[2][FP_BK][FP_BM + 2];  // conj(L), [k][row]
+  double b_re[2][FP_BK][BW + 2], b_im[2][FP_BK][BW + 2];        // W, [k][column]
+  double2 ltail[3][FP_BM];                                      // conj(L[m][KF + t])
+  double2 wtail[3][BW];                                         // W[KF + t][n]
+  double2 vpart[4][FP_BM][3];                                   // vector-ALU columns, per k quarter
+};
+
+template <int NCT, int VC>
+__global__ __launch_bounds__(256, 2) void k_first_product(
+    const double2* __restrict__ Left, int R, int ng, const double2* __restrict__ W,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ cls, int nq, int spc,
+    double2* __restrict__ Tout, const int32_t* info) {
+  using S = FpSmem<NCT>;
+  constexpr int BW = S::BW;
+  constexpr int NA = FP_BM * FP_BK / 256;
+  constexpr int NB = (FP_BK * BW + 255) / 256;
+  __shared__ S sm;
+  if (failed(info)) return;
+  const int q = blockIdx.x / spc, sl = blockIdx.x % spc;
+  if (q >= nq) return;
+  const int s0 = cls[q], nr = (cls[q + 1] - s0) * R;
+  const int m0 = sl * FP_BM;
+  if (m0 >= nr) return;
+  const int rows = min(FP_BM, nr - m0);
+  const int KF = ng & ~3, remk = ng & 3;
+  const double2* __restrict__ Wq = W + (int64_t)q * ng * ng;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = wid * 16;
+
+  auto row_ptr = [&](int mm) {
+    const int gm = m0 + mm, pos = gm / R;
+    return Left + ((int64_t)perm[s0 + pos] * R + (gm - pos * R)) * ng;
+  };
+  const double2* arow[NA];
+  bool aok[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int mm = (tid + 256 * u) >> 3;
+    aok[u] = mm < rows;
+    arow[u] = row_ptr(aok[u] ? mm : 0);
+  }
+  // K tail and the W rows it takes
+  for (int e = tid; e < 3 * FP_BM; e += 256) {
+    const int t = e / FP_BM, mm = e % FP_BM;
+    double2 v = make_double2(0.0, 0.0);
+    if (t < remk && mm < rows) v = row_ptr(mm)[KF + t];
+    sm.ltail[t][mm] = make_double2(v.x, -v.y);
+  }
+  for (int e = tid; e < 3 * BW; e += 256) {
+    const int t = e / BW, n = e % BW;
+    sm.wtail[t][n] = (t < remk && n < ng) ? Wq[(int64_t)(KF + t) * ng + n] : make_double2(0.0, 0.0);
+  }
+
+  double2 ra[NA], rb[NB];  // the next chunk
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int k = k0 + ((tid + 256 * u) & 7);
+      ra[u] = arow[u][k < KF ? k : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + 256 * u;
+      const int kk = e / BW, n = e % BW;
+      const int k = k0 + kk;
+      rb[u] = Wq[(int64_t)(k < KF ? k : 0) * ng + (n < ng ? n : 0)];
+    }
+  };
+  auto put = [&](int buf, int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + 256 * u;
+      const int mm = e >> 3, kk = e & 7;
+      const bool ok = aok[u] && k0 + kk < KF;
+      sm.a_re[buf][kk][mm] = ok ? ra[u].x : 0.0;
+      sm.a_im[buf][kk][mm] = ok ? -ra[u].y : 0.0;  // conj(L)
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + 256 * u;
+      if (e < FP_BK * BW) {
+        const int kk = e / BW, n = e % BW;
+        const bool ok = k0 + kk < KF && n < ng;
+        sm.b_re[buf][kk][n] = ok ? rb[u].x : 0.0;
+        sm.b_im[buf][kk][n] = ok ? rb[u].y : 0.0;
+      }
+    }
+  };
+  d4 p1[NCT], p2[NCT], p3[NCT];
+#pragma unroll
+  for (int j = 0; j < NCT; ++j) p1[j] = p2[j] = p3[j] = d4{0, 0, 0, 0};
+  // vector-ALU columns 16 NCT + c: thread (row lane, k quarter wid)
+  double2 vacc[VC > 0 ? VC : 1];
+#pragma unroll
+  for (int c = 0; c < (VC > 0 ? VC : 1); ++c) vacc[c] = make_double2(0.0, 0.0);
+  auto mma = [&](int buf, int k0) {
+#pragma unroll
+    for (int ks = 0; ks < FP_BK / 4; ++ks) {
+      if (k0 + ks * 4 < KF) {
+        const int kr = ks * 4 + (lane >> 4);
+        const double ar = sm.a_re[buf][kr][wm0 + (lane & 15)];
+        const double ai = sm.a_im[buf][kr][wm0 + (lane & 15)];
+        const double as = ar + ai;
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) {
+          const int n = j * 16 + (lane & 15);
+          const double br = sm.b_re[buf][kr][n];
+          const double bi = sm.b_im[buf][kr][n];
+          p1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, p1[j], 0, 0, 0);
+          p2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, p2[j], 0, 0, 0);
+          p3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, br + bi, p3[j], 0, 0, 0);
+        }
+      }
+    }
+    if constexpr (VC > 0) {
+#pragma unroll
+      for (int kq = 0; kq < 2; ++kq) {
+        const int kk = wid * 2 + kq;
+        const double xr = sm.a_re[buf][kk][lane], xi = sm.a_im[buf][kk][lane];
+#pragma unroll
+        for (int c = 0; c < VC; ++c) {
+          const double yr = sm.b_re[buf][kk][16 * NCT + c], yi = sm.b_im[buf][kk][16 * NCT + c];
+          vacc[c].x = fma(xr, yr, fma(-xi, yi, vacc[c].x));
+          vacc[c].y = fma(xr, yi, fma(xi, yr, vacc[c].y));
+        }
+      }
+    }
+  };
+  const int nch = (KF + FP_BK - 1) / FP_BK;
+  if (nch > 0) {
+    fetch(0);
+    put(0, 0);
+    if (nch > 1) fetch(FP_BK);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    mma(ch & 1, ch * FP_BK);
+    if (ch + 1 < nch) put((ch + 1) & 1, (ch + 1) * FP_BK);
+    __syncthreads();
+    if (ch + 2 < nch) fetch((ch + 2) * FP_BK);
+  }
+
+  double2* __restrict__ Tq = Tout + ((int64_t)s0 * R + m0) * ng;
+  if constexpr (VC > 0) {
+#pragma unroll
+    for (int c = 0; c < VC; ++c) sm.vpart[wid][lane][c] = vacc[c];
+  }
+  // matrix-core columns: T = P1 - P2 + i (P3 - P1 - P2), plus the K tail
+#pragma unroll
+  for (int j = 0; j < NCT; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = wm0 + (lane >> 4) + 4 * r, n = j * 16 + (lane & 15);
+      double2 v = make_double2(p1[j][r] - p2[j][r], p3[j][r] - p1[j][r] - p2[j][r]);
+      for (int t = 0; t < remk; ++t) v = cadd(v, cmul(sm.ltail[t][m], sm.wtail[t][n]));
+      if (m < rows && n < ng) Tq[(int64_t)m * ng + n] = v;
+    }
+  if constexpr (VC > 0) {
+    __syncthreads();
+    if (tid < FP_BM * VC) {
+      const int m = tid & 63, c = tid >> 6;
+      double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq) v = cadd(v, sm.vpart[kq][m][c]);
+      for (int t = 0; t < remk; ++t) v = cadd(v, cmul(sm.ltail[t][m], sm.wtail[t][16 * NCT + c]));
+      if (m < rows) Tq[(int64_t)m * ng + 16 * NCT + c] = v;
+    }
+  }
+}
+
+template <int NCT, int VC>
+void launch_fp(const double2* left, int R, int ng, int nk, const double2* W, const int32_t* perm,
+               const int32_t* cls, int nq, double2* Tout, const int32_t* info, hipStream_t s) {
+  const int spc = (int)cdiv((int64_t)nk * R, FP_BM);  // a class holds at most nk pairs
+  BSE_LAUNCH((k_first_product<NCT, VC>), dim3((unsigned)((int64_t)nq * spc)), dim3(256), 0, s,
+             left, R, ng, W, perm, cls, nq, spc, Tout, info);
+}
+
+// ---- The same product with the operand chunks copied from memory straight
+// into LDS (global_load_lds, 16 bytes per lane: lane l's bytes land at the
+// instruction's LDS base + 16 l), FP_NS chunks in flight, so that no register
+// holds a chunk in transit.  4 wavefronts, each one 16-row tile across the NCT
+// column tiles.  Layout of a chunk in LDS:
+//  * L: 8 blocks of 8 rows x 8 k, slot(row, k) = 64 (row / 8) + 8 (row % 8) +
+//    (k ^ row % 8): one load instruction fills a block (each row's 8 k are 128
+//    contiguous bytes in memory), and the 16 rows x 1 k a matrix-core operand
+//    takes hit distinct banks;
+//  * W: [k][n] over the 16 NCT matrix-core columns.
+// The conjugate of L is folded into the products: with Q2 = sum Li Wi and
+// P3 = sum (Lr - Li)(Wr + Wi), T = P1 + Q2 + i (P3 - P1 + Q2).
+constexpr int FP_NS = 3;
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int NCT>
+struct Fp2Smem {
+  static constexpr int BN = NCT * 16;
+  double2 a[FP_NS][FP_BM * FP_BK];
+  double2 b[FP_NS][FP_BK * BN];
+  double2 wcol[116][3];        // W[k][16 NCT + c]: the vector-ALU columns, all k
+  double2 ltail[3][FP_BM];     // conj(L[m][KF + t])
+};
+
+template <int N>
+BSE_DEV void wait_vmcnt() {  // s_waitcnt vmcnt(N), other counters untouched
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// The compiler cannot tell which LDS bytes a copy in flight writes, so its own
+// LDS reads and barriers wait for every copy (vmcnt(0)), which would stall each
+// chunk on the loads of the chunks behind it.  Reads of the chunk buffers and
+// the barrier between chunks are therefore written out, each read block ending
+// with its own wait; the vmcnt waits are explicit (wait_vmcnt).
+typedef double d2v __attribute__((ext_vector_type(2)));
+BSE_DEV unsigned lds_off(const void* p) { return (unsigned)(uintptr_t)p; }  // low 32 bits
+BSE_DEV void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+BSE_DEV d2v lds_read1(unsigned a) {
+  d2v x;
+  asm volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(x) : "v"(a) : "memory");
+  return x;
+}
+// x at ax; y[j] at ab + 256 j (the seven 16-column tiles of one k).  The
+// outputs are early-clobber: a read's destination must not be an address
+// register that a later read of the block still takes.
+BSE_DEV void lds_read_x_y7(d2v& x, d2v (&y)[7], unsigned ax, unsigned ab) {
+  asm volatile(
+      "ds_read_b128 %0, %8\n\t"
+      "ds_read_b128 %1, %9\n\t"
+      "ds_read_b128 %2, %9 offset:256\n\t"
+      "ds_read_b128 %3, %9 offset:512\n\t"
+      "ds_read_b128 %4, %9 offset:768\n\t"
+      "ds_read_b128 %5, %9 offset:1024\n\t"
+      "ds_read_b128 %6, %9 offset:1280\n\t"
+      "ds_read_b128 %7, %9 offset:1536\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x), "=&v"(y[0]), "=&v"(y[1]), "=&v"(y[2]), "=&v"(y[3]), "=&v"(y[4]), "=&v"(y[5]),
+        "=&v"(y[6])
+      : "v"(ax), "v"(ab)
+      : "memory");
+}
+
+template <int NCT, int VC>
+__global__ __launch_bounds__(256, 2) void k_first_product2(
+    const double2* __restrict__ Left, int R, int ng, const double2* __restrict__ W,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ cls, int nq, int spc,
+    double2* __restrict__ Tout, const int32_t* info) {
+  using S = Fp2Smem<NCT>;
+  constexpr int BN = S::BN;
+  static_assert(NCT <= 7 && FP_NS == 3, "shape");
+  __shared__ S sm;
+  if (failed(info)) return;
+  const int q = blockIdx.x / spc, sl = blockIdx.x % spc;
+  if (q >= nq) return;
+  const int s0 = cls[q], nr = (cls[q + 1] - s0) * R;
+  const int m0 = sl * FP_BM;
+  if (m0 >= nr) return;
+  const int rows = min(FP_BM, nr - m0);
+  const int KF = ng & ~3, remk = ng & 3;
+  const double2* __restrict__ Wq = W + (int64_t)q * ng * ng;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = wid * 16;
+
+  auto row_ptr = [&](int mm) {
+    const int gm = m0 + mm, pos = gm / R;
+    return Left + ((int64_t)perm[s0 + pos] * R + (gm - pos * R)) * ng;
+  };
+  // the two L blocks this wavefront loads: rows 8 (2 wid + i) + lane / 8
+  const double2* arow[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int mm = 8 * (2 * wid + i) + (lane >> 3);
+    arow[i] = row_ptr(mm < rows ? mm : 0);
+  }
+  const int ka = (lane & 7) ^ (lane >> 3);  // k of the chunk this lane loads
+  // vector-ALU columns and the K tail (plain loads, done before any copy to LDS)
+  if constexpr (VC > 0)
+    for (int e = tid; e < ng * VC; e += 256) {
+      const int k = e / VC, c = e % VC;
+      sm.wcol[k][c] = Wq[(int64_t)k * ng + 16 * NCT + c];
+    }
+  for (int e = tid; e < 3 * FP_BM; e += 256) {
+    const int t = e / FP_BM, mm = e % FP_BM;
+    double2 v = make_double2(0.0, 0.0);
+    if (t < remk && mm < rows) v = row_ptr(mm)[KF + t];
+    sm.ltail[t][mm] = make_double2(v.x, -v.y);
+  }
+
+  auto issue = [&](int st, int k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int k = min(k0 + ka, ng - 1);
+      __builtin_amdgcn_global_load_lds((const void*)(arow[i] + k),
+                                       (lds_void_t*)&sm.a[st][(2 * wid + i) * 64], 16, 0, 0);
+    }
+    // W: the chunk's FP_BK x BN slots in 64-slot pieces, piece i on wavefront
+    // i % 4.  Every lane of a copy loads: copies with some lanes switched off
+    // (one per row, the row's tail masked) left parts of W unwritten in LDS
+    // once a row took two copies.
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = wid + 4 * t;
+      if (i < 2 * NCT) {  // wave-uniform; every lane of a piece loads
+        const int e = 64 * i + lane, kk = e / BN, n = e % BN;
+        const int kr = min(k0 + kk, ng - 1);
+        __builtin_amdgcn_global_load_lds((const void*)(Wq + (int64_t)kr * ng + n),
+                                         (lds_void_t*)&sm.b[st][64 * i], 16, 0, 0);
+      }
+    }
+  };
+  // load instructions of one chunk on this wavefront: 2 of L, nbw of W
+  const int nbw = (2 * NCT - wid + 3) / 4;
+
+  d4 p1[NCT], p2[NCT], p3[NCT];
+#pragma unroll
+  for (int j = 0; j < NCT; ++j) p1[j] = p2[j] = p3[j] = d4{0, 0, 0, 0};
+  double2 vacc[VC > 0 ? VC : 1];
+#pragma unroll
+  for (int c = 0; c < (VC > 0 ? VC : 1); ++c) vacc[c] = make_double2(0.0, 0.0);
+  auto mma = [&](int st, int k0) {
+#pragma unroll
+    for (int ks = 0; ks < FP_BK / 4; ++ks) {
+      if (k0 + ks * 4 < KF) {
+        const int k = ks * 4 + (lane >> 4), row = wm0 + (lane & 15);
+        const unsigned ax = lds_off(&sm.a[st][(row >> 3) * 64 + (row & 7) * 8 + (k ^ (row & 7))]);
+        const unsigned ab = lds_off(&sm.b[st][k * BN + (lane & 15)]);
+        d2v x, y[NCT];
+        if constexpr (NCT == 7) {
+          lds_read_x_y7(x, y, ax, ab);
+        } else {
+          x = lds_read1(ax);
+#pragma unroll
+          for (int j = 0; j < NCT; ++j) y[j] = lds_read1(ab + 256 * j);
+        }
+        const double xs = x[0] - x[1];
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) {
+          p1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0], y[j][0], p1[j], 0, 0, 0);
+          p2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1], y[j][1], p2[j], 0, 0, 0);
+          p3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, y[j][0] + y[j][1], p3[j], 0, 0, 0);
+        }
+      }
+    }
+    if constexpr (VC > 0) {
+#pragma unroll
+      for (int kq = 0; kq < 2; ++kq) {
+        const int kk = 2 * wid + kq;
+        if (k0 + kk < KF) {
+          const d2v xv =
+              lds_read1(lds_off(&sm.a[st][(lane >> 3) * 64 + (lane & 7) * 8 + (kk ^ (lane & 7))]));
+          const double2 x = make_double2(xv[0], xv[1]);
+#pragma unroll
+          for (int c = 0; c < VC; ++c) {
+            const d2v yv = lds_read1(lds_off(&sm.wcol[k0 + kk][c]));
+            const double2 y = make_double2(yv[0], yv[1]);
+            vacc[c].x = fma(x.x, y.x, fma(x.y, y.y, vacc[c].x));   // conj(x) y
+            vacc[c].y = fma(x.x, y.y, fma(-x.y, y.x, vacc[c].y));
+          }
+        }
+      }
+    }
+  };
+
+  const int nch = (KF + FP_BK - 1) / FP_BK;
+  if (nch > 0) issue(0, 0);
+  if (nch > 1) issue(1, FP_BK);
+  for (int ch = 0; ch < nch; ++ch) {
+    if (ch + 1 < nch) {  // chunk ch + 1 may still be in flight
+      if (nbw == 4) wait_vmcnt<6>();
+      else if (nbw == 3) wait_vmcnt<5>();
+      else if (nbw == 2) wait_vmcnt<4>();
+      else if (nbw == 1) wait_vmcnt<3>();
+      else wait_vmcnt<2>();
+    } else {
+      wait_vmcnt<0>();
+    }
+    lds_barrier();  // chunk ch in LDS for every wavefront; chunk ch - 1 no longer read
+    if (ch + 2 < nch) issue((ch + 2) % FP_NS, (ch + 2) * FP_BK);
+    mma(ch % FP_NS, ch * FP_BK);
+  }
+
+  double2* __restrict__ Tq = Tout + ((int64_t)s0 * R + m0) * ng;
+  // matrix-core columns, plus the K tail (W rows from memory)
+#pragma unroll
+  for (int j = 0; j < NCT; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = wm0 + (lane >> 4) + 4 * r, n = j * 16 + (lane & 15);
+      double2 v = make_double2(p1[j][r] + p2[j][r], p3[j][r] - p1[j][r] + p2[j][r]);
+      for (int t = 0; t < remk; ++t)
+        v = cadd(v, cmul(sm.ltail[t][m], Wq[(int64_t)(KF + t) * ng + (n < ng ? n : 0)]));
+      if (m < rows && n < ng) Tq[(int64_t)m * ng + n] = v;
+    }
+  if constexpr (VC > 0) {
+    __syncthreads();  // every wavefront done with the chunk buffers
+    double2(*vpart)[FP_BM][VC] = reinterpret_cast<double2(*)[FP_BM][VC]>(&sm.a[0][0]);
+#pragma unroll
+    for (int c = 0; c < VC; ++c) vpart[wid][lane][c] = vacc[c];
+    __syncthreads();
+    if (tid < FP_BM * VC) {
+      const int m = tid & 63, c = tid >> 6;
+      double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq) v = cadd(v, vpart[kq][m][c]);
+      for (int t = 0; t < remk; ++t)
+        v = cadd(v, cmul(sm.ltail[t][m], Wq[(int64_t)(KF + t) * ng + 16 * NCT + c]));
+      if (m < rows) Tq[(int64_t)m * ng + 16 * NCT + c] = v;
+    }
+  }
+}
+
+template <int NCT, int VC>
+void launch_fp2(const double2* left, int R, int ng, int nk, const double2* W,
+                const int32_t* perm, const int32_t* cls, int nq, double2* Tout,
+                const int32_t* info, hipStream_t s) {
+  const int spc = (int)cdiv((int64_t)nk * R, FP_BM);  // a class holds at most nk pairs
+  BSE_LAUNCH((k_first_product2<NCT, VC>), dim3((unsigned)((int64_t)nq * spc)), dim3(256), 0, s,
+             left, R, ng, W, perm, cls, nq, spc, Tout, info);
+}
+
 }  // namespace
 
 // Returns false when the shape is outside what the fused kernel handles
@@ -439,5 +879,38 @@ bool launch_direct_fused(int prec, int variant, const double2* left, const doubl
                             coef, out0, out1, ld, Tout, info, s);
   else
     return false;
+  return hipGetLastError() == hipSuccess;
+}
+
+// (N_G above 113 would need the eighth column tile, which spills registers)
+bool first_product_fits(int ng, int R) { return ng >= 16 && ng <= 113 && R >= 1; }
+
+// First product alone (FP64), written to Tout in class order (the shape must
+// pass first_product_fits).  shape 0: operands through registers; 1: copied
+// straight into LDS.  Returns false on a launch error.
+bool launch_first_product(int shape, const double2* left, int R, int ng, int nk,
+                          const double2* W, const int32_t* perm, const int32_t* cls, int nq,
+                          double2* Tout, const int32_t* info, hipStream_t s) {
+  if (!first_product_fits(ng, R)) return false;
+  // columns past 16 NCT go to the vector ALU when there are at most 3 of them,
+  // else the last tile is padded
+  const int vc = ng % 16 <= 3 ? ng % 16 : 0;
+  const int nct = vc || ng % 16 == 0 ? ng / 16 : ng / 16 + 1;
+#define BSE_FP2(NCT, VC)                                                                \
+  if (shape == 1) launch_fp2<NCT, VC>(left, R, ng, nk, W, perm, cls, nq, Tout, info, s); \
+  else launch_fp<NCT, VC>(left, R, ng, nk, W, perm, cls, nq, Tout, info, s);
+#define BSE_FP(NCT)                             \
+  case NCT:                                     \
+    if (vc == 0) { BSE_FP2(NCT, 0) }            \
+    else if (vc == 1) { BSE_FP2(NCT, 1) }       \
+    else if (vc == 2) { BSE_FP2(NCT, 2) }       \
+    else { BSE_FP2(NCT, 3) }                    \
+    break;
+  switch (nct) {
+    BSE_FP(1) BSE_FP(2) BSE_FP(3) BSE_FP(4) BSE_FP(5) BSE_FP(6) BSE_FP(7)
+    default: return false;
+  }
+#undef BSE_FP
+#undef BSE_FP2
   return hipGetLastError() == hipSuccess;
 }
