@@ -125,7 +125,7 @@ TINY = {
     "small_full_g113": _add(Workload(name="small_full_k3_v3c4_g113", mesh=3, nv=3, nc=4, ng=113,
                                      coupling="full", nw=500, wmin=0.0, wmax=10.0, eta=0.05,
                                      seed=41, kernel_scale=0.03125)),
-    "tiny_full_g51": _add(Workload(name="tiny_full_k2_v2c3_g51", mesh=2, nv=2, nc=3, ng=51,
+    "tiny_full_g51": _add(Workload(name="tiny_full_k2_v3c4_g51", mesh=2, nv=3, nc=4, ng=51,
                                    coupling="full", nw=200, wmin=0.0, wmax=10.0, eta=0.05,
                                    seed=42, kernel_scale=0.015625)),
     # the core-level structure (flat core levels, Gaussian Mcv, Mcc drawn in

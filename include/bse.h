@@ -365,8 +365,10 @@ int64_t bse_timing_report(char* buf, int64_t len);
  *                          3 trailing columns and k on the vector ALU; 64
  *                          rows per block on 4 wavefronts; operands through
  *                          registers or copied straight into LDS) writing T,
- *                          then the two-pass rest (FP64, N_G <= 113; else 4).
- *                          Default 7
+ *                          then the two-pass rest (FP64, N_G <= 113; else 4);
+ *                          9 (default) one pass per term with both products
+ *                          on the matrix cores (FP64, N_G <= 113, 9 <= R <= 16
+ *                          rows and at most 16 columns per pair block; else 7)
  *   BSE_TUNE_GEMM_PRODUCTS size = the larger output dimension of a complex GEMM;
  *                          choice = real matrix-core products per complex one
  *                          on 16- and 32-edge tiles: 4 (re = ar br - ai bi,

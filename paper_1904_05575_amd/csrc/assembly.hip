@@ -359,15 +359,20 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
 
   const int prec = d->prec;
   const int nterms = d->split_terms == 0 ? 6 : d->split_terms;
-  // default 7: the unpadded Gauss first product writing T, then the batched
-  // second product (measured at N = 6144: 5.4 + 2.4 ms, against 5.7 + 2.4 ms
-  // with N_G padded to 128, 7.0 + 2.4 ms on the real view and 10.8 ms fused,
-  // whose vector-ALU second product waits on memory); N_G > 113 and FP32 take 4
-  const int dvar = tune_choice(BSE_TUNE_DIRECT, n, 7);
+  // default 9: one pass per term with both products on the matrix cores
+  // (measured at N = 6144: 6.8 ms for both terms, against 5.3 + 2.4 + 0.3 ms
+  // for the unpadded first product writing T, the batched second product and
+  // the scatter (7), 5.8 + 2.4 + 0.3 ms with N_G padded to 128 (4), and 10.8 ms
+  // fused with a vector-ALU second product waiting on memory (1)); shapes the
+  // one pass does not take run as 7, and those (N_G > 113, FP32) as 4
+  int dvar = tune_choice(BSE_TUNE_DIRECT, n, 9);
   const bool shape_ok = (prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32) && in->Mcc &&
                         ng <= 128 && R1 <= 64 && (!full || R2 <= 64);
-  const bool use_fused = shape_ok && dvar >= 1 && dvar <= 3;
-  const bool use_g3_t = shape_ok && dvar >= 4;  // Gauss first product, then two passes
+  if (dvar == 9 && !(prec == BSE_PREC_FP64 && first_product_fits(ng, (int)R1) && R1 >= 9 &&
+                     R1 <= 16 && N1 <= 16 && (!full || (R2 >= 9 && R2 <= 16))))
+    dvar = 7;
+  const bool use_fused = shape_ok && ((dvar >= 1 && dvar <= 3) || dvar == 9);
+  const bool use_g3_t = shape_ok && dvar >= 4 && dvar <= 8;  // Gauss first product, then two passes
   // the precision form splits W once per build (the two-pass products read
   // it); its buffer holds nk slices
   if (prec != BSE_PREC_FP64 && !use_fused && !use_g3_t) {
@@ -469,15 +474,24 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   // A-B = c rr; then A+B += c ra, A-B -= c ra), unless the tuning table asks
   // for two passes
   if (use_fused) {
-    bool ok = launch_direct_fused(prec, dvar, (const double2*)in->Mvv, (const double2*)in->Mcc,
-                                  (int)R1, (int)N1, ng, nk, nv, nc, (const double2*)in->W,
-                                  perm_rr, cls_rr, nq, 0, c, (double2*)out0,
-                                  full ? (double2*)out1 : nullptr, ld, nullptr, info, s);
+    // one pass per term: on the matrix cores for both products (9, FP64, when
+    // the shape allows), else the vector-ALU second product (1-3)
+    // (the tile lists of the one pass go where T would be: no T is written)
+    auto term = [&](const void* left, const void* right, int R, int N2, const int32_t* perm,
+                    const int32_t* cls, int ra, double2* o1, void* tmap) -> bool {
+      if (dvar == 9)
+        return launch_direct_onepass((const double2*)left, (const double2*)right, R, N2, ng, nk,
+                                     nv, nc, (const double2*)in->W, perm, cls, nq, ra, c,
+                                     (double2*)out0, o1, ld, (int32_t*)tmap, info, s);
+      return launch_direct_fused(prec, dvar, (const double2*)left,
+                                 (const double2*)right, R, N2, ng, nk, nv, nc,
+                                 (const double2*)in->W, perm, cls, nq, ra, c, (double2*)out0, o1,
+                                 ld, nullptr, info, s);
+    };
+    bool ok = term(in->Mvv, in->Mcc, (int)R1, (int)N1, perm_rr, cls_rr, 0,
+                   full ? (double2*)out1 : nullptr, T_rr);
     if (ok && full)
-      ok = launch_direct_fused(prec, dvar, (const double2*)in->Ncv, (const double2*)in->Nvc,
-                               (int)R2, (int)R2, ng, nk, nv, nc, (const double2*)in->W, perm_ra,
-                               cls_ra, nq, 1, c, (double2*)out0, (double2*)out1, ld, nullptr,
-                               info, s);
+      ok = term(in->Ncv, in->Nvc, (int)R2, (int)R2, perm_ra, cls_ra, 1, (double2*)out1, T_ra);
     if (!ok) return BSE_ERR_HIP;
     const int nt = cdiv(n, FT);
     BSE_LAUNCH(k_finalize, dim3(nt, nt), dim3(256), 0, s, (double2*)out0, n, ld, in->eps_v,

@@ -634,13 +634,24 @@ void launch_fp(const double2* left, int R, int ng, int nk, const double2* W, con
 constexpr int FP_NS = 3;
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+constexpr int DF_MAXP = 7;  // pairs per block in the one-pass form (R >= 9)
+
 template <int NCT>
 struct Fp2Smem {
   static constexpr int BN = NCT * 16;
-  double2 a[FP_NS][FP_BM * FP_BK];
-  double2 b[FP_NS][FP_BK * BN];
-  double2 wcol[116][3];        // W[k][16 NCT + c]: the vector-ALU columns, all k
-  double2 ltail[3][FP_BM];     // conj(L[m][KF + t])
+  union {
+    struct {  // first product
+      double2 a[FP_NS][FP_BM * FP_BK];
+      double2 b[FP_NS][FP_BK * BN];
+      double2 wcol[116][3];  // W[k][16 NCT + c]: the vector-ALU columns, all k
+      double2 ltail[3][FP_BM];  // conj(L[m][KF + t])
+    } s1;
+    struct {  // second product of the one-pass form
+      double2 t[FP_BM][17];            // T of one 16-column phase, [row][g]
+      double2 rt[2][DF_MAXP][256];     // R_p[j][g] of the phase, g swizzled by j
+      double2 dummy[64];
+    } s2;
+  };
 };
 
 template <int N>
@@ -682,22 +693,44 @@ BSE_DEV void lds_read_x_y7(d2v& x, d2v (&y)[7], unsigned ax, unsigned ab) {
       : "memory");
 }
 
-template <int NCT, int VC>
+// FUSED = false: T written to Tout in class order (blocks of 64 rows).
+// FUSED = true: blocks of whole pairs (ppt = 64 / R, R >= 9), and the second
+// product follows on the matrix cores, 16 columns of T at a time: each
+// wavefront puts its T tile of the phase into LDS, the block's pairs' second
+// operands R_p[j][g] of the phase arrive by LDS copies (wavefront w owns pairs
+// w and w + 4, and copies their rows for the next phase while multiplying
+// this one), and blk_p = T_p R_p^T runs as one 16 x 16 Gauss tile per pair
+// (rows r < R, columns j < N2 <= 16).  The blocks are then added into the
+// outputs: out0 += coef blk, and out1 = coef blk (resonant) or out1 -= coef
+// blk (coupling).  T never reaches memory.
+template <int NCT, int VC, bool FUSED>
 __global__ __launch_bounds__(256, 2) void k_first_product2(
     const double2* __restrict__ Left, int R, int ng, const double2* __restrict__ W,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ cls, int nq, int spc,
-    double2* __restrict__ Tout, const int32_t* info) {
+    double2* __restrict__ Tout, const int32_t* info, const double2* __restrict__ Right, int N2,
+    int nk, int nv, int nc, int ra, double coef, double2* __restrict__ out0,
+    double2* __restrict__ out1, int64_t ld, const int32_t* __restrict__ tmap) {
   using S = Fp2Smem<NCT>;
   constexpr int BN = S::BN;
   static_assert(NCT <= 7 && FP_NS == 3, "shape");
   __shared__ S sm;
   if (failed(info)) return;
-  const int q = blockIdx.x / spc, sl = blockIdx.x % spc;
+  int q, sl;
+  if (tmap) {  // the occupied tiles only, class by class
+    const int v = tmap[blockIdx.x];
+    if (v < 0) return;
+    q = v & 8191;
+    sl = v >> 13;
+  } else {
+    q = blockIdx.x / spc;
+    sl = blockIdx.x % spc;
+  }
   if (q >= nq) return;
   const int s0 = cls[q], nr = (cls[q + 1] - s0) * R;
-  const int m0 = sl * FP_BM;
+  const int ppt = FUSED ? FP_BM / R : 0;
+  const int m0 = FUSED ? sl * ppt * R : sl * FP_BM;
   if (m0 >= nr) return;
-  const int rows = min(FP_BM, nr - m0);
+  const int rows = min(FUSED ? ppt * R : FP_BM, nr - m0);
   const int KF = ng & ~3, remk = ng & 3;
   const double2* __restrict__ Wq = W + (int64_t)q * ng * ng;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -720,13 +753,13 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
   if constexpr (VC > 0)
     for (int e = tid; e < ng * VC; e += 256) {
       const int k = e / VC, c = e % VC;
-      sm.wcol[k][c] = Wq[(int64_t)k * ng + 16 * NCT + c];
+      sm.s1.wcol[k][c] = Wq[(int64_t)k * ng + 16 * NCT + c];
     }
   for (int e = tid; e < 3 * FP_BM; e += 256) {
     const int t = e / FP_BM, mm = e % FP_BM;
     double2 v = make_double2(0.0, 0.0);
     if (t < remk && mm < rows) v = row_ptr(mm)[KF + t];
-    sm.ltail[t][mm] = make_double2(v.x, -v.y);
+    sm.s1.ltail[t][mm] = make_double2(v.x, -v.y);
   }
 
   auto issue = [&](int st, int k0) {
@@ -734,7 +767,7 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
     for (int i = 0; i < 2; ++i) {
       const int k = min(k0 + ka, ng - 1);
       __builtin_amdgcn_global_load_lds((const void*)(arow[i] + k),
-                                       (lds_void_t*)&sm.a[st][(2 * wid + i) * 64], 16, 0, 0);
+                                       (lds_void_t*)&sm.s1.a[st][(2 * wid + i) * 64], 16, 0, 0);
     }
     // W: the chunk's FP_BK x BN slots in 64-slot pieces, piece i on wavefront
     // i % 4.  Every lane of a copy loads: copies with some lanes switched off
@@ -747,7 +780,7 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
         const int e = 64 * i + lane, kk = e / BN, n = e % BN;
         const int kr = min(k0 + kk, ng - 1);
         __builtin_amdgcn_global_load_lds((const void*)(Wq + (int64_t)kr * ng + n),
-                                         (lds_void_t*)&sm.b[st][64 * i], 16, 0, 0);
+                                         (lds_void_t*)&sm.s1.b[st][64 * i], 16, 0, 0);
       }
     }
   };
@@ -765,8 +798,9 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
     for (int ks = 0; ks < FP_BK / 4; ++ks) {
       if (k0 + ks * 4 < KF) {
         const int k = ks * 4 + (lane >> 4), row = wm0 + (lane & 15);
-        const unsigned ax = lds_off(&sm.a[st][(row >> 3) * 64 + (row & 7) * 8 + (k ^ (row & 7))]);
-        const unsigned ab = lds_off(&sm.b[st][k * BN + (lane & 15)]);
+        const unsigned ax =
+            lds_off(&sm.s1.a[st][(row >> 3) * 64 + (row & 7) * 8 + (k ^ (row & 7))]);
+        const unsigned ab = lds_off(&sm.s1.b[st][k * BN + (lane & 15)]);
         d2v x, y[NCT];
         if constexpr (NCT == 7) {
           lds_read_x_y7(x, y, ax, ab);
@@ -789,14 +823,14 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
       for (int kq = 0; kq < 2; ++kq) {
         const int kk = 2 * wid + kq;
         if (k0 + kk < KF) {
-          const d2v xv =
-              lds_read1(lds_off(&sm.a[st][(lane >> 3) * 64 + (lane & 7) * 8 + (kk ^ (lane & 7))]));
+          const d2v xv = lds_read1(
+              lds_off(&sm.s1.a[st][(lane >> 3) * 64 + (lane & 7) * 8 + (kk ^ (lane & 7))]));
           const double2 x = make_double2(xv[0], xv[1]);
 #pragma unroll
           for (int c = 0; c < VC; ++c) {
-            const d2v yv = lds_read1(lds_off(&sm.wcol[k0 + kk][c]));
+            const d2v yv = lds_read1(lds_off(&sm.s1.wcol[k0 + kk][c]));
             const double2 y = make_double2(yv[0], yv[1]);
-            vacc[c].x = fma(x.x, y.x, fma(x.y, y.y, vacc[c].x));   // conj(x) y
+            vacc[c].x = fma(x.x, y.x, fma(x.y, y.y, vacc[c].x));  // conj(x) y
             vacc[c].y = fma(x.x, y.y, fma(-x.y, y.x, vacc[c].y));
           }
         }
@@ -822,8 +856,9 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
     mma(ch % FP_NS, ch * FP_BK);
   }
 
-  double2* __restrict__ Tq = Tout + ((int64_t)s0 * R + m0) * ng;
-  // matrix-core columns, plus the K tail (W rows from memory)
+  // T = P1 + Q2 + i (P3 - P1 + Q2) on the matrix-core columns, plus the K tail
+  // (W rows from memory); no copy is in flight from here on
+  double tre[NCT][4], tim[NCT][4];
 #pragma unroll
   for (int j = 0; j < NCT; ++j)
 #pragma unroll
@@ -831,23 +866,167 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
       const int m = wm0 + (lane >> 4) + 4 * r, n = j * 16 + (lane & 15);
       double2 v = make_double2(p1[j][r] + p2[j][r], p3[j][r] - p1[j][r] + p2[j][r]);
       for (int t = 0; t < remk; ++t)
-        v = cadd(v, cmul(sm.ltail[t][m], Wq[(int64_t)(KF + t) * ng + (n < ng ? n : 0)]));
-      if (m < rows && n < ng) Tq[(int64_t)m * ng + n] = v;
+        v = cadd(v, cmul(sm.s1.ltail[t][m], Wq[(int64_t)(KF + t) * ng + (n < ng ? n : 0)]));
+      tre[j][r] = v.x;
+      tim[j][r] = v.y;
     }
+  // vector-ALU columns: the four k parts summed through LDS
+  double2 vcv = make_double2(0.0, 0.0);  // T[tid % 64][16 NCT + tid / 64], tid < 64 VC
   if constexpr (VC > 0) {
-    __syncthreads();  // every wavefront done with the chunk buffers
-    double2(*vpart)[FP_BM][VC] = reinterpret_cast<double2(*)[FP_BM][VC]>(&sm.a[0][0]);
+    __syncthreads();  // every wavefront done with the chunk buffers and ltail
+    double2(*vpart)[FP_BM][VC] = reinterpret_cast<double2(*)[FP_BM][VC]>(&sm.s2.t[0][0]);
+    double2 lt[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) lt[t] = sm.s1.ltail[t][tid & 63];  // zero for t >= remk
+    __syncthreads();
 #pragma unroll
     for (int c = 0; c < VC; ++c) vpart[wid][lane][c] = vacc[c];
     __syncthreads();
     if (tid < FP_BM * VC) {
       const int m = tid & 63, c = tid >> 6;
-      double2 v = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int kq = 0; kq < 4; ++kq) v = cadd(v, vpart[kq][m][c]);
-      for (int t = 0; t < remk; ++t)
-        v = cadd(v, cmul(sm.ltail[t][m], Wq[(int64_t)(KF + t) * ng + 16 * NCT + c]));
-      if (m < rows) Tq[(int64_t)m * ng + 16 * NCT + c] = v;
+      for (int kq = 0; kq < 4; ++kq) vcv = cadd(vcv, vpart[kq][m][c]);
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        if (t < remk) vcv = cadd(vcv, cmul(lt[t], Wq[(int64_t)(KF + t) * ng + 16 * NCT + c]));
+    }
+  }
+
+  if constexpr (!FUSED) {
+    double2* __restrict__ Tq = Tout + ((int64_t)s0 * R + m0) * ng;
+#pragma unroll
+    for (int j = 0; j < NCT; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = wm0 + (lane >> 4) + 4 * r, n = j * 16 + (lane & 15);
+        if (m < rows && n < ng) Tq[(int64_t)m * ng + n] = make_double2(tre[j][r], tim[j][r]);
+      }
+    if constexpr (VC > 0)
+      if (tid < FP_BM * VC && (tid & 63) < rows)
+        Tq[(int64_t)(tid & 63) * ng + 16 * NCT + (tid >> 6)] = vcv;
+  } else {
+    // ---- second product
+    constexpr int NPH = NCT + (VC > 0 ? 1 : 0);
+    const int npb = rows / R;                  // pairs of this block
+    const int nq4 = (N2 + 3) >> 2;             // 4-row pieces of R_p
+    __syncthreads();  // LDS free for the second product (vpart, ltail read)
+    // copies of R_p for phase ph: 8 per wavefront and phase (unused ones land
+    // in `dummy`), so that the waits count a fixed number
+    // the second operands of this wavefront's pairs (loaded here, not between
+    // the copies: a load the copies' addresses wait on would wait for them all)
+    const double2* rbase[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int pp = wid + 4 * u;
+      rbase[u] = pp < npb ? Right + (int64_t)perm[s0 + (m0 / R) + pp] * N2 * ng : Right;
+    }
+    auto issue_rt = [&](int buf, int ph) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int jq = 0; jq < 4; ++jq) {
+          const int pp = wid + 4 * u;
+          const bool real = pp < npb && jq < nq4;  // wave-uniform
+          const int j = min(4 * jq + (lane >> 4), N2 - 1);
+          const int g = min(16 * ph + ((lane & 15) ^ (j & 7)), ng - 1);
+          const double2* src = real ? rbase[u] + (int64_t)j * ng + g : Right;
+          lds_void_t* dst = real ? (lds_void_t*)&sm.s2.rt[buf][pp][64 * jq]
+                                 : (lds_void_t*)&sm.s2.dummy[0];
+          __builtin_amdgcn_global_load_lds((const void*)src, dst, 16, 0, 0);
+        }
+    };
+    d4 q1[2], q2[2], q3[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) q1[u] = q2[u] = q3[u] = d4{0, 0, 0, 0};
+    issue_rt(0, 0);
+#pragma unroll
+    for (int ph = 0; ph < NPH; ++ph) {
+      // this wavefront's copies for the next phase (into the buffer it read
+      // in the previous phase)
+      if (ph + 1 < NPH) issue_rt((ph + 1) & 1, ph + 1);
+      if (ph > 0) lds_barrier();  // T of phase ph - 1 no longer read
+      // T of this phase into LDS (columns past N_G as zeros)
+      if (ph < NCT) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = wm0 + (lane >> 4) + 4 * r, n = 16 * ph + (lane & 15);
+          d2v v;
+          v[0] = n < ng ? tre[ph][r] : 0.0;
+          v[1] = n < ng ? tim[ph][r] : 0.0;
+          asm volatile("ds_write_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)"
+                       ::"v"(lds_off(&sm.s2.t[m][lane & 15])), "v"(v) : "memory");
+        }
+      } else {
+        for (int e = tid; e < FP_BM * 16; e += 256) {
+          const int m = e & 63, c = e >> 6;
+          d2v v;
+          v[0] = 0.0;
+          v[1] = 0.0;
+          if (c < VC && e == tid) { v[0] = vcv.x; v[1] = vcv.y; }  // tid < 64 VC holds column c
+          asm volatile("ds_write_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)"
+                       ::"v"(lds_off(&sm.s2.t[m][c])), "v"(v) : "memory");
+        }
+      }
+      lds_barrier();  // T of phase ph complete
+      if (ph + 1 < NPH) wait_vmcnt<8>();  // this wavefront's copies of phase ph done
+      else wait_vmcnt<0>();
+      const int nks = ph < NCT ? 4 : 1;  // the vector-ALU phase holds at most 3 columns
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int pp = wid + 4 * u;
+        if (pp < npb) {  // wave-uniform
+          const int r = lane & 15, j = lane & 15;
+          const int trow = min(pp * R + r, FP_BM - 1);  // rows r >= R are not stored
+          for (int ks = 0; ks < nks; ++ks) {
+            const int g = 4 * ks + (lane >> 4);
+            const d2v a = lds_read1(lds_off(&sm.s2.t[trow][g]));
+            const d2v bv = lds_read1(lds_off(&sm.s2.rt[ph & 1][pp][j * 16 + (g ^ (j & 7))]));
+            q1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], bv[0], q1[u], 0, 0, 0);
+            q2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], bv[1], q2[u], 0, 0, 0);
+            q3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0] + a[1], bv[0] + bv[1], q3[u], 0,
+                                                         0, 0);
+          }
+        }
+      }
+    }
+    // add the blocks into the outputs: entry (r, j) of pair p; resonant rows
+    // r = (v, v'), columns j = (c, c'); coupling rows r = (c, v'), j = (v, c')
+    const int nvnc = nv * nc;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int pp = wid + 4 * u;
+      if (pp >= npb) continue;
+      const int p = perm[s0 + (m0 / R) + pp];
+      const int ik = pair_row(p, nk);
+      const int jk = ik + (int)(p - ((int64_t)ik * nk - (int64_t)ik * (ik - 1) / 2));
+      const int jj = lane & 15;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = (lane >> 4) + 4 * i;
+        if (rr >= R || jj >= N2) continue;
+        int v, c, v2, c2;
+        if (!ra) {
+          v = rr / nv; v2 = rr % nv; c = jj / nc; c2 = jj % nc;
+        } else {
+          c = rr / nv; v2 = rr % nv; v = jj / nc; c2 = jj % nc;
+        }
+        const int64_t row = (int64_t)ik * nvnc + v * nc + c;
+        const int64_t col = (int64_t)jk * nvnc + v2 * nc + c2;
+        const double2 val = make_double2(coef * (q1[u][i] - q2[u][i]),
+                                         coef * (q3[u][i] - q1[u][i] - q2[u][i]));
+        double2* d0 = out0 + row + col * ld;
+        const double2 o = *d0;
+        *d0 = make_double2(o.x + val.x, o.y + val.y);
+        if (out1) {
+          double2* d1 = out1 + row + col * ld;
+          if (!ra) {
+            *d1 = val;  // the resonant term writes A-B first
+          } else {
+            const double2 o1 = *d1;
+            *d1 = make_double2(o1.x - val.x, o1.y - val.y);
+          }
+        }
+      }
     }
   }
 }
@@ -857,8 +1036,55 @@ void launch_fp2(const double2* left, int R, int ng, int nk, const double2* W,
                 const int32_t* perm, const int32_t* cls, int nq, double2* Tout,
                 const int32_t* info, hipStream_t s) {
   const int spc = (int)cdiv((int64_t)nk * R, FP_BM);  // a class holds at most nk pairs
-  BSE_LAUNCH((k_first_product2<NCT, VC>), dim3((unsigned)((int64_t)nq * spc)), dim3(256), 0, s,
-             left, R, ng, W, perm, cls, nq, spc, Tout, info);
+  BSE_LAUNCH((k_first_product2<NCT, VC, false>), dim3((unsigned)((int64_t)nq * spc)), dim3(256),
+             0, s, left, R, ng, W, perm, cls, nq, spc, Tout, info, (const double2*)nullptr, 0,
+             nk, 0, 0, 0, 0.0, (double2*)nullptr, (double2*)nullptr, (int64_t)0,
+             (const int32_t*)nullptr);
+}
+
+// Tiles of ppt pairs of each class, listed class by class: map[b] = q |
+// t << 13 for tile t of class q, -1 from the last tile to cap (one block of
+// 1024 threads; at most cdiv(P, ppt) + nq tiles)
+__global__ __launch_bounds__(1024) void k_tile_map(const int32_t* __restrict__ cls, int nq,
+                                                   int ppt, int32_t* __restrict__ map, int cap) {
+  __shared__ int32_t wtot[16];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int per = cdiv(nq, 1024), q0 = min(nq, tid * per), q1 = min(nq, q0 + per);
+  int tot = 0;
+  for (int q = q0; q < q1; ++q) tot += cdiv(cls[q + 1] - cls[q], ppt);
+  int incl = tot;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) wtot[wid] = incl;
+  __syncthreads();
+  int run = incl - tot, all = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wid) run += wtot[w];
+    all += wtot[w];
+  }
+  for (int q = q0; q < q1; ++q) {
+    const int nt = cdiv(cls[q + 1] - cls[q], ppt);
+    for (int t = 0; t < nt; ++t) map[run + t] = q | (t << 13);
+    run += nt;
+  }
+  for (int b = all + tid; b < cap; b += 1024) map[b] = -1;
+}
+
+template <int NCT, int VC>
+void launch_df(const double2* left, const double2* right, int R, int N2, int ng, int nk, int nv,
+               int nc, const double2* W, const int32_t* perm, const int32_t* cls, int nq, int ra,
+               double coef, double2* out0, double2* out1, int64_t ld, int32_t* tmap,
+               const int32_t* info, hipStream_t s) {
+  const int ppt = FP_BM / R;
+  const int spc = cdiv(nk, ppt);  // a class holds at most nk pairs
+  const int64_t P = (int64_t)nk * (nk + 1) / 2;
+  const int cap = (int)(cdiv(P, ppt) + nq);
+  BSE_LAUNCH(k_tile_map, dim3(1), dim3(1024), 0, s, cls, nq, ppt, tmap, cap);
+  BSE_LAUNCH((k_first_product2<NCT, VC, true>), dim3((unsigned)cap), dim3(256), 0, s, left, R,
+             ng, W, perm, cls, nq, spc, (double2*)nullptr, info, right, N2, nk, nv, nc, ra, coef,
+             out0, out1, ld, (const int32_t*)tmap);
 }
 
 }  // namespace
@@ -912,5 +1138,36 @@ bool launch_first_product(int shape, const double2* left, int R, int ng, int nk,
   }
 #undef BSE_FP
 #undef BSE_FP2
+  return hipGetLastError() == hipSuccess;
+}
+
+// One pass per direct term on the matrix cores (FP64): the first product as
+// in launch_first_product, the second per pair, the blocks added into the
+// outputs.  tmap: cdiv(P, 64 / R) + nq ints of device scratch for the tile
+// list.  Returns false when the shape is not handled (nothing launched):
+// N_G outside 16..113, R outside 9..16 or N2 above 16.
+bool launch_direct_onepass(const double2* left, const double2* right, int R, int N2, int ng,
+                           int nk, int nv, int nc, const double2* W, const int32_t* perm,
+                           const int32_t* cls, int nq, int ra, double coef, double2* out0,
+                           double2* out1, int64_t ld, int32_t* tmap, const int32_t* info,
+                           hipStream_t s) {
+  if (!first_product_fits(ng, R) || R < 9 || R > 16 || N2 < 1 || N2 > 16) return false;
+  const int vc = ng % 16 <= 3 ? ng % 16 : 0;
+  const int nct = vc || ng % 16 == 0 ? ng / 16 : ng / 16 + 1;
+#define BSE_DF2(NCT, VC) \
+  launch_df<NCT, VC>(left, right, R, N2, ng, nk, nv, nc, W, perm, cls, nq, ra, coef, out0, out1, ld, tmap, info, s);
+#define BSE_DF(NCT)                             \
+  case NCT:                                     \
+    if (vc == 0) { BSE_DF2(NCT, 0) }            \
+    else if (vc == 1) { BSE_DF2(NCT, 1) }       \
+    else if (vc == 2) { BSE_DF2(NCT, 2) }       \
+    else { BSE_DF2(NCT, 3) }                    \
+    break;
+  switch (nct) {
+    BSE_DF(1) BSE_DF(2) BSE_DF(3) BSE_DF(4) BSE_DF(5) BSE_DF(6) BSE_DF(7)
+    default: return false;
+  }
+#undef BSE_DF
+#undef BSE_DF2
   return hipGetLastError() == hipSuccess;
 }

@@ -21,7 +21,7 @@ bool valid(const bse_tune_entry& e) {
     case BSE_TUNE_GEMM_EXCHANGE:
       return e.choice == 16 || e.choice == 32 || e.choice == 64;
     case BSE_TUNE_DIRECT:
-      return e.choice >= 0 && e.choice <= 8;
+      return e.choice >= 0 && e.choice <= 9;
     case BSE_TUNE_GEMM_PRODUCTS:
       return e.choice == 3 || e.choice == 4;
     default:

@@ -35,17 +35,19 @@ def test_parity_under_forced_tile_choices(name, unit, tile):
     assert eig < 1e-10 and spec < 1e-10, (eig, spec)
 
 
-@pytest.mark.parametrize("choice", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("choice", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("name", ["mid_full_k4_v3c4_g59", "tda_q0_k4_v2c3_g59",
                                   "tiny_full_k2_v2c3_g15", "small_full_k3s_v3c4_g27",
-                                  "small_full_k3_v3c4_g113", "tiny_full_k2_v2c3_g51"])
+                                  "small_full_k3_v3c4_g113", "tiny_full_k2_v3c4_g51"])
 def test_direct_term_paths(name, choice):
     """The FP64 direct terms through the two-pass path (choice 0), the three
-    fused variants (1-3), the three Gauss first products writing T (4-6) and
-    the two unpadded ones (7, 8; N_G = 113 and 51 take the vector-ALU columns and k,
-    59 and 27 its padded last tile and k tail, 15 falls back to 4): the
-    assembled matrices against the oracle (1e-12 of max|H|, sums of <= 2 N_G
-    products) and the same spectrum."""
+    fused variants (1-3), the three Gauss first products writing T (4-6), the
+    two unpadded ones (7, 8) and the one pass with both products on the matrix
+    cores (9): the assembled matrices against the oracle (1e-12 of max|H|, sums
+    of <= 2 N_G products) and the same spectrum.  N_G = 113 and 51 take the
+    vector-ALU columns and k (one and three of each), 59 and 27 the padded last
+    tile and the k tail, 15 falls back to choice 4; the N_v = 2 workloads take
+    7 in place of 9 (pair blocks of 4 and 6 rows)."""
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
