@@ -368,8 +368,9 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
   int dvar = tune_choice(BSE_TUNE_DIRECT, n, 9);
   const bool shape_ok = (prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32) && in->Mcc &&
                         ng <= 128 && R1 <= 64 && (!full || R2 <= 64);
-  if (dvar == 9 && !(prec == BSE_PREC_FP64 && first_product_fits(ng, (int)R1) && R1 >= 9 &&
-                     R1 <= 16 && N1 <= 16 && (!full || (R2 >= 9 && R2 <= 16))))
+  if (dvar == 9 && !((prec == BSE_PREC_FP64 || prec == BSE_PREC_FP32) &&
+                     first_product_fits(ng, (int)R1) && R1 >= 9 && R1 <= 16 && N1 <= 16 &&
+                     (!full || (R2 >= 9 && R2 <= 16))))
     dvar = 7;
   const bool use_fused = shape_ok && ((dvar >= 1 && dvar <= 3) || dvar == 9);
   const bool use_g3_t = shape_ok && dvar >= 4 && dvar <= 8;  // Gauss first product, then two passes
@@ -480,7 +481,7 @@ bse_status build_fp64(const bse_desc* d, const bse_inputs* in, void* out0, void*
     auto term = [&](const void* left, const void* right, int R, int N2, const int32_t* perm,
                     const int32_t* cls, int ra, double2* o1, void* tmap) -> bool {
       if (dvar == 9)
-        return launch_direct_onepass((const double2*)left, (const double2*)right, R, N2, ng, nk,
+        return launch_direct_onepass(prec, (const double2*)left, (const double2*)right, R, N2, ng, nk,
                                      nv, nc, (const double2*)in->W, perm, cls, nq, ra, c,
                                      (double2*)out0, o1, ld, (int32_t*)tmap, info, s);
       return launch_direct_fused(prec, dvar, (const double2*)left,

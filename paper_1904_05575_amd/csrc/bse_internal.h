@@ -56,8 +56,8 @@ bool first_product_fits(int ng, int R);
 bool launch_first_product(int shape, const double2* left, int R, int ng, int nk,
                           const double2* W, const int32_t* perm, const int32_t* cls, int nq,
                           double2* Tout, const int32_t* info, hipStream_t s);
-bool launch_direct_onepass(const double2* left, const double2* right, int R, int N2, int ng,
-                           int nk, int nv, int nc, const double2* W, const int32_t* perm,
+bool launch_direct_onepass(int prec, const double2* left, const double2* right, int R, int N2,
+                           int ng, int nk, int nv, int nc, const double2* W, const int32_t* perm,
                            const int32_t* cls, int nq, int ra, double coef, double2* out0,
                            double2* out1, int64_t ld, int32_t* tmap, const int32_t* info,
                            hipStream_t s);

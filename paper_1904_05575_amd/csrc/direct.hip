@@ -703,7 +703,7 @@ BSE_DEV void lds_read_x_y7(d2v& x, d2v (&y)[7], unsigned ax, unsigned ab) {
 // (rows r < R, columns j < N2 <= 16).  The blocks are then added into the
 // outputs: out0 += coef blk, and out1 = coef blk (resonant) or out1 -= coef
 // blk (coupling).  T never reaches memory.
-template <int NCT, int VC, bool FUSED>
+template <int NCT, int VC, bool FUSED, int PREC = BSE_PREC_FP64>
 __global__ __launch_bounds__(256, 2) void k_first_product2(
     const double2* __restrict__ Left, int R, int ng, const double2* __restrict__ W,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ cls, int nq, int spc,
@@ -787,9 +787,15 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
   // load instructions of one chunk on this wavefront: 2 of L, nbw of W
   const int nbw = (2 * NCT - wid + 3) / 4;
 
-  d4 p1[NCT], p2[NCT], p3[NCT];
+  // FP64: the three products in FP64 over the whole K.  FP32 (precision form):
+  // operands rounded to FP32 as they leave LDS, products and sums in FP32
+  constexpr bool F32 = PREC == BSE_PREC_FP32;
+  using Acc = typename std::conditional<F32, f4, d4>::type;
+  Acc p1[NCT], p2[NCT], p3[NCT];
 #pragma unroll
-  for (int j = 0; j < NCT; ++j) p1[j] = p2[j] = p3[j] = d4{0, 0, 0, 0};
+  for (int j = 0; j < NCT; ++j) p1[j] = p2[j] = p3[j] = Acc{0, 0, 0, 0};
+  // row of accumulator register r (f64: l/16 + 4r; f32: 4 (l/16) + r)
+  auto acc_row = [&](int r) { return F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r; };
   double2 vacc[VC > 0 ? VC : 1];
 #pragma unroll
   for (int c = 0; c < (VC > 0 ? VC : 1); ++c) vacc[c] = make_double2(0.0, 0.0);
@@ -809,12 +815,23 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
 #pragma unroll
           for (int j = 0; j < NCT; ++j) y[j] = lds_read1(ab + 256 * j);
         }
-        const double xs = x[0] - x[1];
+        if constexpr (F32) {
+          const float xr = (float)x[0], xi = (float)x[1], xs = xr - xi;
 #pragma unroll
-        for (int j = 0; j < NCT; ++j) {
-          p1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0], y[j][0], p1[j], 0, 0, 0);
-          p2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1], y[j][1], p2[j], 0, 0, 0);
-          p3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, y[j][0] + y[j][1], p3[j], 0, 0, 0);
+          for (int j = 0; j < NCT; ++j) {
+            const float yr = (float)y[j][0], yi = (float)y[j][1];
+            p1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, yr, p1[j], 0, 0, 0);
+            p2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yi, p2[j], 0, 0, 0);
+            p3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs, yr + yi, p3[j], 0, 0, 0);
+          }
+        } else {
+          const double xs = x[0] - x[1];
+#pragma unroll
+          for (int j = 0; j < NCT; ++j) {
+            p1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0], y[j][0], p1[j], 0, 0, 0);
+            p2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1], y[j][1], p2[j], 0, 0, 0);
+            p3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, y[j][0] + y[j][1], p3[j], 0, 0, 0);
+          }
         }
       }
     }
@@ -863,8 +880,9 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
   for (int j = 0; j < NCT; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = wm0 + (lane >> 4) + 4 * r, n = j * 16 + (lane & 15);
-      double2 v = make_double2(p1[j][r] + p2[j][r], p3[j][r] - p1[j][r] + p2[j][r]);
+      const int m = wm0 + acc_row(r), n = j * 16 + (lane & 15);
+      double2 v = make_double2((double)(p1[j][r] + p2[j][r]),
+                               (double)(p3[j][r] - p1[j][r] + p2[j][r]));
       for (int t = 0; t < remk; ++t)
         v = cadd(v, cmul(sm.s1.ltail[t][m], Wq[(int64_t)(KF + t) * ng + (n < ng ? n : 0)]));
       tre[j][r] = v.x;
@@ -898,7 +916,7 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
     for (int j = 0; j < NCT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = wm0 + (lane >> 4) + 4 * r, n = j * 16 + (lane & 15);
+        const int m = wm0 + acc_row(r), n = j * 16 + (lane & 15);
         if (m < rows && n < ng) Tq[(int64_t)m * ng + n] = make_double2(tre[j][r], tim[j][r]);
       }
     if constexpr (VC > 0)
@@ -949,7 +967,7 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
       if (ph < NCT) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = wm0 + (lane >> 4) + 4 * r, n = 16 * ph + (lane & 15);
+          const int m = wm0 + acc_row(r), n = 16 * ph + (lane & 15);
           d2v v;
           v[0] = n < ng ? tre[ph][r] : 0.0;
           v[1] = n < ng ? tim[ph][r] : 0.0;
@@ -1073,18 +1091,23 @@ __global__ __launch_bounds__(1024) void k_tile_map(const int32_t* __restrict__ c
 }
 
 template <int NCT, int VC>
-void launch_df(const double2* left, const double2* right, int R, int N2, int ng, int nk, int nv,
-               int nc, const double2* W, const int32_t* perm, const int32_t* cls, int nq, int ra,
-               double coef, double2* out0, double2* out1, int64_t ld, int32_t* tmap,
+void launch_df(int prec, const double2* left, const double2* right, int R, int N2, int ng, int nk,
+               int nv, int nc, const double2* W, const int32_t* perm, const int32_t* cls, int nq,
+               int ra, double coef, double2* out0, double2* out1, int64_t ld, int32_t* tmap,
                const int32_t* info, hipStream_t s) {
   const int ppt = FP_BM / R;
   const int spc = cdiv(nk, ppt);  // a class holds at most nk pairs
   const int64_t P = (int64_t)nk * (nk + 1) / 2;
   const int cap = (int)(cdiv(P, ppt) + nq);
   BSE_LAUNCH(k_tile_map, dim3(1), dim3(1024), 0, s, cls, nq, ppt, tmap, cap);
-  BSE_LAUNCH((k_first_product2<NCT, VC, true>), dim3((unsigned)cap), dim3(256), 0, s, left, R,
-             ng, W, perm, cls, nq, spc, (double2*)nullptr, info, right, N2, nk, nv, nc, ra, coef,
-             out0, out1, ld, (const int32_t*)tmap);
+  if (prec == BSE_PREC_FP32)
+    BSE_LAUNCH((k_first_product2<NCT, VC, true, BSE_PREC_FP32>), dim3((unsigned)cap), dim3(256),
+               0, s, left, R, ng, W, perm, cls, nq, spc, (double2*)nullptr, info, right, N2, nk,
+               nv, nc, ra, coef, out0, out1, ld, (const int32_t*)tmap);
+  else
+    BSE_LAUNCH((k_first_product2<NCT, VC, true>), dim3((unsigned)cap), dim3(256), 0, s, left, R,
+               ng, W, perm, cls, nq, spc, (double2*)nullptr, info, right, N2, nk, nv, nc, ra,
+               coef, out0, out1, ld, (const int32_t*)tmap);
 }
 
 }  // namespace
@@ -1141,21 +1164,23 @@ bool launch_first_product(int shape, const double2* left, int R, int ng, int nk,
   return hipGetLastError() == hipSuccess;
 }
 
-// One pass per direct term on the matrix cores (FP64): the first product as
+// One pass per direct term on the matrix cores (FP64, or the first product in
+// FP32 for the precision form): the first product as
 // in launch_first_product, the second per pair, the blocks added into the
 // outputs.  tmap: cdiv(P, 64 / R) + nq ints of device scratch for the tile
 // list.  Returns false when the shape is not handled (nothing launched):
 // N_G outside 16..113, R outside 9..16 or N2 above 16.
-bool launch_direct_onepass(const double2* left, const double2* right, int R, int N2, int ng,
-                           int nk, int nv, int nc, const double2* W, const int32_t* perm,
+bool launch_direct_onepass(int prec, const double2* left, const double2* right, int R, int N2,
+                           int ng, int nk, int nv, int nc, const double2* W, const int32_t* perm,
                            const int32_t* cls, int nq, int ra, double coef, double2* out0,
                            double2* out1, int64_t ld, int32_t* tmap, const int32_t* info,
                            hipStream_t s) {
   if (!first_product_fits(ng, R) || R < 9 || R > 16 || N2 < 1 || N2 > 16) return false;
+  if (prec != BSE_PREC_FP64 && prec != BSE_PREC_FP32) return false;
   const int vc = ng % 16 <= 3 ? ng % 16 : 0;
   const int nct = vc || ng % 16 == 0 ? ng / 16 : ng / 16 + 1;
 #define BSE_DF2(NCT, VC) \
-  launch_df<NCT, VC>(left, right, R, N2, ng, nk, nv, nc, W, perm, cls, nq, ra, coef, out0, out1, ld, tmap, info, s);
+  launch_df<NCT, VC>(prec, left, right, R, N2, ng, nk, nv, nc, W, perm, cls, nq, ra, coef, out0, out1, ld, tmap, info, s);
 #define BSE_DF(NCT)                             \
   case NCT:                                     \
     if (vc == 0) { BSE_DF2(NCT, 0) }            \

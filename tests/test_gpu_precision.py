@@ -27,7 +27,8 @@ def _problem(name, precision):
 @pytest.mark.parametrize("precision", ["fp32", "bf16x6", "bf16x3"])
 @pytest.mark.parametrize("name", ["small_full_k3_v3c4_g27", "mid_full_k4_v3c4_g59",
                                   "tda_q0_k4_v2c3_g59", "mid_core_k4_c2c8_g59",
-                                  "tiny_core_k2_c2c4_g137", "small_full_k3s_v3c4_g27"])
+                                  "tiny_core_k2_c2c4_g137", "small_full_k3s_v3c4_g27",
+                                  "small_full_k3_v3c4_g113"])
 def test_mixed_precision_against_oracle(name, precision):
     P = _problem(name, precision)
     H0, H1 = P.build()
