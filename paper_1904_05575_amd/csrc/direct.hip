@@ -703,6 +703,37 @@ BSE_DEV void lds_read_x_y7(d2v& x, d2v (&y)[7], unsigned ax, unsigned ab) {
 // (rows r < R, columns j < N2 <= 16).  The blocks are then added into the
 // outputs: out0 += coef blk, and out1 = coef blk (resonant) or out1 -= coef
 // blk (coupling).  T never reaches memory.
+// o[i] at a[i] (four reads, one wait)
+BSE_DEV void lds_read_4(d2v (&o)[4], unsigned a0, unsigned a1, unsigned a2, unsigned a3) {
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %5\n\t"
+      "ds_read_b128 %2, %6\n\t"
+      "ds_read_b128 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+      : "memory");
+}
+
+// a[ks] at aa + 64 ks, b[ks] at ab[ks], ks = 0..3 (early-clobber outputs, as above)
+BSE_DEV void lds_read_4x2(d2v (&a)[4], d2v (&b)[4], unsigned aa, const unsigned (&ab)[4]) {
+  asm volatile(
+      "ds_read_b128 %0, %8\n\t"
+      "ds_read_b128 %1, %8 offset:64\n\t"
+      "ds_read_b128 %2, %8 offset:128\n\t"
+      "ds_read_b128 %3, %8 offset:192\n\t"
+      "ds_read_b128 %4, %9\n\t"
+      "ds_read_b128 %5, %10\n\t"
+      "ds_read_b128 %6, %11\n\t"
+      "ds_read_b128 %7, %12\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3]), "=&v"(b[0]), "=&v"(b[1]),
+        "=&v"(b[2]), "=&v"(b[3])
+      : "v"(aa), "v"(ab[0]), "v"(ab[1]), "v"(ab[2]), "v"(ab[3])
+      : "memory");
+}
+
 template <int NCT, int VC, bool FUSED, int PREC = BSE_PREC_FP64>
 __global__ __launch_bounds__(256, 2) void k_first_product2(
     const double2* __restrict__ Left, int R, int ng, const double2* __restrict__ W,
@@ -836,19 +867,35 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
       }
     }
     if constexpr (VC > 0) {
+      if constexpr (VC == 1) {  // the four values of the chunk in one read block
+        const int kk0 = 2 * wid, kk1 = kk0 + 1;
+        d2v o[4];
+        lds_read_4(o, lds_off(&sm.s1.a[st][(lane >> 3) * 64 + (lane & 7) * 8 + (kk0 ^ (lane & 7))]),
+                   lds_off(&sm.s1.a[st][(lane >> 3) * 64 + (lane & 7) * 8 + (kk1 ^ (lane & 7))]),
+                   lds_off(&sm.s1.wcol[min(k0 + kk0, 115)][0]),
+                   lds_off(&sm.s1.wcol[min(k0 + kk1, 115)][0]));
 #pragma unroll
-      for (int kq = 0; kq < 2; ++kq) {
-        const int kk = 2 * wid + kq;
-        if (k0 + kk < KF) {
-          const d2v xv = lds_read1(
-              lds_off(&sm.s1.a[st][(lane >> 3) * 64 + (lane & 7) * 8 + (kk ^ (lane & 7))]));
-          const double2 x = make_double2(xv[0], xv[1]);
+        for (int kq = 0; kq < 2; ++kq)
+          if (k0 + kk0 + kq < KF) {
+            const d2v x = o[kq], y = o[2 + kq];
+            vacc[0].x = fma(x[0], y[0], fma(x[1], y[1], vacc[0].x));  // conj(x) y
+            vacc[0].y = fma(x[0], y[1], fma(-x[1], y[0], vacc[0].y));
+          }
+      } else {
 #pragma unroll
-          for (int c = 0; c < VC; ++c) {
-            const d2v yv = lds_read1(lds_off(&sm.s1.wcol[k0 + kk][c]));
-            const double2 y = make_double2(yv[0], yv[1]);
-            vacc[c].x = fma(x.x, y.x, fma(x.y, y.y, vacc[c].x));  // conj(x) y
-            vacc[c].y = fma(x.x, y.y, fma(-x.y, y.x, vacc[c].y));
+        for (int kq = 0; kq < 2; ++kq) {
+          const int kk = 2 * wid + kq;
+          if (k0 + kk < KF) {
+            const d2v xv = lds_read1(
+                lds_off(&sm.s1.a[st][(lane >> 3) * 64 + (lane & 7) * 8 + (kk ^ (lane & 7))]));
+            const double2 x = make_double2(xv[0], xv[1]);
+#pragma unroll
+            for (int c = 0; c < VC; ++c) {
+              const d2v yv = lds_read1(lds_off(&sm.s1.wcol[k0 + kk][c]));
+              const double2 y = make_double2(yv[0], yv[1]);
+              vacc[c].x = fma(x.x, y.x, fma(x.y, y.y, vacc[c].x));  // conj(x) y
+              vacc[c].y = fma(x.x, y.y, fma(-x.y, y.x, vacc[c].y));
+            }
           }
         }
       }
@@ -965,15 +1012,21 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
       if (ph > 0) lds_barrier();  // T of phase ph - 1 no longer read
       // T of this phase into LDS (columns past N_G as zeros)
       if (ph < NCT) {
+        d2v v[4];
+        unsigned wa[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = wm0 + acc_row(r), n = 16 * ph + (lane & 15);
-          d2v v;
-          v[0] = n < ng ? tre[ph][r] : 0.0;
-          v[1] = n < ng ? tim[ph][r] : 0.0;
-          asm volatile("ds_write_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)"
-                       ::"v"(lds_off(&sm.s2.t[m][lane & 15])), "v"(v) : "memory");
+          v[r][0] = n < ng ? tre[ph][r] : 0.0;
+          v[r][1] = n < ng ? tim[ph][r] : 0.0;
+          wa[r] = lds_off(&sm.s2.t[m][lane & 15]);
         }
+        asm volatile(
+            "ds_write_b128 %0, %4\n\tds_write_b128 %1, %5\n\t"
+            "ds_write_b128 %2, %6\n\tds_write_b128 %3, %7\n\ts_waitcnt lgkmcnt(0)"
+            ::"v"(wa[0]), "v"(wa[1]), "v"(wa[2]), "v"(wa[3]), "v"(v[0]), "v"(v[1]), "v"(v[2]),
+            "v"(v[3])
+            : "memory");
       } else {
         for (int e = tid; e < FP_BM * 16; e += 256) {
           const int m = e & 63, c = e >> 6;
@@ -995,15 +1048,22 @@ __global__ __launch_bounds__(256, 2) void k_first_product2(
         if (pp < npb) {  // wave-uniform
           const int r = lane & 15, j = lane & 15;
           const int trow = min(pp * R + r, FP_BM - 1);  // rows r >= R are not stored
-          for (int ks = 0; ks < nks; ++ks) {
-            const int g = 4 * ks + (lane >> 4);
-            const d2v a = lds_read1(lds_off(&sm.s2.t[trow][g]));
-            const d2v bv = lds_read1(lds_off(&sm.s2.rt[ph & 1][pp][j * 16 + (g ^ (j & 7))]));
-            q1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], bv[0], q1[u], 0, 0, 0);
-            q2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], bv[1], q2[u], 0, 0, 0);
-            q3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0] + a[1], bv[0] + bv[1], q3[u], 0,
-                                                         0, 0);
-          }
+          // the phase's operands of this pair in one read block (T at g = 4 ks + l / 16:
+          // 64 bytes apart; R_p swizzled by j)
+          d2v a[4], bv[4];
+          unsigned rb[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks)
+            rb[ks] = lds_off(&sm.s2.rt[ph & 1][pp][j * 16 + ((4 * ks + (lane >> 4)) ^ (j & 7))]);
+          lds_read_4x2(a, bv, lds_off(&sm.s2.t[trow][lane >> 4]), rb);
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks)
+            if (ks < nks) {
+              q1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][0], bv[ks][0], q1[u], 0, 0, 0);
+              q2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][1], bv[ks][1], q2[u], 0, 0, 0);
+              q3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks][0] + a[ks][1],
+                                                           bv[ks][0] + bv[ks][1], q3[u], 0, 0, 0);
+            }
         }
       }
     }
