@@ -374,6 +374,13 @@ int64_t bse_timing_report(char* buf, int64_t len);
  *                          on 16- and 32-edge tiles: 4 (re = ar br - ai bi,
  *                          im = ar bi + ai br) or 3 (Gauss: ar br, ai bi,
  *                          (ar + ai)(br + bi)); 64-edge tiles always take 4
+ *   BSE_TUNE_BATCH_SWEEP   size = largest problem order of a batch; choice =
+ *                          blocks of the batched Householder sweep's hemv
+ *                          launches: 0 (default) each problem takes the blocks
+ *                          it takes on its own (results bitwise equal to the
+ *                          single problem path); 1, 2 or 4 that many blocks per
+ *                          compute unit in total, shared among the problems in
+ *                          proportion to their tiles
  * Among the entries of a site, the one with the smallest size_max >= size
  * applies; sizes no entry covers use built-in rules.  Every choice gives the
  * same results up to rounding order.  The table is read on the host when work
@@ -390,7 +397,8 @@ enum {
   BSE_TUNE_GEMM_STAGE2 = 4,
   BSE_TUNE_GEMM_EXCHANGE = 5,
   BSE_TUNE_DIRECT = 6,
-  BSE_TUNE_GEMM_PRODUCTS = 7
+  BSE_TUNE_GEMM_PRODUCTS = 7,
+  BSE_TUNE_BATCH_SWEEP = 8
 };
 typedef struct {
   int32_t site;

@@ -2,11 +2,15 @@
 // decouples per q, paper Sec. 2.3 eq. chimatrixq) recorded once into a HIP
 // graph and replayed with one launch.  Problems are spread over `nbranch`
 // concurrent branches (longest first, by N^3), each with its own slice of the
-// caller's workspace.
+// caller's workspace.  With one branch per problem the Householder sweeps of
+// all problems run as one batched sweep (one launch per sweep step for every
+// problem), between the branches' assembly and factorisation and their
+// eigenvalue stages.
 #include <algorithm>
 #include <vector>
 
 #include "bse_internal.h"
+#include "solve_internal.h"
 #include "timing.h"
 
 struct bse_batch {
@@ -14,8 +18,12 @@ struct bse_batch {
   std::vector<bse_desc> descs;
   std::vector<int> branch_of;
   std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> events;  // [0] fork, [1 + b] join of branch b
+  // [0] fork, [1 + b] join of branch b, [1 + nbranch] second fork (after the
+  // batched sweep), [2 + nbranch + b] second join
+  std::vector<hipEvent_t> events;
   size_t slice = 0;
+  void* trd_table = nullptr;  // device table of the batched sweep (one branch per problem)
+  size_t trd_bytes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -82,12 +90,22 @@ bse_status bse_batch_create(int32_t nprob, const bse_desc* descs, int32_t nbranc
       bse_batch_destroy(b);
       return BSE_ERR_HIP;
     }
-  b->events.assign(1 + b->nbranch, nullptr);
+  b->events.assign(2 + 2 * b->nbranch, nullptr);
   for (auto& e : b->events)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       bse_batch_destroy(b);
       return BSE_ERR_HIP;
     }
+  if (b->nbranch == nprob) {
+    std::vector<int64_t> ns(nprob);
+    for (int i = 0; i < nprob; ++i) ns[i] = (int64_t)descs[i].nk * descs[i].nv * descs[i].nc;
+    b->trd_bytes = trd_batch_table_bytes(ns.data(), nprob);
+    if (hipMalloc(&b->trd_table, b->trd_bytes) != hipSuccess) {
+      b->trd_table = nullptr;
+      bse_batch_destroy(b);
+      return BSE_ERR_HIP;
+    }
+  }
   *out = b;
   return BSE_OK;
 }
@@ -116,33 +134,68 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
     if (d->prec != BSE_PREC_FP64 && in->nq > d->nk) return BSE_ERR_ARG;
   }
   release(b);
+  // batched sweep: every problem's sweep arguments, written to the device
+  // table before capture (a blocking copy; no replay of this batch may run)
+  const bool batched = b->trd_table != nullptr;
+  std::vector<TrdItem> items;
+  if (batched) {
+    for (int i = 0; i < b->nprob; ++i) {
+      void* wsb = (char*)ws + b->slice * (size_t)b->branch_of[i];
+      items.push_back(solve_sweep_item(&b->descs[i], H0[i], wsb, true, info + i));
+    }
+    if (!trd_batch_table(items.data(), b->nprob, b->trd_table, b->trd_bytes)) return BSE_ERR_HIP;
+  }
   const TimingState timing = timing_suspend();  // no events inside the graph
   bse_status st = BSE_OK;
   if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     timing_resume(timing);
     return BSE_ERR_HIP;
   }
+  auto fork = [&](int ev) {
+    hipEventRecord(b->events[ev], stream);
+    for (int br = 0; br < b->nbranch; ++br) hipStreamWaitEvent(b->streams[br], b->events[ev], 0);
+  };
+  auto join = [&](int ev0) {
+    for (int br = 0; br < b->nbranch; ++br) {
+      hipEventRecord(b->events[ev0 + br], b->streams[br]);
+      hipStreamWaitEvent(stream, b->events[ev0 + br], 0);
+    }
+  };
   launch_zero_ints(info, b->nprob, stream);
-  hipEventRecord(b->events[0], stream);
-  for (int br = 0; br < b->nbranch; ++br) hipStreamWaitEvent(b->streams[br], b->events[0], 0);
+  fork(0);
+  const int first = batched ? SOLVE_PRE : SOLVE_ALL;
   for (int i = 0; i < b->nprob && st == BSE_OK; ++i) {
     const bse_desc* d = &b->descs[i];
-    const int br = b->branch_of[i];
-    hipStream_t s = b->streams[br];
-    void* wsb = (char*)ws + b->slice * (size_t)br;
+    hipStream_t s = b->streams[b->branch_of[i]];
+    void* wsb = (char*)ws + b->slice * (size_t)b->branch_of[i];
     void* h1 = (d->coupling == BSE_FULL) ? H1[i] : nullptr;
     const int64_t n = (int64_t)d->nk * d->nv * d->nc;
     st = build_fp64(d, &inputs[i], H0[i], h1, wsb, info + i, s);
     if (st == BSE_OK)
-      st = solve_run(d, H0[i], h1, E[i], nullptr, nullptr, n, probe[i], osc[i], wsb, info + i, s);
-    if (st == BSE_OK &&
+      st = solve_run(d, H0[i], h1, E[i], nullptr, nullptr, n, probe[i], osc[i], wsb, info + i, s,
+                     first);
+    if (st == BSE_OK && !batched &&
         launch_spectrum(n, E[i], osc[i], pref[i], eta[i], nw[i], omega[i], (double2*)eps[i], s) !=
             hipSuccess)
       st = BSE_ERR_HIP;
   }
-  for (int br = 0; br < b->nbranch; ++br) {
-    hipEventRecord(b->events[1 + br], b->streams[br]);
-    hipStreamWaitEvent(stream, b->events[1 + br], 0);
+  join(1);
+  if (batched && st == BSE_OK) {
+    if (!tridiagonalise_batch(items.data(), b->nprob, b->trd_table, stream)) st = BSE_ERR_HIP;
+    fork(1 + b->nbranch);
+    for (int i = 0; i < b->nprob && st == BSE_OK; ++i) {
+      const bse_desc* d = &b->descs[i];
+      hipStream_t s = b->streams[b->branch_of[i]];
+      void* wsb = (char*)ws + b->slice * (size_t)b->branch_of[i];
+      void* h1 = (d->coupling == BSE_FULL) ? H1[i] : nullptr;
+      const int64_t n = (int64_t)d->nk * d->nv * d->nc;
+      st = solve_run(d, H0[i], h1, E[i], nullptr, nullptr, n, probe[i], osc[i], wsb, info + i, s,
+                     SOLVE_POST);
+      if (st == BSE_OK && launch_spectrum(n, E[i], osc[i], pref[i], eta[i], nw[i], omega[i],
+                                          (double2*)eps[i], s) != hipSuccess)
+        st = BSE_ERR_HIP;
+    }
+    join(2 + b->nbranch);
   }
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(stream, &g);
@@ -172,6 +225,7 @@ void bse_batch_destroy(bse_batch_t b) {
     if (s) hipStreamDestroy(s);
   for (auto e : b->events)
     if (e) hipEventDestroy(e);
+  if (b->trd_table) hipFree(b->trd_table);
   delete b;
 }
 

@@ -83,9 +83,16 @@ int tune_choice(int site, int64_t size, int deflt);
 // solve.hip
 void launch_zero_ints(int32_t* p, int n, hipStream_t s);
 size_t solve_workspace(const bse_desc* d);
+// Stages of solve_run: everything before the Householder sweep (Cholesky and
+// the squared form, the probe's projection), the sweep, everything after it.
+constexpr int SOLVE_PRE = 1, SOLVE_SWEEP = 2, SOLVE_POST = 4, SOLVE_ALL = 7;
 bse_status solve_run(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, void* XmY,
                      int64_t ldx, const void* probe, double* osc, void* ws, int32_t* info,
-                     hipStream_t s);
+                     hipStream_t s, int phase = SOLVE_ALL);
+// The sweep's arguments for problem d in workspace ws (as solve_run passes
+// them; `project`: spectrum-only run with a probe).
+struct TrdItem;
+TrdItem solve_sweep_item(const bse_desc* d, void* H0, void* ws, bool project, int32_t* info);
 
 // screening.hip
 size_t screening_workspace(const bse_screen_desc* d);

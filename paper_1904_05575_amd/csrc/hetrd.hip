@@ -20,6 +20,9 @@
 // lower triangle of the trailing matrix.  The panel's V and W live in two
 // n x 2*TRD_NB buffers, VW = [V | W] and WV = [W | V], which make that update
 // one product.
+#include <algorithm>
+#include <vector>
+
 #include "bse_internal.h"
 #include "common.h"
 #include "solve_internal.h"
@@ -103,11 +106,11 @@ BSE_DEV double2 sub_mulc(double2 x, double2 a, double2 b) {
   return make_double2(x.x - (a.x * b.x + a.y * b.y), x.y - (a.y * b.x - a.x * b.y));
 }
 
-__global__ __launch_bounds__(COL_THREADS) void k_trd_col(
+BSE_DEV void trd_col_dev(
     double2* __restrict__ M, int64_t ld, int n, double2* __restrict__ VW, double2* __restrict__ WV,
     int j0, int i, int has_new, const double2* __restrict__ hs, const double2* __restrict__ Y,
     int ycs, int gprev, double2* __restrict__ partA, const double2* __restrict__ partB,
-    double2* __restrict__ yp) {
+    double2* __restrict__ yp, int bx) {
   constexpr int QP = COL_THREADS / ROWS_A;        // threads sharing one row
   constexpr int PER = TRD_NB / QP;                // panel columns per thread
   constexpr int YCH = 8;                          // y slots loaded per round
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
   const int c = j0 + i;
   const int64_t N = n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int rbase = c + blockIdx.x * ROWS_A;
+  const int rbase = c + bx * ROWS_A;
   const int rr = tid % ROWS_A, qq = tid / ROWS_A;  // qq is uniform in a wavefront
   const int r = rbase + rr;
   const bool act = r < n;
@@ -330,8 +333,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
       const double2 s0 = wave_sum2_dpp(make_double2(tail ? cabs2(x) : 0.0, 0.0));
       const double2 s1 = wave_sum2_dpp((tail && yp) ? cmulc(x, ypr) : make_double2(0.0, 0.0));
       if (has_new && lane == 0) {  // the block's |x|^2 and conj(x) y_probe
-        partA[(int64_t)blockIdx.x * NVAL + 0] = s0;
-        partA[(int64_t)blockIdx.x * NVAL + 1] = s1;
+        partA[(int64_t)bx * NVAL + 0] = s0;
+        partA[(int64_t)bx * NVAL + 1] = s1;
       }
     }
   }
@@ -358,12 +361,21 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col(
         pw.y = wave_total63(pw.y);
         // block partials, compact layout [|x|^2, conj(x) y, V^H x (i), W^H x (i)]
         if (lane == 63) {
-          partA[(int64_t)blockIdx.x * NVAL + 2 + ip] = pv;
-          partA[(int64_t)blockIdx.x * NVAL + 2 + i + ip] = pw;
+          partA[(int64_t)bx * NVAL + 2 + ip] = pv;
+          partA[(int64_t)bx * NVAL + 2 + i + ip] = pw;
         }
       }
     }
   }
+}
+
+__global__ __launch_bounds__(COL_THREADS) void k_trd_col(
+    double2* __restrict__ M, int64_t ld, int n, double2* __restrict__ VW, double2* __restrict__ WV,
+    int j0, int i, int has_new, const double2* __restrict__ hs, const double2* __restrict__ Y,
+    int ycs, int gprev, double2* __restrict__ partA, const double2* __restrict__ partB,
+    double2* __restrict__ yp) {
+  trd_col_dev(M, ld, n, VW, WV, j0, i, has_new, hs, Y, ycs, gprev, partA, partB, yp,
+              (int)blockIdx.x);
 }
 
 // Sum over the 16 lanes of each row of the wavefront (DPP within rows); every
@@ -398,12 +410,12 @@ BSE_DEV double row16_sum(double v) {
 // row 16 s + l % 16: four contiguous 256-byte column segments per
 // instruction.  A column's sum over the tile's rows is lane-local over s plus
 // one 16-lane DPP reduction serving four columns.
-__global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
+BSE_DEV void trd_hemv_dev(
     const double2* __restrict__ M, int64_t ld, int n, const double2* __restrict__ VW, int j0,
     int i, double2* __restrict__ hs, const double2* __restrict__ partA,
     double2* __restrict__ partB, double2* __restrict__ Y, int ycs,
     double* __restrict__ dd, double* __restrict__ ee, double2* __restrict__ tau,
-    const double2* __restrict__ yp) {
+    const double2* __restrict__ yp, int bx, int G) {
   constexpr int NW = HV_THREADS / 64;     // 16 wavefronts
   constexpr int NL = 4;                   // matrix loads per lane per tile
   static_assert(NW * 4 == HT, "tile layout");
@@ -426,8 +438,8 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;  // row in slab, column group
   const int jl = 4 * wid + lg;               // this lane's tile column
-  const int nlast = n - 1, G = gridDim.x;
-  const int64_t t_end = hemv_tile_start(T, G, (int)blockIdx.x + 1);
+  const int nlast = n - 1;
+  const int64_t t_end = hemv_tile_start(T, G, bx + 1);
   const double2* xcol = M + (int64_t)c * ld;
   const double2 zero = make_double2(0.0, 0.0);
 
@@ -459,16 +471,16 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   // ---- the small loads first, so that they are not queued behind the tile
   // prefetch of every block: x on the first tile-row's rows and, for
   // wavefront 1, the column kernel's |x|^2 partials and this block's share of
-  // the other partial sums (value t = 1 + blockIdx.x, + G, ...)
+  // the other partial sums (value t = 1 + bx, + G, ...)
   const int nbA = cdiv(n - c, ROWS_A);
   const int nvals = 2 + 2 * i;
-  Pos C = pos_of(hemv_tile_start(T, G, (int)blockIdx.x));
+  Pos C = pos_of(hemv_tile_start(T, G, bx));
   const double2 xv0 = xcol[min(org + C.I * HT + (tid & (HT - 1)), nlast)];
   // x on the rows of the next tile-row, loaded one piece ahead of its use
   double2 xnx = xcol[min(org + (C.I + 1) * HT + lane, nlast)];
   constexpr int PQ = 4;  // partial sums per lane issued together
   double2 pq0[PQ], pq1[PQ];
-  const int t0 = 1 + (int)blockIdx.x;  // first value of wavefront 1
+  const int t0 = 1 + bx;  // first value of wavefront 1
   double2 ax = zero, vw1 = zero, yb0 = zero;
   if (wid == 1) {
     ax = xcol[b0];
@@ -528,7 +540,7 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
       const double q = 1.0 / cabs2(dnm);
       scal = make_double2(dnm.x * q, -dnm.y * q);
     }
-    if (blockIdx.x == 0 && lane == 0) {
+    if (bx == 0 && lane == 0) {
       ee[c] = beta;
       tau[c] = tv;
       dd[c] = M[c + (int64_t)c * ld].x;
@@ -574,7 +586,7 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
   // slot of this block's piece of tile-row I: pieces are counted from the
   // block that holds the row's first tile
   auto row_slot = [&](int I) {
-    return (int)blockIdx.x - hemv_block_of(T, G, (int64_t)I * (I + 1) / 2);
+    return bx - hemv_block_of(T, G, (int64_t)I * (I + 1) / 2);
   };
   // cb: tile C; nb receives tile C + 2 (tile C + 1 is in flight in the third buffer)
   auto tile = [&](const Rec& cb, Rec& nb) {
@@ -654,8 +666,46 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
     double2 t = zero;
 #pragma unroll
     for (int w = 0; w < NW; ++w) t = cadd(t, pred[w]);
-    partB[blockIdx.x] = t;
+    partB[bx] = t;
   }
+}
+
+__global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
+    const double2* __restrict__ M, int64_t ld, int n, const double2* __restrict__ VW, int j0,
+    int i, double2* __restrict__ hs, const double2* __restrict__ partA,
+    double2* __restrict__ partB, double2* __restrict__ Y, int ycs,
+    double* __restrict__ dd, double* __restrict__ ee, double2* __restrict__ tau,
+    const double2* __restrict__ yp) {
+  trd_hemv_dev(M, ld, n, VW, j0, i, hs, partA, partB, Y, ycs, dd, ee, tau, yp, (int)blockIdx.x,
+               (int)gridDim.x);
+}
+
+// ---- the same sweep over several independent problems at once: one launch
+// per kernel and column step serves every problem still reducing (blockIdx.y
+// selects the problem; blocks past a problem's grid return at once).  Every
+// problem goes through the same kernels, launches and values as on its own.
+__global__ __launch_bounds__(COL_THREADS) void k_trd_col_b(TrdBatchArgs a, int j0, int i) {
+  const TrdProb p = a.p[blockIdx.y];
+  const int n = p.n;
+  if (j0 >= n - 1) return;  // this problem's sweep is over
+  const int jb = min(TRD_NB, n - 1 - j0);
+  if (i > jb) return;       // its last panel is shorter
+  const int c = j0 + i;
+  if ((int)blockIdx.x >= cdiv(n - c, ROWS_A)) return;
+  // uniform: readfirstlane keeps it (and all index arithmetic on it) scalar
+  const int gprev = __builtin_amdgcn_readfirstlane(c > 0 ? p.grids[c - 1] : 1);
+  trd_col_dev(p.M, p.ld, n, p.VW, p.WV, j0, i, i < jb ? 1 : 0, p.hs, p.Y, p.ycs, gprev, p.partA,
+              p.partB, p.yp, (int)blockIdx.x);
+}
+
+__global__ __launch_bounds__(HV_THREADS) void k_trd_hemv_b(TrdBatchArgs a, int j0, int i) {
+  const TrdProb p = a.p[blockIdx.y];
+  const int n = p.n;
+  if (j0 >= n - 1 || i >= min(TRD_NB, n - 1 - j0)) return;
+  const int G = __builtin_amdgcn_readfirstlane(p.grids[j0 + i]);  // uniform, kept scalar
+  if ((int)blockIdx.x >= G) return;
+  trd_hemv_dev(p.M, p.ld, n, p.VW, j0, i, p.hs, p.partA, p.partB, p.Y, p.ycs, p.dd, p.ee, p.tau,
+               p.yp, (int)blockIdx.x, G);
 }
 
 __global__ void k_trd_last(const double2* M, int64_t ld, int n, double* dd, const int32_t* info) {
@@ -758,5 +808,192 @@ bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t
     }
   }
   BSE_LAUNCH(k_trd_last, dim3(1), dim3(64), 0, s, M, ld, (int)n, w.dd, info);
+  return hipGetLastError() == hipSuccess;
+}
+
+namespace {
+
+// Device pointers of problem `it`'s share of the partial-sum space.
+void trd_parts(const TrdItem& it, double2** partA, double2** partB, double2** Y) {
+  *partA = it.w.part;
+  *partB = it.w.part + ((it.n + ROWS_A - 1) / ROWS_A + 1) * NVAL;
+  *Y = *partB + hemv_tiles_max(it.n) + 1;
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+// Blocks of every problem's hemv launch for reflector c, c = 0 .. n - 2: by
+// default hemv_grid() blocks, as in the problem's own sweep; in shared mode the
+// launch for step c has `per_cu` blocks per compute unit in all, each problem
+// still reducing at c getting a share proportional to its tiles (at least one,
+// at most one per tile), so that all blocks take runs of about equal length.
+std::vector<std::vector<int32_t>> batch_grids(const TrdItem* it, int np) {
+  int64_t nmax = 0;
+  for (int p = 0; p < np; ++p) nmax = std::max(nmax, it[p].n);
+  const int per_cu = tune_choice(BSE_TUNE_BATCH_SWEEP, nmax, 0);
+  auto tiles = [](int64_t n, int64_t c) {
+    const int64_t nI = (n - trd_org((int)c + 1) + HT - 1) / HT;
+    return nI * (nI + 1) / 2;
+  };
+  std::vector<std::vector<int32_t>> g(np);
+  for (int p = 0; p < np; ++p) g[p].assign((size_t)std::max<int64_t>(it[p].n - 1, 0), 1);
+  const double total = (double)per_cu * device_cus();
+  for (int64_t c = 0; c + 1 < nmax; ++c) {
+    double sum = 0.0;
+    for (int p = 0; p < np; ++p)
+      if (c + 1 < it[p].n) sum += (double)tiles(it[p].n, c);
+    for (int p = 0; p < np; ++p) {
+      if (c + 1 >= it[p].n) continue;
+      const int64_t T = tiles(it[p].n, c);
+      int64_t G;
+      if (per_cu == 0) {
+        G = hemv_grid(it[p].n - trd_org((int)c + 1));
+      } else {
+        G = std::llround(total * (double)T / sum);
+        G = std::max<int64_t>(1, std::min(G, T));
+      }
+      g[p][c] = (int32_t)G;
+    }
+  }
+  return g;
+}
+
+// Per problem with a sweep step at (j0, i): its hemv grid and column grid.
+struct StepGrids {
+  int col = 0, hemv = 0;
+};
+StepGrids step_grids(const TrdItem* it, int np, const std::vector<std::vector<int32_t>>& grids,
+                     int64_t j0, int i) {
+  StepGrids g;
+  for (int p = 0; p < np; ++p) {
+    const int64_t n = it[p].n;
+    if (j0 >= n - 1) continue;
+    const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
+    if (i > jb) continue;
+    const int64_t c = j0 + i;
+    g.col = std::max(g.col, cdiv(n - c, ROWS_A));
+    if (i < jb) g.hemv = std::max(g.hemv, (int)grids[p][c]);
+  }
+  return g;
+}
+
+}  // namespace
+
+size_t trd_batch_table_bytes(const int64_t* n, int np) {
+  size_t b = 0;
+  for (int p = 0; p < np; ++p) b += (size_t)std::max<int64_t>(n[p], 1) * sizeof(int32_t);
+  return b;
+}
+
+namespace {
+// Offset (in int32 entries) of problem p's grid counts in the table.
+std::vector<size_t> grid_offsets(const TrdItem* it, int np) {
+  std::vector<size_t> off(np + 1, 0);
+  for (int p = 0; p < np; ++p) off[p + 1] = off[p] + (size_t)std::max<int64_t>(it[p].n, 1);
+  return off;
+}
+}  // namespace
+
+bool trd_batch_table(const TrdItem* it, int np, void* dev, size_t bytes) {
+  if (np <= 0 || !dev) return false;
+  const std::vector<size_t> off = grid_offsets(it, np);
+  if (bytes < off[np] * sizeof(int32_t)) return false;
+  std::vector<int32_t> host(off[np], 0);
+  for (int g0 = 0; g0 < np; g0 += TRD_BATCH_MAX) {  // groups as tridiagonalise_batch forms them
+    const int ng = std::min(TRD_BATCH_MAX, np - g0);
+    const auto grids = batch_grids(it + g0, ng);
+    for (int p = 0; p < ng; ++p)
+      std::copy(grids[p].begin(), grids[p].end(), host.begin() + off[g0 + p]);
+  }
+  return hipMemcpy(dev, host.data(), off[np] * sizeof(int32_t), hipMemcpyHostToDevice) ==
+         hipSuccess;
+}
+
+bool tridiagonalise_batch(const TrdItem* it_all, int np_all, const void* dev, hipStream_t s) {
+  const std::vector<size_t> off = grid_offsets(it_all, np_all);
+  for (int g0 = 0; g0 < np_all; g0 += TRD_BATCH_MAX) {
+    const TrdItem* it = it_all + g0;
+    const int np = std::min(TRD_BATCH_MAX, np_all - g0);
+    const auto grids = batch_grids(it, np);  // as written into the table
+    TrdBatchArgs A{};
+    int64_t nmax = 0;
+    for (int p = 0; p < np; ++p) {
+      const TrdItem& q = it[p];
+      TrdProb& t = A.p[p];
+      t.M = q.M;
+      t.ld = q.ld;
+      t.n = (int)q.n;
+      t.ycs = (int)ycs_of(q.n);
+      t.VW = q.w.VW;
+      t.WV = q.w.WV;
+      t.hs = q.w.hs;
+      trd_parts(q, &t.partA, &t.partB, &t.Y);
+      t.yp = q.w.yproj;
+      t.tau = q.w.tau;
+      t.dd = q.w.dd;
+      t.ee = q.w.ee;
+      t.grids = (const int32_t*)dev + off[g0 + p];
+      nmax = std::max(nmax, q.n);
+    }
+    for (int64_t j0 = 0; j0 < nmax - 1; j0 += TRD_NB) {
+      int jbmax = 0;
+      for (int p = 0; p < np; ++p) {
+        const TrdItem& q = it[p];
+        if (j0 >= q.n - 1) continue;
+        const int jb = (int)std::min<int64_t>(TRD_NB, q.n - 1 - j0);
+        jbmax = std::max(jbmax, jb);
+        if (jb < TRD_NB)
+          BSE_LAUNCH(k_trd_zero_cols, dim3(256), dim3(256), 0, s, q.w.VW, q.w.WV, q.n, jb);
+      }
+      for (int i = 0; i <= jbmax; ++i) {
+        const StepGrids g = step_grids(it, np, grids, j0, i);
+        if (g.col > 0)
+          BSE_LAUNCH(k_trd_col_b, dim3(g.col, np), dim3(COL_THREADS), 0, s, A, (int)j0, i);
+        if (g.hemv > 0)
+          BSE_LAUNCH(k_trd_hemv_b, dim3(g.hemv, np), dim3(HV_THREADS), 0, s, A, (int)j0, i);
+      }
+      for (int p = 0; p < np; ++p) {
+        const TrdItem& q = it[p];
+        if (j0 >= q.n - 1) continue;
+        const int64_t t = j0 + std::min<int64_t>(TRD_NB, q.n - 1 - j0);
+        const int64_t n = q.n;
+        if (t >= n) continue;
+        ZgemmParams g;  // S[t:, t:] -= [V W] [W V]^H, as in the single sweep
+        g.M = (int)(n - t);
+        g.N = (int)(n - t);
+        g.K = 2 * TRD_NB;
+        g.A = q.w.VW + t;
+        g.a_rs = 1;
+        g.a_cs = n;
+        g.B = q.w.WV + t;
+        g.b_rs = n;
+        g.b_cs = 1;
+        g.conjB = 1;
+        g.C = q.M + t + t * q.ld;
+        g.c_rs = 1;
+        g.c_cs = q.ld;
+        g.c_uplo = 2;
+        g.alpha = make_double2(-1.0, 0.0);
+        g.beta = 1.0;
+        g.info = q.info;
+        g.tag = "zgemm_her2k";
+        g.tile = tune_choice(BSE_TUNE_GEMM_HER2K, n, 0);
+        if (zgemm(g, 1, s) != hipSuccess) return false;
+      }
+    }
+    for (int p = 0; p < np; ++p)
+      BSE_LAUNCH(k_trd_last, dim3(1), dim3(64), 0, s, it[p].M, it[p].ld, (int)it[p].n,
+                 it[p].w.dd, it[p].info);
+  }
   return hipGetLastError() == hipSuccess;
 }

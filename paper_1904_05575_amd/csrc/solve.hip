@@ -1272,7 +1272,7 @@ void launch_zero_ints(int32_t* p, int n, hipStream_t s) {
 
 bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* XpYv, void* XmYv,
                      int64_t ldx, const void* probev, double* osc, void* ws, int32_t* info,
-                     hipStream_t s) {
+                     hipStream_t s, int phase) {
   const int64_t n = (int64_t)d->nk * d->nv * d->nc, ld = d->ld;
   const bool full = d->coupling == BSE_FULL;
   double2* H0 = (double2*)H0v;
@@ -1281,72 +1281,75 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
   double2* XmY = XpY ? (double2*)XmYv : nullptr;
   const double2* probe = (const double2*)probev;
   SolveWs w = carve(d, ws);
-  BSE_LAUNCH(k_zero_ints, dim3(1), dim3(64), 0, s, w.counters, 64);
-  const dim3 cgrid((unsigned)std::min<int64_t>(cdiv(n, 256), 8),
-                   (unsigned)std::min<int64_t>(n, 65535));
-  // X-Y (full BSE) comes from the first of the coupled equations,
-  // (A+B)(X+Y) = (X-Y) E: A+B is kept in the X-Y buffer until X+Y exists
-  if (full && XmY) BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, H0, ld, XmY, ldx, n);
-
   double2* Hm = H0;  // Hermitian matrix handed to the tridiagonalisation
-  if (full) {
-    if (!cholesky(H1, n, ld, w.W1, info, s)) return BSE_ERR_HIP;
-    ZgemmParams a;  // T1 = (A+B) U^H
-    a.M = (int)n;
-    a.N = (int)n;
-    a.K = (int)n;
-    a.A = H0;
-    a.a_rs = 1;
-    a.a_cs = ld;
-    a.B = H1;
-    a.b_rs = ld;
-    a.b_cs = 1;
-    a.conjB = 1;
-    a.b_tri = 2;
-    a.C = w.Wk;
-    a.c_rs = 1;
-    a.c_cs = n;
-    a.info = info;
-    a.tag = "zgemm_sq_t1";
-    a.tile = tune_choice(BSE_TUNE_GEMM_SQUARED, n, 0);
-    if (zgemm(a, 1, s) != hipSuccess) return BSE_ERR_HIP;
-    ZgemmParams b;  // S (lower) = U T1  -> H0
-    b.M = (int)n;
-    b.N = (int)n;
-    b.K = (int)n;
-    b.A = H1;
-    b.a_rs = 1;
-    b.a_cs = ld;
-    b.a_tri = 1;
-    b.B = w.Wk;
-    b.b_rs = 1;
-    b.b_cs = n;
-    b.C = H0;
-    b.c_rs = 1;
-    b.c_cs = ld;
-    b.c_uplo = 2;
-    b.info = info;
-    b.tag = "zgemm_sq_s";
-    b.tile = tune_choice(BSE_TUNE_GEMM_SQUARED, n, 0);
-    if (zgemm(b, 1, s) != hipSuccess) return BSE_ERR_HIP;
-    const int nt = cdiv(n, 32);
-    BSE_LAUNCH(k_hermitize, dim3(nt, nt), dim3(256), 0, s, H0, n, ld, 1, info);
-  }
-
   // spectrum-only: the probe is carried through the reduction, y = Q^H (U p)
   const bool project = (XpY == nullptr) && probe && osc;
-  if (project) {
+  const dim3 cgrid((unsigned)std::min<int64_t>(cdiv(n, 256), 8),
+                   (unsigned)std::min<int64_t>(n, 65535));
+  if (phase & SOLVE_PRE) {
+    BSE_LAUNCH(k_zero_ints, dim3(1), dim3(64), 0, s, w.counters, 64);
+    // X-Y (full BSE) comes from the first of the coupled equations,
+    // (A+B)(X+Y) = (X-Y) E: A+B is kept in the X-Y buffer until X+Y exists
+    if (full && XmY) BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, H0, ld, XmY, ldx, n);
+
     if (full) {
-      // y = U p (the hemv partial-sum space is free until the sweep starts)
-      const dim3 grid((unsigned)cdiv(n, TRMV_ROWS), (unsigned)cdiv(n, TRMV_COLS));
-      BSE_LAUNCH(k_trmv_part, grid, dim3(TRMV_ROWS), 0, s, H1, ld, (int)n, probe, w.part, info);
-      BSE_LAUNCH(k_trmv_sum, dim3(cdiv(n, 256)), dim3(256), 0, s, w.part, (int)n, w.yvec, info);
-    } else {
-      BSE_LAUNCH(k_copy_c, dim3(cdiv(n, 256)), dim3(256), 0, s, probe, w.yvec, n);
+      if (!cholesky(H1, n, ld, w.W1, info, s)) return BSE_ERR_HIP;
+      ZgemmParams a;  // T1 = (A+B) U^H
+      a.M = (int)n;
+      a.N = (int)n;
+      a.K = (int)n;
+      a.A = H0;
+      a.a_rs = 1;
+      a.a_cs = ld;
+      a.B = H1;
+      a.b_rs = ld;
+      a.b_cs = 1;
+      a.conjB = 1;
+      a.b_tri = 2;
+      a.C = w.Wk;
+      a.c_rs = 1;
+      a.c_cs = n;
+      a.info = info;
+      a.tag = "zgemm_sq_t1";
+      a.tile = tune_choice(BSE_TUNE_GEMM_SQUARED, n, 0);
+      if (zgemm(a, 1, s) != hipSuccess) return BSE_ERR_HIP;
+      ZgemmParams b;  // S (lower) = U T1  -> H0
+      b.M = (int)n;
+      b.N = (int)n;
+      b.K = (int)n;
+      b.A = H1;
+      b.a_rs = 1;
+      b.a_cs = ld;
+      b.a_tri = 1;
+      b.B = w.Wk;
+      b.b_rs = 1;
+      b.b_cs = n;
+      b.C = H0;
+      b.c_rs = 1;
+      b.c_cs = ld;
+      b.c_uplo = 2;
+      b.info = info;
+      b.tag = "zgemm_sq_s";
+      b.tile = tune_choice(BSE_TUNE_GEMM_SQUARED, n, 0);
+      if (zgemm(b, 1, s) != hipSuccess) return BSE_ERR_HIP;
+      const int nt = cdiv(n, 32);
+      BSE_LAUNCH(k_hermitize, dim3(nt, nt), dim3(256), 0, s, H0, n, ld, 1, info);
     }
-  }
+
+    if (project) {
+      if (full) {
+        // y = U p (the hemv partial-sum space is free until the sweep starts)
+        const dim3 grid((unsigned)cdiv(n, TRMV_ROWS), (unsigned)cdiv(n, TRMV_COLS));
+        BSE_LAUNCH(k_trmv_part, grid, dim3(TRMV_ROWS), 0, s, H1, ld, (int)n, probe, w.part, info);
+        BSE_LAUNCH(k_trmv_sum, dim3(cdiv(n, 256)), dim3(256), 0, s, w.part, (int)n, w.yvec, info);
+      } else {
+        BSE_LAUNCH(k_copy_c, dim3(cdiv(n, 256)), dim3(256), 0, s, probe, w.yvec, n);
+      }
+    }
+  }  // SOLVE_PRE
   TrdBufs tb{w.VW, w.WV, w.ybuf, w.hs, w.part, w.dd, w.ee, w.tau, project ? w.yvec : nullptr};
-  if (!tridiagonalise(Hm, n, ld, tb, info, s)) return BSE_ERR_HIP;
+  if ((phase & SOLVE_SWEEP) && !tridiagonalise(Hm, n, ld, tb, info, s)) return BSE_ERR_HIP;
+  if (!(phase & SOLVE_POST)) return BSE_OK;
   BSE_LAUNCH(k_tri_prep, dim3(1), dim3(1024), 0, s, w.dd, w.ee, (int)n, w.ds, w.es, w.e2s,
              w.stat, info);
   BSE_LAUNCH(k_sturm_grid, dim3(BS_G / 64), dim3(64), 0, s, w.ds, w.e2s, (int)n, w.stat, w.grid,
@@ -1422,4 +1425,15 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
       return BSE_ERR_HIP;
   }
   return hipGetLastError() == hipSuccess ? BSE_OK : BSE_ERR_HIP;
+}
+
+TrdItem solve_sweep_item(const bse_desc* d, void* H0, void* ws, bool project, int32_t* info) {
+  const SolveWs w = carve(d, ws);
+  TrdItem it;
+  it.M = (double2*)H0;
+  it.n = (int64_t)d->nk * d->nv * d->nc;
+  it.ld = d->ld;
+  it.w = TrdBufs{w.VW, w.WV, w.ybuf, w.hs, w.part, w.dd, w.ee, w.tau, project ? w.yvec : nullptr};
+  it.info = info;
+  return it;
 }

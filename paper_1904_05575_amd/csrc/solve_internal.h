@@ -29,3 +29,42 @@ struct TrdBufs {
 int64_t trd_part_elems(int64_t n);
 bool tridiagonalise(double2* M, int64_t n, int64_t ld, const TrdBufs& w, int32_t* info,
                     hipStream_t s);
+
+// One problem of a batched sweep: its matrix, order, leading dimension,
+// buffers and status word (each problem has its own; none may alias another's).
+struct TrdItem {
+  double2* M;
+  int64_t n, ld;
+  TrdBufs w;
+  int32_t* info;
+};
+
+// Per-problem arguments of the batched kernels (grids[c] = blocks of the hemv
+// launch for reflector c, in device memory written by trd_batch_table).  They
+// travel by value in the kernel arguments, up to TRD_BATCH_MAX problems per
+// launch, so that the compiler knows every pointer to be device memory.
+struct TrdProb {
+  double2* M;
+  int64_t ld;
+  int n, ycs;
+  double2 *VW, *WV, *hs, *Y, *partA, *partB, *yp, *tau;
+  double *dd, *ee;
+  const int32_t* grids;
+};
+constexpr int TRD_BATCH_MAX = 16;
+struct TrdBatchArgs {
+  TrdProb p[TRD_BATCH_MAX];
+};
+
+// Bytes of the device table (the hemv grid counts of every step) for problems
+// of orders n[0..np-1].
+size_t trd_batch_table_bytes(const int64_t* n, int np);
+// Fill the table `dev` (trd_batch_table_bytes long) for these problems: a
+// blocking host-to-device copy, made before the sweep is enqueued or captured.
+bool trd_batch_table(const TrdItem* it, int np, void* dev, size_t bytes);
+// The sweep of every problem at once (in groups of up to TRD_BATCH_MAX): per
+// column step one column-kernel launch and one hemv launch serve all problems
+// of a group still reducing.  With the per-problem grid choice each problem's
+// values are those of tridiagonalise() on its own; with blocks shared among the
+// problems they differ from those in rounding order only.
+bool tridiagonalise_batch(const TrdItem* it, int np, const void* dev, hipStream_t s);

@@ -20,11 +20,15 @@ def _batch(members, precision="fp64", nbranch=3):
     return Batch(members, precision=precision, nbranch=nbranch)
 
 
+@pytest.mark.parametrize("nbranch", [3, 16])
 @pytest.mark.parametrize("name", ["batch4_k2_g15", "batch3_k3_g27"])
-def test_graph_batch_matches_oracle(name):
+def test_graph_batch_matches_oracle(name, nbranch):
+    """Each member's E and eps against the oracle (1e-10); with one branch per
+    problem (nbranch >= members) the Householder sweeps run batched."""
     ms = _members(name)
-    print(f"[gpu] batch {name}: sizes {[m['workload'].n for m in ms]}", flush=True)
-    B = _batch(ms)
+    print(f"[gpu] batch {name} nbranch {nbranch}: sizes {[m['workload'].n for m in ms]}",
+          flush=True)
+    B = _batch(ms, nbranch=nbranch)
     B.run()
     res = B.results()
     for d, out in zip(ms, res):
@@ -53,6 +57,50 @@ def test_graph_replays_and_sequential_path_agree():
     seq = B.results()
     for a, b in zip(first, seq):
         assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["eps"], b["eps"])
+
+
+def test_batched_sweep_reproduces_per_problem_sweeps():
+    """Uneven sizes (short last panels at different steps, problems finishing
+    early).  With each problem's own hemv grids (tuning choice 0, the default)
+    the graph with the batched sweep (one branch per problem), the graph with
+    per-branch sweeps and the plain entry points give identical E, osc and eps;
+    with the blocks shared among the problems (choices 1, 2, 4) the batched
+    graph repeats its own bits on replay and matches the others to rounding."""
+    from paper_1904_05575_amd import _lib as L
+    ms = _members("batch4_k2_g15")
+    print(f"[gpu] batched sweep: sizes {[m['workload'].n for m in ms]}", flush=True)
+    old = L.bse_tune_get()
+    try:
+        L.bse_tune_set(old + [(L.TUNE_SITES["batch_sweep"], 1 << 20, 0)])
+        Bb = _batch(ms, nbranch=len(ms))
+        Bb.run()
+        bat = Bb.results()
+        Bp = _batch(ms, nbranch=2)
+        Bp.run()
+        per = Bp.results()
+        Bb.run_sequential()
+        seq = Bb.results()
+        for i in range(len(ms)):
+            for other in (per[i], seq[i]):
+                for key in ("E", "osc", "eps"):
+                    assert np.array_equal(bat[i][key], other[key]), (i, key)
+        Bb.close()
+        for per_cu in (1, 2, 4):
+            L.bse_tune_set(old + [(L.TUNE_SITES["batch_sweep"], 1 << 20, per_cu)])
+            Bs = _batch(ms, nbranch=len(ms))
+            Bs.run()
+            sh = Bs.results()
+            Bs.run()
+            for i in range(len(ms)):
+                a = Bs.results()[i]
+                assert np.array_equal(a["E"], sh[i]["E"]) and np.array_equal(a["eps"], sh[i]["eps"])
+                assert np.abs(sh[i]["E"] - seq[i]["E"]).max() < 1e-12 * seq[i]["E"].max(), (per_cu, i)
+                assert np.abs(sh[i]["eps"] - seq[i]["eps"]).max() < 1e-10 * np.abs(
+                    seq[i]["eps"] - 1).max(), (per_cu, i)
+            Bs.close()
+        Bp.close()
+    finally:
+        L.bse_tune_set(old)
 
 
 def test_graph_batch_mixed_precision():
@@ -97,9 +145,9 @@ def test_full_size_batch_sum_rules():
             else:
                 fs += 2.0 * np.vdot(p[i], blk @ p[j]).real
         assert abs(np.sum(out["E"] * out["osc"]) - fs) < 1e-9 * fs, (idx, fs)
-    # sixteen concurrent branches change the timing only: a replay and the plain
-    # entry points one problem after another reproduce every bit (a kernel
-    # whose blocks read what another block of it writes would not)
+    # sixteen problems in one batched sweep change the timing only: a replay and
+    # the plain entry points one problem after another reproduce every bit (a
+    # kernel whose blocks read what another block of it writes would not)
     for again in (lambda: B.run(), lambda: B.run_sequential()):
         again()
         for i, (a, b) in enumerate(zip(res, B.results())):
