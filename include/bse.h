@@ -184,6 +184,26 @@ bse_status bse_solve_noalloc(const bse_desc* desc, void* H0, void* H1, double* E
                              void* XmY, int64_t ldx, const void* probe, double* osc,
                              int32_t* info, hipStream_t stream);
 
+/* The exchange term's Coulomb potential without its macroscopic part (Sec.
+ * 4.2, eq. vbar_def), as bse_inputs.vbar takes it:
+ *   vbar[G] = 4 pi / |G + q|^2 for every G except G_Q, where vbar[G_Q] = 0;
+ * G_Q is the G nearest to the momentum transfer Q (the lowest index among
+ * equally near ones) and q = Q - G_Q.  gvec: DEVICE int32 [ng][3], the G
+ * vectors in units of 2 pi / alat (bohr); Q: HOST double[3] in bohr^-1 (not
+ * kept after return); vbar: DEVICE double[ng] (output); gq: DEVICE int32[1],
+ * receives the index of G_Q (for bse_probe).  One kernel on `stream`.
+ * BSE_ERR_ARG for ng <= 0, a null pointer, alat <= 0 or a non-finite alat or Q. */
+bse_status bse_coulomb(int32_t ng, const int32_t* gvec, double alat, const double* Q,
+                       double* vbar, int32_t* gq, hipStream_t stream);
+
+/* Probe vector of the spectrum (Sec. 4.4, eq. osci): probe[a] = conj(Mcv[a][gq[0]])
+ * for a = 0..n-1, Mcv complex [n][ng] row-major (the layout bse_inputs.Mcv has),
+ * gq: DEVICE int32[1] (as bse_coulomb writes it; 0 <= gq < ng is the caller's
+ * to ensure).  probe: DEVICE complex [n] (output).  BSE_ERR_ARG for n <= 0,
+ * ng <= 0 or a null pointer. */
+bse_status bse_probe(int64_t n, int32_t ng, const void* Mcv, const int32_t* gq, void* probe,
+                     hipStream_t stream);
+
 /* Oscillator strengths from eigenvectors: osc[l] = |sum_a conj(XpY[a,l]) probe[a]|^2
  * (eq. osci without the 1/V_c factor, which the prefactor of bse_spectrum carries). */
 bse_status bse_oscillator(int64_t n, const void* XpY, int64_t ldx, const void* probe, double* osc,

@@ -91,6 +91,10 @@ def lib() -> ctypes.CDLL:
         L.bse_pair_elements.argtypes = [ctypes.POINTER(BseOrbDesc), vp, vp, vp, vp, vp, vp, vp,
                                         vp, vp]
         L.bse_pair_elements.restype = ctypes.c_int
+        L.bse_coulomb.argtypes = [i32, vp, dbl, ctypes.POINTER(dbl), vp, vp, vp]
+        L.bse_coulomb.restype = ctypes.c_int
+        L.bse_probe.argtypes = [i64, i32, vp, vp, vp, vp]
+        L.bse_probe.restype = ctypes.c_int
         L.bse_oscillator.argtypes = [i64, vp, i64, vp, vp, vp]
         L.bse_oscillator.restype = ctypes.c_int
         L.bse_spectrum.argtypes = [i64, vp, vp, dbl, dbl, i64, vp, vp, vp]
@@ -168,6 +172,15 @@ def bse_pair_elements(desc: BseOrbDesc, C: int, kpg: int, mkg: int, Mcv: int, Mv
     _check(lib().bse_pair_elements(ctypes.byref(desc), C, kpg, mkg or None, Mcv, Mvv, Mcc,
                                    Ncv or None, Nvc or None, stream or None),
            "bse_pair_elements")
+
+
+def bse_coulomb(ng: int, gvec: int, alat: float, Q, vbar: int, gq: int, stream: int) -> None:
+    q = (ctypes.c_double * 3)(*[float(x) for x in Q])
+    _check(lib().bse_coulomb(ng, gvec, alat, q, vbar, gq, stream or None), "bse_coulomb")
+
+
+def bse_probe(n: int, ng: int, Mcv: int, gq: int, probe: int, stream: int) -> None:
+    _check(lib().bse_probe(n, ng, Mcv, gq, probe, stream or None), "bse_probe")
 
 
 def bse_oscillator(n: int, XpY: int, ldx: int, probe: int, osc: int, stream: int) -> None:

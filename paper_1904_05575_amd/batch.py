@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .bse import (PRECISIONS, TYPES, _dev, coulomb_v0, coulomb_vbar, g_index_of_q,
+from .bse import (PRECISIONS, TYPES, _dev, coulomb_v0, device_vbar_probe,
                   kernel_prefactor)
 
 
@@ -39,9 +39,8 @@ class Batch:
             if full:
                 t["Ncv"] = self.shared["Ncv"][:, :nc, :nv, :].contiguous()
                 t["Nvc"] = self.shared["Nvc"][:, :nv, :nc, :].contiguous()
-            t["vbar"] = _dev(coulomb_vbar(d["gvec"], d["alat"], w.q), f64, dv)
-            gq = g_index_of_q(d["gvec"], d["alat"], w.q)
-            t["probe"] = _dev(np.conj(d["Mcv"][:, gq]), c128, dv)
+            t["vbar"], t["probe"] = device_vbar_probe(d["gvec"], d["alat"], w.q, w.n, w.ng,
+                                                      t["Mcv"], dv)
             t["omega"] = _dev(d["omega"], f64, dv)
             n = w.n
             t["H0"] = torch.empty((n, n), dtype=c128, device=dv)

@@ -1,10 +1,10 @@
 """Host-side driver of the BSE library: device buffers, descriptor, calls.
 
 PyTorch supplies device memory and the stream; every step of the method runs
-in libbse.so.  The small host computations here are the problem's geometry
-(Coulomb potential without its macroscopic term, eq. vbar_def; the kernel
-prefactor 1/V_c of eq. vft), the probe vector of eq. osci and the probe
-vectors conj(D) of eq. tlambdai.
+in libbse.so.  The small host computations here are scalars of the problem's geometry
+(the kernel prefactor 1/V_c of eq. vft, v(Q) of the spectrum's prefactor) and
+the probe vectors conj(D) of eq. tlambdai; the Coulomb potential of eq.
+vbar_def and the probe of eq. osci are formed by the library.
 """
 from __future__ import annotations
 
@@ -21,23 +21,21 @@ PRECISIONS = {"fp64": (L.BSE_PREC_FP64, 0), "fp32": (L.BSE_PREC_FP32, 0),
               "bf16x6": (L.BSE_PREC_BF16X3, 6), "bf16x3": (L.BSE_PREC_BF16X3, 3)}
 
 
-def g_index_of_q(gvec: np.ndarray, alat: float, q) -> int:
-    """Index of the reciprocal lattice vector nearest to Q (Q = G_Q + q)."""
-    G = gvec.astype(np.float64) * (2.0 * np.pi / alat)
-    return int(np.argmin(((G - np.asarray(q, dtype=np.float64)) ** 2).sum(axis=1)))
-
-
-def coulomb_vbar(gvec: np.ndarray, alat: float, q) -> np.ndarray:
-    """4 pi / |G + q|^2 for every G, zero at G_Q (the macroscopic term)."""
-    G = gvec.astype(np.float64) * (2.0 * np.pi / alat)
-    Q = np.asarray(q, dtype=np.float64)
-    gq = g_index_of_q(gvec, alat, Q)
-    qred = Q - G[gq]
-    p2 = ((G + qred) ** 2).sum(axis=1)
-    out = np.zeros(len(G))
-    keep = np.arange(len(G)) != gq
-    out[keep] = 4.0 * np.pi / p2[keep]
-    return out
+def device_vbar_probe(gvec: np.ndarray, alat: float, q, n: int, ng: int, Mcv: torch.Tensor,
+                      device) -> tuple[torch.Tensor, torch.Tensor]:
+    """The exchange term's vbar (eq. vbar_def) and the probe conj(M(G_Q)) of eq.
+    osci, formed by the library (bse_coulomb, bse_probe) on the current stream."""
+    g = np.ascontiguousarray(gvec, dtype=np.int32)
+    if g.shape != (ng, 3):
+        raise ValueError(f"gvec has shape {g.shape}, expected ({ng}, 3)")
+    gd = _dev(g, torch.int32, device)
+    vbar = torch.empty(ng, dtype=torch.float64, device=device)
+    gq = torch.zeros(1, dtype=torch.int32, device=device)
+    probe = torch.empty(n, dtype=torch.complex128, device=device)
+    s = torch.cuda.current_stream().cuda_stream
+    L.bse_coulomb(ng, gd.data_ptr(), float(alat), q, vbar.data_ptr(), gq.data_ptr(), s)
+    L.bse_probe(n, ng, Mcv.data_ptr(), gq.data_ptr(), probe.data_ptr(), s)
+    return vbar, probe
 
 
 def coulomb_v0(q) -> float:
@@ -99,11 +97,9 @@ class Problem:
         }
         if self.full:
             self.t["qramap"] = _dev(inputs["qramap"], torch.int32, dv)
-        gq = g_index_of_q(inputs["gvec"], inputs["alat"], w.q)
         if inputs.get("C") is not None:
             # pair elements formed on the device from the orbitals
             self.form_pair_elements(inputs)
-            mcv_gq = self.t["Mcv"][:, gq].cpu().numpy()
         else:
             self.t["Mcv"] = _dev(inputs["Mcv"], c128, dv)
             self.t["Mvv"] = _dev(inputs["Mvv"], c128, dv)
@@ -114,10 +110,8 @@ class Problem:
             if self.full:
                 self.t["Ncv"] = _dev(inputs["Ncv"], c128, dv)
                 self.t["Nvc"] = _dev(inputs["Nvc"], c128, dv)
-            mcv_gq = inputs["Mcv"][:, gq]
-        vbar = coulomb_vbar(inputs["gvec"], inputs["alat"], w.q)
-        self.t["vbar"] = _dev(vbar, f64, dv)
-        self.t["probe"] = _dev(np.conj(mcv_gq), c128, dv)
+        self.t["vbar"], self.t["probe"] = device_vbar_probe(
+            inputs["gvec"], inputs["alat"], w.q, self.n, w.ng, self.t["Mcv"], dv)
         self.t["omega"] = _dev(inputs["omega"], f64, dv)
         if inputs.get("Dcv") is not None:  # column i = conj(D_{., i}), column-major n x 3
             self.t["dprobe"] = _dev(np.conj(inputs["Dcv"]).T, c128, dv)

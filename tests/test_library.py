@@ -111,6 +111,21 @@ def test_argument_errors_are_reported_without_launching(lib):
     assert lib.bse_status_string(2) == b"workspace too small"
 
 
+def test_coulomb_and_probe_reject_bad_arguments(lib):
+    """Argument checks of bse_coulomb and bse_probe, before any device call."""
+    import ctypes
+    q = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    for args in ((0, 1, 10.0, q, 1, 1), (5, None, 10.0, q, 1, 1), (5, 1, 0.0, q, 1, 1),
+                 (5, 1, float("nan"), q, 1, 1), (5, 1, 10.0, None, 1, 1), (5, 1, 10.0, q, None, 1),
+                 (5, 1, 10.0, q, 1, None)):
+        assert lib.bse_coulomb(*args, None) == 1
+    q[1] = float("inf")
+    assert lib.bse_coulomb(5, 1, 10.0, q, 1, 1, None) == 1
+    for args in ((0, 5, 1, 1, 1), (4, 0, 1, 1, 1), (4, 5, None, 1, 1), (4, 5, 1, None, 1),
+                 (4, 5, 1, 1, None)):
+        assert lib.bse_probe(*args, None) == 1
+
+
 def test_tuning_table_round_trip_and_validation(lib):
     old = L.bse_tune_get()
     try:
