@@ -2,10 +2,10 @@
 // decouples per q, paper Sec. 2.3 eq. chimatrixq) recorded once into a HIP
 // graph and replayed with one launch.  Problems are spread over `nbranch`
 // concurrent branches (longest first, by N^3), each with its own slice of the
-// caller's workspace.  With one branch per problem the Householder sweeps of
-// all problems run as one batched sweep (one launch per sweep step for every
-// problem), between the branches' assembly and factorisation and their
-// eigenvalue stages.
+// caller's workspace.  With one branch per problem the Cholesky factorisations
+// and the Householder sweeps of all problems run batched on the capture stream
+// (one launch per step serving every problem), between rounds of per-problem
+// work on the branches: assembly; squared form; eigenvalue stages and spectrum.
 #include <algorithm>
 #include <vector>
 
@@ -18,8 +18,8 @@ struct bse_batch {
   std::vector<bse_desc> descs;
   std::vector<int> branch_of;
   std::vector<hipStream_t> streams;
-  // [0] fork, [1 + b] join of branch b, [1 + nbranch] second fork (after the
-  // batched sweep), [2 + nbranch + b] second join
+  // per round r of branch work (one round without the batched stages, three
+  // with them): [r (1 + nbranch)] fork, [r (1 + nbranch) + 1 + b] join of branch b
   std::vector<hipEvent_t> events;
   size_t slice = 0;
   void* trd_table = nullptr;  // device table of the batched sweep (one branch per problem)
@@ -90,7 +90,7 @@ bse_status bse_batch_create(int32_t nprob, const bse_desc* descs, int32_t nbranc
       bse_batch_destroy(b);
       return BSE_ERR_HIP;
     }
-  b->events.assign(2 + 2 * b->nbranch, nullptr);
+  b->events.assign(3 * (1 + b->nbranch), nullptr);
   for (auto& e : b->events)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       bse_batch_destroy(b);
@@ -151,51 +151,81 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
     timing_resume(timing);
     return BSE_ERR_HIP;
   }
-  auto fork = [&](int ev) {
-    hipEventRecord(b->events[ev], stream);
-    for (int br = 0; br < b->nbranch; ++br) hipStreamWaitEvent(b->streams[br], b->events[ev], 0);
+  const int nb = b->nbranch;
+  auto fork = [&](int r) {  // round r: events[r (1 + nb)] forks, the next nb join
+    hipEvent_t e = b->events[r * (1 + nb)];
+    hipEventRecord(e, stream);
+    for (int br = 0; br < nb; ++br) hipStreamWaitEvent(b->streams[br], e, 0);
   };
-  auto join = [&](int ev0) {
-    for (int br = 0; br < b->nbranch; ++br) {
-      hipEventRecord(b->events[ev0 + br], b->streams[br]);
-      hipStreamWaitEvent(stream, b->events[ev0 + br], 0);
+  auto join = [&](int r) {
+    for (int br = 0; br < nb; ++br) {
+      hipEvent_t e = b->events[r * (1 + nb) + 1 + br];
+      hipEventRecord(e, b->streams[br]);
+      hipStreamWaitEvent(stream, e, 0);
     }
+  };
+  auto branch = [&](int i) { return b->streams[b->branch_of[i]]; };
+  auto slice = [&](int i) { return (void*)((char*)ws + b->slice * (size_t)b->branch_of[i]); };
+  auto h1_of = [&](int i) { return b->descs[i].coupling == BSE_FULL ? H1[i] : nullptr; };
+  auto order_of = [&](int i) {
+    return (int64_t)b->descs[i].nk * b->descs[i].nv * b->descs[i].nc;
+  };
+  // the solve's stages of problem i on its branch
+  auto solve = [&](int i, int phase) {
+    return solve_run(&b->descs[i], H0[i], h1_of(i), E[i], nullptr, nullptr, order_of(i),
+                     probe[i], osc[i], slice(i), info + i, branch(i), phase);
+  };
+  auto spectrum = [&](int i) {
+    return launch_spectrum(order_of(i), E[i], osc[i], pref[i], eta[i], nw[i], omega[i],
+                           (double2*)eps[i], branch(i)) == hipSuccess
+               ? BSE_OK
+               : BSE_ERR_HIP;
   };
   launch_zero_ints(info, b->nprob, stream);
+  // round 0 on the branches: assembly, and everything (one branch per problem:
+  // the stages before the Cholesky factorisation)
   fork(0);
-  const int first = batched ? SOLVE_PRE : SOLVE_ALL;
   for (int i = 0; i < b->nprob && st == BSE_OK; ++i) {
-    const bse_desc* d = &b->descs[i];
-    hipStream_t s = b->streams[b->branch_of[i]];
-    void* wsb = (char*)ws + b->slice * (size_t)b->branch_of[i];
-    void* h1 = (d->coupling == BSE_FULL) ? H1[i] : nullptr;
-    const int64_t n = (int64_t)d->nk * d->nv * d->nc;
-    st = build_fp64(d, &inputs[i], H0[i], h1, wsb, info + i, s);
-    if (st == BSE_OK)
-      st = solve_run(d, H0[i], h1, E[i], nullptr, nullptr, n, probe[i], osc[i], wsb, info + i, s,
-                     first);
-    if (st == BSE_OK && !batched &&
-        launch_spectrum(n, E[i], osc[i], pref[i], eta[i], nw[i], omega[i], (double2*)eps[i], s) !=
-            hipSuccess)
-      st = BSE_ERR_HIP;
+    st = build_fp64(&b->descs[i], &inputs[i], H0[i], h1_of(i), slice(i), info + i, branch(i));
+    if (st == BSE_OK) st = solve(i, batched ? SOLVE_PRE1 : SOLVE_ALL);
+    if (st == BSE_OK && !batched) st = spectrum(i);
   }
-  join(1);
+  join(0);
   if (batched && st == BSE_OK) {
-    if (!tridiagonalise_batch(items.data(), b->nprob, b->trd_table, stream)) st = BSE_ERR_HIP;
-    fork(1 + b->nbranch);
-    for (int i = 0; i < b->nprob && st == BSE_OK; ++i) {
-      const bse_desc* d = &b->descs[i];
-      hipStream_t s = b->streams[b->branch_of[i]];
-      void* wsb = (char*)ws + b->slice * (size_t)b->branch_of[i];
-      void* h1 = (d->coupling == BSE_FULL) ? H1[i] : nullptr;
-      const int64_t n = (int64_t)d->nk * d->nv * d->nc;
-      st = solve_run(d, H0[i], h1, E[i], nullptr, nullptr, n, probe[i], osc[i], wsb, info + i, s,
-                     SOLVE_POST);
-      if (st == BSE_OK && launch_spectrum(n, E[i], osc[i], pref[i], eta[i], nw[i], omega[i],
-                                          (double2*)eps[i], s) != hipSuccess)
-        st = BSE_ERR_HIP;
+    // the Cholesky factorisations in step (problems of one tuned GEMM tile
+    // together), on the capture stream
+    std::vector<CholItem> chol;
+    std::vector<int> tiles;
+    for (int i = 0; i < b->nprob; ++i)
+      if (b->descs[i].coupling == BSE_FULL) {
+        chol.push_back(solve_chol_item(&b->descs[i], H1[i], slice(i), info + i));
+        tiles.push_back(tune_choice(BSE_TUNE_GEMM_POTRF, order_of(i), 0));
+      }
+    std::vector<char> done(chol.size(), 0);
+    for (size_t i = 0; i < chol.size() && st == BSE_OK; ++i) {
+      if (done[i]) continue;
+      std::vector<CholItem> grp;
+      for (size_t j = i; j < chol.size() && (int)grp.size() < CHOL_GROUP_MAX; ++j)
+        if (!done[j] && tiles[j] == tiles[i]) {
+          grp.push_back(chol[j]);
+          done[j] = 1;
+        }
+      if (!cholesky_batch(grp.data(), (int)grp.size(), stream)) st = BSE_ERR_HIP;
     }
-    join(2 + b->nbranch);
+    // round 1 on the branches: squared form and the probe's projection
+    fork(1);
+    for (int i = 0; i < b->nprob && st == BSE_OK; ++i) st = solve(i, SOLVE_PRE2);
+    join(1);
+    // the Householder sweeps of all problems as one, on the capture stream
+    if (st == BSE_OK && !tridiagonalise_batch(items.data(), b->nprob, b->trd_table, stream))
+      st = BSE_ERR_HIP;
+    // round 2 on the branches: eigenvalues, oscillator strengths, spectrum
+    fork(2);
+    for (int i = 0; i < b->nprob && st == BSE_OK; ++i) {
+      st = solve(i, SOLVE_POST);
+      if (st == BSE_OK) st = spectrum(i);
+    }
+    join(2);
   }
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(stream, &g);

@@ -83,12 +83,31 @@ int tune_choice(int site, int64_t size, int deflt);
 // solve.hip
 void launch_zero_ints(int32_t* p, int n, hipStream_t s);
 size_t solve_workspace(const bse_desc* d);
-// Stages of solve_run: everything before the Householder sweep (Cholesky and
-// the squared form, the probe's projection), the sweep, everything after it.
-constexpr int SOLVE_PRE = 1, SOLVE_SWEEP = 2, SOLVE_POST = 4, SOLVE_ALL = 7;
+// Stages of solve_run: before the Cholesky factorisation (counters, the
+// copy of A+B), the factorisation, from it to the sweep (the squared form, the
+// probe's projection), the Householder sweep, everything after it.
+constexpr int SOLVE_PRE1 = 1, SOLVE_CHOL = 8, SOLVE_PRE2 = 16, SOLVE_SWEEP = 2, SOLVE_POST = 4;
+constexpr int SOLVE_PRE = SOLVE_PRE1 | SOLVE_CHOL | SOLVE_PRE2;
+constexpr int SOLVE_ALL = SOLVE_PRE | SOLVE_SWEEP | SOLVE_POST;
 bse_status solve_run(const bse_desc* d, void* H0, void* H1, double* E, void* XpY, void* XmY,
                      int64_t ldx, const void* probe, double* osc, void* ws, int32_t* info,
                      hipStream_t s, int phase = SOLVE_ALL);
+// Cholesky factorisation A - B = U^H U of several problems in step (the
+// factorisation of the full solve): each problem's matrix (upper triangle,
+// leading dimension ld, order n), its U11 staging (solve workspace) and status.
+struct CholItem {
+  double2* A;
+  int64_t ld, n;
+  double2* u11;
+  int32_t* info;
+};
+constexpr int CHOL_GROUP_MAX = 16;
+// Up to CHOL_GROUP_MAX problems whose tuned Cholesky GEMM tile is the same;
+// each problem's values are those of its own factorisation in solve_run.
+bool cholesky_batch(const CholItem* it, int np, hipStream_t s);
+// The factorisation's arguments for problem d (full coupling) in workspace ws.
+CholItem solve_chol_item(const bse_desc* d, void* H1, void* ws, int32_t* info);
+
 // The sweep's arguments for problem d in workspace ws (as solve_run passes
 // them; `project`: spectrum-only run with a probe).
 struct TrdItem;

@@ -106,15 +106,13 @@ namespace {
 // k_potrf_store moves every U11 into A once the factorisation is complete.
 constexpr int PCOLS = 256;
 constexpr int PEL = CH_NB * CH_NB / PCOLS;  // diagonal-block elements per thread
-__global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, int64_t ld,
-                                                       int64_t n, int j0, int jb,
-                                                       double2* __restrict__ u11,
-                                                       int32_t* info) {
+BSE_DEV void potrf_panel_dev(double2* __restrict__ A, int64_t ld, int64_t n, int j0, int jb,
+                             double2* __restrict__ u11, int32_t* info, int bx) {
   __shared__ double2 u[CH_NB][CH_NB + 1];  // rows of U11 as they are finished
   __shared__ double dsh[CH_NB];
   if (failed(info)) return;
   const int tid = threadIdx.x;
-  const int64_t c0 = (int64_t)j0 + jb + (int64_t)blockIdx.x * PCOLS;
+  const int64_t c0 = (int64_t)j0 + jb + (int64_t)bx * PCOLS;
   const bool solve = jb == CH_NB && c0 + tid < n;
   // this thread's column of A12 (rows j0 .. j0 + jb - 1)
   double2 x[CH_NB];
@@ -140,7 +138,7 @@ __global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, 
     __syncthreads();
     const double d = u[j][j].x;  // the same value in every thread: uniform exit
     if (!(d > 0.0) || !isfinite(d)) {
-      if (tid == 0 && blockIdx.x == 0) set_info(info, j0 + j + 1);
+      if (tid == 0 && bx == 0) set_info(info, j0 + j + 1);
       return;
     }
     const double rd = 1.0 / d;
@@ -158,7 +156,7 @@ __global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, 
       u[r][c] = (r == c) ? make_double2(dsh[r], 0.0) : cscale(u[r][c], 1.0 / dsh[r]);
   }
   __syncthreads();
-  if (blockIdx.x == 0) {
+  if (bx == 0) {
     double2* dst = u11 + (int64_t)(j0 / CH_NB) * CH_NB * CH_NB;
     for (int e = tid; e < jb * jb; e += PCOLS) {
       const int r = e % jb, c = e / jb;
@@ -176,6 +174,28 @@ __global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, 
   if (solve)
 #pragma unroll
     for (int r = 0; r < CH_NB; ++r) A[(int64_t)(j0 + r) + (c0 + tid) * ld] = x[r];
+}
+
+__global__ __launch_bounds__(PCOLS) void k_potrf_panel(double2* __restrict__ A, int64_t ld,
+                                                       int64_t n, int j0, int jb,
+                                                       double2* __restrict__ u11,
+                                                       int32_t* info) {
+  potrf_panel_dev(A, ld, n, j0, jb, u11, info, (int)blockIdx.x);
+}
+
+// The panel at column j0 of every problem of a group whose order exceeds j0
+// (blockIdx.y = problem; the problems travel by value, so that every load is a
+// global load).
+struct PotrfGroup {
+  CholItem it[CHOL_GROUP_MAX];
+};
+__global__ __launch_bounds__(PCOLS) void k_potrf_panel_b(PotrfGroup g, int j0) {
+  const CholItem& q = g.it[blockIdx.y];
+  if (j0 >= q.n) return;
+  const int jb = (int)min<int64_t>(CH_NB, q.n - j0);
+  const int64_t rest = q.n - j0 - jb;
+  if ((int64_t)blockIdx.x >= (rest > 0 ? (rest + PCOLS - 1) / PCOLS : 1)) return;
+  potrf_panel_dev(q.A, q.ld, q.n, j0, jb, q.u11, q.info, (int)blockIdx.x);
 }
 
 // U11 of every panel (staged by k_potrf_panel) into the upper triangle of A.
@@ -1194,6 +1214,92 @@ bool cholesky(double2* H1, int64_t n, int64_t ld, double2* u11, int32_t* info, h
   return true;
 }
 
+ZgemmItem herk_item(const CholItem& q, int64_t u0, int k, int64_t r0, int rows, int64_t c0,
+                    int cols) {
+  ZgemmItem h;  // as herk_update: C(r0.., c0..) -= U(u0.., r0..)^H U(u0.., c0..)
+  h.M = rows;
+  h.N = cols;
+  h.K = k;
+  h.A = q.A + u0 + r0 * q.ld;
+  h.a_rs = q.ld;
+  h.a_cs = 1;
+  h.B = q.A + u0 + c0 * q.ld;
+  h.b_rs = 1;
+  h.b_cs = q.ld;
+  h.C = q.A + r0 + c0 * q.ld;
+  h.c_rs = 1;
+  h.c_cs = q.ld;
+  h.info = q.info;
+  return h;
+}
+
+}  // namespace
+
+// cholesky() of several problems in step: one panel launch per panel serves
+// every problem, and the updates after it run as one grouped GEMM (each item
+// with the tile zgemm() would give it alone): every problem's values are those
+// of cholesky() on its own.  Problems with the same tuned tile only (the
+// caller groups them); at most CHOL_GROUP_MAX per call.
+bool cholesky_batch(const CholItem* it, int np, hipStream_t s) {
+  if (np <= 0) return true;
+  if (np > CHOL_GROUP_MAX) return false;
+  PotrfGroup g{};
+  int64_t nmax = 0;
+  for (int p = 0; p < np; ++p) {
+    g.it[p] = it[p];
+    nmax = std::max(nmax, it[p].n);
+  }
+  const int tile = tune_choice(BSE_TUNE_GEMM_POTRF, it[0].n, 0);
+  ZgemmParams base;
+  base.conjA = 1;
+  base.alpha = make_double2(-1.0, 0.0);
+  base.beta = 1.0;
+  base.c_uplo = 1;
+  base.tile = tile;
+  std::vector<ZgemmItem> up;
+  auto panel = [&](int64_t j0) {
+    int gx = 0;
+    for (int p = 0; p < np; ++p) {
+      if (j0 >= it[p].n) continue;
+      const int64_t rest = it[p].n - j0 - std::min<int64_t>(CH_NB, it[p].n - j0);
+      gx = std::max(gx, rest > 0 ? cdiv(rest, PCOLS) : 1);
+    }
+    if (gx > 0)
+      BSE_LAUNCH(k_potrf_panel_b, dim3((unsigned)gx, (unsigned)np), dim3(PCOLS), 0, s, g,
+                 (int)j0);
+  };
+  for (int64_t j0 = 0; j0 < nmax; j0 += 2 * CH_NB) {
+    panel(j0);
+    const int64_t j1 = j0 + CH_NB;
+    up.clear();
+    for (int p = 0; p < np; ++p) {  // rows j1 .. j2-1 over columns j1 .. n-1
+      const int64_t n = it[p].n, rest1 = n - j1;
+      if (j0 >= n || rest1 <= 0) continue;
+      const int jb2 = (int)std::min<int64_t>(CH_NB, rest1);
+      up.push_back(herk_item(it[p], j0, CH_NB, j1, jb2, j1, (int)rest1));
+    }
+    base.tag = "zgemm_potrf_rows";
+    if (!up.empty() && zgemm_group(base, up.data(), (int)up.size(), s) != hipSuccess) return false;
+    panel(j1);
+    up.clear();
+    for (int p = 0; p < np; ++p) {  // trailing matrix: rows and columns j2 .. n-1
+      const int64_t n = it[p].n, rest1 = n - j1;
+      if (j0 >= n || rest1 <= 0) continue;
+      const int64_t j2 = j1 + std::min<int64_t>(CH_NB, rest1), rest2 = n - j2;
+      if (rest2 <= 0) continue;
+      up.push_back(herk_item(it[p], j0, 2 * CH_NB, j2, (int)rest2, j2, (int)rest2));
+    }
+    base.tag = "zgemm_potrf_herk";
+    if (!up.empty() && zgemm_group(base, up.data(), (int)up.size(), s) != hipSuccess) return false;
+  }
+  for (int p = 0; p < np; ++p)
+    BSE_LAUNCH(k_potrf_store, dim3((unsigned)cdiv(it[p].n, CH_NB)), dim3(256), 0, s, it[p].A,
+               it[p].ld, it[p].n, it[p].u11, it[p].info);
+  return hipGetLastError() == hipSuccess;
+}
+
+namespace {
+
 // Z := Q Z for the n x ncols complex matrix Z (column-major, ldz).
 bool apply_q(const double2* M, int64_t n, int64_t ld, double2* Z, int64_t ldz, int64_t ncols,
              SolveWs& w, int32_t* info, hipStream_t s) {
@@ -1286,14 +1392,15 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
   const bool project = (XpY == nullptr) && probe && osc;
   const dim3 cgrid((unsigned)std::min<int64_t>(cdiv(n, 256), 8),
                    (unsigned)std::min<int64_t>(n, 65535));
-  if (phase & SOLVE_PRE) {
+  if (phase & SOLVE_PRE1) {
     BSE_LAUNCH(k_zero_ints, dim3(1), dim3(64), 0, s, w.counters, 64);
     // X-Y (full BSE) comes from the first of the coupled equations,
     // (A+B)(X+Y) = (X-Y) E: A+B is kept in the X-Y buffer until X+Y exists
     if (full && XmY) BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, H0, ld, XmY, ldx, n);
-
+  }
+  if (full && (phase & SOLVE_CHOL) && !cholesky(H1, n, ld, w.W1, info, s)) return BSE_ERR_HIP;
+  if (phase & SOLVE_PRE2) {
     if (full) {
-      if (!cholesky(H1, n, ld, w.W1, info, s)) return BSE_ERR_HIP;
       ZgemmParams a;  // T1 = (A+B) U^H
       a.M = (int)n;
       a.N = (int)n;
@@ -1346,7 +1453,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
         BSE_LAUNCH(k_copy_c, dim3(cdiv(n, 256)), dim3(256), 0, s, probe, w.yvec, n);
       }
     }
-  }  // SOLVE_PRE
+  }  // SOLVE_PRE2
   TrdBufs tb{w.VW, w.WV, w.ybuf, w.hs, w.part, w.dd, w.ee, w.tau, project ? w.yvec : nullptr};
   if ((phase & SOLVE_SWEEP) && !tridiagonalise(Hm, n, ld, tb, info, s)) return BSE_ERR_HIP;
   if (!(phase & SOLVE_POST)) return BSE_OK;
@@ -1434,6 +1541,17 @@ TrdItem solve_sweep_item(const bse_desc* d, void* H0, void* ws, bool project, in
   it.n = (int64_t)d->nk * d->nv * d->nc;
   it.ld = d->ld;
   it.w = TrdBufs{w.VW, w.WV, w.ybuf, w.hs, w.part, w.dd, w.ee, w.tau, project ? w.yvec : nullptr};
+  it.info = info;
+  return it;
+}
+
+CholItem solve_chol_item(const bse_desc* d, void* H1, void* ws, int32_t* info) {
+  const SolveWs w = carve(d, ws);
+  CholItem it;
+  it.A = (double2*)H1;
+  it.ld = d->ld;
+  it.n = (int64_t)d->nk * d->nv * d->nc;
+  it.u11 = w.W1;
   it.info = info;
   return it;
 }

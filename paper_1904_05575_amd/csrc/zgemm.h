@@ -38,3 +38,24 @@ struct ZgemmParams {
 
 // Enqueue `batch` products on `stream`.
 hipError_t zgemm(const ZgemmParams& p, int batch, hipStream_t stream);
+
+// One product of a group: its own shape, operands, strides and status word.
+struct ZgemmItem {
+  const double2* A = nullptr;
+  const double2* B = nullptr;
+  double2* C = nullptr;
+  const int32_t* info = nullptr;
+  int M = 0, N = 0, K = 0;
+  int64_t a_rs = 0, a_cs = 0, b_rs = 0, b_cs = 0, c_rs = 0, c_cs = 0;
+};
+constexpr int ZGEMM_GROUP_MAX = 16;
+struct ZgemmGroup {
+  ZgemmItem it[ZGEMM_GROUP_MAX];
+};
+// Enqueue the products `items` (every other parameter from `base`, whose
+// shape, operand, stride and info fields are ignored): each item's values are
+// those zgemm(item, 1) gives (same tile edge and products per complex one);
+// items that share them run in launches of up to ZGEMM_GROUP_MAX items; items
+// with an empty output are skipped.
+hipError_t zgemm_group(const ZgemmParams& base, const ZgemmItem* items, int count,
+                       hipStream_t stream);

@@ -1,4 +1,7 @@
 // Strided / batched complex FP64 GEMM on MFMA (see zgemm.h).
+#include <algorithm>
+#include <vector>
+
 #include "bse_internal.h"
 #include "common.h"
 #include "mfma_tile.h"
@@ -7,15 +10,15 @@
 
 namespace {
 
+// One output tile (bx, by) of batch entry b.
 template <int BM, int BN, int WM, int WN, bool G3>
-__global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b_off) {
+BSE_DEV void zgemm_tile(const ZgemmParams& p, int bx, int by, int b) {
   using T = ZTile<BM, BN, WM, WN, G3>;
   __shared__ typename T::Smem2 sm;
   if (failed(p.info)) return;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int m0 = bx * BM, n0 = by * BN;
   if (p.c_uplo == 1 && m0 > n0 + BN - 1) return;
   if (p.c_uplo == 2 && n0 > m0 + BM - 1) return;
-  const int b = blockIdx.z + b_off;
   const int64_t bb = p.b_batch_idx ? (int64_t)p.b_batch_idx[b] : (int64_t)b;
   const double2* __restrict__ A = p.A + b * p.a_bs;
   const double2* __restrict__ B = p.B + bb * p.b_bs;
@@ -79,6 +82,53 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
 }
 
 template <int BM, int BN, int WM, int WN, bool G3>
+__global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b_off) {
+  zgemm_tile<BM, BN, WM, WN, G3>(p, blockIdx.x, blockIdx.y, blockIdx.z + b_off);
+}
+
+// Products of different shapes and operands (blockIdx.z = item), the rest of
+// the parameters shared; the items travel by value so that every operand load
+// is a global load.
+template <int BM, int BN, int WM, int WN, bool G3>
+__global__ __launch_bounds__(WM* WN * 64) void zgemm_group_kernel(ZgemmParams base, ZgemmGroup g) {
+  const ZgemmItem& q = g.it[blockIdx.z];
+  if ((int)blockIdx.x * BM >= q.M || (int)blockIdx.y * BN >= q.N) return;
+  ZgemmParams p = base;
+  p.M = q.M;
+  p.N = q.N;
+  p.K = q.K;
+  p.A = q.A;
+  p.a_rs = q.a_rs;
+  p.a_cs = q.a_cs;
+  p.B = q.B;
+  p.b_rs = q.b_rs;
+  p.b_cs = q.b_cs;
+  p.C = q.C;
+  p.c_rs = q.c_rs;
+  p.c_cs = q.c_cs;
+  p.info = q.info;
+  zgemm_tile<BM, BN, WM, WN, G3>(p, blockIdx.x, blockIdx.y, 0);
+}
+
+template <int BM, int BN, int WM, int WN, bool G3>
+hipError_t launch_group(const ZgemmParams& base, const ZgemmGroup& g, int count, hipStream_t s) {
+  int gm = 1, gn = 1;
+  for (int i = 0; i < count; ++i) {
+    gm = gm > cdiv(g.it[i].M, BM) ? gm : cdiv(g.it[i].M, BM);
+    gn = gn > cdiv(g.it[i].N, BN) ? gn : cdiv(g.it[i].N, BN);
+  }
+  TimedLaunch tl(base.tag, s);
+  if (tl.a)
+    hipExtLaunchKernelGGL((zgemm_group_kernel<BM, BN, WM, WN, G3>), dim3(gm, gn, count),
+                          dim3(WM * WN * 64), 0, s, tl.a, tl.b, 0, base, g);
+  else
+    hipLaunchKernelGGL((zgemm_group_kernel<BM, BN, WM, WN, G3>), dim3(gm, gn, count),
+                       dim3(WM * WN * 64), 0, s, base, g);
+  launch_check(base.tag);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int WM, int WN, bool G3>
 hipError_t launch(const ZgemmParams& p, int batch, hipStream_t s) {
   TimedLaunch tl(p.tag, s);
   // a timed product spans its first and last chunk of at most 65535 batch entries
@@ -109,6 +159,55 @@ int tile_edge(const ZgemmParams& p, int batch) {
 // Gauss's three products take a third more accumulators; measured at N = 6144
 // they pay on the 16- and 32-edge tiles (Householder and Cholesky updates,
 // exchange) and lose on the 64-edge tile, whose four-product form is kept.
+// Each item takes the tile edge and the products per complex one that zgemm()
+// would take for it alone, so that its values are those of that call; items
+// sharing both go into one launch.
+hipError_t zgemm_group(const ZgemmParams& base, const ZgemmItem* items, int count,
+                       hipStream_t s) {
+  std::vector<int> key(count, -1);
+  for (int i = 0; i < count; ++i) {
+    if (items[i].M <= 0 || items[i].N <= 0) continue;
+    ZgemmParams one = base;
+    one.M = items[i].M;
+    one.N = items[i].N;
+    const int prods = base.products ? base.products
+                                    : tune_choice(BSE_TUNE_GEMM_PRODUCTS,
+                                                  std::max(one.M, one.N), 3);
+    const int edge = tile_edge(one, 1);
+    key[i] = edge * 8 + (edge == 64 ? 4 : prods);
+  }
+  std::vector<char> done(count, 0);
+  for (int i = 0; i < count; ++i) {
+    if (key[i] < 0 || done[i]) continue;
+    ZgemmGroup g{};
+    int ng = 0;
+    for (int j = i; j < count && ng < ZGEMM_GROUP_MAX; ++j)
+      if (!done[j] && key[j] == key[i]) {
+        g.it[ng++] = items[j];
+        done[j] = 1;
+      }
+    hipError_t e;
+    switch (key[i]) {
+      case 16 * 8 + 3:
+        e = launch_group<16, 16, 1, 1, true>(base, g, ng, s);
+        break;
+      case 16 * 8 + 4:
+        e = launch_group<16, 16, 1, 1, false>(base, g, ng, s);
+        break;
+      case 32 * 8 + 3:
+        e = launch_group<32, 32, 2, 2, true>(base, g, ng, s);
+        break;
+      case 32 * 8 + 4:
+        e = launch_group<32, 32, 2, 2, false>(base, g, ng, s);
+        break;
+      default:
+        e = launch_group<64, 64, 2, 2, false>(base, g, ng, s);
+    }
+    if (e != hipSuccess) return e;  // items of this key past the first launch: later in the loop
+  }
+  return hipSuccess;
+}
+
 hipError_t zgemm(const ZgemmParams& p, int batch, hipStream_t s) {
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
   const int prods = p.products ? p.products
