@@ -962,13 +962,17 @@ bool tridiagonalise_batch(const TrdItem* it_all, int np_all, const void* dev, hi
         if (g.hemv > 0)
           BSE_LAUNCH(k_trd_hemv_b, dim3(g.hemv, np), dim3(HV_THREADS), 0, s, A, (int)j0, i);
       }
+      // S[t:, t:] -= [V W] [W V]^H for every problem, as one grouped GEMM per
+      // tuned tile (each item with the tile the single sweep gives it)
+      std::vector<ZgemmItem> up;
+      std::vector<int> tiles;
       for (int p = 0; p < np; ++p) {
         const TrdItem& q = it[p];
         if (j0 >= q.n - 1) continue;
         const int64_t t = j0 + std::min<int64_t>(TRD_NB, q.n - 1 - j0);
         const int64_t n = q.n;
         if (t >= n) continue;
-        ZgemmParams g;  // S[t:, t:] -= [V W] [W V]^H, as in the single sweep
+        ZgemmItem g;
         g.M = (int)(n - t);
         g.N = (int)(n - t);
         g.K = 2 * TRD_NB;
@@ -978,17 +982,31 @@ bool tridiagonalise_batch(const TrdItem* it_all, int np_all, const void* dev, hi
         g.B = q.w.WV + t;
         g.b_rs = n;
         g.b_cs = 1;
-        g.conjB = 1;
         g.C = q.M + t + t * q.ld;
         g.c_rs = 1;
         g.c_cs = q.ld;
-        g.c_uplo = 2;
-        g.alpha = make_double2(-1.0, 0.0);
-        g.beta = 1.0;
         g.info = q.info;
-        g.tag = "zgemm_her2k";
-        g.tile = tune_choice(BSE_TUNE_GEMM_HER2K, n, 0);
-        if (zgemm(g, 1, s) != hipSuccess) return false;
+        up.push_back(g);
+        tiles.push_back(tune_choice(BSE_TUNE_GEMM_HER2K, n, 0));
+      }
+      std::vector<char> done(up.size(), 0);
+      std::vector<ZgemmItem> grp;
+      for (size_t a = 0; a < up.size(); ++a) {
+        if (done[a]) continue;
+        grp.clear();
+        for (size_t b = a; b < up.size(); ++b)
+          if (!done[b] && tiles[b] == tiles[a]) {
+            grp.push_back(up[b]);
+            done[b] = 1;
+          }
+        ZgemmParams base;
+        base.conjB = 1;
+        base.c_uplo = 2;  // lower triangle only
+        base.alpha = make_double2(-1.0, 0.0);
+        base.beta = 1.0;
+        base.tag = "zgemm_her2k";
+        base.tile = tiles[a];
+        if (zgemm_group(base, grp.data(), (int)grp.size(), s) != hipSuccess) return false;
       }
     }
     for (int p = 0; p < np; ++p)
