@@ -207,6 +207,14 @@ BATCHES["batch4_k2_g15"] = _batch("batch4_k2_g15", mesh=2, ng=15, nq=4, qmax=1.5
 BATCHES["batch3_k3_g27"] = _batch("batch3_k3_g27", mesh=3, ng=27, nq=3, qmax=0.9,
                                   nvs=(2, 3, 2), ncs=(3, 4, 2), seed=22, kernel_scale=0.03125,
                                   nw=300, wmax=10.0)
+# more problems than one batched launch takes (16): the batched stages run in two groups
+BATCHES["batch18_k2_g15"] = _batch("batch18_k2_g15", mesh=2, ng=15, nq=18, qmax=1.5,
+                                   nvs=(1, 2, 3), ncs=(2, 3), seed=23, kernel_scale=0.015625,
+                                   nw=200, wmax=10.0)
+# Tamm-Dancoff members (no Cholesky factorisation, no coupling block)
+BATCHES["batch5_tda_k2_g15"] = _batch("batch5_tda_k2_g15", mesh=2, ng=15, nq=5, qmax=1.2,
+                                      nvs=(1, 2, 3), ncs=(2, 3), seed=24, kernel_scale=0.015625,
+                                      nw=200, wmax=10.0, coupling="tda")
 
 
 def get(name: str) -> Workload:

@@ -103,6 +103,29 @@ def test_batched_sweep_reproduces_per_problem_sweeps():
         L.bse_tune_set(old)
 
 
+@pytest.mark.parametrize("name", ["batch18_k2_g15", "batch5_tda_k2_g15"])
+def test_batched_stages_in_groups_and_tda(name):
+    """One branch per problem, so the factorisations and sweeps run batched: 18
+    problems (two groups of batched launches) and Tamm-Dancoff problems (no
+    factorisation).  Each member against the oracle (1e-10) and bit for bit
+    equal to the plain entry points one problem after another."""
+    ms = _members(name)
+    print(f"[gpu] batched stages {name}: sizes {[m['workload'].n for m in ms]}", flush=True)
+    B = _batch(ms, nbranch=len(ms))
+    B.run()
+    res = B.results()
+    for d, out in zip(ms, res):
+        r = O.run(d)
+        eig = np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min()
+        spec = np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max()
+        assert eig < 1e-10 and spec < 1e-10, (d["workload"].name, eig, spec)
+    B.run_sequential()
+    for i, (a, b) in enumerate(zip(res, B.results())):
+        for key in ("E", "osc", "eps"):
+            assert np.array_equal(a[key], b[key]), (i, key)
+    B.close()
+
+
 def test_graph_batch_mixed_precision():
     ms = _members("batch3_k3_g27")
     B = _batch(ms, precision="bf16x6")
