@@ -123,14 +123,18 @@ def _reflect(a, v):
             + 4.0 * c * np.outer(v, v.conj()))
 
 
-def test_order_beyond_lds_staging_known_spectrum():
+@pytest.mark.parametrize("nc", [3328, 4160])
+def test_order_beyond_lds_staging_known_spectrum(nc):
     """n = 6656, above the order whose shared rows the eigenvector kernel keeps
-    in LDS: A = Q diag(lam) Q^H with Q a product of three Householder
-    reflectors, so the eigenvalues are lam and the oscillator strengths
-    |(Q^H p)_l|^2 by construction.  lam holds two triples of equal values (the
-    cluster path) among values spaced 3e-4 apart."""
+    in LDS, and n = 8320, whose first trailing blocks have more than 128
+    tile-rows, so that the Householder column kernel gathers each row's hemv
+    slots in more than one round: A = Q diag(lam) Q^H with Q a product of three
+    Householder reflectors, so the eigenvalues are lam and the oscillator
+    strengths |(Q^H p)_l|^2 by construction.  lam holds two triples of equal
+    values (the cluster path) among values spaced 3e-4 apart (2.4e-4 at
+    n = 8320)."""
     torch = pytest.importorskip("torch")
-    nv, nc = 2, 3328
+    nv = 2
     P = _problem(nv, nc)
     n = P.n
     rng = np.random.default_rng(9)
