@@ -1301,8 +1301,129 @@ bool cholesky_batch(const CholItem* it, int np, hipStream_t s) {
 namespace {
 
 // Z := Q Z for the n x ncols complex matrix Z (column-major, ldz).
+// Groups of QG consecutive panels at a time (Z := P_a0 P_a1 ... Z, P_p = I - V_p
+// T_p V_p^H): with V = [V_a0 V_a1 ...] (columns J0.., rows J0+1..), W = V^H Z and
+// the Gram blocks G = V^H V, the panels' coefficient rows are Y_b = T_b (W_b -
+// sum_{c > b} G_bc Y_c), taken from the last panel back, and then Z -= V Y in one
+// product: one launch of K = m rows (W and G side by side) and one product of
+// K = 32 QG columns per group in place of QG of each with 32 (the panel products
+// of a 32-wide V use a small part of the machine at these orders).
+bool apply_q_grouped(const double2* M, int64_t n, int64_t ld, double2* Z, int64_t ldz,
+                     int64_t ncols, int QG, SolveWs& w, int32_t* info, hipStream_t s) {
+  const int GW = QG * TRD_NB;  // leading dimension of W, Y and G
+  const int64_t npnl = (n - 1 + TRD_NB - 1) / TRD_NB;
+  double2* W = (double2*)w.Dp;     // GW x ncols (pivot arrays: free after the eigenvectors)
+  double2* Y = (double2*)w.Dm;     // GW x ncols
+  double2* G = (double2*)w.Ztri;   // GW x GW (free once Z holds the eigenvectors)
+  const int64_t ngrp = (npnl + QG - 1) / QG;
+  for (int64_t g = ngrp - 1; g >= 0; --g) {
+    const int64_t p0 = g * QG, J0 = p0 * TRD_NB, m = n - J0 - 1;
+    const int k = (int)std::min<int64_t>(QG, npnl - p0);
+    const int wg = (int)std::min<int64_t>(GW, n - 1 - J0);
+    const double2* V = M + (J0 + 1) + J0 * ld;
+    // W = V^H Z[J0+1:, :] and G = V^H V (only its blocks above the diagonal
+    // are used) in one launch: the Gram's few tiles run beside W's
+    ZgemmItem it[2];
+    it[0].M = wg;
+    it[0].N = (int)ncols;
+    it[0].K = (int)m;
+    it[0].A = V;
+    it[0].a_rs = ld;
+    it[0].a_cs = 1;
+    it[0].a_tri = 1;
+    it[0].B = Z + (J0 + 1);
+    it[0].b_rs = 1;
+    it[0].b_cs = ldz;
+    it[0].C = W;
+    it[0].c_rs = 1;
+    it[0].c_cs = GW;
+    it[0].info = info;
+    it[1] = it[0];
+    it[1].N = wg;
+    it[1].B = V;
+    it[1].b_cs = ld;
+    it[1].b_tri = 2;
+    it[1].C = G;
+    ZgemmParams a;
+    a.conjA = 1;
+    a.products = tune_choice(BSE_TUNE_GEMM_PRODUCTS, std::max<int64_t>(wg, ncols), 3);
+    a.tag = "zgemm_bt_vhz";
+    if (zgemm_group(a, it, k > 1 ? 2 : 1, s) != hipSuccess) return false;
+    for (int b = k - 1; b >= 0; --b) {
+      const int64_t pnl = p0 + b;
+      const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - pnl * TRD_NB);
+      const int r0 = b * TRD_NB, rest = wg - r0 - jb;  // rows of the later panels in Y
+      if (rest > 0) {
+        ZgemmParams c;  // W_b -= G[b, later] Y[later]
+        c.M = jb;
+        c.N = (int)ncols;
+        c.K = rest;
+        c.A = G + r0 + (int64_t)(r0 + jb) * GW;
+        c.a_rs = 1;
+        c.a_cs = GW;
+        c.B = Y + (r0 + jb);
+        c.b_rs = 1;
+        c.b_cs = GW;
+        c.C = W + r0;
+        c.c_rs = 1;
+        c.c_cs = GW;
+        c.alpha = make_double2(-1.0, 0.0);
+        c.beta = 1.0;
+        c.info = info;
+        c.tag = "zgemm_bt_gw";
+        if (zgemm(c, 1, s) != hipSuccess) return false;
+      }
+      ZgemmParams t;  // Y_b = T_b W_b
+      t.M = jb;
+      t.N = (int)ncols;
+      t.K = jb;
+      t.A = w.Tall + pnl * TRD_NB * TRD_NB;
+      t.a_rs = 1;
+      t.a_cs = TRD_NB;
+      t.a_tri = 1;
+      t.B = W + r0;
+      t.b_rs = 1;
+      t.b_cs = GW;
+      t.C = Y + r0;
+      t.c_rs = 1;
+      t.c_cs = GW;
+      t.info = info;
+      t.tag = "zgemm_bt_tw";
+      if (zgemm(t, 1, s) != hipSuccess) return false;
+    }
+    ZgemmParams u;  // Z[J0+1:, :] -= V Y
+    u.M = (int)m;
+    u.N = (int)ncols;
+    u.K = wg;
+    u.A = V;
+    u.a_rs = 1;
+    u.a_cs = ld;
+    u.a_tri = 2;
+    u.B = Y;
+    u.b_rs = 1;
+    u.b_cs = GW;
+    u.C = Z + (J0 + 1);
+    u.c_rs = 1;
+    u.c_cs = ldz;
+    u.alpha = make_double2(-1.0, 0.0);
+    u.beta = 1.0;
+    u.info = info;
+    u.tag = "zgemm_bt_update";
+    if (zgemm(u, 1, s) != hipSuccess) return false;
+  }
+  return true;
+}
+
 bool apply_q(const double2* M, int64_t n, int64_t ld, double2* Z, int64_t ldz, int64_t ncols,
              SolveWs& w, int32_t* info, hipStream_t s) {
+  // groups of 8, else 4 panels, when the pivot arrays hold W and Y (32 QG rows
+  // of Z's columns each) and Ztri holds G (measured at N = 6144 with vectors:
+  // solve 358 ms panel by panel, 320 ms in groups of 4, 316 ms in groups of 8)
+  for (int qg : {8, 4}) {
+    const int64_t gw = (int64_t)qg * TRD_NB;
+    if (gw * ncols * 16 <= n * (n + EV_JUNK) * 8 && gw * gw * 16 <= n * n * 8)
+      return apply_q_grouped(M, n, ld, Z, ldz, ncols, qg, w, info, s);
+  }
   const int64_t npnl = (n - 1 + TRD_NB - 1) / TRD_NB;
   double2* W1 = w.W1;  // jb x ncols
   double2* W2 = w.W2;  // jb x ncols

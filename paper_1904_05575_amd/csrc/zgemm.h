@@ -46,6 +46,7 @@ struct ZgemmItem {
   double2* C = nullptr;
   const int32_t* info = nullptr;
   int M = 0, N = 0, K = 0;
+  int a_tri = 0, b_tri = 0;  // as in ZgemmParams (the base's are not used)
   int64_t a_rs = 0, a_cs = 0, b_rs = 0, b_cs = 0, c_rs = 0, c_cs = 0;
 };
 constexpr int ZGEMM_GROUP_MAX = 16;
@@ -53,7 +54,7 @@ struct ZgemmGroup {
   ZgemmItem it[ZGEMM_GROUP_MAX];
 };
 // Enqueue the products `items` (every other parameter from `base`, whose
-// shape, operand, stride and info fields are ignored): each item's values are
+// shape, operand, stride, triangle and info fields are ignored): each item's values are
 // those zgemm(item, 1) gives (same tile edge and products per complex one);
 // items that share them run in launches of up to ZGEMM_GROUP_MAX items; items
 // with an empty output are skipped.

@@ -107,6 +107,8 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_group_kernel(ZgemmParams ba
   p.c_rs = q.c_rs;
   p.c_cs = q.c_cs;
   p.info = q.info;
+  p.a_tri = q.a_tri;
+  p.b_tri = q.b_tri;
   zgemm_tile<BM, BN, WM, WN, G3>(p, blockIdx.x, blockIdx.y, 0);
 }
 
