@@ -732,10 +732,8 @@ int64_t hemv_tiles_max(int64_t n) {
   return nI * (nI + 1) / 2;
 }
 
-// Blocks of a hemv launch over a trailing block of order m: one per compute
-// unit, or fewer so that each takes at least the tuned number of tiles (1, 2,
-// 4 or 8; fewer, longer runs can pay for small trailing matrices).
-int hemv_grid(int64_t m) {
+// Compute units of the current device (256 when the query fails).
+int device_cus() {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
@@ -744,6 +742,14 @@ int hemv_grid(int64_t m) {
         cus <= 0)
       cus = 256;
   }
+  return cus;
+}
+
+// Blocks of a hemv launch over a trailing block of order m: one per compute
+// unit, or fewer so that each takes at least the tuned number of tiles (1, 2,
+// 4 or 8; fewer, longer runs can pay for small trailing matrices).
+int hemv_grid(int64_t m) {
+  const int cus = device_cus();
   const int64_t nI = (m + HT - 1) / HT, T = nI * (nI + 1) / 2;
   const int least = tune_choice(BSE_TUNE_HEMV_UNIT, m, 1);
   return (int)std::max<int64_t>(1, std::min<int64_t>(cus, (T + least - 1) / least));
@@ -818,18 +824,6 @@ void trd_parts(const TrdItem& it, double2** partA, double2** partB, double2** Y)
   *partA = it.w.part;
   *partB = it.w.part + ((it.n + ROWS_A - 1) / ROWS_A + 1) * NVAL;
   *Y = *partB + hemv_tiles_max(it.n) + 1;
-}
-
-int device_cus() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-  }
-  return cus;
 }
 
 // Blocks of every problem's hemv launch for reflector c, c = 0 .. n - 2: by
