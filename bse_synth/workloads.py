@@ -211,6 +211,9 @@ BATCHES["batch3_k3_g27"] = _batch("batch3_k3_g27", mesh=3, ng=27, nq=3, qmax=0.9
 BATCHES["batch18_k2_g15"] = _batch("batch18_k2_g15", mesh=2, ng=15, nq=18, qmax=1.5,
                                    nvs=(1, 2, 3), ncs=(2, 3), seed=23, kernel_scale=0.015625,
                                    nw=200, wmax=10.0)
+# the smallest orders (N = 1, 2, 6: no Householder step, a single one, one panel)
+BATCHES["batch3_k1_g9"] = _batch("batch3_k1_g9", mesh=1, ng=9, nq=3, qmax=0.5, nvs=(1, 2, 2),
+                                 ncs=(1, 1, 3), seed=25, kernel_scale=0.004, nw=100, wmax=10.0)
 # Tamm-Dancoff members (no Cholesky factorisation, no coupling block)
 BATCHES["batch5_tda_k2_g15"] = _batch("batch5_tda_k2_g15", mesh=2, ng=15, nq=5, qmax=1.2,
                                       nvs=(1, 2, 3), ncs=(2, 3), seed=24, kernel_scale=0.015625,

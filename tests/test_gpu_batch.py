@@ -103,11 +103,11 @@ def test_batched_sweep_reproduces_per_problem_sweeps():
         L.bse_tune_set(old)
 
 
-@pytest.mark.parametrize("name", ["batch18_k2_g15", "batch5_tda_k2_g15"])
+@pytest.mark.parametrize("name", ["batch18_k2_g15", "batch5_tda_k2_g15", "batch3_k1_g9"])
 def test_batched_stages_in_groups_and_tda(name):
     """One branch per problem, so the factorisations and sweeps run batched: 18
-    problems (two groups of batched launches) and Tamm-Dancoff problems (no
-    factorisation).  Each member against the oracle (1e-10) and bit for bit
+    problems (two groups of batched launches), Tamm-Dancoff problems (no
+    factorisation) and the smallest orders (N = 1, 2, 6).  Each member against the oracle (1e-10) and bit for bit
     equal to the plain entry points one problem after another."""
     ms = _members(name)
     print(f"[gpu] batched stages {name}: sizes {[m['workload'].n for m in ms]}", flush=True)
