@@ -326,10 +326,18 @@ bse_status bse_screening(const bse_screen_desc* desc, const double* eps_v, const
  * recorded once into a HIP graph and replayed with one graph launch.
  * Problems run on `nbranch` concurrent branches (streams the batch creates
  * at default priority), largest N^3 first, each branch with its own slice of
- * the workspace.  All pointers given to bse_batch_capture stay baked into the
- * graph: they must stay valid until bse_batch_destroy.  `info` holds one
- * int32 per problem and is cleared at the start of every replay.  Capture
- * needs a created stream (not the NULL stream). */
+ * the workspace.  With one branch per problem (nbranch >= nprob) the Cholesky
+ * factorisations (Sec. 4.3) and the Householder sweeps of all problems run
+ * batched on the capture stream, each launch serving every problem (up to 16
+ * per launch), between per-problem stages on the branches; each problem's
+ * results are bitwise those of the plain entry points (with the default
+ * BSE_TUNE_BATCH_SWEEP choice).  bse_batch_create then allocates a small device
+ * table (the sweep's grid counts, 4 bytes per unit of problem order), which
+ * bse_batch_capture fills with a blocking copy: no replay of the batch may be
+ * running during a capture.  All pointers given to bse_batch_capture stay
+ * baked into the graph: they must stay valid until bse_batch_destroy.  `info`
+ * holds one int32 per problem and is cleared at the start of every replay.
+ * Capture needs a created stream (not the NULL stream). */
 typedef struct bse_batch* bse_batch_t;
 
 size_t bse_batch_workspace_size(int32_t nprob, const bse_desc* descs, int32_t nbranch);
