@@ -331,10 +331,10 @@ bse_status bse_screening(const bse_screen_desc* desc, const double* eps_v, const
  * batched on the capture stream, each launch serving every problem (up to 16
  * per launch), between per-problem stages on the branches; each problem's
  * results are bitwise those of the plain entry points (with the default
- * BSE_TUNE_BATCH_SWEEP choice).  bse_batch_create then allocates a small device
- * table (the sweep's grid counts, 4 bytes per unit of problem order), which
- * bse_batch_capture fills with a blocking copy: no replay of the batch may be
- * running during a capture.  All pointers given to bse_batch_capture stay
+ * BSE_TUNE_BATCH_SWEEP choice).  The workspace then also holds a small table
+ * (the sweep's grid counts, 4 bytes per unit of problem order, after the
+ * branch slices), which bse_batch_capture fills with a blocking host-to-device
+ * copy: no replay of the batch may be running during a capture.  All pointers given to bse_batch_capture stay
  * baked into the graph: they must stay valid until bse_batch_destroy.  `info`
  * holds one int32 per problem and is cleared at the start of every replay.
  * Capture needs a created stream (not the NULL stream). */

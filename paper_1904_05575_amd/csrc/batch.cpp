@@ -22,7 +22,9 @@ struct bse_batch {
   // with them): [r (1 + nbranch)] fork, [r (1 + nbranch) + 1 + b] join of branch b
   std::vector<hipEvent_t> events;
   size_t slice = 0;
-  void* trd_table = nullptr;  // device table of the batched sweep (one branch per problem)
+  // batched stages (one branch per problem): the sweep's device table sits in
+  // the caller's workspace after the branch slices
+  bool batched = false;
   size_t trd_bytes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -41,6 +43,13 @@ size_t slice_bytes(int nprob, const bse_desc* descs) {
   return (s + 255) & ~(size_t)255;
 }
 
+// Bytes of the batched sweep's device table, rounded to 256.
+size_t table_bytes(int nprob, const bse_desc* descs) {
+  std::vector<int64_t> ns(nprob);
+  for (int i = 0; i < nprob; ++i) ns[i] = (int64_t)descs[i].nk * descs[i].nv * descs[i].nc;
+  return (trd_batch_table_bytes(ns.data(), nprob) + 255) & ~(size_t)255;
+}
+
 void release(bse_batch* b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
@@ -56,7 +65,8 @@ size_t bse_batch_workspace_size(int32_t nprob, const bse_desc* descs, int32_t nb
   if (nprob <= 0 || !descs || nbranch <= 0) return 0;
   for (int i = 0; i < nprob; ++i)
     if (!batch_desc_ok(&descs[i])) return 0;
-  return slice_bytes(nprob, descs) * (size_t)std::min(nbranch, nprob);
+  return slice_bytes(nprob, descs) * (size_t)std::min(nbranch, nprob) +
+         (nbranch >= nprob ? table_bytes(nprob, descs) : 0);
 }
 
 bse_status bse_batch_create(int32_t nprob, const bse_desc* descs, int32_t nbranch,
@@ -97,14 +107,8 @@ bse_status bse_batch_create(int32_t nprob, const bse_desc* descs, int32_t nbranc
       return BSE_ERR_HIP;
     }
   if (b->nbranch == nprob) {
-    std::vector<int64_t> ns(nprob);
-    for (int i = 0; i < nprob; ++i) ns[i] = (int64_t)descs[i].nk * descs[i].nv * descs[i].nc;
-    b->trd_bytes = trd_batch_table_bytes(ns.data(), nprob);
-    if (hipMalloc(&b->trd_table, b->trd_bytes) != hipSuccess) {
-      b->trd_table = nullptr;
-      bse_batch_destroy(b);
-      return BSE_ERR_HIP;
-    }
+    b->batched = true;
+    b->trd_bytes = table_bytes(nprob, descs);
   }
   *out = b;
   return BSE_OK;
@@ -120,7 +124,7 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
       !ws || !info)
     return BSE_ERR_ARG;
   if (stream == nullptr) return BSE_ERR_ARG;  // the legacy NULL stream cannot be captured
-  if (ws_bytes < b->slice * (size_t)b->nbranch) return BSE_ERR_WORKSPACE;
+  if (ws_bytes < b->slice * (size_t)b->nbranch + b->trd_bytes) return BSE_ERR_WORKSPACE;
   for (int i = 0; i < b->nprob; ++i) {
     const bse_desc* d = &b->descs[i];
     const bse_inputs* in = &inputs[i];
@@ -136,14 +140,15 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
   release(b);
   // batched sweep: every problem's sweep arguments, written to the device
   // table before capture (a blocking copy; no replay of this batch may run)
-  const bool batched = b->trd_table != nullptr;
+  const bool batched = b->batched;
+  void* trd_table = (char*)ws + b->slice * (size_t)b->nbranch;
   std::vector<TrdItem> items;
   if (batched) {
     for (int i = 0; i < b->nprob; ++i) {
       void* wsb = (char*)ws + b->slice * (size_t)b->branch_of[i];
       items.push_back(solve_sweep_item(&b->descs[i], H0[i], wsb, true, info + i));
     }
-    if (!trd_batch_table(items.data(), b->nprob, b->trd_table, b->trd_bytes)) return BSE_ERR_HIP;
+    if (!trd_batch_table(items.data(), b->nprob, trd_table, b->trd_bytes)) return BSE_ERR_HIP;
   }
   const TimingState timing = timing_suspend();  // no events inside the graph
   bse_status st = BSE_OK;
@@ -217,7 +222,7 @@ bse_status bse_batch_capture(bse_batch_t b, const bse_inputs* inputs, void* cons
     for (int i = 0; i < b->nprob && st == BSE_OK; ++i) st = solve(i, SOLVE_PRE2);
     join(1);
     // the Householder sweeps of all problems as one, on the capture stream
-    if (st == BSE_OK && !tridiagonalise_batch(items.data(), b->nprob, b->trd_table, stream))
+    if (st == BSE_OK && !tridiagonalise_batch(items.data(), b->nprob, trd_table, stream))
       st = BSE_ERR_HIP;
     // round 2 on the branches: eigenvalues, oscillator strengths, spectrum
     fork(2);
@@ -255,7 +260,6 @@ void bse_batch_destroy(bse_batch_t b) {
     if (s) hipStreamDestroy(s);
   for (auto e : b->events)
     if (e) hipEventDestroy(e);
-  if (b->trd_table) hipFree(b->trd_table);
   delete b;
 }
 
