@@ -682,8 +682,9 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
 
 // ---- the same sweep over several independent problems at once: one launch
 // per kernel and column step serves every problem still reducing (blockIdx.y
-// selects the problem; blocks past a problem's grid return at once).  Every
-// problem goes through the same kernels, launches and values as on its own.
+// selects the problem; blocks past a problem's grid return at once).  The
+// kernel bodies are those of the single sweep, so with each problem's own hemv
+// grid (the default) every problem gets the values it gets on its own.
 __global__ __launch_bounds__(COL_THREADS) void k_trd_col_b(TrdBatchArgs a, int j0, int i) {
   const TrdProb p = a.p[blockIdx.y];
   const int n = p.n;
