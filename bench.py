@@ -550,7 +550,11 @@ def main() -> int:
         roof = {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": u,
                 "frac": ach / peak, "traffic": tr["bytes"] if tr else None,
                 "traffic_unit": "B per launch", "traffic_source": tr["source"] if tr else None,
-                "traffic_note": tr["note"] if tr else None,
+                "traffic_note": tr["note"] if tr else (
+                    "no counter summary of this kernel's current source: counter runs of "
+                    "processes that run the Householder sweep ended in a crash or a hang and "
+                    "are not taken" if bound == "hbm"
+                    else None),
                 "launches_per_step": launches / args.steps,
                 "avg_launch_us": total_ms / launches * 1e3,
                 "ms_per_step_with_events": roof_step_ms,
