@@ -149,8 +149,8 @@ bse_status bse_build(const bse_desc* desc, const bse_inputs* in, void* H0, void*
  *        X+Y = U^H Z E^-1/2  (same E and, up to phase, the same X+Y as the
  *        (A-B)^1/2 form of eq. auxham),
  *        X-Y = U^-1 Z E^1/2  (the (A-B)^-1/2 E^1/2 Z of the same section in
- *        Cholesky form), formed from the first coupled equation
- *        (A+B)(X+Y) = (X-Y) E; then (X+Y)^H (X-Y) = I.
+ *        Cholesky form), by a triangular solve with U; then
+ *        (X+Y)^H (X-Y) = I and (A+B)(X+Y) = (X-Y) E.
  *  TDA : A X = E X.
  *  H0, H1: the matrices from bse_build (overwritten).
  *  E     : [n] excitation energies, ascending (output).

@@ -44,6 +44,53 @@ __global__ __launch_bounds__(256) void k_copy_mat(const double2* __restrict__ sr
       dst[i + j * ldd] = src[i + j * lds];
 }
 
+// dst[:, j] = src[:, j] * e[j] (n x n, column-major)
+__global__ __launch_bounds__(256) void k_copy_scale_cols(const double2* __restrict__ src,
+                                                         int64_t lds, double2* __restrict__ dst,
+                                                         int64_t ldd, int64_t n,
+                                                         const double* __restrict__ e,
+                                                         const int32_t* info) {
+  if (failed(info)) return;
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+    const double f = e[j];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+      dst[i + j * ldd] = cscale(src[i + j * lds], f);
+  }
+}
+
+// X := U_b^-1 X for one nb x nb diagonal block U_b (nb <= 32) of an upper
+// triangular U with a real diagonal, over the nb rows of X: one thread per
+// column of X, backward substitution in registers, U_b in LDS.
+__global__ __launch_bounds__(256) void k_trsm_diag(const double2* __restrict__ U, int64_t ld,
+                                                   int nb, double2* __restrict__ X, int64_t ldx,
+                                                   int64_t ncols, const int32_t* info) {
+  __shared__ double2 u[32][33];
+  if (failed(info)) return;
+  const double2 zero = make_double2(0.0, 0.0);
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int r = e % 32, c = e / 32;
+    u[r][c] = (r < nb && c < nb && r <= c) ? U[r + (int64_t)c * ld] : zero;
+  }
+  __syncthreads();
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= ncols) return;
+  double2* xc = X + col * ldx;
+  double2 x[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) x[r] = r < nb ? xc[r] : zero;
+#pragma unroll
+  for (int r = 31; r >= 0; --r) {
+    double2 t = x[r];
+#pragma unroll
+    for (int k = r + 1; k < 32; ++k) t = csub(t, cmul(u[r][k], x[k]));  // u = 0 past nb
+    x[r] = r < nb ? cscale(t, 1.0 / u[r][r].x) : zero;
+  }
+#pragma unroll
+  for (int r = 0; r < 32; ++r)
+    if (r < nb) xc[r] = x[r];
+}
+
 __global__ void k_zero_ints(int32_t* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -1185,6 +1232,45 @@ bool herk_update(double2* H1, int64_t ld, int64_t u0, int k, int64_t r0, int row
   return zgemm(h, 1, s) == hipSuccess;
 }
 
+// X := U^-1 X for the n x n upper triangular U (real diagonal; column-major,
+// ld) and n x ncols X (ldx): blocks of TS_NB rows from the bottom, each solved
+// in 32-row diagonal blocks (the rows above them within the block updated by a
+// product of K <= 32), then the rows above the block updated by one product of
+// K = TS_NB.
+constexpr int TS_NB = 256;
+bool trsm_upper(const double2* U, int64_t ld, int64_t n, double2* X, int64_t ldx, int64_t ncols,
+                int32_t* info, hipStream_t s) {
+  auto update = [&](int64_t r0, int64_t rows, int64_t c0, int64_t k, const char* tag) {
+    ZgemmParams g;  // X[r0 : r0+rows] -= U[r0 : r0+rows, c0 : c0+k] X[c0 : c0+k]
+    g.M = (int)rows;
+    g.N = (int)ncols;
+    g.K = (int)k;
+    g.A = U + r0 + c0 * ld;
+    g.a_rs = 1;
+    g.a_cs = ld;
+    g.B = X + c0;
+    g.b_rs = 1;
+    g.b_cs = ldx;
+    g.C = X + r0;
+    g.c_rs = 1;
+    g.c_cs = ldx;
+    g.alpha = make_double2(-1.0, 0.0);
+    g.beta = 1.0;
+    g.info = info;
+    g.tag = tag;
+    return zgemm(g, 1, s) == hipSuccess;
+  };
+  for (int64_t i0 = ((n - 1) / TS_NB) * TS_NB, i1 = n; i1 > 0; i1 = i0, i0 -= TS_NB) {
+    for (int64_t s0 = i0 + ((i1 - 1 - i0) / 32) * 32, s1 = i1; s1 > i0; s1 = s0, s0 -= 32) {
+      BSE_LAUNCH(k_trsm_diag, dim3((unsigned)cdiv(ncols, 256)), dim3(256), 0, s,
+                 U + s0 + s0 * ld, ld, (int)(s1 - s0), X + s0, ldx, ncols, info);
+      if (s0 > i0 && !update(i0, s0 - i0, s0, s1 - s0, "zgemm_trsm_in")) return false;
+    }
+    if (i0 > 0 && !update(0, i0, i0, i1 - i0, "zgemm_trsm")) return false;
+  }
+  return hipGetLastError() == hipSuccess;
+}
+
 // A - B = U^H U (upper).  Panels of CH_NB columns are factored in pairs: after
 // the first panel of a pair only the second panel's rows are updated (K =
 // CH_NB), and after the second the trailing matrix takes one update of
@@ -1515,9 +1601,6 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
                    (unsigned)std::min<int64_t>(n, 65535));
   if (phase & SOLVE_PRE1) {
     BSE_LAUNCH(k_zero_ints, dim3(1), dim3(64), 0, s, w.counters, 64);
-    // X-Y (full BSE) comes from the first of the coupled equations,
-    // (A+B)(X+Y) = (X-Y) E: A+B is kept in the X-Y buffer until X+Y exists
-    if (full && XmY) BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, H0, ld, XmY, ldx, n);
   }
   if (full && (phase & SOLVE_CHOL) && !cholesky(H1, n, ld, w.W1, info, s)) return BSE_ERR_HIP;
   if (phase & SOLVE_PRE2) {
@@ -1627,24 +1710,10 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
       g.tag = "zgemm_recon";
       if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
       if (XmY) {
-        ZgemmParams h;  // X-Y = (A+B)(X+Y) E^-1 = U^-1 Z E^1/2  (Z free after the above)
-        h.M = (int)n;
-        h.N = (int)n;
-        h.K = (int)n;
-        h.A = XmY;
-        h.a_rs = 1;
-        h.a_cs = ldx;
-        h.B = XpY;
-        h.b_rs = 1;
-        h.b_cs = ldx;
-        h.C = w.Wk;
-        h.c_rs = 1;
-        h.c_cs = n;
-        h.ndiv = E;
-        h.info = info;
-        h.tag = "zgemm_xmy";
-        if (zgemm(h, 1, s) != hipSuccess) return BSE_ERR_HIP;
-        BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, w.Wk, n, XmY, ldx, n);
+        // X-Y = U^-1 Z E^1/2 = U^-1 (Z E^-1/2) E: the triangular solve in place on
+        // the scaled Z (free after the product above), columns then scaled by E
+        if (!trsm_upper(H1, ld, n, w.Wk, n, n, info, s)) return BSE_ERR_HIP;
+        BSE_LAUNCH(k_copy_scale_cols, cgrid, dim3(256), 0, s, w.Wk, n, XmY, ldx, n, E, info);
       }
     } else if (XmY) {  // TDA: Y = 0, X-Y = X+Y = X
       BSE_LAUNCH(k_copy_mat, cgrid, dim3(256), 0, s, XpY, ldx, XmY, ldx, n);
