@@ -409,6 +409,11 @@ int64_t bse_timing_report(char* buf, int64_t len);
  *                          single problem path); 1, 2 or 4 that many blocks per
  *                          compute unit in total, shared among the problems in
  *                          proportion to their tiles
+ *   BSE_TUNE_GEMM_VECTORS  size = problem order n; choice = GEMM tile edge
+ *                          16, 32 or 64 of the eigenvector path's products:
+ *                          the back-transform (W = V^H Z, Z -= V Y), X+Y =
+ *                          U^H Z and the updates of the triangular solve for
+ *                          X-Y (default 32 where no entry applies)
  * Among the entries of a site, the one with the smallest size_max >= size
  * applies; sizes no entry covers use built-in rules.  Every choice gives the
  * same results up to rounding order.  The table is read on the host when work
@@ -426,7 +431,8 @@ enum {
   BSE_TUNE_GEMM_EXCHANGE = 5,
   BSE_TUNE_DIRECT = 6,
   BSE_TUNE_GEMM_PRODUCTS = 7,
-  BSE_TUNE_BATCH_SWEEP = 8
+  BSE_TUNE_BATCH_SWEEP = 8,
+  BSE_TUNE_GEMM_VECTORS = 9
 };
 typedef struct {
   int32_t site;

@@ -25,7 +25,7 @@ EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bs
 NOALLOC_SCRATCH_BYTES = 32 << 20  # BSE_NOALLOC_SCRATCH_BYTES of bse.h
 TUNE_SITES = {"hemv_unit": 0, "gemm_squared": 1, "gemm_potrf": 2, "gemm_her2k": 3,
               "gemm_stage2": 4, "gemm_exchange": 5, "direct": 6, "gemm_products": 7,
-              "batch_sweep": 8}
+              "batch_sweep": 8, "gemm_vectors": 9}
 
 
 class BseDesc(ctypes.Structure):

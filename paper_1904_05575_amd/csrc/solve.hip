@@ -1258,6 +1258,7 @@ bool trsm_upper(const double2* U, int64_t ld, int64_t n, double2* X, int64_t ldx
     g.beta = 1.0;
     g.info = info;
     g.tag = tag;
+    g.tile = tune_choice(BSE_TUNE_GEMM_VECTORS, n, 32);
     return zgemm(g, 1, s) == hipSuccess;
   };
   for (int64_t i0 = ((n - 1) / TS_NB) * TS_NB, i1 = n; i1 > 0; i1 = i0, i0 -= TS_NB) {
@@ -1434,6 +1435,7 @@ bool apply_q_grouped(const double2* M, int64_t n, int64_t ld, double2* Z, int64_
     a.conjA = 1;
     a.products = tune_choice(BSE_TUNE_GEMM_PRODUCTS, std::max<int64_t>(wg, ncols), 3);
     a.tag = "zgemm_bt_vhz";
+    a.tile = tune_choice(BSE_TUNE_GEMM_VECTORS, n, 32);
     if (zgemm_group(a, it, k > 1 ? 2 : 1, s) != hipSuccess) return false;
     for (int b = k - 1; b >= 0; --b) {
       const int64_t pnl = p0 + b;
@@ -1495,6 +1497,7 @@ bool apply_q_grouped(const double2* M, int64_t n, int64_t ld, double2* Z, int64_
     u.beta = 1.0;
     u.info = info;
     u.tag = "zgemm_bt_update";
+    u.tile = tune_choice(BSE_TUNE_GEMM_VECTORS, n, 32);
     if (zgemm(u, 1, s) != hipSuccess) return false;
   }
   return true;
@@ -1535,6 +1538,7 @@ bool apply_q(const double2* M, int64_t n, int64_t ld, double2* Z, int64_t ldz, i
     a.c_cs = jb;
     a.info = info;
     a.tag = "zgemm_bt_vhz";
+    a.tile = tune_choice(BSE_TUNE_GEMM_VECTORS, n, 32);
     if (zgemm(a, 1, s) != hipSuccess) return false;
     ZgemmParams b;  // W2 = T W1
     b.M = jb;
@@ -1571,6 +1575,7 @@ bool apply_q(const double2* M, int64_t n, int64_t ld, double2* Z, int64_t ldz, i
     c.beta = 1.0;
     c.info = info;
     c.tag = "zgemm_bt_update";
+    c.tile = tune_choice(BSE_TUNE_GEMM_VECTORS, n, 32);
     if (zgemm(c, 1, s) != hipSuccess) return false;
   }
   return true;
@@ -1708,6 +1713,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
       g.c_cs = ldx;
       g.info = info;
       g.tag = "zgemm_recon";
+      g.tile = tune_choice(BSE_TUNE_GEMM_VECTORS, n, 32);
       if (zgemm(g, 1, s) != hipSuccess) return BSE_ERR_HIP;
       if (XmY) {
         // X-Y = U^-1 Z E^1/2 = U^-1 (Z E^-1/2) E: the triangular solve in place on

@@ -1,6 +1,6 @@
 """Autotuner of the library's tile choices (run on the GPU; writes a JSON table).
 
-    python -m paper_1904_05575_amd.tune [--out PATH] [--reps 2] [--hemv-only]
+    python -m paper_1904_05575_amd.tune [--out PATH] [--reps 2] [--hemv-only | --gemm-site SITE]
 
 For every tunable call site of the FP64 path (see bse_tune_entry in
 include/bse.h) the tuner builds and solves seeded synthetic problems of the
@@ -9,7 +9,8 @@ library's per-kernel events under each candidate choice, and keeps the
 fastest:
   * GEMM tile edge (32 or 64; 16 or 32 for the per-pair second contraction)
     for the squared form, the Cholesky and Householder trailing updates, the
-    per-pair contraction and the exchange term, per problem order n;
+    per-pair contraction, the exchange term and the eigenvector path's
+    products (timed in a solve with X+Y and X-Y), per problem order n;
   * the least number of tiles per block of the Householder hemv kernel
     (1, 2, 4, 8), per bucket of the trailing order m, on the largest problem.
 `load()` installs the table in the library (Problem and Batch call it once).
@@ -32,7 +33,10 @@ GEMM_SITES = {  # site -> (candidates, kernel tags timed)
     "gemm_her2k": ((32, 64), ("zgemm_her2k",)),
     "gemm_stage2": ((16, 32), ("zgemm_direct_stage2",)),
     "gemm_exchange": ((32, 64), ("zgemm_exchange",)),
+    "gemm_vectors": ((32, 64), ("zgemm_bt_vhz", "zgemm_bt_update", "zgemm_recon",
+                                "zgemm_trsm", "zgemm_trsm_in")),
 }
+VECTOR_SITES = ("gemm_vectors",)  # timed in a solve that forms X+Y and X-Y
 HEMV_BUCKETS = (1024, 2048, 3072, 4096, 8192)  # upper bounds of the trailing order m
 HEMV_UNITS = (1, 2, 4, 8)
 HEMV_TAGS = ("k_trd_hemv", "k_trd_col")
@@ -57,8 +61,9 @@ def load(path: str | None = None, force: bool = False) -> int:
     return len(entries)
 
 
-def _time_sites(P, tags, reps):
-    """Best-of-reps total event time (ms) of the kernels named in tags for build + solve."""
+def _time_sites(P, tags, reps, vectors=False):
+    """Best-of-reps total event time (ms) of the kernels named in tags for build +
+    solve (with X+Y and X-Y when `vectors`)."""
     import torch
     best = None
     for _ in range(reps):
@@ -66,12 +71,13 @@ def _time_sites(P, tags, reps):
         torch.cuda.synchronize()
         L.bse_timing_enable(True)
         P.build(H0, H1)
-        E, _, osc = P.solve(H0, H1)
+        out = P.solve(H0, H1, xmy=vectors)
         torch.cuda.synchronize()
         L.bse_timing_enable(False)
         P.check_info()
         k = L.bse_timing_report()
         t = sum(k[name][1] for name in tags if name in k)
+        del out
         best = t if best is None else min(best, t)
         del H0, H1
     return best
@@ -117,6 +123,47 @@ def run_hemv_only(out: str, reps: int = 2) -> dict:
     return tab
 
 
+def run_gemm_site_only(out: str, site: str, reps: int = 2) -> dict:
+    """Re-tune one GEMM site on every problem order, keeping the table's other
+    entries (installed while the site's choices are timed)."""
+    import torch
+    from bse_synth import BATCHES, get, make_batch_inputs, make_inputs
+    from .bse import Problem
+
+    cands, tags = GEMM_SITES[site]
+    with open(TABLE) as f:
+        tab = json.load(f)
+    keep = [e for e in tab["entries"] if e["site"] != site]
+    base = [(L.TUNE_SITES[e["site"]], int(e["size_max"]), int(e["choice"])) for e in keep]
+    measured = {k: v for k, v in tab.get("measured_ms", {}).items()
+                if not k.startswith(site + "@")}
+    problems = {}
+    for d in make_batch_inputs(BATCHES["batch16_k6_g89"]):
+        problems.setdefault(d["workload"].n, d)
+    big = make_inputs(get("full_q0_k8_v3c4_g113"))
+    problems[big["workload"].n] = big
+    t0 = time.time()
+    entries = list(keep)
+    for n in sorted(problems):
+        P = Problem(problems[n])
+        times = {}
+        for c in cands:
+            L.bse_tune_set(base + [(L.TUNE_SITES[site], n, c)])
+            times[c] = _time_sites(P, tags, reps, site in VECTOR_SITES)
+        best = min(times, key=times.get)
+        entries.append({"site": site, "size_max": n, "choice": best})
+        measured[f"{site}@{n}"] = {str(c): round(v, 4) for c, v in times.items()}
+        print(f"[tune] n={n} {site}: {times} -> {best}", file=sys.stderr, flush=True)
+        del P
+        torch.cuda.empty_cache()
+    L.bse_tune_set([])
+    tab["entries"], tab["measured_ms"] = entries, measured
+    tab[f"seconds_{site}"] = round(time.time() - t0, 1)
+    with open(out, "w") as f:
+        json.dump(tab, f, indent=1)
+    return tab
+
+
 def run(out: str, reps: int = 2) -> dict:
     import torch
     from bse_synth import BATCHES, get, make_batch_inputs, make_inputs
@@ -137,7 +184,7 @@ def run(out: str, reps: int = 2) -> dict:
             times = {}
             for c in cands:
                 L.bse_tune_set([(L.TUNE_SITES[site], n, c)])
-                times[c] = _time_sites(P, tags, reps)
+                times[c] = _time_sites(P, tags, reps, site in VECTOR_SITES)
             best = min(times, key=times.get)
             entries.append({"site": site, "size_max": n, "choice": best})
             measured[f"{site}@{n}"] = {str(c): round(v, 4) for c, v in times.items()}
@@ -174,8 +221,15 @@ def main() -> int:
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--hemv-only", action="store_true",
                     help="re-tune the hemv buckets only, keeping the other entries")
+    ap.add_argument("--gemm-site", choices=sorted(GEMM_SITES),
+                    help="re-tune one GEMM site only, keeping the other entries")
     args = ap.parse_args()
-    tab = run_hemv_only(args.out, args.reps) if args.hemv_only else run(args.out, args.reps)
+    if args.hemv_only:
+        tab = run_hemv_only(args.out, args.reps)
+    elif args.gemm_site:
+        tab = run_gemm_site_only(args.out, args.gemm_site, args.reps)
+    else:
+        tab = run(args.out, args.reps)
     print(json.dumps({"entries": len(tab["entries"]), "seconds": tab.get("seconds"),
                       "out": args.out}))
     return 0

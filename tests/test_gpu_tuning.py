@@ -103,3 +103,36 @@ def test_gemm_products(name, products):
         assert np.abs(A @ X - X * E).max() < 1e-11 * E.max()
     else:
         assert np.abs((A - B) @ ((A + B) @ X) - X * E ** 2).max() < 1e-10 * E.max() ** 2
+
+
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_vectors_under_forced_tile_choices(tile):
+    """The eigenvector path's products (back-transform, X+Y = U^H Z, the
+    triangular solve for X-Y) under every tile edge of their site: the coupled
+    equations (A+B)(X+Y) = (X-Y)E and (A-B)(X-Y) = (X+Y)E with the oracle's
+    A and B, the normalisation (X+Y)^H (X-Y) = I and the oracle's eigenvalues.
+    N = 768 spans three 256-row blocks of the solve and three reflector groups."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_05575_amd import _lib as L
+    from paper_1904_05575_amd.bse import Problem
+    name = "mid_full_k4_v3c4_g59"
+    print(f"[gpu] {name} vectors tile {tile}", flush=True)
+    P = Problem(inputs(name))
+    old = L.bse_tune_get()
+    try:
+        L.bse_tune_set([(L.TUNE_SITES["gemm_vectors"], 1 << 20, tile)])
+        H0, H1 = P.build()
+        E, XpY, XmY, _ = P.solve(H0, H1, xmy=True)
+        P.check_info()
+    finally:
+        L.bse_tune_set(old)
+    E, XpY, XmY = E.cpu().numpy(), XpY.T.cpu().numpy(), XmY.T.cpu().numpy()
+    r = oracle_run(name)
+    A, B = r["A"], r["B"]
+    n, scale = len(E), E.max()
+    assert np.abs(E - r["E"]).max() / np.abs(r["E"]).min() < 1e-10
+    assert np.abs((A + B) @ XpY - XmY * E).max() < 1e-10 * scale
+    assert np.abs((A - B) @ XmY - XpY * E).max() < 1e-10 * scale
+    assert np.abs(XpY.conj().T @ XmY - np.eye(n)).max() < 1e-10
