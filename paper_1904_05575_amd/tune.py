@@ -1,6 +1,7 @@
 """Autotuner of the library's tile choices (run on the GPU; writes a JSON table).
 
-    python -m paper_1904_05575_amd.tune [--out PATH] [--reps 2] [--hemv-only | --gemm-site SITE]
+    python -m paper_1904_05575_amd.tune [--out PATH] [--reps 2]
+                                        [--hemv-only | --gemm-site SITE | --batch-sweep-only]
 
 For every tunable call site of the FP64 path (see bse_tune_entry in
 include/bse.h) the tuner builds and solves seeded synthetic problems of the
@@ -12,7 +13,10 @@ fastest:
     per-pair contraction, the exchange term and the eigenvector path's
     products (timed in a solve with X+Y and X-Y), per problem order n;
   * the least number of tiles per block of the Householder hemv kernel
-    (1, 2, 4, 8), per bucket of the trailing order m, on the largest problem.
+    (1, 2, 4, 8), per bucket of the trailing order m, on the largest problem;
+  * the blocks of the batched sweep's hemv launches (each problem's own grid,
+    or 1, 2, 4 per compute unit shared among the problems), timed on the
+    batch16 graph, for batches up to its largest order.
 `load()` installs the table in the library (Problem and Batch call it once).
 """
 from __future__ import annotations
@@ -40,6 +44,8 @@ VECTOR_SITES = ("gemm_vectors",)  # timed in a solve that forms X+Y and X-Y
 HEMV_BUCKETS = (1024, 2048, 3072, 4096, 8192)  # upper bounds of the trailing order m
 HEMV_UNITS = (1, 2, 4, 8)
 HEMV_TAGS = ("k_trd_hemv", "k_trd_col")
+BATCH_SWEEP_CHOICES = (0, 1, 2, 4)
+BATCH_WORKLOAD = "batch16_k6_g89"
 
 _loaded = False
 
@@ -81,6 +87,60 @@ def _time_sites(P, tags, reps, vectors=False):
         best = t if best is None else min(best, t)
         del H0, H1
     return best
+
+
+def _tune_batch_sweep(base, reps, measured):
+    """Time the batch16 graph (one branch per problem, FP64) under each batched
+    sweep choice with the entries `base` installed; returns the table entry."""
+    import torch
+    from bse_synth import BATCHES, make_batch_inputs
+    from .batch import Batch
+
+    load()  # Batch() installs the stored table once; do it before the candidates
+    ms = make_batch_inputs(BATCHES[BATCH_WORKLOAD])
+    nmax = max(d["workload"].n for d in ms)
+    times = {}
+    for c in BATCH_SWEEP_CHOICES:
+        L.bse_tune_set(base + [(L.TUNE_SITES["batch_sweep"], nmax, c)])
+        B = Batch(ms, precision="fp64", nbranch=len(ms))
+        B.run()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            B.run()
+            b.record()
+            torch.cuda.synchronize()
+            t = a.elapsed_time(b)
+            best = t if best is None else min(best, t)
+        B.results()  # raises on a device error
+        B.close()
+        del B
+        torch.cuda.empty_cache()
+        times[c] = best
+    best = min(times, key=times.get)
+    measured[f"batch_sweep@{BATCH_WORKLOAD}"] = {str(c): round(v, 2) for c, v in times.items()}
+    print(f"[tune] {BATCH_WORKLOAD} batch_sweep: {times} -> {best}", file=sys.stderr, flush=True)
+    return {"site": "batch_sweep", "size_max": nmax, "choice": best}
+
+
+def run_batch_sweep_only(out: str, reps: int = 2) -> dict:
+    """Re-tune only the batched sweep's choice, keeping the table's other entries."""
+    with open(TABLE) as f:
+        tab = json.load(f)
+    keep = [e for e in tab["entries"] if e["site"] != "batch_sweep"]
+    base = [(L.TUNE_SITES[e["site"]], int(e["size_max"]), int(e["choice"])) for e in keep]
+    measured = {k: v for k, v in tab.get("measured_ms", {}).items()
+                if not k.startswith("batch_sweep@")}
+    t0 = time.time()
+    entry = _tune_batch_sweep(base, reps, measured)
+    L.bse_tune_set([])
+    tab["entries"], tab["measured_ms"] = keep + [entry], measured
+    tab["seconds_batch_sweep"] = round(time.time() - t0, 1)
+    with open(out, "w") as f:
+        json.dump(tab, f, indent=1)
+    return tab
 
 
 def run_hemv_only(out: str, reps: int = 2) -> dict:
@@ -206,6 +266,10 @@ def run(out: str, reps: int = 2) -> dict:
         measured[f"hemv_unit@m<={hi}"] = {str(k): round(v, 4) for k, v in times.items()}
         print(f"[tune] m<={hi} hemv_unit: {times} -> {best}", file=sys.stderr, flush=True)
         lo = hi
+    del P
+    torch.cuda.empty_cache()
+    base = [(L.TUNE_SITES[e["site"]], int(e["size_max"]), int(e["choice"])) for e in entries]
+    entries.append(_tune_batch_sweep(base, reps, measured))
     L.bse_tune_set([])
     tab = {"device": torch.cuda.get_device_name(0), "entries": entries,
            "measured_ms": measured, "seconds": round(time.time() - t0, 1),
@@ -223,9 +287,13 @@ def main() -> int:
                     help="re-tune the hemv buckets only, keeping the other entries")
     ap.add_argument("--gemm-site", choices=sorted(GEMM_SITES),
                     help="re-tune one GEMM site only, keeping the other entries")
+    ap.add_argument("--batch-sweep-only", action="store_true",
+                    help="re-tune the batched sweep's choice only, keeping the other entries")
     args = ap.parse_args()
     if args.hemv_only:
         tab = run_hemv_only(args.out, args.reps)
+    elif args.batch_sweep_only:
+        tab = run_batch_sweep_only(args.out, args.reps)
     elif args.gemm_site:
         tab = run_gemm_site_only(args.out, args.gemm_site, args.reps)
     else:

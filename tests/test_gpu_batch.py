@@ -1,4 +1,6 @@
 """Batched finite-Q problems replayed as one HIP graph, against the oracle."""
+import contextlib
+
 import numpy as np
 import pytest
 
@@ -18,6 +20,23 @@ def _batch(members, precision="fp64", nbranch=3):
         pytest.skip("no GPU")
     from paper_1904_05575_amd.batch import Batch
     return Batch(members, precision=precision, nbranch=nbranch)
+
+
+@contextlib.contextmanager
+def _sweep_choice(choice):
+    """The stored tuning table with its batched-sweep entries replaced by
+    `choice` for every size (0: each problem's own hemv grid, whose values are
+    those of the problem's own sweep bit for bit)."""
+    from paper_1904_05575_amd import _lib as L
+    from paper_1904_05575_amd import tune
+    tune.load()
+    old = L.bse_tune_get()
+    site = L.TUNE_SITES["batch_sweep"]
+    try:
+        L.bse_tune_set([e for e in old if e[0] != site] + [(site, 1 << 20, choice)])
+        yield
+    finally:
+        L.bse_tune_set(old)
 
 
 @pytest.mark.parametrize("nbranch", [3, 16])
@@ -66,12 +85,9 @@ def test_batched_sweep_reproduces_per_problem_sweeps():
     per-branch sweeps and the plain entry points give identical E, osc and eps;
     with the blocks shared among the problems (choices 1, 2, 4) the batched
     graph repeats its own bits on replay and matches the others to rounding."""
-    from paper_1904_05575_amd import _lib as L
     ms = _members("batch4_k2_g15")
     print(f"[gpu] batched sweep: sizes {[m['workload'].n for m in ms]}", flush=True)
-    old = L.bse_tune_get()
-    try:
-        L.bse_tune_set(old + [(L.TUNE_SITES["batch_sweep"], 1 << 20, 0)])
+    with _sweep_choice(0):
         Bb = _batch(ms, nbranch=len(ms))
         Bb.run()
         bat = Bb.results()
@@ -85,8 +101,9 @@ def test_batched_sweep_reproduces_per_problem_sweeps():
                 for key in ("E", "osc", "eps"):
                     assert np.array_equal(bat[i][key], other[key]), (i, key)
         Bb.close()
-        for per_cu in (1, 2, 4):
-            L.bse_tune_set(old + [(L.TUNE_SITES["batch_sweep"], 1 << 20, per_cu)])
+        Bp.close()
+    for per_cu in (1, 2, 4):
+        with _sweep_choice(per_cu):
             Bs = _batch(ms, nbranch=len(ms))
             Bs.run()
             sh = Bs.results()
@@ -98,17 +115,16 @@ def test_batched_sweep_reproduces_per_problem_sweeps():
                 assert np.abs(sh[i]["eps"] - seq[i]["eps"]).max() < 1e-10 * np.abs(
                     seq[i]["eps"] - 1).max(), (per_cu, i)
             Bs.close()
-        Bp.close()
-    finally:
-        L.bse_tune_set(old)
 
 
 @pytest.mark.parametrize("name", ["batch18_k2_g15", "batch5_tda_k2_g15", "batch3_k1_g9"])
 def test_batched_stages_in_groups_and_tda(name):
     """One branch per problem, so the factorisations and sweeps run batched: 18
     problems (two groups of batched launches), Tamm-Dancoff problems (no
-    factorisation) and the smallest orders (N = 1, 2, 6).  Each member against the oracle (1e-10) and bit for bit
-    equal to the plain entry points one problem after another."""
+    factorisation) and the smallest orders (N = 1, 2, 6).  Each member against
+    the oracle (1e-10) with the stored tuning table (a replay repeating its
+    bits), and, with each problem's own hemv grids, bit for bit equal to the
+    plain entry points one problem after another."""
     ms = _members(name)
     print(f"[gpu] batched stages {name}: sizes {[m['workload'].n for m in ms]}", flush=True)
     B = _batch(ms, nbranch=len(ms))
@@ -119,11 +135,20 @@ def test_batched_stages_in_groups_and_tda(name):
         eig = np.abs(out["E"] - r["E"]).max() / np.abs(r["E"]).min()
         spec = np.abs(out["eps"] - r["eps"]).max() / np.abs(r["eps"] - 1).max()
         assert eig < 1e-10 and spec < 1e-10, (d["workload"].name, eig, spec)
-    B.run_sequential()
+    B.run()
     for i, (a, b) in enumerate(zip(res, B.results())):
         for key in ("E", "osc", "eps"):
             assert np.array_equal(a[key], b[key]), (i, key)
     B.close()
+    with _sweep_choice(0):
+        B = _batch(ms, nbranch=len(ms))
+        B.run()
+        own = B.results()
+        B.run_sequential()
+        for i, (a, b) in enumerate(zip(own, B.results())):
+            for key in ("E", "osc", "eps"):
+                assert np.array_equal(a[key], b[key]), (i, key)
+        B.close()
 
 
 def test_graph_batch_mixed_precision():
@@ -140,7 +165,10 @@ def test_full_size_batch_sum_rules():
     """16 momentum transfers, N = 1296..5184, one graph: every member's E is
     positive and ascending, Im eps >= 0, and for three members the f-sum rule
     sum E |t|^2 = p^H (A-B) p holds with A-B from the oracle's blocks; a
-    replay and the sequential path give identical results."""
+    replay gives identical results and the sequential path the same to
+    rounding (the stored table shares the batched hemv blocks among the
+    problems); with each problem's own hemv grids the graph and the sequential
+    path agree bit for bit."""
     ms = _members("batch16_k6_g89")
     print(f"[gpu] batch16: sizes {[m['workload'].n for m in ms]}", flush=True)
     B = _batch(ms, nbranch=16)  # the benchmark's launch configuration
@@ -168,13 +196,27 @@ def test_full_size_batch_sum_rules():
             else:
                 fs += 2.0 * np.vdot(p[i], blk @ p[j]).real
         assert abs(np.sum(out["E"] * out["osc"]) - fs) < 1e-9 * fs, (idx, fs)
-    # sixteen problems in one batched sweep change the timing only: a replay and
-    # the plain entry points one problem after another reproduce every bit (a
-    # kernel whose blocks read what another block of it writes would not)
-    for again in (lambda: B.run(), lambda: B.run_sequential()):
-        again()
-        for i, (a, b) in enumerate(zip(res, B.results())):
+    B.run()
+    for i, (a, b) in enumerate(zip(res, B.results())):
+        assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["osc"], b["osc"]), i
+    B.run_sequential()
+    for i, (a, b) in enumerate(zip(res, B.results())):
+        assert np.abs(a["E"] - b["E"]).max() < 1e-12 * b["E"].max(), i
+        assert np.abs(a["osc"] - b["osc"]).max() < 1e-9 * b["osc"].max(), i
+        assert np.abs(a["eps"] - b["eps"]).max() < 1e-10 * np.abs(b["eps"] - 1).max(), i
+    B.close()
+    # with each problem's own hemv grids, sixteen problems in one batched sweep
+    # change the timing only: the plain entry points one problem after another
+    # reproduce every bit (a kernel whose blocks read what another block of it
+    # writes would not)
+    with _sweep_choice(0):
+        B = _batch(ms, nbranch=16)
+        B.run()
+        own = B.results()
+        B.run_sequential()
+        for i, (a, b) in enumerate(zip(own, B.results())):
             assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["osc"], b["osc"]), i
+        B.close()
 
 
 def test_concurrent_streams_reproduce_the_sequential_path():
