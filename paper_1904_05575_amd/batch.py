@@ -144,3 +144,43 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def main() -> int:
+    """Replay one batch workload's graph (one branch per problem, the stored
+    tuning table) and print the time per replay:
+
+        python -m paper_1904_05575_amd.batch [--workload batch16_k6_g89] [--replays 3]
+                                             [--precision fp64]
+    """
+    import argparse
+    import json
+    import sys
+    import time
+
+    from bse_synth import BATCHES, make_batch_inputs
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="batch16_k6_g89", choices=sorted(BATCHES))
+    ap.add_argument("--replays", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
+    args = ap.parse_args()
+    ms = make_batch_inputs(BATCHES[args.workload])
+    B = Batch(ms, precision=args.precision, nbranch=len(ms))
+    B.run()  # capture and a first replay
+    B.results()
+    times = []
+    for _ in range(args.replays):
+        t0 = time.perf_counter()
+        B.run()
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0))
+        print(f"[batch] replay {len(times)}: {times[-1]:.1f} ms", file=sys.stderr, flush=True)
+    B.results()  # raises on a device error
+    B.close()
+    print(json.dumps({"workload": args.workload, "problems": len(ms),
+                      "precision": args.precision, "replay_ms": [round(t, 1) for t in times]}))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
