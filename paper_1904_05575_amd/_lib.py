@@ -25,7 +25,8 @@ EXPORTS = ("bse_workspace_size", "bse_build", "bse_solve", "bse_oscillator", "bs
 NOALLOC_SCRATCH_BYTES = 32 << 20  # BSE_NOALLOC_SCRATCH_BYTES of bse.h
 TUNE_SITES = {"hemv_unit": 0, "gemm_squared": 1, "gemm_potrf": 2, "gemm_her2k": 3,
               "gemm_stage2": 4, "gemm_exchange": 5, "direct": 6, "gemm_products": 7,
-              "batch_sweep": 8, "gemm_vectors": 9}
+              "batch_sweep": 8, "gemm_vectors": 9,
+              "batch_align": 10}
 
 
 class BseDesc(ctypes.Structure):
@@ -74,6 +75,14 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise BseError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1904_05575_amd.build`")
+        # PyTorch ships its own HIP and HSA runtimes under the same sonames as
+        # the system's.  Loaded after them, this library binds to torch's copy;
+        # loaded first, it would bind the system's and torch would then load a
+        # second runtime, in which case this library's launches find no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, dbl, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                  ctypes.c_double, ctypes.c_size_t)
