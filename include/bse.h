@@ -414,6 +414,13 @@ int64_t bse_timing_report(char* buf, int64_t len);
  *                          the back-transform (W = V^H Z, Z -= V Y), X+Y =
  *                          U^H Z and the updates of the triangular solve for
  *                          X-Y (default 32 where no entry applies)
+ *   BSE_TUNE_BATCH_ALIGN   size = largest problem order of a batch; choice =
+ *                          when each problem's batched Householder sweep
+ *                          starts: 0 (default) all at the first step; 1 late
+ *                          by the largest multiple of the panel width that
+ *                          keeps it within the largest problem's steps, so that
+ *                          the sweeps end together (every problem's values
+ *                          unchanged)
  * Among the entries of a site, the one with the smallest size_max >= size
  * applies; sizes no entry covers use built-in rules.  Every choice gives the
  * same results up to rounding order.  The table is read on the host when work
@@ -432,7 +439,8 @@ enum {
   BSE_TUNE_DIRECT = 6,
   BSE_TUNE_GEMM_PRODUCTS = 7,
   BSE_TUNE_BATCH_SWEEP = 8,
-  BSE_TUNE_GEMM_VECTORS = 9
+  BSE_TUNE_GEMM_VECTORS = 9,
+  BSE_TUNE_BATCH_ALIGN = 10
 };
 typedef struct {
   int32_t site;

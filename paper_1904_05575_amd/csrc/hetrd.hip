@@ -685,10 +685,11 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
 // selects the problem; blocks past a problem's grid return at once).  The
 // kernel bodies are those of the single sweep, so with each problem's own hemv
 // grid (the default) every problem gets the values it gets on its own.
-__global__ __launch_bounds__(COL_THREADS) void k_trd_col_b(TrdBatchArgs a, int j0, int i) {
+__global__ __launch_bounds__(COL_THREADS) void k_trd_col_b(TrdBatchArgs a, int jg, int i) {
   const TrdProb p = a.p[blockIdx.y];
   const int n = p.n;
-  if (j0 >= n - 1) return;  // this problem's sweep is over
+  const int j0 = jg - p.shift;  // this problem's panel at global panel step jg
+  if (j0 < 0 || j0 >= n - 1) return;  // its sweep has not started or is over
   const int jb = min(TRD_NB, n - 1 - j0);
   if (i > jb) return;       // its last panel is shorter
   const int c = j0 + i;
@@ -699,10 +700,11 @@ __global__ __launch_bounds__(COL_THREADS) void k_trd_col_b(TrdBatchArgs a, int j
               p.partB, p.yp, (int)blockIdx.x);
 }
 
-__global__ __launch_bounds__(HV_THREADS) void k_trd_hemv_b(TrdBatchArgs a, int j0, int i) {
+__global__ __launch_bounds__(HV_THREADS) void k_trd_hemv_b(TrdBatchArgs a, int jg, int i) {
   const TrdProb p = a.p[blockIdx.y];
   const int n = p.n;
-  if (j0 >= n - 1 || i >= min(TRD_NB, n - 1 - j0)) return;
+  const int j0 = jg - p.shift;
+  if (j0 < 0 || j0 >= n - 1 || i >= min(TRD_NB, n - 1 - j0)) return;
   const int G = __builtin_amdgcn_readfirstlane(p.grids[j0 + i]);  // uniform, kept scalar
   if ((int)blockIdx.x >= G) return;
   trd_hemv_dev(p.M, p.ld, n, p.VW, j0, i, p.hs, p.partA, p.partB, p.Y, p.ycs, p.dd, p.ee, p.tau,
@@ -832,10 +834,25 @@ void trd_parts(const TrdItem& it, double2** partA, double2** partB, double2** Y)
 // launch for step c has `per_cu` blocks per compute unit in all, each problem
 // still reducing at c getting a share proportional to its tiles (at least one,
 // at most one per tile), so that all blocks take runs of about equal length.
+// Global panel step at which each problem of a group starts its sweep: 0 for
+// all (BSE_TUNE_BATCH_ALIGN choice 0), or late by the largest multiple of
+// TRD_NB that keeps it within the largest problem's steps (choice 1), so that
+// the sweeps end together and every step reduces about the same bytes.
+std::vector<int> batch_shifts(const TrdItem* it, int np) {
+  int64_t nmax = 0;
+  for (int p = 0; p < np; ++p) nmax = std::max(nmax, it[p].n);
+  const int align = tune_choice(BSE_TUNE_BATCH_ALIGN, nmax, 0);
+  std::vector<int> sh(np, 0);
+  if (align == 1)
+    for (int p = 0; p < np; ++p) sh[p] = (int)(((nmax - it[p].n) / TRD_NB) * TRD_NB);
+  return sh;
+}
+
 std::vector<std::vector<int32_t>> batch_grids(const TrdItem* it, int np) {
   int64_t nmax = 0;
   for (int p = 0; p < np; ++p) nmax = std::max(nmax, it[p].n);
   const int per_cu = tune_choice(BSE_TUNE_BATCH_SWEEP, nmax, 0);
+  const std::vector<int> sh = batch_shifts(it, np);
   auto tiles = [](int64_t n, int64_t c) {
     const int64_t nI = (n - trd_org((int)c + 1) + HT - 1) / HT;
     return nI * (nI + 1) / 2;
@@ -843,12 +860,16 @@ std::vector<std::vector<int32_t>> batch_grids(const TrdItem* it, int np) {
   std::vector<std::vector<int32_t>> g(np);
   for (int p = 0; p < np; ++p) g[p].assign((size_t)std::max<int64_t>(it[p].n - 1, 0), 1);
   const double total = (double)per_cu * device_cus();
-  for (int64_t c = 0; c + 1 < nmax; ++c) {
+  // global column cg: problem p reduces its column cg - shift_p (if it has one)
+  for (int64_t cg = 0; cg + 1 < nmax; ++cg) {
     double sum = 0.0;
-    for (int p = 0; p < np; ++p)
-      if (c + 1 < it[p].n) sum += (double)tiles(it[p].n, c);
     for (int p = 0; p < np; ++p) {
-      if (c + 1 >= it[p].n) continue;
+      const int64_t c = cg - sh[p];
+      if (c >= 0 && c + 1 < it[p].n) sum += (double)tiles(it[p].n, c);
+    }
+    for (int p = 0; p < np; ++p) {
+      const int64_t c = cg - sh[p];
+      if (c < 0 || c + 1 >= it[p].n) continue;
       const int64_t T = tiles(it[p].n, c);
       int64_t G;
       if (per_cu == 0) {
@@ -868,11 +889,11 @@ struct StepGrids {
   int col = 0, hemv = 0;
 };
 StepGrids step_grids(const TrdItem* it, int np, const std::vector<std::vector<int32_t>>& grids,
-                     int64_t j0, int i) {
+                     const std::vector<int>& sh, int64_t jg, int i) {
   StepGrids g;
   for (int p = 0; p < np; ++p) {
-    const int64_t n = it[p].n;
-    if (j0 >= n - 1) continue;
+    const int64_t n = it[p].n, j0 = jg - sh[p];
+    if (j0 < 0 || j0 >= n - 1) continue;
     const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
     if (i > jb) continue;
     const int64_t c = j0 + i;
@@ -920,6 +941,7 @@ bool tridiagonalise_batch(const TrdItem* it_all, int np_all, const void* dev, hi
     const TrdItem* it = it_all + g0;
     const int np = std::min(TRD_BATCH_MAX, np_all - g0);
     const auto grids = batch_grids(it, np);  // as written into the table
+    const std::vector<int> sh = batch_shifts(it, np);
     TrdBatchArgs A{};
     int64_t nmax = 0;
     for (int p = 0; p < np; ++p) {
@@ -938,24 +960,26 @@ bool tridiagonalise_batch(const TrdItem* it_all, int np_all, const void* dev, hi
       t.dd = q.w.dd;
       t.ee = q.w.ee;
       t.grids = (const int32_t*)dev + off[g0 + p];
+      t.shift = sh[p];
       nmax = std::max(nmax, q.n);
     }
-    for (int64_t j0 = 0; j0 < nmax - 1; j0 += TRD_NB) {
+    for (int64_t jg = 0; jg < nmax - 1; jg += TRD_NB) {  // global panel steps
       int jbmax = 0;
       for (int p = 0; p < np; ++p) {
         const TrdItem& q = it[p];
-        if (j0 >= q.n - 1) continue;
+        const int64_t j0 = jg - sh[p];
+        if (j0 < 0 || j0 >= q.n - 1) continue;
         const int jb = (int)std::min<int64_t>(TRD_NB, q.n - 1 - j0);
         jbmax = std::max(jbmax, jb);
         if (jb < TRD_NB)
           BSE_LAUNCH(k_trd_zero_cols, dim3(256), dim3(256), 0, s, q.w.VW, q.w.WV, q.n, jb);
       }
       for (int i = 0; i <= jbmax; ++i) {
-        const StepGrids g = step_grids(it, np, grids, j0, i);
+        const StepGrids g = step_grids(it, np, grids, sh, jg, i);
         if (g.col > 0)
-          BSE_LAUNCH(k_trd_col_b, dim3(g.col, np), dim3(COL_THREADS), 0, s, A, (int)j0, i);
+          BSE_LAUNCH(k_trd_col_b, dim3(g.col, np), dim3(COL_THREADS), 0, s, A, (int)jg, i);
         if (g.hemv > 0)
-          BSE_LAUNCH(k_trd_hemv_b, dim3(g.hemv, np), dim3(HV_THREADS), 0, s, A, (int)j0, i);
+          BSE_LAUNCH(k_trd_hemv_b, dim3(g.hemv, np), dim3(HV_THREADS), 0, s, A, (int)jg, i);
       }
       // S[t:, t:] -= [V W] [W V]^H for every problem, as one grouped GEMM per
       // tuned tile (each item with the tile the single sweep gives it)
@@ -963,7 +987,8 @@ bool tridiagonalise_batch(const TrdItem* it_all, int np_all, const void* dev, hi
       std::vector<int> tiles;
       for (int p = 0; p < np; ++p) {
         const TrdItem& q = it[p];
-        if (j0 >= q.n - 1) continue;
+        const int64_t j0 = jg - sh[p];
+        if (j0 < 0 || j0 >= q.n - 1) continue;
         const int64_t t = j0 + std::min<int64_t>(TRD_NB, q.n - 1 - j0);
         const int64_t n = q.n;
         if (t >= n) continue;

@@ -40,7 +40,9 @@ struct TrdItem {
 };
 
 // Per-problem arguments of the batched kernels (grids[c] = blocks of the hemv
-// launch for reflector c, in device memory written by trd_batch_table).  They
+// launch for reflector c, in device memory written by trd_batch_table; shift =
+// the global panel step, a multiple of TRD_NB, at which this problem's sweep
+// starts: column c of the problem is reduced at global column shift + c).  They
 // travel by value in the kernel arguments, up to TRD_BATCH_MAX problems per
 // launch, so that the compiler knows every pointer to be device memory.
 struct TrdProb {
@@ -50,6 +52,7 @@ struct TrdProb {
   double2 *VW, *WV, *hs, *Y, *partA, *partB, *yp, *tau;
   double *dd, *ee;
   const int32_t* grids;
+  int shift;
 };
 constexpr int TRD_BATCH_MAX = 16;
 struct TrdBatchArgs {

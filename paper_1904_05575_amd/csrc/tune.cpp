@@ -27,6 +27,8 @@ bool valid(const bse_tune_entry& e) {
       return e.choice == 3 || e.choice == 4;
     case BSE_TUNE_BATCH_SWEEP:
       return e.choice == 0 || e.choice == 1 || e.choice == 2 || e.choice == 4;
+    case BSE_TUNE_BATCH_ALIGN:
+      return e.choice == 0 || e.choice == 1;
     default:
       return false;
   }

@@ -15,8 +15,10 @@ fastest:
   * the least number of tiles per block of the Householder hemv kernel
     (1, 2, 4, 8), per bucket of the trailing order m, on the largest problem;
   * the blocks of the batched sweep's hemv launches (each problem's own grid,
-    or 1, 2, 4 per compute unit shared among the problems), timed on the
-    batch16 graph, for batches up to its largest order.
+    or 1, 2, 4 per compute unit shared among the problems) together with when
+    the problems' sweeps start (all at once, or late so that they end
+    together), timed on the batch16 graph, for batches up to its largest
+    order.
 `load()` installs the table in the library (Problem and Batch call it once).
 """
 from __future__ import annotations
@@ -45,6 +47,8 @@ HEMV_BUCKETS = (1024, 2048, 3072, 4096, 8192)  # upper bounds of the trailing or
 HEMV_UNITS = (1, 2, 4, 8)
 HEMV_TAGS = ("k_trd_hemv", "k_trd_col")
 BATCH_SWEEP_CHOICES = (0, 1, 2, 4)
+BATCH_ALIGN_CHOICES = (0, 1)
+BATCH_SITES = ("batch_sweep", "batch_align")
 BATCH_WORKLOAD = "batch16_k6_g89"
 
 _loaded = False
@@ -90,8 +94,9 @@ def _time_sites(P, tags, reps, vectors=False):
 
 
 def _tune_batch_sweep(base, reps, measured):
-    """Time the batch16 graph (one branch per problem, FP64) under each batched
-    sweep choice with the entries `base` installed; returns the table entry."""
+    """Time the batch16 graph (one branch per problem, FP64) under each pair of
+    batched-sweep choices (hemv blocks; sweeps starting together or ending
+    together) with the entries `base` installed; returns the two table entries."""
     import torch
     from bse_synth import BATCHES, make_batch_inputs
     from .batch import Batch
@@ -100,43 +105,48 @@ def _tune_batch_sweep(base, reps, measured):
     ms = make_batch_inputs(BATCHES[BATCH_WORKLOAD])
     nmax = max(d["workload"].n for d in ms)
     times = {}
-    for c in BATCH_SWEEP_CHOICES:
-        L.bse_tune_set(base + [(L.TUNE_SITES["batch_sweep"], nmax, c)])
-        B = Batch(ms, precision="fp64", nbranch=len(ms))
-        B.run()
-        torch.cuda.synchronize()
-        best = None
-        for _ in range(reps):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
+    for al in BATCH_ALIGN_CHOICES:
+        for c in BATCH_SWEEP_CHOICES:
+            L.bse_tune_set(base + [(L.TUNE_SITES["batch_sweep"], nmax, c),
+                                   (L.TUNE_SITES["batch_align"], nmax, al)])
+            B = Batch(ms, precision="fp64", nbranch=len(ms))
             B.run()
-            b.record()
             torch.cuda.synchronize()
-            t = a.elapsed_time(b)
-            best = t if best is None else min(best, t)
-        B.results()  # raises on a device error
-        B.close()
-        del B
-        torch.cuda.empty_cache()
-        times[c] = best
-    best = min(times, key=times.get)
-    measured[f"batch_sweep@{BATCH_WORKLOAD}"] = {str(c): round(v, 2) for c, v in times.items()}
-    print(f"[tune] {BATCH_WORKLOAD} batch_sweep: {times} -> {best}", file=sys.stderr, flush=True)
-    return {"site": "batch_sweep", "size_max": nmax, "choice": best}
+            best = None
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                B.run()
+                b.record()
+                torch.cuda.synchronize()
+                t = a.elapsed_time(b)
+                best = t if best is None else min(best, t)
+            B.results()  # raises on a device error
+            B.close()
+            del B
+            torch.cuda.empty_cache()
+            times[(c, al)] = best
+    c, al = min(times, key=times.get)
+    measured[f"batch_sweep@{BATCH_WORKLOAD}"] = {f"{k[0]}/align{k[1]}": round(v, 2)
+                                                 for k, v in times.items()}
+    print(f"[tune] {BATCH_WORKLOAD} batch_sweep/align: {times} -> {(c, al)}", file=sys.stderr,
+          flush=True)
+    return [{"site": "batch_sweep", "size_max": nmax, "choice": c},
+            {"site": "batch_align", "size_max": nmax, "choice": al}]
 
 
 def run_batch_sweep_only(out: str, reps: int = 2) -> dict:
-    """Re-tune only the batched sweep's choice, keeping the table's other entries."""
+    """Re-tune only the batched sweep's choices, keeping the table's other entries."""
     with open(TABLE) as f:
         tab = json.load(f)
-    keep = [e for e in tab["entries"] if e["site"] != "batch_sweep"]
+    keep = [e for e in tab["entries"] if e["site"] not in BATCH_SITES]
     base = [(L.TUNE_SITES[e["site"]], int(e["size_max"]), int(e["choice"])) for e in keep]
     measured = {k: v for k, v in tab.get("measured_ms", {}).items()
                 if not k.startswith("batch_sweep@")}
     t0 = time.time()
-    entry = _tune_batch_sweep(base, reps, measured)
+    new = _tune_batch_sweep(base, reps, measured)
     L.bse_tune_set([])
-    tab["entries"], tab["measured_ms"] = keep + [entry], measured
+    tab["entries"], tab["measured_ms"] = keep + new, measured
     tab["seconds_batch_sweep"] = round(time.time() - t0, 1)
     with open(out, "w") as f:
         json.dump(tab, f, indent=1)
@@ -269,7 +279,7 @@ def run(out: str, reps: int = 2) -> dict:
     del P
     torch.cuda.empty_cache()
     base = [(L.TUNE_SITES[e["site"]], int(e["size_max"]), int(e["choice"])) for e in entries]
-    entries.append(_tune_batch_sweep(base, reps, measured))
+    entries += _tune_batch_sweep(base, reps, measured)
     L.bse_tune_set([])
     tab = {"device": torch.cuda.get_device_name(0), "entries": entries,
            "measured_ms": measured, "seconds": round(time.time() - t0, 1),

@@ -23,20 +23,60 @@ def _batch(members, precision="fp64", nbranch=3):
 
 
 @contextlib.contextmanager
-def _sweep_choice(choice):
+def _sweep_choice(choice, align=None):
     """The stored tuning table with its batched-sweep entries replaced by
     `choice` for every size (0: each problem's own hemv grid, whose values are
-    those of the problem's own sweep bit for bit)."""
+    those of the problem's own sweep bit for bit), and, if given, its
+    start-alignment entries by `align`."""
     from paper_1904_05575_amd import _lib as L
     from paper_1904_05575_amd import tune
     tune.load()
     old = L.bse_tune_get()
-    site = L.TUNE_SITES["batch_sweep"]
+    sites = {L.TUNE_SITES["batch_sweep"]: choice}
+    if align is not None:
+        sites[L.TUNE_SITES["batch_align"]] = align
     try:
-        L.bse_tune_set([e for e in old if e[0] != site] + [(site, 1 << 20, choice)])
+        L.bse_tune_set([e for e in old if e[0] not in sites] +
+                       [(site, 1 << 20, c) for site, c in sites.items()])
         yield
     finally:
         L.bse_tune_set(old)
+
+
+@pytest.mark.parametrize("name", ["batch4_k2_g15", "batch18_k2_g15", "batch3_k1_g9"])
+def test_batched_sweeps_ending_together(name):
+    """Each problem's sweep started late so that all end together (tuning site
+    batch_align): with each problem's own hemv grid every member's E, osc and
+    eps equal the plain entry points bit for bit; with the hemv blocks shared
+    among the problems a replay repeats its bits and the members agree with the
+    plain entry points to rounding.  Uneven orders, two groups of launches
+    (18 problems) and the smallest orders (N = 1, 2, 6)."""
+    ms = _members(name)
+    print(f"[gpu] sweeps ending together {name}: sizes {[m['workload'].n for m in ms]}",
+          flush=True)
+    with _sweep_choice(0, align=1):
+        B = _batch(ms, nbranch=len(ms))
+        B.run()
+        own = B.results()
+        B.run_sequential()
+        seq = B.results()
+        B.close()
+    for i, (a, b) in enumerate(zip(own, seq)):
+        for key in ("E", "osc", "eps"):
+            assert np.array_equal(a[key], b[key]), (i, key)
+    with _sweep_choice(4, align=1):
+        B = _batch(ms, nbranch=len(ms))
+        B.run()
+        sh = B.results()
+        B.run()
+        again = B.results()
+        B.close()
+    for i in range(len(ms)):
+        for key in ("E", "osc", "eps"):
+            assert np.array_equal(sh[i][key], again[i][key]), (i, key)
+        assert np.abs(sh[i]["E"] - seq[i]["E"]).max() <= 1e-12 * seq[i]["E"].max(), i
+        assert np.abs(sh[i]["eps"] - seq[i]["eps"]).max() <= 1e-10 * np.abs(
+            seq[i]["eps"] - 1).max(), i
 
 
 @pytest.mark.parametrize("nbranch", [3, 16])
