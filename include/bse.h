@@ -414,6 +414,11 @@ int64_t bse_timing_report(char* buf, int64_t len);
  *                          the back-transform (W = V^H Z, Z -= V Y), X+Y =
  *                          U^H Z and the updates of the triangular solve for
  *                          X-Y (default 32 where no entry applies)
+ *   BSE_TUNE_GEMM_SQUARED_S size = problem order n; choice = GEMM tile edge
+ *                          16, 32 or 64 of the squared form's second product
+ *                          (S = U T1, lower triangle); where no entry applies,
+ *                          that of BSE_TUNE_GEMM_SQUARED, which then sets the
+ *                          first product T1 = (A+B) U^H
  *   BSE_TUNE_BATCH_ALIGN   size = largest problem order of a batch; choice =
  *                          when each problem's batched Householder sweep
  *                          starts: 0 (default) all at the first step; 1 late
@@ -440,7 +445,8 @@ enum {
   BSE_TUNE_GEMM_PRODUCTS = 7,
   BSE_TUNE_BATCH_SWEEP = 8,
   BSE_TUNE_GEMM_VECTORS = 9,
-  BSE_TUNE_BATCH_ALIGN = 10
+  BSE_TUNE_BATCH_ALIGN = 10,
+  BSE_TUNE_GEMM_SQUARED_S = 11
 };
 typedef struct {
   int32_t site;

@@ -26,7 +26,7 @@ NOALLOC_SCRATCH_BYTES = 32 << 20  # BSE_NOALLOC_SCRATCH_BYTES of bse.h
 TUNE_SITES = {"hemv_unit": 0, "gemm_squared": 1, "gemm_potrf": 2, "gemm_her2k": 3,
               "gemm_stage2": 4, "gemm_exchange": 5, "direct": 6, "gemm_products": 7,
               "batch_sweep": 8, "gemm_vectors": 9,
-              "batch_align": 10}
+              "batch_align": 10, "gemm_squared_s": 11}
 
 
 class BseDesc(ctypes.Structure):

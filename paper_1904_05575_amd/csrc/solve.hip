@@ -1646,7 +1646,7 @@ bse_status solve_run(const bse_desc* d, void* H0v, void* H1v, double* E, void* X
       b.c_uplo = 2;
       b.info = info;
       b.tag = "zgemm_sq_s";
-      b.tile = tune_choice(BSE_TUNE_GEMM_SQUARED, n, 0);
+      b.tile = tune_choice(BSE_TUNE_GEMM_SQUARED_S, n, tune_choice(BSE_TUNE_GEMM_SQUARED, n, 0));
       if (zgemm(b, 1, s) != hipSuccess) return BSE_ERR_HIP;
       const int nt = cdiv(n, 32);
       BSE_LAUNCH(k_hermitize, dim3(nt, nt), dim3(256), 0, s, H0, n, ld, 1, info);

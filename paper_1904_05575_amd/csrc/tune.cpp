@@ -20,6 +20,7 @@ bool valid(const bse_tune_entry& e) {
     case BSE_TUNE_GEMM_STAGE2:
     case BSE_TUNE_GEMM_EXCHANGE:
     case BSE_TUNE_GEMM_VECTORS:
+    case BSE_TUNE_GEMM_SQUARED_S:
       return e.choice == 16 || e.choice == 32 || e.choice == 64;
     case BSE_TUNE_DIRECT:
       return e.choice >= 0 && e.choice <= 9;

@@ -9,7 +9,7 @@ batched and single-problem workloads, times the site's kernels with the
 library's per-kernel events under each candidate choice, and keeps the
 fastest:
   * GEMM tile edge (32 or 64; 16 or 32 for the per-pair second contraction)
-    for the squared form, the Cholesky and Householder trailing updates, the
+    for the squared form's two products, the Cholesky and Householder trailing updates, the
     per-pair contraction, the exchange term and the eigenvector path's
     products (timed in a solve with X+Y and X-Y), per problem order n;
   * the least number of tiles per block of the Householder hemv kernel
@@ -34,7 +34,8 @@ from . import _lib as L
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
 GEMM_SITES = {  # site -> (candidates, kernel tags timed)
-    "gemm_squared": ((32, 64), ("zgemm_sq_t1", "zgemm_sq_s")),
+    "gemm_squared": ((32, 64), ("zgemm_sq_t1",)),
+    "gemm_squared_s": ((32, 64), ("zgemm_sq_s",)),
     "gemm_potrf": ((32, 64), ("zgemm_potrf_herk",)),
     "gemm_her2k": ((32, 64), ("zgemm_her2k",)),
     "gemm_stage2": ((16, 32), ("zgemm_direct_stage2",)),

@@ -7,7 +7,7 @@ from tests._cache import inputs, oracle_run
 
 pytestmark = pytest.mark.gpu
 
-SITES = ("gemm_squared", "gemm_potrf", "gemm_her2k", "gemm_exchange")
+SITES = ("gemm_squared", "gemm_squared_s", "gemm_potrf", "gemm_her2k", "gemm_exchange")
 
 
 @pytest.mark.parametrize("unit,tile", [(1, 32), (8, 64), (2, 16)])

@@ -131,8 +131,8 @@ def test_tuning_table_round_trip_and_validation(lib):
     try:
         L.bse_tune_set([(0, 4096, 4), (1, 6144, 64), (4, 2000, 16)])
         assert L.bse_tune_get() == [(0, 4096, 4), (1, 6144, 64), (4, 2000, 16)]
-        for bad in ([(0, 4096, 3)], [(1, 6144, 48)], [(11, 10, 32)], [(2, 0, 32)], [(6, 100, 10)],
-                    [(8, 100, 3)], [(9, 100, 48)], [(10, 100, 2)]):
+        for bad in ([(0, 4096, 3)], [(1, 6144, 48)], [(12, 10, 32)], [(2, 0, 32)], [(6, 100, 10)],
+                    [(8, 100, 3)], [(9, 100, 48)], [(10, 100, 2)], [(11, 100, 8)]):
             with pytest.raises(L.BseError, match="BSE_ERR_ARG"):
                 L.bse_tune_set(bad)
             assert len(L.bse_tune_get()) == 3  # a rejected table changes nothing
