@@ -685,30 +685,44 @@ __global__ __launch_bounds__(HV_THREADS) void k_trd_hemv(
 // selects the problem; blocks past a problem's grid return at once).  The
 // kernel bodies are those of the single sweep, so with each problem's own hemv
 // grid (the default) every problem gets the values it gets on its own.
-__global__ __launch_bounds__(COL_THREADS) void k_trd_col_b(TrdBatchArgs a, int jg, int i) {
-  const TrdProb p = a.p[blockIdx.y];
+// The problem that owns this block of a batched launch (a uniform scan of the
+// block ranges in the kernel arguments).
+BSE_DEV int batch_problem(const TrdFirst& f) {
+  int p = 0;
+  while (p + 1 < TRD_BATCH_MAX && (int)blockIdx.x >= f.b[p + 1]) ++p;
+  return p;
+}
+
+__global__ __launch_bounds__(COL_THREADS) void k_trd_col_b(TrdBatchArgs a, TrdFirst f, int jg,
+                                                           int i) {
+  const int pi = batch_problem(f);
+  const TrdProb p = a.p[pi];
+  const int bx = (int)blockIdx.x - f.b[pi];  // block within the problem's column kernel
   const int n = p.n;
   const int j0 = jg - p.shift;  // this problem's panel at global panel step jg
   if (j0 < 0 || j0 >= n - 1) return;  // its sweep has not started or is over
   const int jb = min(TRD_NB, n - 1 - j0);
   if (i > jb) return;       // its last panel is shorter
   const int c = j0 + i;
-  if ((int)blockIdx.x >= cdiv(n - c, ROWS_A)) return;
+  if (bx >= cdiv(n - c, ROWS_A)) return;
   // uniform: readfirstlane keeps it (and all index arithmetic on it) scalar
   const int gprev = __builtin_amdgcn_readfirstlane(c > 0 ? p.grids[c - 1] : 1);
   trd_col_dev(p.M, p.ld, n, p.VW, p.WV, j0, i, i < jb ? 1 : 0, p.hs, p.Y, p.ycs, gprev, p.partA,
-              p.partB, p.yp, (int)blockIdx.x);
+              p.partB, p.yp, bx);
 }
 
-__global__ __launch_bounds__(HV_THREADS) void k_trd_hemv_b(TrdBatchArgs a, int jg, int i) {
-  const TrdProb p = a.p[blockIdx.y];
+__global__ __launch_bounds__(HV_THREADS) void k_trd_hemv_b(TrdBatchArgs a, TrdFirst f, int jg,
+                                                           int i) {
+  const int pi = batch_problem(f);
+  const TrdProb p = a.p[pi];
+  const int bx = (int)blockIdx.x - f.b[pi];
   const int n = p.n;
   const int j0 = jg - p.shift;
   if (j0 < 0 || j0 >= n - 1 || i >= min(TRD_NB, n - 1 - j0)) return;
-  const int G = __builtin_amdgcn_readfirstlane(p.grids[j0 + i]);  // uniform, kept scalar
-  if ((int)blockIdx.x >= G) return;
+  const int G = f.b[pi + 1] - f.b[pi];  // the table's grid count for this step
+  if (bx >= G) return;
   trd_hemv_dev(p.M, p.ld, n, p.VW, j0, i, p.hs, p.partA, p.partB, p.Y, p.ycs, p.dd, p.ee, p.tau,
-               p.yp, (int)blockIdx.x, G);
+               p.yp, bx, G);
 }
 
 __global__ void k_trd_last(const double2* M, int64_t ld, int n, double* dd, const int32_t* info) {
@@ -884,22 +898,30 @@ std::vector<std::vector<int32_t>> batch_grids(const TrdItem* it, int np) {
   return g;
 }
 
-// Per problem with a sweep step at (j0, i): its hemv grid and column grid.
+// The block ranges of the column-kernel and hemv launches of step (jg, i): per
+// problem reducing at that step its column grid and its hemv grid, in problem
+// order (compact grids: no block of a launch is idle).
 struct StepGrids {
-  int col = 0, hemv = 0;
+  TrdFirst col{}, hemv{};
 };
 StepGrids step_grids(const TrdItem* it, int np, const std::vector<std::vector<int32_t>>& grids,
                      const std::vector<int>& sh, int64_t jg, int i) {
   StepGrids g;
-  for (int p = 0; p < np; ++p) {
+  int nc = 0, nh = 0;
+  for (int p = 0; p < TRD_BATCH_MAX; ++p) {
+    g.col.b[p] = nc;
+    g.hemv.b[p] = nh;
+    if (p >= np) continue;
     const int64_t n = it[p].n, j0 = jg - sh[p];
     if (j0 < 0 || j0 >= n - 1) continue;
     const int jb = (int)std::min<int64_t>(TRD_NB, n - 1 - j0);
     if (i > jb) continue;
     const int64_t c = j0 + i;
-    g.col = std::max(g.col, cdiv(n - c, ROWS_A));
-    if (i < jb) g.hemv = std::max(g.hemv, (int)grids[p][c]);
+    nc += cdiv(n - c, ROWS_A);
+    if (i < jb) nh += (int)grids[p][c];
   }
+  g.col.b[TRD_BATCH_MAX] = nc;
+  g.hemv.b[TRD_BATCH_MAX] = nh;
   return g;
 }
 
@@ -976,10 +998,11 @@ bool tridiagonalise_batch(const TrdItem* it_all, int np_all, const void* dev, hi
       }
       for (int i = 0; i <= jbmax; ++i) {
         const StepGrids g = step_grids(it, np, grids, sh, jg, i);
-        if (g.col > 0)
-          BSE_LAUNCH(k_trd_col_b, dim3(g.col, np), dim3(COL_THREADS), 0, s, A, (int)jg, i);
-        if (g.hemv > 0)
-          BSE_LAUNCH(k_trd_hemv_b, dim3(g.hemv, np), dim3(HV_THREADS), 0, s, A, (int)jg, i);
+        const int ncol = g.col.b[TRD_BATCH_MAX], nhemv = g.hemv.b[TRD_BATCH_MAX];
+        if (ncol > 0)
+          BSE_LAUNCH(k_trd_col_b, dim3(ncol), dim3(COL_THREADS), 0, s, A, g.col, (int)jg, i);
+        if (nhemv > 0)
+          BSE_LAUNCH(k_trd_hemv_b, dim3(nhemv), dim3(HV_THREADS), 0, s, A, g.hemv, (int)jg, i);
       }
       // S[t:, t:] -= [V W] [W V]^H for every problem, as one grouped GEMM per
       // tuned tile (each item with the tile the single sweep gives it)

@@ -58,6 +58,12 @@ constexpr int TRD_BATCH_MAX = 16;
 struct TrdBatchArgs {
   TrdProb p[TRD_BATCH_MAX];
 };
+// A batched launch's blocks, problem after problem: problem p owns blocks
+// [b[p], b[p+1]); entries past the group's last problem equal the total, so a
+// problem with nothing to do at a step owns no block.
+struct TrdFirst {
+  int32_t b[TRD_BATCH_MAX + 1];
+};
 
 // Bytes of the device table (the hemv grid counts of every step) for problems
 // of orders n[0..np-1].
