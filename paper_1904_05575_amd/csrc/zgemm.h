@@ -52,6 +52,9 @@ struct ZgemmItem {
 constexpr int ZGEMM_GROUP_MAX = 16;
 struct ZgemmGroup {
   ZgemmItem it[ZGEMM_GROUP_MAX];
+  // the launch's blocks, item after item: item i owns [first[i], first[i+1])
+  // (entries past the last item equal the total)
+  int32_t first[ZGEMM_GROUP_MAX + 1];
 };
 // Enqueue the products `items` (every other parameter from `base`, whose
 // shape, operand, stride, triangle and info fields are ignored): each item's values are

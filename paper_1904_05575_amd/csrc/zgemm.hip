@@ -86,13 +86,44 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_kernel(ZgemmParams p, int b
   zgemm_tile<BM, BN, WM, WN, G3>(p, blockIdx.x, blockIdx.y, blockIdx.z + b_off);
 }
 
+// Square products that store one triangle (c_uplo 1 or 2, M = N, square
+// tiles) run on the triangle's tiles only: tile t of the nt (nt + 1) / 2 is
+// (I, J), I >= J, in row order of the lower triangle, i.e. (bx, by) = (I, J)
+// for the lower triangle and (J, I) for the upper one.
+BSE_DEV void tri_tile(int64_t t, int uplo, int& bx, int& by) {
+  int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  if ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
+  if ((int64_t)I * (I + 1) / 2 > t) --I;
+  const int J = (int)(t - (int64_t)I * (I + 1) / 2);
+  bx = uplo == 2 ? I : J;
+  by = uplo == 2 ? J : I;
+}
+
+template <int BM, int BN, int WM, int WN, bool G3>
+__global__ __launch_bounds__(WM* WN * 64) void zgemm_tri_kernel(ZgemmParams p, int b_off) {
+  int bx, by;
+  tri_tile((int64_t)blockIdx.x, p.c_uplo, bx, by);
+  zgemm_tile<BM, BN, WM, WN, G3>(p, bx, by, blockIdx.z + b_off);
+}
+
 // Products of different shapes and operands (blockIdx.z = item), the rest of
 // the parameters shared; the items travel by value so that every operand load
 // is a global load.
 template <int BM, int BN, int WM, int WN, bool G3>
 __global__ __launch_bounds__(WM* WN * 64) void zgemm_group_kernel(ZgemmParams base, ZgemmGroup g) {
-  const ZgemmItem& q = g.it[blockIdx.z];
-  if ((int)blockIdx.x * BM >= q.M || (int)blockIdx.y * BN >= q.N) return;
+  int i = 0;  // the item that owns this block (uniform scan of the ranges)
+  while (i + 1 < ZGEMM_GROUP_MAX && (int)blockIdx.x >= g.first[i + 1]) ++i;
+  const ZgemmItem& q = g.it[i];
+  const int64_t t = (int64_t)blockIdx.x - g.first[i];  // the item's tile
+  int bx, by;
+  if (base.c_uplo != 0 && q.M == q.N && BM == BN) {
+    tri_tile(t, base.c_uplo, bx, by);
+  } else {
+    const int gm = cdiv(q.M, BM);
+    bx = (int)(t % gm);
+    by = (int)(t / gm);
+  }
+  if (bx * BM >= q.M || by * BN >= q.N) return;
   ZgemmParams p = base;
   p.M = q.M;
   p.N = q.N;
@@ -109,22 +140,27 @@ __global__ __launch_bounds__(WM* WN * 64) void zgemm_group_kernel(ZgemmParams ba
   p.info = q.info;
   p.a_tri = q.a_tri;
   p.b_tri = q.b_tri;
-  zgemm_tile<BM, BN, WM, WN, G3>(p, blockIdx.x, blockIdx.y, 0);
+  zgemm_tile<BM, BN, WM, WN, G3>(p, bx, by, 0);
 }
 
 template <int BM, int BN, int WM, int WN, bool G3>
-hipError_t launch_group(const ZgemmParams& base, const ZgemmGroup& g, int count, hipStream_t s) {
-  int gm = 1, gn = 1;
-  for (int i = 0; i < count; ++i) {
-    gm = gm > cdiv(g.it[i].M, BM) ? gm : cdiv(g.it[i].M, BM);
-    gn = gn > cdiv(g.it[i].N, BN) ? gn : cdiv(g.it[i].N, BN);
+hipError_t launch_group(const ZgemmParams& base, ZgemmGroup g, int count, hipStream_t s) {
+  int64_t total = 0;  // compact grid: each item's tiles (its triangle's, when it stores one)
+  for (int i = 0; i < ZGEMM_GROUP_MAX; ++i) {
+    g.first[i] = (int32_t)total;
+    if (i >= count) continue;
+    const ZgemmItem& q = g.it[i];
+    const int64_t gm = cdiv(q.M, BM), gn = cdiv(q.N, BN);
+    total += (base.c_uplo != 0 && q.M == q.N && BM == BN) ? gm * (gm + 1) / 2 : gm * gn;
   }
+  g.first[ZGEMM_GROUP_MAX] = (int32_t)total;
+  if (total == 0) return hipSuccess;
   TimedLaunch tl(base.tag, s);
   if (tl.a)
-    hipExtLaunchKernelGGL((zgemm_group_kernel<BM, BN, WM, WN, G3>), dim3(gm, gn, count),
+    hipExtLaunchKernelGGL((zgemm_group_kernel<BM, BN, WM, WN, G3>), dim3((unsigned)total),
                           dim3(WM * WN * 64), 0, s, tl.a, tl.b, 0, base, g);
   else
-    hipLaunchKernelGGL((zgemm_group_kernel<BM, BN, WM, WN, G3>), dim3(gm, gn, count),
+    hipLaunchKernelGGL((zgemm_group_kernel<BM, BN, WM, WN, G3>), dim3((unsigned)total),
                        dim3(WM * WN * 64), 0, s, base, g);
   launch_check(base.tag);
   return hipGetLastError();
@@ -133,12 +169,21 @@ hipError_t launch_group(const ZgemmParams& base, const ZgemmGroup& g, int count,
 template <int BM, int BN, int WM, int WN, bool G3>
 hipError_t launch(const ZgemmParams& p, int batch, hipStream_t s) {
   TimedLaunch tl(p.tag, s);
+  const bool tri = p.c_uplo != 0 && p.M == p.N && BM == BN;  // the triangle's tiles only
+  const int64_t nt = cdiv(p.M, BM);
   // a timed product spans its first and last chunk of at most 65535 batch entries
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
-    dim3 grid(cdiv(p.M, BM), cdiv(p.N, BN), nb);
+    const dim3 grid = tri ? dim3((unsigned)(nt * (nt + 1) / 2), 1, nb)
+                          : dim3(cdiv(p.M, BM), cdiv(p.N, BN), nb);
     const bool first = b0 == 0, last = b0 + nb >= batch;
-    if (tl.a)
+    if (tri && tl.a)
+      hipExtLaunchKernelGGL((zgemm_tri_kernel<BM, BN, WM, WN, G3>), grid, dim3(WM * WN * 64), 0,
+                            s, first ? tl.a : nullptr, last ? tl.b : nullptr, 0, p, b0);
+    else if (tri)
+      hipLaunchKernelGGL((zgemm_tri_kernel<BM, BN, WM, WN, G3>), grid, dim3(WM * WN * 64), 0, s,
+                         p, b0);
+    else if (tl.a)
       hipExtLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN, G3>), grid, dim3(WM * WN * 64), 0, s,
                             first ? tl.a : nullptr, last ? tl.b : nullptr, 0, p, b0);
     else
