@@ -873,14 +873,20 @@ std::vector<std::vector<int32_t>> batch_grids(const TrdItem* it, int np) {
   };
   std::vector<std::vector<int32_t>> g(np);
   for (int p = 0; p < np; ++p) g[p].assign((size_t)std::max<int64_t>(it[p].n - 1, 0), 1);
-  const double total = (double)per_cu * device_cus();
   // global column cg: problem p reduces its column cg - shift_p (if it has one)
   for (int64_t cg = 0; cg + 1 < nmax; ++cg) {
     double sum = 0.0;
+    int nact = 0;  // problems reducing at this step
     for (int p = 0; p < np; ++p) {
       const int64_t c = cg - sh[p];
-      if (c >= 0 && c + 1 < it[p].n) sum += (double)tiles(it[p].n, c);
+      if (c >= 0 && c + 1 < it[p].n) {
+        sum += (double)tiles(it[p].n, c);
+        ++nact;
+      }
     }
+    // at most one block per CU per problem reducing: a problem alone keeps the
+    // one-per-CU grid of its own sweep
+    const double total = (double)std::min(per_cu, std::max(nact, 1)) * device_cus();
     for (int p = 0; p < np; ++p) {
       const int64_t c = cg - sh[p];
       if (c < 0 || c + 1 >= it[p].n) continue;
