@@ -843,11 +843,6 @@ void trd_parts(const TrdItem& it, double2** partA, double2** partB, double2** Y)
   *Y = *partB + hemv_tiles_max(it.n) + 1;
 }
 
-// Blocks of every problem's hemv launch for reflector c, c = 0 .. n - 2: by
-// default hemv_grid() blocks, as in the problem's own sweep; in shared mode the
-// launch for step c has `per_cu` blocks per compute unit in all, each problem
-// still reducing at c getting a share proportional to its tiles (at least one,
-// at most one per tile), so that all blocks take runs of about equal length.
 // Global panel step at which each problem of a group starts its sweep: 0 for
 // all (BSE_TUNE_BATCH_ALIGN choice 0), or late by the largest multiple of
 // TRD_NB that keeps it within the largest problem's steps (choice 1), so that
@@ -862,6 +857,12 @@ std::vector<int> batch_shifts(const TrdItem* it, int np) {
   return sh;
 }
 
+// Blocks of every problem's hemv launch for its reflector c, c = 0 .. n - 2: by
+// default hemv_grid() blocks, as in the problem's own sweep; in shared mode the
+// launch of a global step has `per_cu` blocks per compute unit in all (at most
+// one per CU per problem reducing at that step), each such problem getting a
+// share proportional to its tiles (at least one, at most one per tile), so that
+// all blocks take runs of about equal length.
 std::vector<std::vector<int32_t>> batch_grids(const TrdItem* it, int np) {
   int64_t nmax = 0;
   for (int p = 0; p < np; ++p) nmax = std::max(nmax, it[p].n);
